@@ -1,0 +1,140 @@
+/*
+ * ccsd_k.h — C ABI of libccsdk: the double-excitation (T2) residual of periodic
+ * (k-point) spin-orbital CCSD, and the iteration around it, on one AMD MI355X (gfx950).
+ *
+ * What is computed (Yamashita, Kosugi, Matsushita, Sakurai, "A Parallel Computing Method
+ * for the Coupled-Cluster Singles and Doubles", arXiv:1911.00242):
+ *   - R2: the right-hand side of the T2 equation (Sec. 2, eq. ori_EqDouble) with the
+ *     intermediates W (hole-hole, particle-particle, ring; Sec. 2 up to eq. Def_Woovv),
+ *     F (eqs. ori_F_oo, ori_F_vv, ori_F_ov) and the effective amplitudes tau, tau-tilde;
+ *   - R1: the right-hand side of the T1 equation (eq. ori_EqSingle);
+ *   - the update t <- t + D^-1 R and the convergence test of Sec. 4.4 (successive
+ *     substitution), optionally accelerated by Pulay DIIS;
+ *   - the correlation energy (not printed in the paper; the standard spin-orbital
+ *     expression  E = sum f_ia t_i^a + 1/4 sum <ij||ab> t_ij^ab + 1/2 sum <ij||ab> t_i^a t_j^b).
+ * Momentum conservation (Sec. 3.2.5): k_p + k_q = k_r + k_s modulo a reciprocal lattice
+ * vector on a Gamma-containing regular mesh.  A k label is the C-order linear index
+ * k = (k0*grid[1] + k1)*grid[2] + k2.
+ *
+ * Array layouts (host and device alike; complex numbers interleaved re, im; row-major):
+ *   fock  [N_k][n][n]                 complex128, n = n_occ + n_vir, occupied first
+ *   eri[c][kp][kq][kr][p][q][r][s]    complex128 <pq||rs>, k_s fixed by conservation,
+ *                                     c = 0..5 for classes oooo, ooov, oovv, ovvo, ovvv, vvvv
+ *   t1, r1 [k][i][a]                  complex128
+ *   t2, r2 [ki][kj][ka][i][j][a][b]   complex128, k_b fixed by conservation; every block
+ *                                     and element stored (the antisymmetric copies too)
+ *
+ * Ownership: host arrays are read or written only during the call that receives them.
+ * The device workspace is allocated by the caller (for instance a torch uint8 tensor),
+ * must stay alive until ccsd_k_free, and is owned by the context while bound.  All device
+ * work is enqueued on the HIP stream given to ccsd_k_init; calls that return host results
+ * synchronize that stream.
+ *
+ * Errors: every int function returns CCSD_K_OK (0), a positive warning, or a negative
+ * error; ccsd_k_last_error() describes the last failure.  After CCSD_K_EDEVICE the
+ * context refuses further work (CCSD_K_ESTATE).  No C++ exception crosses the ABI.
+ * A context is not thread safe; two contexts may be used from different threads.
+ */
+#ifndef CCSD_K_H
+#define CCSD_K_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCSD_K_OK 0
+#define CCSD_K_NOT_CONVERGED 1 /* iterate: max_iter reached before ||R|| < tol      */
+#define CCSD_K_EINVAL (-1)     /* bad argument, size, pointer or index                */
+#define CCSD_K_ENOMEM (-2)     /* workspace smaller than ccsd_k_workspace_bytes       */
+#define CCSD_K_EDEVICE (-3)    /* a HIP runtime call failed                            */
+#define CCSD_K_ESTATE (-4)     /* call out of order (e.g. before bind) or after EDEVICE */
+#define CCSD_K_ENUMERIC (-5)   /* non-finite residual norm or energy                   */
+
+#define CCSD_K_PREC_FP64 0  /* complex128 storage, FP64 MFMA contractions            */
+#define CCSD_K_PREC_MIXED 1 /* complex64 operands of the big contractions, split-BF16
+                               MFMA products accumulated in FP32; FP64 master amplitudes,
+                               denominators, norm, energy and DIIS                     */
+
+typedef struct ccsd_k_ctx ccsd_k_ctx;
+
+typedef struct {
+    int32_t grid[3];    /* k mesh, each >= 1; N_k = grid[0]*grid[1]*grid[2]              */
+    int32_t n_occ;      /* occupied spin orbitals per k, >= 1                           */
+    int32_t n_vir;      /* virtual spin orbitals per k, >= 1                            */
+    int32_t precision;  /* CCSD_K_PREC_FP64 or CCSD_K_PREC_MIXED                         */
+    int32_t diis_space; /* 0: plain successive substitution; 2..16: Pulay DIIS depth     */
+    int32_t synthetic;  /* 1: bind fills Fock and integrals on the device from
+                           (seed, eri_scale) by the seeded recipe; 0: ccsd_k_set_inputs  */
+    uint64_t seed;
+    double eri_scale;   /* scale of the raw complex Gaussians of the synthetic recipe   */
+} ccsd_k_system;
+
+/* Plan n_sys independent systems (1..4096).  hip_stream: a hipStream_t, or NULL for the
+ * default stream.  Validates sizes; allocates host memory only.  On failure *out is NULL
+ * and ccsd_k_last_error(NULL) holds the reason. */
+int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out);
+
+/* Device workspace, in bytes, that ccsd_k_bind_workspace needs. */
+int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes);
+
+/* Hand the context a device buffer of at least ccsd_k_workspace_bytes bytes (256-byte
+ * aligned).  Uploads the momentum and contraction tables, generates synthetic inputs
+ * where requested, and sets every amplitude to zero.  ENOMEM if bytes is too small. */
+int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes);
+
+/* Copy one system's Fock matrix and integral classes from host memory (layouts above). */
+int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]);
+
+/* One evaluation of (R1, R2) (eqs. ori_EqSingle, ori_EqDouble) for system sys.
+ * t1/t2: host amplitudes to evaluate at (they become the system's current amplitudes);
+ * NULL = the current device amplitudes.  r1/r2: host buffers for the result, or NULL to
+ * keep it on the device only. */
+int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1,
+                    double *r2);
+
+/* Iterate every unconverged system: each iteration evaluates R, its 2-norm over all
+ * stored elements of (R1, R2) and, if the norm is >= tol, applies t <- t + D^-1 R (then
+ * DIIS when diis_space > 0).  Stops when every system has ||R|| < tol or after max_iter
+ * residual evaluations.  *iters: evaluations done (max over systems); *max_rnorm: largest
+ * last norm.  Returns CCSD_K_NOT_CONVERGED if some system did not converge. */
+int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm);
+
+/* Last residual 2-norm of system sys (after ccsd_k_residual or ccsd_k_iterate). */
+int ccsd_k_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm);
+
+/* Correlation energy (supercell total, no 1/N_k) at the current amplitudes, FP64. */
+int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im);
+
+/* Copy the current (FP64 master) amplitudes out / in (checkpoint and restart). */
+int ccsd_k_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2);
+int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2);
+
+/* Algorithmic work of one residual evaluation of system sys: real flops of the five
+ * grouped products (8 per complex multiply-add) and of all other terms. */
+int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops);
+
+/* Per-stage device timing with HIP events on the context's stream (0 = off).  Stages:
+ * 0 particle-particle ladder, 1 hole-hole ladder, 2 W_mnij build, 3 ring W build,
+ * 4 ring product, 5 the whole residual evaluation (all of the above and every other term). */
+int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable);
+int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches);
+
+/* Diagnostic: dense grouped complex product C[g] = A[g] . B[g]^T on the device with the
+ * tiled FP64 MFMA kernel (reference = 0) or the one-thread-per-element kernel
+ * (reference = 1).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
+ * Allocates and frees its own device buffers; synchronizes the default stream. */
+int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
+                       double *C, int32_t reference);
+
+/* Release host state; the caller frees the workspace afterwards. NULL is ignored. */
+void ccsd_k_free(ccsd_k_ctx *ctx);
+
+/* Description of the last failure of ctx (or of ccsd_k_init when ctx is NULL). */
+const char *ccsd_k_last_error(const ccsd_k_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCSD_K_H */

@@ -1,0 +1,817 @@
+// Host driver of libccsdk: plan, workspace carving, contraction tables, the residual
+// pipeline, the iteration with optional DIIS, and the C ABI declared in include/ccsd_k.h.
+//
+// The residual follows the T2 equation of Sec. 2 of the paper (eq. ori_EqDouble), with
+// one regrouping that is exact: the 1/4 tau<mn||ef> part of W_abef is folded into the
+// hole-hole intermediate (which then carries 1/2 tau<mn||ef>), since
+//   1/2 sum_ef (1/4 sum_mn tau_mn^ab <mn||ef>) tau_ij^ef
+//     = 1/2 sum_mn tau_mn^ab (1/4 sum_ef tau_ij^ef <mn||ef>),
+// so the particle-particle ladder contracts only the T1-dressed <ab||ef>.
+#include "../../include/ccsd_k.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "terms.h"
+
+namespace {
+
+thread_local std::string g_init_error;
+
+using ck::cd;
+
+enum Stage { ST_PP = 0, ST_HH = 1, ST_WMN = 2, ST_WR = 3, ST_RING = 4, ST_RES = 5, ST_COUNT = 6 };
+
+struct Gemm {
+    ck::GemmOps<cd> op;
+    int stage;
+    size_t tab[6];  // offsets (in int64 units) of a_row, a_k, b_col, b_k, c_row, c_col in the table blob
+};
+
+struct System {
+    ccsd_k_system desc{};
+    ck::Mesh mesh{};
+    ck::Dims d{};
+    std::vector<int32_t> kc;
+    std::vector<int64_t> tables;
+    Gemm g[5];
+    // device memory (carved from the workspace)
+    cd *fock = nullptr, *eri[6] = {};
+    cd *amp = nullptr, *res = nullptr;  // [t1 | t2], [r1 | r2]
+    cd *tau = nullptr, *tauT = nullptr, *Vt = nullptr, *WT = nullptr, *WR = nullptr, *X = nullptr;
+    cd *scr = nullptr, *P1 = nullptr;
+    ck::FWork fw{};
+    double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
+    int32_t *dkc = nullptr;
+    int64_t *dtab = nullptr;
+    std::vector<cd *> dvec, derr;
+    // host state
+    int diis_n = 0, diis_head = 0;
+    std::vector<double> B;  // diis_space x diis_space error overlaps
+    double rnorm = -1.0;
+    bool converged = false, inputs = false;
+
+    int64_t n1() const { return d.t1(); }
+    int64_t n2() const { return d.t2(); }
+    cd *t1() const { return amp; }
+    cd *t2() const { return amp + n1(); }
+    cd *r1() const { return res; }
+    cd *r2() const { return res + n1(); }
+    ck::SysDev dev() const {
+        ck::SysDev s;
+        s.d = d;
+        s.kc = dkc;
+        s.eo = eo;
+        s.ev = ev;
+        s.fock = fock;
+        s.oooo = eri[0];
+        s.ooov = eri[1];
+        s.oovv = eri[2];
+        s.ovvo = eri[3];
+        s.ovvv = eri[4];
+        s.vvvv = eri[5];
+        return s;
+    }
+};
+
+struct EventPair {
+    hipEvent_t a, b;
+    int stage;
+};
+
+}  // namespace
+
+struct ccsd_k_ctx {
+    std::vector<System> sys;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    bool bound = false, failed = false;
+    std::string err;
+    bool timing = false;
+    std::vector<EventPair> pending, pool;
+    double stage_ms[ST_COUNT] = {};
+    int64_t stage_n[ST_COUNT] = {};
+};
+
+namespace {
+
+int fail(ccsd_k_ctx *c, int code, const std::string &msg) {
+    if (c) {
+        c->err = msg;
+        if (code == CCSD_K_EDEVICE) c->failed = true;
+    } else {
+        g_init_error = msg;
+    }
+    return code;
+}
+
+int kcons(const ck::Mesh &m, int kp, int kq, int kr) {
+    int p2 = kp % m.g2, q2 = kq % m.g2, r2 = kr % m.g2;
+    int p1 = (kp / m.g2) % m.g1, q1 = (kq / m.g2) % m.g1, r1 = (kr / m.g2) % m.g1;
+    int p0 = kp / (m.g2 * m.g1), q0 = kq / (m.g2 * m.g1), r0 = kr / (m.g2 * m.g1);
+    int s0 = ((p0 + q0 - r0) % m.g0 + m.g0) % m.g0;
+    int s1 = ((p1 + q1 - r1) % m.g1 + m.g1) % m.g1;
+    int s2 = ((p2 + q2 - r2) % m.g2 + m.g2) % m.g2;
+    return (s0 * m.g1 + s1) * m.g2 + s2;
+}
+
+// ---------------------------------------------------------------- contraction tables
+// Offsets in complex elements.  Group label: total pair momentum K for the ladder
+// family, momentum transfer q for the ring family.
+void build_tables(System &S) {
+    const int64_t N = S.d.N, o = S.d.no, v = S.d.nv;
+    const int64_t oo = o * o, vv = v * v, ov = o * v, t2b = oo * vv, o4 = oo * oo, v4 = vv * vv;
+    auto kc = [&](int a, int b, int c) { return (int64_t)S.kc[((int64_t)a * N + b) * N + c]; };
+    std::vector<int64_t> &T = S.tables;
+    T.clear();
+    auto put = [&](Gemm &g, int which, int64_t len, auto fn) {
+        g.tab[which] = T.size();
+        for (int64_t x = 0; x < len; ++x) T.push_back(fn(x));
+    };
+    const int64_t Mpp = N * oo, Npp = N * vv, Mph = N * ov;
+
+    // G1: W_mnij(T) += 1/2 tau . <mn||ef>^T       rows (ki,i,j), cols (km,m,n), k (ke,e,f)
+    // G2: r2 += 1/2 tau . Vt^T                      rows (ki,i,j), cols (ka,a,b), k (ke,e,f)
+    // G3: r2 += 1/2 W_mnij(T) . tauT                rows (ki,i,j), cols (ka,a,b), k (km,m,n)
+    auto row_t2 = [&](int64_t K, int64_t x) {  // (ki,i,j) -> t2/r2 block [ki][K-ki][.]
+        int64_t ki = x / oo, ij = x % oo;
+        return ((ki * N + kc(K, 0, ki)) * N) * t2b + ij * vv;
+    };
+    auto row_wt = [&](int64_t K, int64_t x) {
+        int64_t ki = x / oo, ij = x % oo;
+        return ((ki * N + kc(K, 0, ki)) * N) * o4 + ij * oo;
+    };
+    Gemm &g1 = S.g[0], &g2 = S.g[1], &g3 = S.g[2], &g4 = S.g[3], &g5 = S.g[4];
+    put(g1, 0, N * Mpp, [&](int64_t x) { return row_t2(x / Mpp, x % Mpp); });
+    put(g1, 1, N * Npp, [&](int64_t x) { int64_t y = x % Npp; return (y / vv) * t2b + y % vv; });
+    put(g1, 2, N * Mpp, [&](int64_t x) {
+        int64_t K = x / Mpp, y = x % Mpp, km = y / oo;
+        return ((km * N + kc(K, 0, km)) * N) * t2b + (y % oo) * vv;
+    });
+    g1.tab[3] = g1.tab[1];
+    put(g1, 4, N * Mpp, [&](int64_t x) { return row_wt(x / Mpp, x % Mpp); });
+    put(g1, 5, N * Mpp, [&](int64_t x) { int64_t y = x % Mpp; return (y / oo) * o4 + y % oo; });
+    g1.op.G = (int)N; g1.op.M = (int)Mpp; g1.op.N = (int)Mpp; g1.op.K = (int)Npp;
+    g1.op.alpha = 0.5; g1.op.beta = 1.0; g1.stage = ST_WMN;
+
+    g2.tab[0] = g1.tab[0];
+    g2.tab[1] = g1.tab[1];
+    put(g2, 2, N * Npp, [&](int64_t x) {
+        int64_t K = x / Npp, y = x % Npp, ka = y / vv;
+        return ((ka * N + kc(K, 0, ka)) * N) * v4 + (y % vv) * vv;
+    });
+    put(g2, 3, N * Npp, [&](int64_t x) { int64_t y = x % Npp; return (y / vv) * v4 + y % vv; });
+    g2.tab[4] = g1.tab[0];
+    put(g2, 5, N * Npp, [&](int64_t x) { int64_t y = x % Npp; return (y / vv) * t2b + y % vv; });
+    g2.op.G = (int)N; g2.op.M = (int)Mpp; g2.op.N = (int)Npp; g2.op.K = (int)Npp;
+    g2.op.alpha = 0.5; g2.op.beta = 1.0; g2.stage = ST_PP;
+
+    g3.tab[0] = g1.tab[4];
+    g3.tab[1] = g1.tab[5];
+    put(g3, 2, N * Npp, [&](int64_t x) { int64_t y = x % Npp; return (y / vv) * t2b + (y % vv) * oo; });
+    put(g3, 3, N * Mpp, [&](int64_t x) {
+        int64_t K = x / Mpp, y = x % Mpp, km = y / oo;
+        return ((km * N + kc(K, 0, km)) * N) * t2b + y % oo;
+    });
+    g3.tab[4] = g2.tab[4];
+    g3.tab[5] = g2.tab[5];
+    g3.op.G = (int)N; g3.op.M = (int)Mpp; g3.op.N = (int)Npp; g3.op.K = (int)Mpp;
+    g3.op.alpha = 0.5; g3.op.beta = 1.0; g3.stage = ST_HH;
+
+    // G4: WR += 1/2 t_{jn}^{bf} <mn||ef>   rows (kj,j,b), cols (km,m,e), k (kn,n,f)
+    // G5: X  += t_{im}^{ae} W_mbej          rows (ki,i,a), cols (kj,j,b), k (km,m,e)
+    put(g4, 0, N * Mph, [&](int64_t x) {
+        int64_t q = x / Mph, y = x % Mph, kj = y / ov, j = (y % ov) / v, b = y % v;
+        return (kj * N * N + kc(kj, 0, q)) * t2b + j * o * vv + b * v;
+    });
+    put(g4, 1, N * Mph, [&](int64_t x) {
+        int64_t y = x % Mph, kn = y / ov, n = (y % ov) / v, f = y % v;
+        return kn * N * t2b + n * vv + f;
+    });
+    put(g4, 2, N * Mph, [&](int64_t x) {
+        int64_t q = x / Mph, y = x % Mph, km = y / ov, m = (y % ov) / v, e = y % v;
+        return (km * N * N + kc(km, 0, q)) * t2b + m * o * vv + e * v;
+    });
+    g4.tab[3] = g4.tab[1];
+    put(g4, 4, N * Mph, [&](int64_t x) {
+        int64_t q = x / Mph, y = x % Mph, kj = y / ov;
+        return ((q * N + kj) * N) * ov * ov + (y % ov) * ov;
+    });
+    put(g4, 5, N * Mph, [&](int64_t x) { int64_t y = x % Mph; return (y / ov) * ov * ov + y % ov; });
+    g4.op.G = (int)N; g4.op.M = (int)Mph; g4.op.N = (int)Mph; g4.op.K = (int)Mph;
+    g4.op.alpha = 0.5; g4.op.beta = 1.0; g4.stage = ST_WR;
+
+    put(g5, 0, N * Mph, [&](int64_t x) {
+        int64_t q = x / Mph, y = x % Mph, ki = y / ov, i = (y % ov) / v, a = y % v;
+        return (ki * N * N + kc(ki, q, 0)) * t2b + i * o * vv + a * v;
+    });
+    put(g5, 1, N * Mph, [&](int64_t x) {
+        int64_t y = x % Mph, km = y / ov, m = (y % ov) / v, e = y % v;
+        return km * N * t2b + m * vv + e;
+    });
+    g5.tab[2] = g4.tab[4];
+    g5.tab[3] = g4.tab[5];
+    put(g5, 4, N * Mph, [&](int64_t x) {
+        int64_t q = x / Mph, y = x % Mph, ki = y / ov;
+        return ((q * N + ki) * N) * ov * ov + (y % ov) * ov;
+    });
+    put(g5, 5, N * Mph, [&](int64_t x) { int64_t y = x % Mph; return (y / ov) * ov * ov + y % ov; });
+    g5.op.G = (int)N; g5.op.M = (int)Mph; g5.op.N = (int)Mph; g5.op.K = (int)Mph;
+    g5.op.alpha = 1.0; g5.op.beta = 1.0; g5.stage = ST_RING;
+}
+
+// ---------------------------------------------------------------- workspace plan
+struct Carver {
+    uintptr_t base, off = 0;
+    bool assign;
+    template <class T>
+    void take(T *&p, int64_t count) {
+        off = (off + 255) & ~(uintptr_t)255;
+        if (assign) p = reinterpret_cast<T *>(base + off);
+        off += (uintptr_t)count * sizeof(T);
+    }
+};
+
+void carve(System &S, Carver &c) {
+    const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, n = o + v, N3 = N * N * N;
+    const int64_t cls[6] = {o * o * o * o, o * o * o * v, o * o * v * v, o * v * v * o, o * v * v * v, v * v * v * v};
+    c.take(S.fock, N * n * n);
+    for (int i = 0; i < 6; ++i) c.take(S.eri[i], N3 * cls[i]);
+    c.take(S.amp, S.n1() + S.n2());
+    c.take(S.res, S.n1() + S.n2());
+    c.take(S.tau, S.n2());
+    c.take(S.tauT, S.n2());
+    c.take(S.Vt, N3 * cls[5]);
+    c.take(S.WT, N3 * cls[0]);
+    c.take(S.WR, N3 * o * v * o * v);
+    c.take(S.X, N3 * o * v * o * v);
+    c.take(S.scr, N3 * o * o * o * v);
+    c.take(S.P1, N * N * o * v);
+    c.take(S.fw.Fov, N * o * v);
+    c.take(S.fw.Foo, N * o * o);
+    c.take(S.fw.Fvv, N * v * v);
+    c.take(S.fw.Fot, N * o * o);
+    c.take(S.fw.Fvt, N * v * v);
+    c.take(S.fw.Poo, N * N * o * o);
+    c.take(S.fw.Pvv, N * N * v * v);
+    c.take(S.eo, N * o);
+    c.take(S.ev, N * v);
+    c.take(S.red, 16 * ck::RED_BLOCKS);
+    c.take(S.redout, 32);
+    c.take(S.dkc, N3);
+    c.take(S.dtab, (int64_t)S.tables.size());
+    int m = S.desc.diis_space;
+    S.dvec.assign(m, nullptr);
+    S.derr.assign(m, nullptr);
+    for (int i = 0; i < m; ++i) {
+        c.take(S.dvec[i], S.n1() + S.n2());
+        c.take(S.derr[i], S.n1() + S.n2());
+    }
+}
+
+void bind_ops(System &S) {
+    const int64_t *T = S.dtab;
+    const cd *A[5] = {S.tau, S.tau, S.WT, S.t2(), S.t2()};
+    const cd *Bm[5] = {S.eri[2], S.Vt, S.tauT, S.eri[2], S.WR};
+    cd *C[5] = {S.WT, S.r2(), S.r2(), S.WR, S.X};
+    for (int i = 0; i < 5; ++i) {
+        Gemm &g = S.g[i];
+        g.op.A = A[i];
+        g.op.B = Bm[i];
+        g.op.C = C[i];
+        g.op.a_row = T + g.tab[0];
+        g.op.a_k = T + g.tab[1];
+        g.op.b_col = T + g.tab[2];
+        g.op.b_k = T + g.tab[3];
+        g.op.c_row = T + g.tab[4];
+        g.op.c_col = T + g.tab[5];
+    }
+}
+
+// ---------------------------------------------------------------- timing
+void stage_begin(ccsd_k_ctx *c, EventPair &ep, int stage) {
+    if (!c->timing) return;
+    if (c->pool.empty()) {
+        EventPair p;
+        CK_CHECK(hipEventCreate(&p.a));
+        CK_CHECK(hipEventCreate(&p.b));
+        c->pool.push_back(p);
+    }
+    ep = c->pool.back();
+    c->pool.pop_back();
+    ep.stage = stage;
+    CK_CHECK(hipEventRecord(ep.a, c->stream));
+}
+void stage_end(ccsd_k_ctx *c, EventPair &ep) {
+    if (!c->timing) return;
+    CK_CHECK(hipEventRecord(ep.b, c->stream));
+    c->pending.push_back(ep);
+}
+void collect_timing(ccsd_k_ctx *c) {
+    if (c->pending.empty()) return;
+    CK_CHECK(hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        CK_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
+        c->stage_ms[p.stage] += ms;
+        c->stage_n[p.stage] += 1;
+        c->pool.push_back(p);
+    }
+    c->pending.clear();
+}
+
+void run_gemm(ccsd_k_ctx *c, System &S, int i) {
+    EventPair ep{};
+    stage_begin(c, ep, S.g[i].stage);
+    ck::gemm_f64(S.g[i].op, c->stream);
+    stage_end(c, ep);
+}
+
+// One evaluation of (R1, R2) at the current amplitudes, left in S.res.
+void residual_device(ccsd_k_ctx *c, System &S) {
+    hipStream_t st = c->stream;
+    ck::SysDev s = S.dev();
+    EventPair all{};
+    stage_begin(c, all, ST_RES);
+    ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
+    ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
+    ck::launch_wmnij_init(s, S.t1(), S.WT, st);
+    run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>
+    ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+    ck::launch_ring_init(s, S.t1(), S.scr, S.WR, S.X, st);
+    run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
+    run_gemm(c, S, 4);  // X += t2 W_mbej
+    ck::launch_assemble_r2(s, S.t1(), S.t2(), S.fw, S.X, S.r2(), st);
+    run_gemm(c, S, 1);  // particle-particle ladder
+    run_gemm(c, S, 2);  // hole-hole ladder
+    ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
+    stage_end(c, all);
+}
+
+double read_scalar(ccsd_k_ctx *c, const double *dptr) {
+    double h = 0.0;
+    CK_CHECK(hipMemcpyAsync(&h, dptr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CK_CHECK(hipStreamSynchronize(c->stream));
+    return h;
+}
+
+int check_ctx(ccsd_k_ctx *c, bool need_bound = true) {
+    if (!c) return CCSD_K_EINVAL;
+    if (c->failed) return fail(c, CCSD_K_ESTATE, "context is unusable after a device error: " + c->err);
+    if (need_bound && !c->bound) return fail(c, CCSD_K_ESTATE, "no workspace bound");
+    return CCSD_K_OK;
+}
+
+int check_sys(ccsd_k_ctx *c, int32_t sys, bool need_inputs = true) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (sys < 0 || sys >= (int32_t)c->sys.size()) return fail(c, CCSD_K_EINVAL, "system index out of range");
+    if (need_inputs && !c->sys[sys].inputs)
+        return fail(c, CCSD_K_ESTATE, "inputs of system " + std::to_string(sys) + " not set");
+    return CCSD_K_OK;
+}
+
+// Pulay DIIS step on [t1|t2] after the Jacobi update (error = R/D).  Solves the bordered
+// system of error overlaps on the host in FP64 (Gaussian elimination with pivoting).
+bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &c) {
+    int n = m + 1;
+    std::vector<double> A((size_t)n * n, 0.0), r(n, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) A[i * n + j] = B[i * m + j];
+    for (int i = 0; i < m; ++i) A[i * n + m] = A[m * n + i] = 1.0;
+    r[m] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < n; ++i)
+            if (std::fabs(A[i * n + col]) > std::fabs(A[piv * n + col])) piv = i;
+        if (A[piv * n + col] == 0.0) return false;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) std::swap(A[col * n + j], A[piv * n + j]);
+            std::swap(r[col], r[piv]);
+        }
+        for (int i = col + 1; i < n; ++i) {
+            double f = A[i * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j) A[i * n + j] -= f * A[col * n + j];
+            r[i] -= f * r[col];
+        }
+    }
+    std::vector<double> x(n, 0.0);
+    for (int i = n - 1; i >= 0; --i) {
+        double s = r[i];
+        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+        x[i] = s / A[i * n + i];
+    }
+    c.assign(x.begin(), x.begin() + m);
+    return true;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out) {
+    if (out) *out = nullptr;
+    if (!sys || !out) return fail(nullptr, CCSD_K_EINVAL, "null argument");
+    if (n_sys < 1 || n_sys > 4096) return fail(nullptr, CCSD_K_EINVAL, "n_sys must be in 1..4096");
+    auto *c = new ccsd_k_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    c->sys.resize(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+        const ccsd_k_system &d = sys[s];
+        System &S = c->sys[s];
+        S.desc = d;
+        std::string id = "system " + std::to_string(s) + ": ";
+        if (d.grid[0] < 1 || d.grid[1] < 1 || d.grid[2] < 1 || (int64_t)d.grid[0] * d.grid[1] * d.grid[2] > 4096) {
+            delete c;
+            return fail(nullptr, CCSD_K_EINVAL, id + "grid entries must be >= 1 with N_k <= 4096");
+        }
+        if (d.n_occ < 1 || d.n_vir < 1 || d.n_occ > 256 || d.n_vir > 256) {
+            delete c;
+            return fail(nullptr, CCSD_K_EINVAL, id + "n_occ and n_vir must be in 1..256");
+        }
+        if (d.precision != CCSD_K_PREC_FP64) {
+            delete c;
+            return fail(nullptr, CCSD_K_EINVAL, id + "unsupported precision");
+        }
+        if (d.diis_space != 0 && (d.diis_space < 2 || d.diis_space > 16)) {
+            delete c;
+            return fail(nullptr, CCSD_K_EINVAL, id + "diis_space must be 0 or 2..16");
+        }
+        if (d.synthetic && !(d.eri_scale > 0.0 && std::isfinite(d.eri_scale))) {
+            delete c;
+            return fail(nullptr, CCSD_K_EINVAL, id + "eri_scale must be positive");
+        }
+        S.mesh = ck::Mesh{d.grid[0], d.grid[1], d.grid[2], d.grid[0] * d.grid[1] * d.grid[2]};
+        S.d = ck::Dims{S.mesh.N, d.n_occ, d.n_vir};
+        int64_t N = S.mesh.N;
+        S.kc.resize(N * N * N);
+        for (int a = 0; a < N; ++a)
+            for (int b = 0; b < N; ++b)
+                for (int k = 0; k < N; ++k) S.kc[((int64_t)a * N + b) * N + k] = kcons(S.mesh, a, b, k);
+        build_tables(S);
+        S.B.assign((size_t)d.diis_space * d.diis_space, 0.0);
+    }
+    *out = c;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
+    if (!ctx || !bytes) return CCSD_K_EINVAL;
+    Carver cv{0, 0, false};
+    for (auto &S : const_cast<ccsd_k_ctx *>(ctx)->sys) carve(S, cv);
+    *bytes = cv.off + 256;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    if (ctx->bound) return fail(ctx, CCSD_K_ESTATE, "workspace already bound");
+    if (!device_ptr || ((uintptr_t)device_ptr & 255)) return fail(ctx, CCSD_K_EINVAL, "workspace must be 256-byte aligned");
+    uint64_t need = 0;
+    ccsd_k_workspace_bytes(ctx, &need);
+    if (bytes < need)
+        return fail(ctx, CCSD_K_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    try {
+        Carver cv{(uintptr_t)device_ptr, 0, true};
+        for (auto &S : ctx->sys) carve(S, cv);
+        for (auto &S : ctx->sys) {
+            CK_CHECK(hipMemcpyAsync(S.dkc, S.kc.data(), S.kc.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+            CK_CHECK(hipMemcpyAsync(S.dtab, S.tables.data(), S.tables.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                                    ctx->stream));
+            CK_CHECK(hipMemsetAsync(S.amp, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            CK_CHECK(hipMemsetAsync(S.res, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            bind_ops(S);
+            if (S.desc.synthetic) {
+                static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
+                ck::launch_synth_fock(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.fock, ctx->stream);
+                for (int i = 0; i < 6; ++i)
+                    ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
+                                         ctx->stream);
+                ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+                S.inputs = true;
+            }
+        }
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    ctx->ws = (char *)device_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->bound = true;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    if (!fock || !eri) return fail(ctx, CCSD_K_EINVAL, "null input");
+    for (int i = 0; i < 6; ++i)
+        if (!eri[i]) return fail(ctx, CCSD_K_EINVAL, "null integral class");
+    System &S = ctx->sys[sys];
+    const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, n = o + v, N3 = N * N * N;
+    const int64_t cls[6] = {o * o * o * o, o * o * o * v, o * o * v * v, o * v * v * o, o * v * v * v, v * v * v * v};
+    // denominators need f_ii != f_aa for every pair (Sec. 4.4 divides by D)
+    for (int64_t k = 0; k < N; ++k)
+        for (int64_t i = 0; i < o; ++i)
+            for (int64_t a = 0; a < v; ++a) {
+                double fi = fock[2 * ((k * n + i) * n + i)], fa = fock[2 * ((k * n + o + a) * n + o + a)];
+                if (!(std::isfinite(fi) && std::isfinite(fa)) || fi == fa)
+                    return fail(ctx, CCSD_K_EINVAL, "orbital energies give a zero or non-finite denominator");
+            }
+    try {
+        CK_CHECK(hipMemcpyAsync(S.fock, fock, N * n * n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        for (int i = 0; i < 6; ++i)
+            CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    S.inputs = true;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1, double *r2) {
+    int rc = check_sys(ctx, sys);
+    if (rc) return rc;
+    System &S = ctx->sys[sys];
+    try {
+        if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        residual_device(ctx, S);
+        ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, ctx->stream);
+        S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
+        if (r1) CK_CHECK(hipMemcpyAsync(r1, S.r1(), S.n1() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        if (r2) CK_CHECK(hipMemcpyAsync(r2, S.r2(), S.n2() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+        collect_timing(ctx);
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    if (!std::isfinite(S.rnorm)) return fail(ctx, CCSD_K_ENUMERIC, "non-finite residual norm");
+    return CCSD_K_OK;
+}
+
+int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (max_iter < 0 || !(tol >= 0.0)) return fail(ctx, CCSD_K_EINVAL, "bad max_iter or tol");
+    for (size_t s = 0; s < ctx->sys.size(); ++s)
+        if (!ctx->sys[s].inputs) return fail(ctx, CCSD_K_ESTATE, "inputs of system " + std::to_string(s) + " not set");
+    int done = 0;
+    bool numeric_error = false;
+    try {
+        for (auto &S : ctx->sys) S.converged = false;
+        for (int it = 0; it < max_iter; ++it) {
+            std::vector<System *> active;
+            for (auto &S : ctx->sys)
+                if (!S.converged) active.push_back(&S);
+            if (active.empty()) break;
+            for (System *S : active) {
+                residual_device(ctx, *S);
+                ck::launch_norm2(S->d, S->r1(), S->r2(), S->red, S->redout, ctx->stream);
+            }
+            CK_CHECK(hipStreamSynchronize(ctx->stream));
+            done = it + 1;
+            std::vector<System *> upd;
+            for (System *S : active) {
+                double h = 0.0;
+                CK_CHECK(hipMemcpy(&h, S->redout, sizeof(double), hipMemcpyDeviceToHost));
+                S->rnorm = std::sqrt(h);
+                if (!std::isfinite(S->rnorm)) numeric_error = true;
+                if (S->rnorm < tol) S->converged = true;
+                else upd.push_back(S);
+            }
+            if (numeric_error) break;
+            for (System *S : upd) {
+                ck::SysDev sd = S->dev();
+                int m = S->desc.diis_space;
+                if (m == 0) {
+                    ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, ctx->stream);
+                    continue;
+                }
+                int slot = S->diis_head;
+                cd *err = S->derr[slot];
+                ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), err, err + S->n1(), ctx->stream);
+                ck::launch_copy(S->n1() + S->n2(), S->amp, S->dvec[slot], ctx->stream);
+                int held = std::min(S->diis_n + 1, m);
+                std::vector<const cd *> ys(held);
+                for (int j = 0; j < held; ++j) ys[j] = S->derr[j];
+                ck::launch_dots(S->n1() + S->n2(), err, ys.data(), held, S->red, S->redout, ctx->stream);
+            }
+            CK_CHECK(hipStreamSynchronize(ctx->stream));
+            for (System *S : upd) {
+                int m = S->desc.diis_space;
+                if (m == 0) continue;
+                int slot = S->diis_head;
+                int held = std::min(S->diis_n + 1, m);
+                double dots[16];
+                CK_CHECK(hipMemcpy(dots, S->redout, held * sizeof(double), hipMemcpyDeviceToHost));
+                for (int j = 0; j < held; ++j) S->B[slot * m + j] = S->B[j * m + slot] = dots[j];
+                S->diis_n = held;
+                S->diis_head = (slot + 1) % m;
+                if (held < 2) continue;
+                // the held slots in FIFO order do not matter for the solution
+                std::vector<double> Bs((size_t)held * held), coef;
+                for (int i = 0; i < held; ++i)
+                    for (int j = 0; j < held; ++j) Bs[i * held + j] = S->B[i * m + j];
+                if (!diis_solve(Bs, held, coef)) continue;
+                std::vector<const cd *> src(held);
+                for (int j = 0; j < held; ++j) src[j] = S->dvec[j];
+                ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), held, S->amp, ctx->stream);
+            }
+            CK_CHECK(hipStreamSynchronize(ctx->stream));
+            collect_timing(ctx);
+        }
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    double worst = 0.0;
+    bool all = true;
+    for (auto &S : ctx->sys) {
+        worst = std::max(worst, S.rnorm);
+        all = all && S.converged;
+    }
+    if (iters) *iters = done;
+    if (max_rnorm) *max_rnorm = worst;
+    if (numeric_error) return fail(ctx, CCSD_K_ENUMERIC, "non-finite residual norm");
+    return all ? CCSD_K_OK : CCSD_K_NOT_CONVERGED;
+}
+
+int ccsd_k_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    if (!rnorm) return CCSD_K_EINVAL;
+    *rnorm = ctx->sys[sys].rnorm;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
+    int rc = check_sys(ctx, sys);
+    if (rc) return rc;
+    System &S = ctx->sys[sys];
+    double e[2] = {0.0, 0.0};
+    try {
+        ck::launch_energy(S.dev(), S.t1(), S.t2(), S.red, S.redout, ctx->stream);
+        CK_CHECK(hipMemcpyAsync(e, S.redout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &er) {
+        return fail(ctx, CCSD_K_EDEVICE, er.what);
+    }
+    if (e_re) *e_re = e[0];
+    if (e_im) *e_im = e[1];
+    if (!std::isfinite(e[0]) || !std::isfinite(e[1])) return fail(ctx, CCSD_K_ENUMERIC, "non-finite energy");
+    return CCSD_K_OK;
+}
+
+int ccsd_k_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    System &S = ctx->sys[sys];
+    try {
+        if (t1) CK_CHECK(hipMemcpyAsync(t1, S.t1(), S.n1() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        if (t2) CK_CHECK(hipMemcpyAsync(t2, S.t2(), S.n2() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    return CCSD_K_OK;
+}
+
+int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    System &S = ctx->sys[sys];
+    try {
+        if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    S.diis_n = 0;
+    S.diis_head = 0;
+    S.converged = false;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops) {
+    if (!ctx || sys < 0 || sys >= (int32_t)ctx->sys.size()) return CCSD_K_EINVAL;
+    const ck::Dims &d = ctx->sys[sys].d;
+    double N = d.N, o = d.no, v = d.nv;
+    double N4 = N * N * N * N;
+    double macs = N4 * o * o * v * v * v * v      // particle-particle ladder
+                  + 2.0 * N4 * o * o * o * o * v * v  // W_mnij build + hole-hole ladder
+                  + 2.0 * N4 * o * o * o * v * v * v;  // ring W build + ring product
+    if (gemm_flops) *gemm_flops = 8.0 * macs;
+    double N3 = N * N * N;
+    double small = N3 * (o * v * v * v * v * 2.0     // T1 dressing of <ab||ef>
+                         + o * o * v * v * (4.0 * (o + v))  // assembly
+                         + 2.0 * o * o * o * v * v           // ring seeds
+                         + o * o * v * v * (v + o))          // W_mbej seed
+                  + N3 * N * (o * o * o * v * v + o * o * v * v * v) * 2.0;  // F and R1 sums
+    if (other_flops) *other_flops = 8.0 * small;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
+    if (!ctx) return CCSD_K_EINVAL;
+    try {
+        collect_timing(ctx);
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    ctx->timing = enable != 0;
+    for (int i = 0; i < ST_COUNT; ++i) {
+        ctx->stage_ms[i] = 0.0;
+        ctx->stage_n[i] = 0;
+    }
+    return CCSD_K_OK;
+}
+
+int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches) {
+    if (!ctx || stage < 0 || stage >= ST_COUNT) return CCSD_K_EINVAL;
+    try {
+        collect_timing(ctx);
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    if (total_ms) *total_ms = ctx->stage_ms[stage];
+    if (launches) *launches = ctx->stage_n[stage];
+    return CCSD_K_OK;
+}
+
+int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
+                       int32_t reference) {
+    if (G < 1 || M < 1 || N < 1 || K < 0 || !A || !B || !C) return fail(nullptr, CCSD_K_EINVAL, "bad gemm arguments");
+    std::vector<int64_t> tab;
+    size_t o_arow = tab.size();
+    for (int g = 0; g < G; ++g)
+        for (int m = 0; m < M; ++m) tab.push_back(((int64_t)g * M + m) * K);
+    size_t o_k = tab.size();
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < K; ++k) tab.push_back(k);
+    size_t o_bcol = tab.size();
+    for (int g = 0; g < G; ++g)
+        for (int n = 0; n < N; ++n) tab.push_back(((int64_t)g * N + n) * K);
+    size_t o_crow = tab.size();
+    for (int g = 0; g < G; ++g)
+        for (int m = 0; m < M; ++m) tab.push_back(((int64_t)g * M + m) * N);
+    size_t o_ccol = tab.size();
+    for (int g = 0; g < G; ++g)
+        for (int n = 0; n < N; ++n) tab.push_back(n);
+    const size_t na = (size_t)G * M * K, nb = (size_t)G * N * K, nc = (size_t)G * M * N;
+    cd *dA = nullptr, *dB = nullptr, *dC = nullptr;
+    int64_t *dT = nullptr;
+    int rc = CCSD_K_OK;
+    try {
+        CK_CHECK(hipMalloc(&dA, std::max<size_t>(na, 1) * sizeof(cd)));
+        CK_CHECK(hipMalloc(&dB, std::max<size_t>(nb, 1) * sizeof(cd)));
+        CK_CHECK(hipMalloc(&dC, nc * sizeof(cd)));
+        CK_CHECK(hipMalloc(&dT, tab.size() * sizeof(int64_t)));
+        CK_CHECK(hipMemcpy(dA, A, na * sizeof(cd), hipMemcpyHostToDevice));
+        CK_CHECK(hipMemcpy(dB, B, nb * sizeof(cd), hipMemcpyHostToDevice));
+        CK_CHECK(hipMemcpy(dT, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        CK_CHECK(hipMemset(dC, 0, nc * sizeof(cd)));
+        ck::GemmOps<cd> op{};
+        op.A = dA; op.B = dB; op.C = dC;
+        op.a_row = dT + o_arow; op.a_k = dT + o_k; op.b_col = dT + o_bcol; op.b_k = dT + o_k;
+        op.c_row = dT + o_crow; op.c_col = dT + o_ccol;
+        op.G = G; op.M = M; op.N = N; op.K = K; op.alpha = 1.0; op.beta = 0.0;
+        if (reference) ck::gemm_f64_reference(op, nullptr);
+        else ck::gemm_f64(op, nullptr);
+        CK_CHECK(hipDeviceSynchronize());
+        CK_CHECK(hipMemcpy(C, dC, nc * sizeof(cd), hipMemcpyDeviceToHost));
+    } catch (const ck::HipError &e) {
+        rc = fail(nullptr, CCSD_K_EDEVICE, e.what);
+    }
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dC);
+    (void)hipFree(dT);
+    return rc;
+}
+
+void ccsd_k_free(ccsd_k_ctx *ctx) {
+    if (!ctx) return;
+    if (!ctx->failed) {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto &p : ctx->pending) ctx->pool.push_back(p);
+        for (auto &p : ctx->pool) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    }
+    delete ctx;
+}
+
+const char *ccsd_k_last_error(const ccsd_k_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal declarations shared by the HIP translation units of libccsdk.
+// Complex numbers are interleaved (re, im): double2 in FP64 storage, float2 in FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#define CK_CHECK(expr)                                                           \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) throw ck::HipError(e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+namespace ck {
+
+struct HipError {
+    hipError_t code;
+    std::string what;
+    HipError(hipError_t c, const char *expr, const char *file, int line)
+        : code(c),
+          what(std::string(hipGetErrorString(c)) + " in " + expr + " at " + file + ":" +
+               std::to_string(line)) {}
+};
+
+using cd = double2;
+using cf = float2;
+
+__host__ __device__ inline cd cmul(cd a, cd b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cd cadd(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cd cscale(cd a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline cd cconj(cd a) { return make_double2(a.x, -a.y); }
+// a += b * c
+__host__ __device__ inline void cfma(cd &a, cd b, cd c) {
+    a.x = fma(b.x, c.x, fma(-b.y, c.y, a.x));
+    a.y = fma(b.x, c.y, fma(b.y, c.x, a.y));
+}
+
+// Momentum mesh: k labels are C-order linear indices into grid[0] x grid[1] x grid[2].
+struct Mesh {
+    int g0, g1, g2, N;
+};
+
+// Sizes of one system.
+struct Dims {
+    int N, no, nv;
+    __host__ __device__ int64_t t1() const { return (int64_t)N * no * nv; }
+    __host__ __device__ int64_t t2blk() const { return (int64_t)no * no * nv * nv; }
+    __host__ __device__ int64_t t2() const { return (int64_t)N * N * N * t2blk(); }
+};
+
+// Device views of one system's arrays (FP64 storage).
+struct SysDev {
+    Dims d;
+    const int32_t *kc;  // [N][N][N] k_s = k_p + k_q - k_r
+    const double *eo;   // [N][no]   occupied orbital energies (Fock diagonal)
+    const double *ev;   // [N][nv]   virtual orbital energies
+    const cd *fock;     // [N][n][n]
+    const cd *oooo, *ooov, *oovv, *ovvo, *ovvv, *vvvv;  // [kp][kq][kr][p][q][r][s]
+};
+
+// ---------------------------------------------------------------------------------
+// Grouped complex GEMM with gathered operands (all element offsets in complex units):
+//   C(g,m,n) = alpha * sum_k A(g,m,k) * B(g,k,n) + beta * C(g,m,n)
+//   A(g,m,k) = A[a_row[g*M+m] + a_k[g*K+k]],  B(g,k,n) = B[b_col[g*N+n] + b_k[g*K+k]]
+//   C(g,m,n) = C[c_row[g*M+m] + c_col[g*N+n]]
+// ---------------------------------------------------------------------------------
+template <class T>
+struct GemmOps {
+    const T *A;
+    const T *B;
+    T *C;
+    const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
+    int G, M, N, K;
+    double alpha, beta;
+};
+
+void gemm_f64(const GemmOps<cd> &op, hipStream_t s);
+void gemm_f64_reference(const GemmOps<cd> &op, hipStream_t s);
+
+}  // namespace ck

@@ -1,0 +1,47 @@
+// Launchers of the residual's elementwise / small-contraction kernels and of the
+// reductions, update and DIIS kernels (internal to libccsdk).
+#pragma once
+#include "common.h"
+
+namespace ck {
+
+struct FWork {
+    cd *Fov, *Foo, *Fvv;  // [N][o][v], [N][o][o], [N][v][v]
+    cd *Fot, *Fvt;        // [N][o][o], [N][v][v]
+    cd *Poo, *Pvv;        // [N][N][o][o], [N][N][v][v] partial sums
+};
+
+void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);
+void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st);
+void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st);
+void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st);
+void launch_ring_init(const SysDev &s, const cd *t1, cd *scratch, cd *WR, cd *X, hipStream_t st);
+void launch_assemble_r2(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, const cd *X, cd *r2,
+                        hipStream_t st);
+void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
+
+// reductions (deterministic: fixed grid, fixed-order partial sums) -------------------
+constexpr int RED_BLOCKS = 1024;
+// out[0] = sum |r1|^2 + |r2|^2 ; partials must hold RED_BLOCKS doubles
+void launch_norm2(const Dims &d, const cd *r1, const cd *r2, double *partials, double *out, hipStream_t st);
+// out[0..1] = complex correlation energy; partials must hold 2*RED_BLOCKS doubles
+void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials, double *out, hipStream_t st);
+// t += r / D, and (optionally) err = r / D
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
+                   hipStream_t st);
+// out[j] = Re <x, y_j> over n complex elements, j < m ; partials must hold m*RED_BLOCKS doubles
+void launch_dots(int64_t n, const cd *x, const cd *const *y, int m, double *partials, double *out,
+                 hipStream_t st);
+// dst = sum_j c[j] * src_j over n complex elements (m <= 16)
+void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st);
+// copies and fills
+void launch_copy(int64_t n, const cd *src, cd *dst, hipStream_t st);
+void launch_add(int64_t n, const cd *a, const cd *b, cd *dst, hipStream_t st);  // dst = a + b
+
+// device synthetic inputs (same recipe as the host generator) ------------------------
+void launch_synth_fock(const Mesh &m, int no, int nv, uint64_t seed, cd *fock, hipStream_t st);
+void launch_synth_eri(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls, cd *out,
+                      hipStream_t st);
+void launch_diag(const Dims &d, const cd *fock, double *eo, double *ev, hipStream_t st);
+
+}  // namespace ck

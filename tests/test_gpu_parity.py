@@ -1,0 +1,232 @@
+"""GPU parity of libccsdk (FP64 path) against the FP64 oracle, through the C ABI.
+
+Bars (FP64 path): one residual from identical amplitudes, max|dR| <= 1e-12 max|R|;
+energies to 1e-12 relative; converged energies to 1e-11 Eh.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ccsd_k as O
+
+pytestmark = pytest.mark.gpu
+
+ck = pytest.importorskip("paper_1911_00242_amd", reason="libccsdk.so not built")
+
+
+def _ctx(systems):
+    return ck.Context(systems)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _random_fock(rng, N, no, nv, ov=0.05):
+    n = no + nv
+    f = np.zeros((N, n, n), dtype=np.complex128)
+    for k in range(N):
+        a = 0.03 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+        h = a + a.conj().T
+        h[:no, no:] *= ov / 0.03
+        h[no:, :no] = h[:no, no:].conj().T
+        d = np.concatenate([rng.uniform(-2, -0.5, no), rng.uniform(0.5, 3, nv)])
+        f[k] = h + np.diag(d)
+    return f
+
+
+@pytest.mark.parametrize("G,M,N,K", [(1, 16, 16, 4), (3, 37, 45, 29), (2, 130, 200, 70), (1, 64, 64, 1),
+                                     (2, 5, 3, 0)])
+def test_debug_zgemm_matches_numpy(G, M, N, K):
+    print(f"zgemm G={G} M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(G * 1000 + M + N + K)
+    A = rng.standard_normal((G, M, K)) + 1j * rng.standard_normal((G, M, K))
+    B = rng.standard_normal((G, N, K)) + 1j * rng.standard_normal((G, N, K))
+    ref = np.einsum("gmk,gnk->gmn", A, B)
+    C = ck.ccsd_k_debug_zgemm(A, B)
+    Cr = ck.ccsd_k_debug_zgemm(A, B, reference=True)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(C - ref).max() <= 1e-13 * scale * max(1, K) ** 0.5
+    assert np.abs(Cr - ref).max() <= 1e-13 * scale * max(1, K) ** 0.5
+
+
+RES_CASES = [
+    # grid, n_occ, n_vir, random Fock with occupied-virtual coupling
+    ((2, 1, 1), 4, 8, False),
+    ((3, 1, 1), 2, 3, True),
+    ((2, 2, 1), 3, 5, False),
+    ((1, 1, 1), 5, 7, True),
+    ((3, 1, 1), 1, 1, False),
+]
+
+
+@pytest.mark.parametrize("grid,no,nv,general_fock", RES_CASES)
+def test_residual_matches_oracle(grid, no, nv, general_fock):
+    print(f"residual grid={grid} no={no} nv={nv}", flush=True)
+    N = int(np.prod(grid))
+    kc = O.kconserv(grid)
+    f, eris = synth.system(303 + N, grid, no, nv, scale=0.1)
+    if general_fock:
+        f = _random_fock(np.random.default_rng(N), N, no, nv)
+    t1, t2 = synth.test_amplitudes(17 + N, grid, no, nv, scale=0.2)
+    R1, R2 = O.residual(f, eris, t1, t2, kc)
+    E = O.energy(f, eris, t1, t2, kc)
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(0, f, eris)
+        g1, g2 = c.residual(0, t1, t2)
+        ge = c.energy(0)
+        rn = c.residual_norm(0)
+    assert _rel(g2, R2) <= 1e-12
+    assert _rel(g1, R1) <= 1e-12
+    assert abs(ge - E) <= 1e-12 * max(1.0, abs(E))
+    assert abs(rn - O.residual_norm(R1, R2)) <= 1e-12 * O.residual_norm(R1, R2)
+
+
+def test_zero_amplitudes_give_the_driver_term():
+    grid, no, nv = (3, 1, 1), 3, 4
+    f, eris = synth.system(5, grid, no, nv)
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(0, f, eris)
+        r1, r2 = c.residual(0)
+    assert np.array_equal(r2, np.conj(eris["oovv"]))
+    assert np.array_equal(r1, np.zeros_like(r1))
+
+
+def test_device_synthetic_inputs_match_host_generator():
+    grid, no, nv = (3, 1, 1), 2, 4
+    N = 3
+    f, eris = synth.system(101, grid, no, nv)
+    t1, t2 = synth.test_amplitudes(3, grid, no, nv, scale=0.2)
+    with _ctx([dict(grid=grid, no=no, nv=nv, synthetic=1, seed=101, eri_scale=0.05),
+               dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(1, f, eris)
+        a1, a2 = c.residual(0, t1, t2)
+        b1, b2 = c.residual(1, t1, t2)
+    # libm and device transcendental functions may differ in the last bits only
+    assert _rel(a2, b2) <= 1e-13
+    assert _rel(a1, b1) <= 1e-13
+    assert N == 3
+
+
+def test_jacobi_converged_energy_cfg0():
+    """N_k=2 (1-D), n_occ=4, n_vir=8, plain successive substitution to ||R|| < 1e-10."""
+    grid, no, nv = (2, 1, 1), 4, 8
+    f, eris = synth.system(101, grid, no, nv)
+    ref = O.solve(f, eris, grid, max_iter=30, tol=1e-10)
+    assert ref["converged"]
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(0, f, eris)
+        rc, iters, rn = c.iterate(31, 1e-10)
+        e = c.energy(0)
+        t1, t2 = c.get_amplitudes(0)
+    assert rc == ck.OK
+    assert iters == ref["iterations"] + 1  # one more evaluation than updates
+    assert abs(e - ref["energy"]) <= 1e-11
+    assert np.abs(t2 - ref["t2"]).max() <= 1e-10
+
+
+def test_diis_converged_energy():
+    grid, no, nv = (3, 1, 1), 2, 4
+    f, eris = synth.system(77, grid, no, nv, scale=0.1)
+    ref = O.solve(f, eris, grid, max_iter=40, tol=1e-11, diis_space=6)
+    assert ref["converged"]
+    with _ctx([dict(grid=grid, no=no, nv=nv, diis_space=6)]) as c:
+        c.set_inputs(0, f, eris)
+        rc, iters, rn = c.iterate(41, 1e-11)
+        e = c.energy(0)
+    assert rc == ck.OK
+    assert abs(iters - (ref["iterations"] + 1)) <= 1
+    assert abs(e - ref["energy"]) <= 1e-11
+
+
+def test_mp2_first_update():
+    grid, no, nv = (3, 1, 1), 3, 5
+    f, eris = synth.system(9, grid, no, nv)
+    ref = O.solve(f, eris, grid, max_iter=1, tol=0.0)
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(0, f, eris)
+        rc, iters, _ = c.iterate(1, 0.0)
+        e = c.energy(0)
+    assert rc == ck.NOT_CONVERGED and iters == 1
+    assert abs(e - ref["energy"]) <= 1e-13 * abs(ref["energy"])
+
+
+def test_checkpoint_restart_is_bitwise():
+    grid, no, nv = (2, 1, 1), 3, 4
+    f, eris = synth.system(12, grid, no, nv)
+    sysd = dict(grid=grid, no=no, nv=nv)
+    with _ctx([sysd]) as c:
+        c.set_inputs(0, f, eris)
+        c.iterate(8, 0.0)
+        e_full = c.energy(0)
+        a1, a2 = c.get_amplitudes(0)
+    with _ctx([sysd]) as c:
+        c.set_inputs(0, f, eris)
+        c.iterate(4, 0.0)
+        s1, s2 = c.get_amplitudes(0)
+    with _ctx([sysd]) as c:
+        c.set_inputs(0, f, eris)
+        c.set_amplitudes(0, s1, s2)
+        c.iterate(4, 0.0)
+        e_rest = c.energy(0)
+        b1, b2 = c.get_amplitudes(0)
+    assert e_full == e_rest
+    assert np.array_equal(a2, b2) and np.array_equal(a1, b1)
+
+
+def test_batch_equals_single_systems():
+    descs = [dict(grid=(2, 1, 1), no=2, nv=3), dict(grid=(3, 1, 1), no=3, nv=4), dict(grid=(1, 1, 1), no=4, nv=6)]
+    inputs = [synth.system(40 + i, d["grid"], d["no"], d["nv"]) for i, d in enumerate(descs)]
+    singles = []
+    for d, (f, e) in zip(descs, inputs):
+        with _ctx([d]) as c:
+            c.set_inputs(0, f, e)
+            c.iterate(6, 0.0)
+            singles.append(c.energy(0))
+    with _ctx(descs) as c:
+        for i, (f, e) in enumerate(inputs):
+            c.set_inputs(i, f, e)
+        c.iterate(6, 0.0)
+        batch = [c.energy(i) for i in range(3)]
+    assert batch == singles
+
+
+def test_error_paths():
+    grid, no, nv = (2, 1, 1), 2, 3
+    f, eris = synth.system(1, grid, no, nv)
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        with pytest.raises(ck.CcsdKError) as e:
+            c.residual(0)
+        assert e.value.code == ck.ESTATE
+        bad = f.copy()
+        bad[0, 0, 0] = bad[0, no, no]  # f_ii == f_aa: zero denominator
+        with pytest.raises(ck.CcsdKError) as e:
+            c.set_inputs(0, bad, eris)
+        assert e.value.code == ck.EINVAL
+        c.set_inputs(0, f, eris)
+        with pytest.raises(ck.CcsdKError) as e:
+            ck.ccsd_k_residual(c.ctx, 5)
+        assert e.value.code == ck.EINVAL
+        t1 = np.zeros((2, no, nv), np.complex128)
+        t2 = np.zeros((2, 2, 2, no, no, nv, nv), np.complex128)
+        t2[0, 0, 0, 0, 1, 0, 1] = np.nan
+        with pytest.raises(ck.CcsdKError) as e:
+            c.residual(0, t1, t2)
+        assert e.value.code == ck.ENUMERIC
+
+
+@pytest.mark.timeout(900)
+def test_residual_matches_oracle_cfg1_size():
+    """3-D 2x2x2 mesh (N_k=8), n_occ=8, n_vir=24: one residual at random amplitudes."""
+    grid, no, nv = (2, 2, 2), 8, 24
+    print("cfg1-size residual: generating inputs", flush=True)
+    f, eris = synth.system(202, grid, no, nv)
+    t1, t2 = synth.test_amplitudes(21, grid, no, nv, scale=0.02)
+    print("oracle residual", flush=True)
+    R1, R2 = O.residual(f, eris, t1, t2, O.kconserv(grid))
+    print("gpu residual", flush=True)
+    with _ctx([dict(grid=grid, no=no, nv=nv)]) as c:
+        c.set_inputs(0, f, eris)
+        g1, g2 = c.residual(0, t1, t2)
+    assert _rel(g2, R2) <= 1e-12
+    assert _rel(g1, R1) <= 1e-12
