@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the k-point CCSD T2 residual on one MI355X.
+
+Workload (default): seeded synthetic system on a 3x3x3 k mesh (N_k = 27), n_occ = 8,
+n_vir = 16 spin orbitals per k, integrals generated on the device by the seeded recipe
+(complex Gaussians x 0.05, antisymmetrized and Hermitized), diagonal Fock, DIIS(6).
+A step is one iteration of the whole path: the residual (tau, F, W_mnij, T1-dressed
+<ab||ef>, ring W, ring product, T2 assembly, particle-particle and hole-hole ladders,
+T1 residual), its norm, the correlation energy, the update t <- t + R/D and DIIS.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line: value = residual evaluations per second of the headline path,
+with the dominant kernel's roofline (particle-particle ladder, HIP events on the
+library's stream) and the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "T2 residual evals/s + TFLOP/s at N_k=27 (split-BF16 vs FP64, |ΔE|≤1e-8)"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s, MI355X
+
+
+def measured_traffic(key, source):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
+        return rec["hbm_bytes_per_launch"] if sha == rec["source_sha256_16"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="fp64")
+    ap.add_argument("--grid", default="3,3,3")
+    ap.add_argument("--no", type=int, default=8)
+    ap.add_argument("--nv", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=303)
+    ap.add_argument("--diis", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup):
+    desc = dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=diis, synthetic=1, seed=seed,
+                eri_scale=0.05)
+    print(f"[bench] {('fp64', 'mixed')[prec]}: binding workspace", file=sys.stderr, flush=True)
+    ctx = ck.Context([desc], device="cuda:0")
+    gemm_flops, other_flops = ctx.flops(0)
+    for w in range(warmup):
+        ctx.iterate(1, 0.0)
+        print(f"[bench] warmup {w + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    energy = None
+    for s in range(steps):
+        ctx.iterate(1, 0.0)
+        energy = ctx.energy(0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = {name: ctx.timing_get(name) for name in ck.STAGES}
+    ctx.timing(False)
+    print(f"[bench] {steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    out = dict(seconds=dt, gemm_flops=gemm_flops, other_flops=other_flops, stages=stages,
+               energy=energy, workspace_bytes=ctx.nbytes, rnorm=ctx.residual_norm(0))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(no, nv, N_target):
+    """The FP64 oracle on a bounded sample: one residual on a 3x1x1 mesh with the same
+    per-k block shapes, scaled to the target mesh by the N_k^4 algorithmic flop ratio."""
+    import numpy as np
+
+    import synth
+    from oracle import ccsd_k as O
+
+    grid = (3, 1, 1)
+    f, eris = synth.system(303, grid, no, nv)
+    t1, t2 = synth.test_amplitudes(1, grid, no, nv, scale=0.01)
+    kc = O.kconserv(grid)
+    t0 = time.perf_counter()
+    O.residual(f, eris, t1, t2, kc)
+    dt = time.perf_counter() - t0
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+    except Exception:
+        pass
+    ratio = (N_target / 3.0) ** 4
+    return {"value": 1.0 / (dt * ratio), "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one oracle residual on a 3x1x1 mesh with n_occ={no}, n_vir={nv} per k "
+                      f"({dt:.2f} s), scaled by the N_k^4 flop ratio {ratio:.0f} to N_k={N_target}",
+            "sample_seconds": dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each k-pair group is independent; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1911_00242_amd as ck
+
+    grid = tuple(int(x) for x in a.grid.split(","))
+    N = grid[0] * grid[1] * grid[2]
+    paths = {"fp64": [0], "mixed": [1], "both": [0, 1]}[a.precision]
+    res = {}
+    for p in paths:
+        res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup)
+    head = 1 if 1 in res else 0
+    r = res[head]
+    ms = 1000.0 * r["seconds"] / a.steps
+    value = 1000.0 / ms
+    tflops = r["gemm_flops"] / (ms / 1000.0) / 1e12
+    pp_ms, pp_n = r["stages"]["pp_ladder"]
+    N4 = float(N) ** 4
+    pp_cmacs = N4 * a.no ** 2 * a.nv ** 4
+    if head == 0:
+        pp_flops, peak, dtype = 8.0 * pp_cmacs, PEAK["fp64"], "f64"
+        traffic = measured_traffic("pp_ladder_fp64", "paper_1911_00242_amd/csrc/gemm_f64.hip")
+    else:
+        pp_flops, peak, dtype = 24.0 * pp_cmacs, PEAK["bf16"], "bf16x3/f32acc+f64"
+        traffic = measured_traffic("pp_ladder_mixed", "paper_1911_00242_amd/csrc/gemm_mixed.hip")
+    if (grid, a.no, a.nv) != ((3, 3, 3), 8, 16):
+        traffic = None
+    pp_avg = pp_ms / max(pp_n, 1)
+    achieved = pp_flops / (pp_avg / 1000.0) / 1e12 if pp_n else None
+    line = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"k-point CCSD T2 residual iteration, {grid[0]}x{grid[1]}x{grid[2]} mesh "
+                               f"(N_k={N}), n_occ={a.no}, n_vir={a.nv} spin orbitals per k, DIIS({a.diis})",
+                   "grid": list(grid), "n_occ": a.no, "n_vir": a.nv, "seed": a.seed},
+        "tflops": tflops,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": (achieved / peak) if achieved else None,
+                     "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
+                     "kernel": "particle-particle ladder grouped GEMM", "avg_launch_ms": pp_avg},
+        "stages_ms_per_step": {k: v[0] / a.steps for k, v in r["stages"].items()},
+        "energy": [r["energy"].real, r["energy"].imag],
+    }
+    if 0 in res and 1 in res:
+        line["fp64_path"] = {"evals_per_s": a.steps / res[0]["seconds"],
+                             "tflops": res[0]["gemm_flops"] * a.steps / res[0]["seconds"] / 1e12}
+        line["speedup_vs_fp64"] = res[0]["seconds"] / res[1]["seconds"]
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(a.no, a.nv, N)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
