@@ -122,8 +122,8 @@ int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable);
 int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches);
 
 /* Diagnostic: dense grouped complex product C[g] = A[g] . B[g]^T on the device with the
- * tiled FP64 MFMA kernel (reference = 0) or the one-thread-per-element kernel
- * (reference = 1).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
+ * tiled FP64 MFMA kernel (reference = 0), the one-thread-per-element FP64 kernel
+ * (reference = 1), or the split-BF16 MFMA kernel of the mixed path (reference = 2).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
  * Allocates and frees its own device buffers; synchronizes the default stream. */
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
                        double *C, int32_t reference);

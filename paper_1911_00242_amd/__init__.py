@@ -181,14 +181,15 @@ def ccsd_k_timing_get(ctx, stage: int):
     return float(ms.value), int(n.value)
 
 
-def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference: bool = False) -> np.ndarray:
-    """C[g] = A[g] @ B[g].T on the device (A [G,M,K], B [G,N,K] complex128)."""
+def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference=False) -> np.ndarray:
+    """C[g] = A[g] @ B[g].T on the device (A [G,M,K], B [G,N,K] complex128).
+    reference: False/0 tiled FP64 MFMA, True/1 per-element FP64, 2 split-BF16 MFMA."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     B = np.ascontiguousarray(B, dtype=np.complex128)
     G, M, K = A.shape
     N = B.shape[1]
     C = np.empty((G, M, N), np.complex128)
-    _check(_lib_dbg_gemm(G, M, N, K, _ptr(A), _ptr(B), _ptr(C), 1 if reference else 0), None)
+    _check(_lib_dbg_gemm(G, M, N, K, _ptr(A), _ptr(B), _ptr(C), int(reference)), None)
     return C
 
 

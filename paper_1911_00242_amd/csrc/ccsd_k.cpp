@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mixed.h"
 #include "terms.h"
 
 namespace {
@@ -49,6 +50,12 @@ struct System {
     int32_t *dkc = nullptr;
     int64_t *dtab = nullptr;
     std::vector<cd *> dvec, derr;
+    // mixed precision: split-BF16 operands (four planes each) of the five products
+    bool mixed = false;
+    uint16_t *sp_tau = nullptr, *sp_tauT = nullptr, *sp_t2 = nullptr, *sp_WT = nullptr, *sp_WR = nullptr,
+             *sp_Vt = nullptr, *sp_oovv = nullptr;
+    int64_t pl_t2 = 0, pl_o4 = 0, pl_v4 = 0;
+    ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
     std::vector<double> B;  // diis_space x diis_space error overlaps
@@ -245,8 +252,22 @@ void carve(System &S, Carver &c) {
     c.take(S.amp, S.n1() + S.n2());
     c.take(S.res, S.n1() + S.n2());
     c.take(S.tau, S.n2());
-    c.take(S.tauT, S.n2());
-    c.take(S.Vt, N3 * cls[5]);
+    if (!S.mixed) {
+        c.take(S.tauT, S.n2());
+        c.take(S.Vt, N3 * cls[5]);
+    } else {
+        auto plane = [](int64_t n) { return (n + 63) / 64 * 64; };
+        S.pl_t2 = plane(S.n2());
+        S.pl_o4 = plane(N3 * cls[0]);
+        S.pl_v4 = plane(N3 * cls[5]);
+        c.take(S.sp_tau, 4 * S.pl_t2);
+        c.take(S.sp_tauT, 4 * S.pl_t2);
+        c.take(S.sp_t2, 4 * S.pl_t2);
+        c.take(S.sp_WR, 4 * S.pl_t2);
+        c.take(S.sp_oovv, 4 * S.pl_t2);
+        c.take(S.sp_WT, 4 * S.pl_o4);
+        c.take(S.sp_Vt, 4 * S.pl_v4);
+    }
     c.take(S.WT, N3 * cls[0]);
     c.take(S.WR, N3 * o * v * o * v);
     c.take(S.X, N3 * o * v * o * v);
@@ -274,6 +295,28 @@ void carve(System &S, Carver &c) {
     }
 }
 
+// True when every aligned group of 8 k indices of both operands is a contiguous,
+// 16-byte aligned run in every group, and all row/column bases are 8-aligned.
+bool fast_ok(const System &S, int i) {
+    const Gemm &g = S.g[i];
+    const int64_t G = g.op.G, M = g.op.M, N = g.op.N, K = g.op.K;
+    if (K % 8) return false;
+    const int64_t *T = S.tables.data();
+    for (int64_t x = 0; x < G * M; ++x)
+        if (T[g.tab[0] + x] % 8) return false;
+    for (int64_t x = 0; x < G * N; ++x)
+        if (T[g.tab[2] + x] % 8) return false;
+    for (int w : {1, 3})
+        for (int64_t gg = 0; gg < G; ++gg)
+            for (int64_t k0 = 0; k0 < K; k0 += 8) {
+                const int64_t *r = T + g.tab[w] + gg * K + k0;
+                if (r[0] % 8) return false;
+                for (int j = 1; j < 8; ++j)
+                    if (r[j] != r[0] + j) return false;
+            }
+    return true;
+}
+
 void bind_ops(System &S) {
     const int64_t *T = S.dtab;
     const cd *A[5] = {S.tau, S.tau, S.WT, S.t2(), S.t2()};
@@ -290,6 +333,23 @@ void bind_ops(System &S) {
         g.op.b_k = T + g.tab[3];
         g.op.c_row = T + g.tab[4];
         g.op.c_col = T + g.tab[5];
+    }
+    if (!S.mixed) return;
+    const uint16_t *SA[5] = {S.sp_tau, S.sp_tau, S.sp_WT, S.sp_t2, S.sp_t2};
+    const uint16_t *SB[5] = {S.sp_oovv, S.sp_Vt, S.sp_tauT, S.sp_oovv, S.sp_WR};
+    const int64_t PA[5] = {S.pl_t2, S.pl_t2, S.pl_o4, S.pl_t2, S.pl_t2};
+    const int64_t PB[5] = {S.pl_t2, S.pl_v4, S.pl_t2, S.pl_t2, S.pl_t2};
+    for (int i = 0; i < 5; ++i) {
+        const ck::GemmOps<cd> &o = S.g[i].op;
+        ck::SplitOps &s = S.sg[i];
+        s.A = SA[i];
+        s.B = SB[i];
+        s.a_plane = PA[i];
+        s.b_plane = PB[i];
+        s.C = o.C;
+        s.a_row = o.a_row; s.a_k = o.a_k; s.b_col = o.b_col; s.b_k = o.b_k; s.c_row = o.c_row; s.c_col = o.c_col;
+        s.G = o.G; s.M = o.M; s.N = o.N; s.K = o.K; s.alpha = o.alpha; s.beta = o.beta;
+        s.fast = fast_ok(S, i) ? 1 : 0;
     }
 }
 
@@ -328,7 +388,8 @@ void collect_timing(ccsd_k_ctx *c) {
 void run_gemm(ccsd_k_ctx *c, System &S, int i) {
     EventPair ep{};
     stage_begin(c, ep, S.g[i].stage);
-    ck::gemm_f64(S.g[i].op, c->stream);
+    if (S.mixed) ck::gemm_split(S.sg[i], c->stream);
+    else ck::gemm_f64(S.g[i].op, c->stream);
     stage_end(c, ep);
 }
 
@@ -338,13 +399,27 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     ck::SysDev s = S.dev();
     EventPair all{};
     stage_begin(c, all, ST_RES);
-    ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
+    if (!S.mixed) {
+        ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
+    } else {
+        ck::launch_tau(s, S.t1(), S.t2(), S.tau, nullptr, st);
+        ck::launch_split(S.n2(), S.tau, S.sp_tau, S.pl_t2, st);
+        ck::launch_split_transpose(S.d, S.tau, S.sp_tauT, S.pl_t2, st);
+        ck::launch_split(S.n2(), S.t2(), S.sp_t2, S.pl_t2, st);
+    }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
     ck::launch_wmnij_init(s, S.t1(), S.WT, st);
     run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>
-    ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+    if (!S.mixed) {
+        ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+    } else {
+        ck::launch_split((int64_t)S.d.N * S.d.N * S.d.N * S.d.no * S.d.no * S.d.no * S.d.no, S.WT, S.sp_WT,
+                         S.pl_o4, st);
+        ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, S.pl_v4, st);
+    }
     ck::launch_ring_init(s, S.t1(), S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
+    if (S.mixed) ck::launch_split(S.n2(), S.WR, S.sp_WR, S.pl_t2, st);
     run_gemm(c, S, 4);  // X += t2 W_mbej
     ck::launch_assemble_r2(s, S.t1(), S.t2(), S.fw, S.X, S.r2(), st);
     run_gemm(c, S, 1);  // particle-particle ladder
@@ -435,10 +510,11 @@ int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_
             delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "n_occ and n_vir must be in 1..256");
         }
-        if (d.precision != CCSD_K_PREC_FP64) {
+        if (d.precision != CCSD_K_PREC_FP64 && d.precision != CCSD_K_PREC_MIXED) {
             delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "unsupported precision");
         }
+        S.mixed = d.precision == CCSD_K_PREC_MIXED;
         if (d.diis_space != 0 && (d.diis_space < 2 || d.diis_space > 16)) {
             delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "diis_space must be 0 or 2..16");
@@ -495,6 +571,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                     ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
                                          ctx->stream);
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+                if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
                 S.inputs = true;
             }
         }
@@ -530,6 +607,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         for (int i = 0; i < 6; ++i)
             CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+        if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
@@ -785,8 +863,30 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
         op.a_row = dT + o_arow; op.a_k = dT + o_k; op.b_col = dT + o_bcol; op.b_k = dT + o_k;
         op.c_row = dT + o_crow; op.c_col = dT + o_ccol;
         op.G = G; op.M = M; op.N = N; op.K = K; op.alpha = 1.0; op.beta = 0.0;
-        if (reference) ck::gemm_f64_reference(op, nullptr);
-        else ck::gemm_f64(op, nullptr);
+        if (reference == 1) {
+            ck::gemm_f64_reference(op, nullptr);
+        } else if (reference == 2) {
+            // split-BF16 operands of A and B, product on the bf16 MFMA kernel
+            auto plane = [](int64_t n) { return (n + 63) / 64 * 64; };
+            int64_t pa = plane((int64_t)na), pb = plane((int64_t)nb);
+            uint16_t *sA = nullptr, *sB = nullptr;
+            CK_CHECK(hipMalloc(&sA, 4 * pa * sizeof(uint16_t)));
+            CK_CHECK(hipMalloc(&sB, 4 * pb * sizeof(uint16_t)));
+            ck::launch_split((int64_t)na, dA, sA, pa, nullptr);
+            ck::launch_split((int64_t)nb, dB, sB, pb, nullptr);
+            ck::SplitOps so{};
+            so.A = sA; so.B = sB; so.a_plane = pa; so.b_plane = pb; so.C = dC;
+            so.a_row = op.a_row; so.a_k = op.a_k; so.b_col = op.b_col; so.b_k = op.b_k;
+            so.c_row = op.c_row; so.c_col = op.c_col;
+            so.G = G; so.M = M; so.N = N; so.K = K; so.alpha = 1.0; so.beta = 0.0;
+            so.fast = (K % 8 == 0) ? 1 : 0;
+            ck::gemm_split(so, nullptr);
+            CK_CHECK(hipDeviceSynchronize());
+            (void)hipFree(sA);
+            (void)hipFree(sB);
+        } else {
+            ck::gemm_f64(op, nullptr);
+        }
         CK_CHECK(hipDeviceSynchronize());
         CK_CHECK(hipMemcpy(C, dC, nc * sizeof(cd), hipMemcpyDeviceToHost));
     } catch (const ck::HipError &e) {

@@ -468,6 +468,7 @@ __global__ void k_r1(SysDev s, const cd *t1, const cd *t2, const cd *Foo, const 
 
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st) {
     LAUNCH(k_tau, s.d.t2(), s.d, s.kc, t1, t2, tau);
+    if (!tauT) return;
     int R = s.d.no * s.d.no, C = s.d.nv * s.d.nv;
     dim3 g((unsigned)((int64_t)((R + 31) / 32) * ((C + 31) / 32) * s.d.N * s.d.N * s.d.N));
     hipLaunchKernelGGL(k_block_transpose, g, dim3(256), 0, st, s.d, tau, tauT);
