@@ -3,7 +3,7 @@
 
 Workload (default): seeded synthetic system on a 3x3x3 k mesh (N_k = 27), n_occ = 8,
 n_vir = 16 spin orbitals per k, integrals generated on the device by the seeded recipe
-(complex Gaussians x 0.05, antisymmetrized and Hermitized), diagonal Fock, DIIS(6).
+(complex Gaussians x 0.05/N_k, antisymmetrized and Hermitized), diagonal Fock, DIIS(6).
 A step is one iteration of the whole path: the residual (tau, F, W_mnij, T1-dressed
 <ab||ef>, ring W, ring product, T2 assembly, particle-particle and hole-hole ladders,
 T1 residual), its norm, the correlation energy, the update t <- t + R/D and DIIS.
@@ -45,19 +45,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--grid", default="3,3,3")
     ap.add_argument("--no", type=int, default=8)
     ap.add_argument("--nv", type=int, default=16)
     ap.add_argument("--seed", type=int, default=303)
     ap.add_argument("--diis", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--converge", type=int, default=1, help="after timing, iterate to convergence and "
+                    "compare the paths' energies and amplitudes (0 = skip)")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--tol-mixed", type=float, default=1e-7,
+                    help="the split-BF16 residual has a rounding floor near 1e-8..1e-7 at N_k=27")
+    ap.add_argument("--max-iter", type=int, default=60)
     return ap.parse_args()
 
 
-def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup):
+def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter):
+    N = grid[0] * grid[1] * grid[2]
     desc = dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=diis, synthetic=1, seed=seed,
-                eri_scale=0.05)
+                eri_scale=0.05 / N)
     print(f"[bench] {('fp64', 'mixed')[prec]}: binding workspace", file=sys.stderr, flush=True)
     ctx = ck.Context([desc], device="cuda:0")
     gemm_flops, other_flops = ctx.flops(0)
@@ -78,6 +85,13 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup):
     print(f"[bench] {steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
     out = dict(seconds=dt, gemm_flops=gemm_flops, other_flops=other_flops, stages=stages,
                energy=energy, workspace_bytes=ctx.nbytes, rnorm=ctx.residual_norm(0))
+    if converge:
+        done = warmup + steps
+        rc, it, rn = ctx.iterate(max(0, max_iter - done), tol)
+        out.update(conv_rc=rc, conv_iters=done + it, conv_rnorm=rn, conv_energy=ctx.energy(0),
+                   t2=ctx.get_amplitudes(0)[1])
+        print(f"[bench] converge: rc={rc} evaluations={done + it} |R|={rn:.3e} E={out['conv_energy']}",
+              file=sys.stderr, flush=True)
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -93,7 +107,7 @@ def cpu_baseline(no, nv, N_target):
     from oracle import ccsd_k as O
 
     grid = (3, 1, 1)
-    f, eris = synth.system(303, grid, no, nv)
+    f, eris = synth.system(303, grid, no, nv, scale=0.05 / 3)
     t1, t2 = synth.test_amplitudes(1, grid, no, nv, scale=0.01)
     kc = O.kconserv(grid)
     t0 = time.perf_counter()
@@ -128,7 +142,8 @@ def main():
     paths = {"fp64": [0], "mixed": [1], "both": [0, 1]}[a.precision]
     res = {}
     for p in paths:
-        res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup)
+        res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup, a.converge,
+                          a.tol if p == 0 else a.tol_mixed, a.max_iter)
     head = 1 if 1 in res else 0
     r = res[head]
     ms = 1000.0 * r["seconds"] / a.steps
@@ -166,6 +181,17 @@ def main():
         line["fp64_path"] = {"evals_per_s": a.steps / res[0]["seconds"],
                              "tflops": res[0]["gemm_flops"] * a.steps / res[0]["seconds"] / 1e12}
         line["speedup_vs_fp64"] = res[0]["seconds"] / res[1]["seconds"]
+    if a.converge:
+        import numpy as np
+
+        line["convergence"] = {("fp64", "mixed")[p]: {"status": v["conv_rc"], "evaluations": v["conv_iters"],
+                                                        "rnorm": v["conv_rnorm"],
+                                                        "energy": [v["conv_energy"].real, v["conv_energy"].imag]}
+                               for p, v in res.items()}
+        if 0 in res and 1 in res:
+            line["mixed_vs_fp64"] = {"abs_dE": abs(res[1]["conv_energy"] - res[0]["conv_energy"]),
+                                     "max_abs_dT2": float(np.abs(res[1]["t2"] - res[0]["t2"]).max()),
+                                     "reference": "FP64 GPU path converged to ||R|| < tol"}
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(a.no, a.nv, N)
