@@ -45,6 +45,7 @@ struct System {
     cd *amp = nullptr, *res = nullptr;  // [t1 | t2], [r1 | r2]
     cd *tau = nullptr, *tauT = nullptr, *Vt = nullptr, *WT = nullptr, *WR = nullptr, *X = nullptr;
     cd *scr = nullptr, *P1 = nullptr;
+    cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
     int32_t *dkc = nullptr;
@@ -280,6 +281,7 @@ void carve(System &S, Carver &c) {
     c.take(S.fw.Fvt, N * v * v);
     c.take(S.fw.Poo, N * N * o * o);
     c.take(S.fw.Pvv, N * N * v * v);
+    c.take(S.zeros, 16);
     c.take(S.eo, N * o);
     c.take(S.ev, N * v);
     c.take(S.red, 16 * ck::RED_BLOCKS);
@@ -333,6 +335,7 @@ void bind_ops(System &S) {
         g.op.b_k = T + g.tab[3];
         g.op.c_row = T + g.tab[4];
         g.op.c_col = T + g.tab[5];
+        g.op.zeros = S.zeros;
     }
     if (!S.mixed) return;
     const uint16_t *SA[5] = {S.sp_tau, S.sp_tau, S.sp_WT, S.sp_t2, S.sp_t2};
@@ -344,6 +347,7 @@ void bind_ops(System &S) {
         ck::SplitOps &s = S.sg[i];
         s.A = SA[i];
         s.B = SB[i];
+        s.zeros = reinterpret_cast<const uint16_t *>(S.zeros);
         s.a_plane = PA[i];
         s.b_plane = PB[i];
         s.C = o.C;
@@ -563,6 +567,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                                     ctx->stream));
             CK_CHECK(hipMemsetAsync(S.amp, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.res, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            CK_CHECK(hipMemsetAsync(S.zeros, 0, 16 * sizeof(cd), ctx->stream));
             bind_ops(S);
             if (S.desc.synthetic) {
                 static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
@@ -846,7 +851,7 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
     for (int g = 0; g < G; ++g)
         for (int n = 0; n < N; ++n) tab.push_back(n);
     const size_t na = (size_t)G * M * K, nb = (size_t)G * N * K, nc = (size_t)G * M * N;
-    cd *dA = nullptr, *dB = nullptr, *dC = nullptr;
+    cd *dA = nullptr, *dB = nullptr, *dC = nullptr, *dZ = nullptr;
     int64_t *dT = nullptr;
     int rc = CCSD_K_OK;
     try {
@@ -854,12 +859,14 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
         CK_CHECK(hipMalloc(&dB, std::max<size_t>(nb, 1) * sizeof(cd)));
         CK_CHECK(hipMalloc(&dC, nc * sizeof(cd)));
         CK_CHECK(hipMalloc(&dT, tab.size() * sizeof(int64_t)));
+        CK_CHECK(hipMalloc(&dZ, 16 * sizeof(cd)));
+        CK_CHECK(hipMemset(dZ, 0, 16 * sizeof(cd)));
         CK_CHECK(hipMemcpy(dA, A, na * sizeof(cd), hipMemcpyHostToDevice));
         CK_CHECK(hipMemcpy(dB, B, nb * sizeof(cd), hipMemcpyHostToDevice));
         CK_CHECK(hipMemcpy(dT, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice));
         CK_CHECK(hipMemset(dC, 0, nc * sizeof(cd)));
         ck::GemmOps<cd> op{};
-        op.A = dA; op.B = dB; op.C = dC;
+        op.A = dA; op.B = dB; op.C = dC; op.zeros = dZ;
         op.a_row = dT + o_arow; op.a_k = dT + o_k; op.b_col = dT + o_bcol; op.b_k = dT + o_k;
         op.c_row = dT + o_crow; op.c_col = dT + o_ccol;
         op.G = G; op.M = M; op.N = N; op.K = K; op.alpha = 1.0; op.beta = 0.0;
@@ -876,6 +883,7 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
             ck::launch_split((int64_t)nb, dB, sB, pb, nullptr);
             ck::SplitOps so{};
             so.A = sA; so.B = sB; so.a_plane = pa; so.b_plane = pb; so.C = dC;
+            so.zeros = reinterpret_cast<const uint16_t *>(dZ);
             so.a_row = op.a_row; so.a_k = op.a_k; so.b_col = op.b_col; so.b_k = op.b_k;
             so.c_row = op.c_row; so.c_col = op.c_col;
             so.G = G; so.M = M; so.N = N; so.K = K; so.alpha = 1.0; so.beta = 0.0;
@@ -896,6 +904,7 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
     (void)hipFree(dB);
     (void)hipFree(dC);
     (void)hipFree(dT);
+    (void)hipFree(dZ);
     return rc;
 }
 

@@ -74,6 +74,7 @@ struct GemmOps {
     const T *A;
     const T *B;
     T *C;
+    const T *zeros;  // >= 16 bytes of zeros: the load address of out-of-range elements
     const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
     int G, M, N, K;
     double alpha, beta;

@@ -39,38 +39,24 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
     const int kl = tid % BK;        // this thread's k lane within a stage
     const int rl = tid / BK;        // first row/col handled by this thread
 
-    // per-thread row (A) and column (B) base offsets; -1 marks out-of-range rows
+    // Per-thread row (A) and column (B) base offsets, clamped to a valid row; the loads are
+    // branch free from always-valid addresses and out-of-range rows / k are zeroed when
+    // the staged registers go to LDS, so loads stay in flight across the MFMA work.  The
+    // k-table offsets are fetched one stage ahead of the data they address.
     int64_t arow[RA], bcol[RB];
+    bool aok[RA], bok[RB];
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
         int m = m0 + rl + i * ROWS_PER_PASS;
-        arow[i] = m < M ? op.a_row[(int64_t)g * M + m] : -1;
+        aok[i] = m < M;
+        arow[i] = op.a_row[(int64_t)g * M + (aok[i] ? m : M - 1)];
     }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
         int n = n0 + rl + i * ROWS_PER_PASS;
-        bcol[i] = n < N ? op.b_col[(int64_t)g * N + n] : -1;
+        bok[i] = n < N;
+        bcol[i] = op.b_col[(int64_t)g * N + (bok[i] ? n : N - 1)];
     }
-
-    cd ra[RA], rb[RB];
-    auto load = [&](int k0) {
-        int k = k0 + kl;
-        bool kin = k < K;
-        int64_t ak = kin ? op.a_k[(int64_t)g * K + k] : 0;
-        int64_t bk = kin ? op.b_k[(int64_t)g * K + k] : 0;
-#pragma unroll
-        for (int i = 0; i < RA; ++i)
-            ra[i] = (kin && arow[i] >= 0) ? op.A[arow[i] + ak] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-            rb[i] = (kin && bcol[i] >= 0) ? op.B[bcol[i] + bk] : make_double2(0.0, 0.0);
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < RA; ++i) As[buf][kl][rl + i * ROWS_PER_PASS] = ra[i];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) Bs[buf][kl][rl + i * ROWS_PER_PASS] = rb[i];
-    };
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -85,13 +71,57 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
             acc_im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
         }
 
+    // Staged elements of the next stage and the k-table offsets of the one after it.
+    // Every iteration loads (out-of-range elements read the zero buffer), so no
+    // data-dependent select sits between a load and its LDS store.
+    cd ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    int64_t ak_cur = 0, bk_cur = 0;
+#define CK_KOFS(k0, ak, bk)                                \
+    {                                                      \
+        const int k_ = min((k0) + kl, K - 1);              \
+        ak = op.a_k[(int64_t)g * K + k_];                  \
+        bk = op.b_k[(int64_t)g * K + k_];                  \
+    }
+#define CK_LOAD(k0)                                                                                     \
+    {                                                                                                   \
+        const bool kin_ = (k0) + kl < K;                                                                \
+        static_assert(RA == 4 && RB == 4, "loader written for four rows per thread");                   \
+        ra0 = *((kin_ && aok[0]) ? op.A + arow[0] + ak_cur : op.zeros);                                 \
+        ra1 = *((kin_ && aok[1]) ? op.A + arow[1] + ak_cur : op.zeros);                                 \
+        ra2 = *((kin_ && aok[2]) ? op.A + arow[2] + ak_cur : op.zeros);                                 \
+        ra3 = *((kin_ && aok[3]) ? op.A + arow[3] + ak_cur : op.zeros);                                 \
+        rb0 = *((kin_ && bok[0]) ? op.B + bcol[0] + bk_cur : op.zeros);                                 \
+        rb1 = *((kin_ && bok[1]) ? op.B + bcol[1] + bk_cur : op.zeros);                                 \
+        rb2 = *((kin_ && bok[2]) ? op.B + bcol[2] + bk_cur : op.zeros);                                 \
+        rb3 = *((kin_ && bok[3]) ? op.B + bcol[3] + bk_cur : op.zeros);                                 \
+    }
+#define CK_STORE(buf)                                          \
+    {                                                          \
+        As[buf][kl][rl] = ra0;                                 \
+        As[buf][kl][rl + ROWS_PER_PASS] = ra1;                 \
+        As[buf][kl][rl + 2 * ROWS_PER_PASS] = ra2;             \
+        As[buf][kl][rl + 3 * ROWS_PER_PASS] = ra3;             \
+        Bs[buf][kl][rl] = rb0;                                 \
+        Bs[buf][kl][rl + ROWS_PER_PASS] = rb1;                 \
+        Bs[buf][kl][rl + 2 * ROWS_PER_PASS] = rb2;             \
+        Bs[buf][kl][rl + 3 * ROWS_PER_PASS] = rb3;             \
+    }
+
     const int nk = (K + BK - 1) / BK;
-    load(0);
-    store(0);
+    if (K > 0) {
+        CK_KOFS(0, ak_cur, bk_cur);
+        CK_LOAD(0);
+        CK_STORE(0);
+        CK_KOFS(BK, ak_cur, bk_cur);
+    }
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK);
+        int64_t ak_nxt, bk_nxt;
+        CK_LOAD((kt + 1) * BK);  // zeros past the end
+        CK_KOFS((kt + 2) * BK, ak_nxt, bk_nxt);
+        // keep the prefetch issued here, ahead of the MFMA work it overlaps with
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             cd af[FM], bf[FN];
@@ -109,9 +139,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
                     acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].y, bf[j].x, acc_im[i][j], 0, 0, 0);
                 }
         }
-        if (kt + 1 < nk) store(buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+        CK_STORE(buf ^ 1);  // buf ^ 1 was last read before the previous barrier
+        ak_cur = ak_nxt;
+        bk_cur = bk_nxt;
         __syncthreads();
     }
+#undef CK_KOFS
+#undef CK_LOAD
+#undef CK_STORE
 
     // epilogue: for the f64 16x16x4 MFMA, register r of a lane holds row 4*r + lane/16
     // of column lane%16 of each 16x16 tile

@@ -94,6 +94,20 @@ void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, int64_t
 }
 
 // ------------------------------------------------------------------ the GEMM
+// Eight consecutive k of one row of one plane, element by element (zeros out of range).
+__device__ inline uint4 gather8(const uint16_t *base, const int64_t *ktab, const uint16_t *zeros, int g, int K,
+                                int kb, bool rok, int64_t row, int64_t plane_off) {
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const int k = kb + j;
+        const uint16_t *x0 = (rok && k < K) ? base + plane_off + row + ktab[(int64_t)g * K + min(k, K - 1)] : zeros;
+        const uint16_t *x1 = (rok && k + 1 < K) ? base + plane_off + row + ktab[(int64_t)g * K + min(k + 1, K - 1)] : zeros;
+        v[j / 2] = (uint32_t)*x0 | (uint32_t)*x1 << 16;
+    }
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 template <bool FAST>
 __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
     constexpr int BM = 128, BN = 128, BK = 16, PADK = BK + 8;
@@ -105,49 +119,15 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
     const int g = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int M = op.M, N = op.N, K = op.K;
-    // loader: thread -> (row = tid/2, chunk of 8 k = tid%2), all four planes
+    // loader: thread -> (row = tid/2, chunk of 8 k = tid%2), all four planes.  Loads are
+    // branch free from clamped, always valid addresses; out-of-range rows and k are
+    // zeroed when the staged registers are written to LDS, so the compiler can keep the
+    // loads in flight across the MFMA work of the current stage.
     const int lrow = tid >> 1, lkc = tid & 1;
     const int am = m0 + lrow, bn = n0 + lrow;
-    const int64_t arow = am < M ? op.a_row[(int64_t)g * M + am] : -1;
-    const int64_t bcol = bn < N ? op.b_col[(int64_t)g * N + bn] : -1;
-
-    uint4 sa[4], sb[4];
-    auto load = [&](int k0) {
-        const int kb = k0 + lkc * 8;
-        if (FAST) {
-            const bool kin = kb < K;
-            const int64_t ak = kin ? op.a_k[(int64_t)g * K + kb] : 0;
-            const int64_t bk = kin ? op.b_k[(int64_t)g * K + kb] : 0;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                sa[p] = (kin && arow >= 0) ? *(const uint4 *)(op.A + p * op.a_plane + arow + ak) : make_uint4(0, 0, 0, 0);
-                sb[p] = (kin && bcol >= 0) ? *(const uint4 *)(op.B + p * op.b_plane + bcol + bk) : make_uint4(0, 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                uint16_t va[8], vb[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int k = kb + j;
-                    const bool kin = k < K;
-                    va[j] = (kin && arow >= 0) ? op.A[p * op.a_plane + arow + op.a_k[(int64_t)g * K + k]] : 0;
-                    vb[j] = (kin && bcol >= 0) ? op.B[p * op.b_plane + bcol + op.b_k[(int64_t)g * K + k]] : 0;
-                }
-                sa[p] = make_uint4(va[0] | (uint32_t)va[1] << 16, va[2] | (uint32_t)va[3] << 16,
-                                   va[4] | (uint32_t)va[5] << 16, va[6] | (uint32_t)va[7] << 16);
-                sb[p] = make_uint4(vb[0] | (uint32_t)vb[1] << 16, vb[2] | (uint32_t)vb[3] << 16,
-                                   vb[4] | (uint32_t)vb[5] << 16, vb[6] | (uint32_t)vb[7] << 16);
-            }
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            *(uint4 *)(&As[buf][p * PLANE + lrow * PADK + lkc * 8]) = sa[p];
-            *(uint4 *)(&Bs[buf][p * PLANE + lrow * PADK + lkc * 8]) = sb[p];
-        }
-    };
+    const bool aok = am < M, bok = bn < N;
+    const int64_t arow = op.a_row[(int64_t)g * M + (aok ? am : M - 1)];
+    const int64_t bcol = op.b_col[(int64_t)g * N + (bok ? bn : N - 1)];
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -164,13 +144,76 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
                 acci[i][j][r] = 0.f;
             }
 
+    // Staged chunk of the next stage (registers), and the k-table offsets of the stage
+    // after it.  Every iteration loads (out-of-range chunks read the zero buffer), so no
+    // data-dependent select sits between a load and its LDS store.
+    uint4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
+    int64_t ak_cur = 0, bk_cur = 0;
+    // FAST implies K % 8 == 0 and K >= 8: clamp to the last whole 8-run so a 16-byte load
+    // never leaves the operand; otherwise clamp to the last k
+    const int kclamp = FAST ? K - 8 : K - 1;
+#define CK_KOFS(k0, ak, bk)                                          \
+    {                                                                \
+        const int kb_ = min((k0) + lkc * 8, kclamp);                 \
+        ak = op.a_k[(int64_t)g * K + kb_];                           \
+        bk = op.b_k[(int64_t)g * K + kb_];                           \
+    }
+#define CK_LOAD(k0)                                                                                   \
+    {                                                                                                 \
+        const int kb_ = (k0) + lkc * 8;                                                               \
+        if (FAST) {                                                                                   \
+            const uint16_t *pa_ = (kb_ < K && aok) ? op.A + arow + ak_cur : op.zeros;                 \
+            const uint16_t *pb_ = (kb_ < K && bok) ? op.B + bcol + bk_cur : op.zeros;                 \
+            const int64_t sa_ = (kb_ < K && aok) ? op.a_plane : 0, sb_ = (kb_ < K && bok) ? op.b_plane : 0; \
+            sa0 = *(const uint4 *)(pa_);                                                              \
+            sa1 = *(const uint4 *)(pa_ + sa_);                                                        \
+            sa2 = *(const uint4 *)(pa_ + 2 * sa_);                                                    \
+            sa3 = *(const uint4 *)(pa_ + 3 * sa_);                                                    \
+            sb0 = *(const uint4 *)(pb_);                                                              \
+            sb1 = *(const uint4 *)(pb_ + sb_);                                                        \
+            sb2 = *(const uint4 *)(pb_ + 2 * sb_);                                                    \
+            sb3 = *(const uint4 *)(pb_ + 3 * sb_);                                                    \
+        } else {                                                                                      \
+            sa0 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 0);                            \
+            sa1 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, op.a_plane);                   \
+            sa2 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 2 * op.a_plane);               \
+            sa3 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 3 * op.a_plane);               \
+            sb0 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 0);                            \
+            sb1 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, op.b_plane);                   \
+            sb2 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 2 * op.b_plane);               \
+            sb3 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 3 * op.b_plane);               \
+        }                                                                                             \
+    }
+#define CK_STORE(buf)                                                     \
+    {                                                                     \
+        uint16_t *a_ = &As[buf][lrow * PADK + lkc * 8];                   \
+        uint16_t *b_ = &Bs[buf][lrow * PADK + lkc * 8];                   \
+        *(uint4 *)(a_) = sa0;                                             \
+        *(uint4 *)(a_ + PLANE) = sa1;                                     \
+        *(uint4 *)(a_ + 2 * PLANE) = sa2;                                 \
+        *(uint4 *)(a_ + 3 * PLANE) = sa3;                                 \
+        *(uint4 *)(b_) = sb0;                                             \
+        *(uint4 *)(b_ + PLANE) = sb1;                                     \
+        *(uint4 *)(b_ + 2 * PLANE) = sb2;                                 \
+        *(uint4 *)(b_ + 3 * PLANE) = sb3;                                 \
+    }
+
     const int nk = (K + BK - 1) / BK;
-    load(0);
-    store(0);
+    if (K > 0) {
+        CK_KOFS(0, ak_cur, bk_cur);
+        CK_LOAD(0);
+        CK_STORE(0);
+        CK_KOFS(BK, ak_cur, bk_cur);
+    }
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load((kt + 1) * BK);
+        int64_t ak_nxt, bk_nxt;
+        // next stage's data (zeros past the end) and the k offsets of the one after it,
+        // issued ahead of the MFMA work they overlap with
+        CK_LOAD((kt + 1) * BK);
+        CK_KOFS((kt + 2) * BK, ak_nxt, bk_nxt);
+        __builtin_amdgcn_sched_barrier(0);
         // fragments: lane holds 8 consecutive k of row (lane % 32), k offset 8 * (lane / 32)
         bf16x8 a[2][4], b[2][4];
 #pragma unroll
@@ -215,9 +258,15 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
                 accr[i][j] = cr;
                 acci[i][j] = ci;
             }
-        if (kt + 1 < nk) store(buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+        CK_STORE(buf ^ 1);  // buf ^ 1 was last read before the previous barrier
+        ak_cur = ak_nxt;
+        bk_cur = bk_nxt;
         __syncthreads();
     }
+#undef CK_KOFS
+#undef CK_LOAD
+#undef CK_STORE
 
     // epilogue: 32x32 f32 output, register r of a lane holds row 8*(r/4) + 4*(lane/32) + r%4
     // of column lane%32

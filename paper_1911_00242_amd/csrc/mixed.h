@@ -10,6 +10,7 @@ namespace ck {
 // contiguous and 16-byte aligned in both operands (then loads move 8 k at once).
 struct SplitOps {
     const uint16_t *A, *B;
+    const uint16_t *zeros;  // >= 16 bytes of zeros: the load address of out-of-range chunks
     int64_t a_plane, b_plane;
     cd *C;
     const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
