@@ -45,6 +45,8 @@ struct System {
     cd *amp = nullptr, *res = nullptr;  // [t1 | t2], [r1 | r2]
     cd *tau = nullptr, *tauT = nullptr, *Vt = nullptr, *WT = nullptr, *WR = nullptr, *X = nullptr;
     cd *scr = nullptr, *P1 = nullptr;
+    cd *ovvoT = nullptr;  // static ovvo, ovvv, oovv classes with their last two indices swapped
+    cd *ovvvT = nullptr, *oovvT = nullptr;
     cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
@@ -82,6 +84,9 @@ struct System {
         s.ovvo = eri[3];
         s.ovvv = eri[4];
         s.vvvv = eri[5];
+        s.ovvoT = ovvoT;
+        s.ovvvT = ovvvT;
+        s.oovvT = oovvT;
         return s;
     }
 };
@@ -273,14 +278,17 @@ void carve(System &S, Carver &c) {
     c.take(S.WR, N3 * o * v * o * v);
     c.take(S.X, N3 * o * v * o * v);
     c.take(S.scr, N3 * o * o * o * v);
-    c.take(S.P1, N * N * o * v);
+    c.take(S.ovvoT, S.n2());
+    c.take(S.ovvvT, N3 * cls[4]);
+    c.take(S.oovvT, S.n2());
+    c.take(S.P1, 2 * N3 * o * v);
     c.take(S.fw.Fov, N * o * v);
     c.take(S.fw.Foo, N * o * o);
     c.take(S.fw.Fvv, N * v * v);
     c.take(S.fw.Fot, N * o * o);
     c.take(S.fw.Fvt, N * v * v);
-    c.take(S.fw.Poo, N * N * o * o);
-    c.take(S.fw.Pvv, N * N * v * v);
+    c.take(S.fw.Poo, N3 * o * o);
+    c.take(S.fw.Pvv, N3 * v * v);
     c.take(S.zeros, 16);
     c.take(S.eo, N * o);
     c.take(S.ev, N * v);
@@ -421,11 +429,11 @@ void residual_device(ccsd_k_ctx *c, System &S) {
                          S.pl_o4, st);
         ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, S.pl_v4, st);
     }
-    ck::launch_ring_init(s, S.t1(), S.scr, S.WR, S.X, st);
+    ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
     if (S.mixed) ck::launch_split(S.n2(), S.WR, S.sp_WR, S.pl_t2, st);
     run_gemm(c, S, 4);  // X += t2 W_mbej
-    ck::launch_assemble_r2(s, S.t1(), S.t2(), S.fw, S.X, S.r2(), st);
+    ck::launch_assemble_r2(s, S.X, S.r2(), st);
     run_gemm(c, S, 1);  // particle-particle ladder
     run_gemm(c, S, 2);  // hole-hole ladder
     ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
@@ -576,6 +584,8 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                     ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
                                          ctx->stream);
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+                ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
+                ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
                 if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
                 S.inputs = true;
             }
@@ -612,6 +622,8 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         for (int i = 0; i < 6; ++i)
             CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
+        ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
+        ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
         if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {

@@ -61,6 +61,9 @@ struct SysDev {
     const double *ev;   // [N][nv]   virtual orbital energies
     const cd *fock;     // [N][n][n]
     const cd *oooo, *ooov, *oovv, *ovvo, *ovvv, *vvvv;  // [kp][kq][kr][p][q][r][s]
+    const cd *ovvoT;  // ovvo with the last two indices swapped: [km][kb][ke][m][b][j][e]
+    const cd *ovvvT;  // ovvv with the last two indices swapped: [km][kb][ke][m][b][f][e]
+    const cd *oovvT;  // oovv with the last two indices swapped: [km][kn][ke][m][n][f][e]
 };
 
 // ---------------------------------------------------------------------------------

@@ -8,16 +8,23 @@ namespace ck {
 struct FWork {
     cd *Fov, *Foo, *Fvv;  // [N][o][v], [N][o][o], [N][v][v]
     cd *Fot, *Fvt;        // [N][o][o], [N][v][v]
-    cd *Poo, *Pvv;        // [N][N][o][o], [N][N][v][v] partial sums
+    cd *Poo, *Pvv;        // [N][N][N][o][o], [N][N][N][v][v] partial sums
 };
 
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st);
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st);
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st);
-void launch_ring_init(const SysDev &s, const cd *t1, cd *scratch, cd *WR, cd *X, hipStream_t st);
-void launch_assemble_r2(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, const cd *X, cd *r2,
-                        hipStream_t st);
+// ring seeds: W_mbej without its t2 part (WR) and X = every non-ladder, non-driver term
+// arranged for one P(ij)P(ab); needs the F combinations of w
+void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
+                      hipStream_t st);
+// r2 = <ab||ij> + P(ij)P(ab) X
+void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st);
+// the static ovvo class with its last two indices swapped (once per set of inputs)
+void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st);
+// ovvv and oovv with their last two indices swapped (once per set of inputs)
+void launch_static_swaps(const SysDev &s, cd *ovvvT, cd *oovvT, hipStream_t st);
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
 
 // reductions (deterministic: fixed grid, fixed-order partial sums) -------------------

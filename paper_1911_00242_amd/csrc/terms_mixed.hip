@@ -18,22 +18,26 @@ __device__ inline void split_pair(double x, uint16_t &hi, uint16_t &lo) {
 }
 
 // Vt[ka][kb][ke](a,b,e,f) = <ab||ef> + t_m^b <m kb, a ka||ef> - t_m^a <m ka, b kb||ef>
+// One workgroup per (ka, kb, ke, a), XCD-contiguous block order (see the FP64 kernel).
 __global__ void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt, int64_t plane) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t v4 = (int64_t)nv * nv * nv * nv, ov3 = (int64_t)no * nv * nv * nv;
-    const int64_t total = (int64_t)N * N * N * v4;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int f = (int)(idx % nv), e = (int)((idx / nv) % nv);
-        int b = (int)((idx / ((int64_t)nv * nv)) % nv), a = (int)((idx / ((int64_t)nv * nv * nv)) % nv);
-        int64_t blk = idx / v4;
-        int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
+    const int64_t v3 = (int64_t)nv * nv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
+    const int64_t nblk = (int64_t)N * N * N * nv;
+    const int64_t per = (nblk + 7) / 8;
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int a = (int)(L % nv);
+    const int64_t blk = L / nv;
+    const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
+    const cd *g1b = s.ovvv + (((int64_t)kb * N + ka) * N + ke) * ov3 + (int64_t)a * nv * nv;
+    const cd *g2b = s.ovvv + (((int64_t)ka * N + kb) * N + ke) * ov3;
+    for (int64_t e = threadIdx.x; e < v3; e += blockDim.x) {
+        const int ef = (int)(e % (nv * nv)), b = (int)(e / (nv * nv));
+        const int64_t idx = blk * v4 + (int64_t)a * v3 + e;
         cd acc = s.vvvv[idx];
-        const cd *g1 = s.ovvv + (((int64_t)kb * N + ka) * N + ke) * ov3 + ((int64_t)a * nv + e) * nv + f;
-        const cd *g2 = s.ovvv + (((int64_t)ka * N + kb) * N + ke) * ov3 + ((int64_t)b * nv + e) * nv + f;
         for (int m = 0; m < no; ++m) {
-            cfma(acc, t1[((int64_t)kb * no + m) * nv + b], g1[(int64_t)m * nv * nv * nv]);
-            acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], g2[(int64_t)m * nv * nv * nv]));
+            cfma(acc, t1[((int64_t)kb * no + m) * nv + b], g1b[(int64_t)m * v3 + ef]);
+            acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], g2b[(int64_t)m * v3 + (int64_t)b * nv * nv + ef]));
         }
         uint16_t p0, p1, p2, p3;
         split_pair(acc.x, p0, p1);
@@ -46,10 +50,8 @@ __global__ void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt, int64_t
 }
 
 void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, int64_t plane, hipStream_t st) {
-    const int64_t total = (int64_t)s.d.N * s.d.N * s.d.N * s.d.nv * s.d.nv * s.d.nv * s.d.nv;
-    int64_t b = std::min<int64_t>((total + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(k_vvvv_dress_split, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, s, t1, Vt,
-                       plane);
+    const int64_t nblk = (int64_t)s.d.N * s.d.N * s.d.N * s.d.nv;
+    hipLaunchKernelGGL(k_vvvv_dress_split, dim3((unsigned)(((nblk + 7) / 8) * 8)), dim3(256), 0, st, s, t1, Vt, plane);
     CK_CHECK(hipGetLastError());
 }
 
