@@ -14,6 +14,7 @@
 //   WR[q][kj][km][j][b][m][e]   = ring intermediate W_{m b e j}, k_b = k_j - q, k_e = k_m - q
 //   X [q][ki][kj][i][a][j][b]   = ring product, k_a = k_i + q, k_b = k_j - q
 #include "common.h"
+#include "mixed.h"
 #include "terms.h"
 
 namespace ck {
@@ -48,6 +49,18 @@ __device__ inline cd tau_el(const cd *t1, const cd *t2, int64_t idx, int ki, int
         v.y -= fac * p.y;
     }
     return v;
+}
+
+// hi = RNE_bf16(x), lo = RNE_bf16(x - hi): the split-BF16 pair of the mixed path
+__device__ inline uint16_t rne_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline void split_rne2(double x, uint16_t &hi, uint16_t &lo) {
+    hi = rne_bf16((float)x);
+    lo = rne_bf16((float)(x - (double)__builtin_bit_cast(float, (uint32_t)hi << 16)));
 }
 
 // ------------------------------------------------------------------ tau and its transpose
@@ -155,27 +168,33 @@ __global__ void k_fvv_partial(SysDev s, const cd *t1, const cd *t2, cd *Pvv) {
 //   Pvv[r][p][q](a,e) = -1/2 sum_{m,n,f} taut(m,n,a,f) <mn||ef>    (k = r, km = p, kn = q)
 constexpr int FB_SLAB = 2176;  // o * v * (v + 1) complex elements per staged slab (o=8, v=16)
 inline bool f_blocks_fit(const Dims &d) {
-    return (int64_t)d.no * d.nv * (d.nv + 1) <= FB_SLAB && d.no * d.no <= 256 && d.nv * d.nv <= 1024;
+    return (int64_t)d.no * d.nv * (d.nv + 1) <= FB_SLAB && d.no * d.no <= 1024 && d.nv * d.nv <= 1024;
 }
 
-__global__ __launch_bounds__(256) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
+constexpr int FB_NT = 1024;
+__global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
     __shared__ cd Ts[FB_SLAB], Gs[FB_SLAB];
-    __shared__ cd red[256];
+    __shared__ cd red[FB_NT];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int kb = kcv(s.kc, N, p, q, r);
     const int64_t base = blk * s.d.t2blk();
-    const int oo = no * no, parts = 256 / oo;
+    const int oo = no * no, parts = FB_NT / oo;
     const int u = tid % oo, part = tid / oo;  // Foo output (m,i) = u, ef slice = part
     const int um = u / no, ui = u % no;
     const int ef0 = part < parts ? (int)((int64_t)part * vv / parts) : 0;
     const int ef1 = part < parts ? (int)((int64_t)(part + 1) * vv / parts) : 0;
-    cd aoo = make_double2(0.0, 0.0);
-    cd avv[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    const int vparts = FB_NT / vv;  // threads per Fvv output (v^2 <= FB_NT)
+    const int vo = tid % vv, vpart = tid / vv;
+    const int va = vo / nv, ve = vo % nv;
+    const int mf0 = vpart < vparts ? (int)((int64_t)vpart * no * nv / vparts) : 0;
+    const int mf1 = vpart < vparts ? (int)((int64_t)(vpart + 1) * no * nv / vparts) : 0;
+    cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0);
     for (int n = 0; n < no; ++n) {
-        for (int x = tid; x < no * vv; x += 256) {
+#pragma unroll 4
+        for (int x = tid; x < no * vv; x += FB_NT) {
             const int row = x / vv, e = (x % vv) / nv, f = x % nv;
             const int64_t gi = base + (((int64_t)row * no + n) * nv + e) * nv + f;
             Ts[(row * nv + e) * rs + f] = tau_el(t1, t2, gi, p, q, r, kb, row, n, e, f, no, nv, 0.5);
@@ -186,15 +205,9 @@ __global__ __launch_bounds__(256) void k_f_blocks(SysDev s, const cd *t1, const 
             const int e = ef / nv, f = ef % nv;
             cfma(aoo, Ts[(ui * nv + e) * rs + f], Gs[(um * nv + e) * rs + f]);
         }
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int o = tid + 256 * w;
-            if (o < vv) {
-                const int a = o / nv, e = o % nv;
-                for (int m = 0; m < no; ++m)
-                    for (int f = 0; f < nv; ++f)
-                        cfma(avv[w], Ts[(m * nv + a) * rs + f], Gs[(m * nv + e) * rs + f]);
-            }
+        for (int mf = mf0; mf < mf1; ++mf) {
+            const int m = mf / nv, f = mf % nv;
+            cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
         }
         __syncthreads();
     }
@@ -205,11 +218,13 @@ __global__ __launch_bounds__(256) void k_f_blocks(SysDev s, const cd *t1, const 
         for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * oo + tid]);
         Poo[blk * oo + (int64_t)um * no + ui] = cscale(sum, 0.5);
     }
-    const int64_t pv = (((int64_t)r * N + p) * N + q) * vv;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int o = tid + 256 * w;
-        if (o < vv) Pvv[pv + o] = cscale(avv[w], -0.5);
+    __syncthreads();
+    red[tid] = avv;
+    __syncthreads();
+    if (tid < vv) {
+        cd sum = make_double2(0.0, 0.0);
+        for (int pp = 0; pp < vparts; ++pp) sum = cadd(sum, red[pp * vv + tid]);
+        Pvv[(((int64_t)r * N + p) * N + q) * vv + tid] = cscale(sum, -0.5);
     }
 }
 
@@ -222,53 +237,65 @@ __global__ __launch_bounds__(256) void k_f_blocks(SysDev s, const cd *t1, const 
 constexpr int RB_T = 2176, RB_G = 4352, RB_H = 1152;
 inline bool r1_blocks_fit(const Dims &d) {
     return (int64_t)d.no * d.nv * (d.nv + 1) <= RB_T && (int64_t)d.nv * (d.nv * d.nv + 1) <= RB_G &&
-           (int64_t)d.no * d.no * (d.nv + 1) <= RB_H && 2 * d.no * d.nv <= 256;
+           (int64_t)d.no * d.no * (d.nv + 1) <= RB_H && d.no * d.nv <= 1024;
 }
 
-__global__ __launch_bounds__(256) void k_r1_blocks(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
+constexpr int RB_NT = 1024;
+__global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
     __shared__ cd Ts[RB_T], Gs[RB_G], Hs[RB_H];
+    __shared__ cd red[RB_NT];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1, gs = vv + 1;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int64_t tb = blk * s.d.t2blk();
     const int64_t ov3 = (int64_t)no * nv * vv, o3v = (int64_t)no * no * no * nv;
-    const int64_t gb = blk3(N, q, p, r) * ov3;     // ovvv block [q,p,r]: (n, a, e, f)
-    const int64_t hb = blk * o3v;                  // ooov block [p,q,r]: (m, n, i, f)
-    const int nout = no * nv;                      // outputs (i, a)
-    const int half = tid / nout, oi = tid % nout;  // term A: two threads per output
+    const int64_t gb = blk3(N, q, p, r) * ov3;  // ovvv block [q,p,r]: (n, a, e, f)
+    const int64_t hb = blk * o3v;               // ooov block [p,q,r]: (m, n, i, f)
+    const int nout = no * nv;                   // outputs (i, a)
+    const int parts = RB_NT / nout;             // threads per output
+    const int part = tid / nout, oi = tid % nout;
     const int ii = oi / nv, aa = oi % nv;
+    const int ef0 = part < parts ? (int)((int64_t)part * vv / parts) : 0;
+    const int ef1 = part < parts ? (int)((int64_t)(part + 1) * vv / parts) : 0;
+    const int mf0 = part < parts ? (int)((int64_t)part * no * nv / parts) : 0;
+    const int mf1 = part < parts ? (int)((int64_t)(part + 1) * no * nv / parts) : 0;
     cd accA = make_double2(0.0, 0.0), accB = make_double2(0.0, 0.0);
     for (int n = 0; n < no; ++n) {
-        for (int x = tid; x < no * vv; x += 256) {  // t2(x, n, e, f)
+#pragma unroll 4
+        for (int x = tid; x < no * vv; x += RB_NT) {  // t2(x, n, e, f)
             const int row = x / vv, e = (x % vv) / nv, f = x % nv;
             Ts[(row * nv + e) * rs + f] = t2[tb + (((int64_t)row * no + n) * nv + e) * nv + f];
         }
-        for (int x = tid; x < nv * vv; x += 256) {  // <n q, a p || e r, f>: (a, ef)
+#pragma unroll 4
+        for (int x = tid; x < nv * vv; x += RB_NT)  // <n q, a p || e r, f>: (a, ef)
             Gs[(x / vv) * gs + x % vv] = s.ovvv[gb + (int64_t)n * nv * vv + x];
-        }
-        for (int x = tid; x < no * no * nv; x += 256) {  // <m p, n q || i r, f>: (m, i, f)
+        for (int x = tid; x < no * no * nv; x += RB_NT) {  // <m p, n q || i r, f>: (m, i, f)
             const int m = x / (no * nv), i = (x / nv) % no, f = x % nv;
             Hs[(m * no + i) * rs + f] = s.ooov[hb + (((int64_t)m * no + n) * no + i) * nv + f];
         }
         __syncthreads();
-        if (half < 2 && tid < 2 * nout) {
-            for (int ef = half * (vv / 2); ef < (half + 1) * (vv / 2) + (half ? vv % 2 : 0); ++ef)
-                cfma(accA, Ts[(ii * nv + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
-        }
-        if (tid < nout) {
-            for (int m = 0; m < no; ++m)
-                for (int f = 0; f < nv; ++f) cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+        for (int ef = ef0; ef < ef1; ++ef) cfma(accA, Ts[(ii * nv + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
+        for (int mf = mf0; mf < mf1; ++mf) {
+            const int m = mf / nv, f = mf % nv;
+            cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
         }
         __syncthreads();
     }
-    // term A: combine the two halves through LDS (reuse Ts)
-    if (half == 1 && tid < 2 * nout) Ts[oi] = accA;
+    red[tid] = accA;
     __syncthreads();
     if (tid < nout) {
-        cd a = cadd(accA, Ts[oi]);
-        P1a[blk * nout + oi] = cscale(a, -0.5);
-        P1b[((((int64_t)r * N + p) * N + q)) * nout + oi] = cscale(accB, -0.5);
+        cd sum = make_double2(0.0, 0.0);
+        for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
+        P1a[blk * nout + tid] = cscale(sum, -0.5);
+    }
+    __syncthreads();
+    red[tid] = accB;
+    __syncthreads();
+    if (tid < nout) {
+        cd sum = make_double2(0.0, 0.0);
+        for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
+        P1b[(((int64_t)r * N + p) * N + q) * nout + tid] = cscale(sum, -0.5);
     }
 }
 
@@ -354,6 +381,7 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
         cd acc = s.oooo[blk3(N, km, kn, ki) * o4 + (((int64_t)m * no + nn) * no + i) * no + j];
         const cd *g1 = s.ooov + blk3(N, km, kn, ki) * o3v + (((int64_t)m * no + nn) * no + i) * nv;
         const cd *g2 = s.ooov + blk3(N, km, kn, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv;
+#pragma unroll 8
         for (int e = 0; e < nv; ++e) {
             cfma(acc, t1[((int64_t)kj * no + j) * nv + e], g1[e]);
             cd p = cmul(t1[((int64_t)ki * no + i) * nv + e], g2[e]);
@@ -376,29 +404,68 @@ __device__ inline int64_t xcd_block(int64_t n) {
 // ------------------------------------------------------------------ T1-dressed <ab||ef>
 // Vt[ka][kb][ke](a,b,e,f) = <ab||ef> - P(ab) sum_m t_{m kb}^{b} <a ka, m kb || e f>
 //   = <ab||ef> + t_m^b <m kb, a ka||ef> - t_m^a <m ka, b kb||ef>
-// One workgroup per (ka, kb, ke, a): the <m kb, a ka||ef> rows of its a are reused for
-// every b, and neighbouring a share the <m ka, b kb||ef> block in L2.
-__global__ void k_vvvv_dress(SysDev s, const cd *t1, cd *Vt) {
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t v3 = (int64_t)nv * nv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
+// One workgroup per (ka, kb, ke, a), XCD-contiguous order.  The <m kb, a ka||ef> rows of
+// its a (o x v^2, reused for every b) and t_{m kb}^b, t_{m ka}^a are staged in LDS, so an
+// element costs one <ab||ef> and o <m ka, b kb||ef> global reads; neighbouring a share the
+// latter block in L2.
+constexpr int DR_G1 = 2048, DR_T1 = 512;
+__host__ __device__ inline bool dress_fits(const Dims &d) {
+    return (int64_t)d.no * d.nv * d.nv <= DR_G1 && d.no * d.nv <= DR_T1;
+}
+
+template <bool SPLIT>
+__device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs, int64_t plane) {
+    __shared__ cd G1[DR_G1];
+    __shared__ cd TB[DR_T1];
+    __shared__ cd TA[64];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
+    const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
     const int64_t nblk = (int64_t)N * N * N * nv;
     const int64_t L = xcd_block(nblk);
     if (L >= nblk) return;
     const int a = (int)(L % nv);
     const int64_t blk = L / nv;
     const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
-    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)a * nv * nv;
+    const bool lds = dress_fits(s.d);
+    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)a * vv;
     const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3;
+    if (lds) {
+        for (int x = threadIdx.x; x < no * vv; x += blockDim.x) G1[x] = g1b[(int64_t)(x / vv) * v3 + x % vv];
+        for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TB[x] = t1[(int64_t)kb * no * nv + x];
+        for (int x = threadIdx.x; x < no; x += blockDim.x) TA[x] = t1[((int64_t)ka * no + x) * nv + a];
+        __syncthreads();
+    }
     for (int64_t e = threadIdx.x; e < v3; e += blockDim.x) {
-        const int ef = (int)(e % (nv * nv)), b = (int)(e / (nv * nv));
+        const int ef = (int)(e % vv), b = (int)(e / vv);
         const int64_t idx = blk * v4 + (int64_t)a * v3 + e;
         cd acc = s.vvvv[idx];
+#pragma unroll 8
         for (int m = 0; m < no; ++m) {
-            cfma(acc, t1[((int64_t)kb * no + m) * nv + b], g1b[(int64_t)m * v3 + ef]);
-            acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], g2b[(int64_t)m * v3 + (int64_t)b * nv * nv + ef]));
+            const cd g1 = lds ? G1[m * vv + ef] : g1b[(int64_t)m * v3 + ef];
+            const cd tb = lds ? TB[m * nv + b] : t1[((int64_t)kb * no + m) * nv + b];
+            const cd ta = lds ? TA[m] : t1[((int64_t)ka * no + m) * nv + a];
+            cfma(acc, tb, g1);
+            acc = csub(acc, cmul(ta, g2b[(int64_t)m * v3 + (int64_t)b * vv + ef]));
         }
-        Vt[idx] = acc;
+        if (SPLIT) {
+            uint16_t p0, p1, p2, p3;
+            split_rne2(acc.x, p0, p1);
+            split_rne2(acc.y, p2, p3);
+            Vs[idx] = p0;
+            Vs[plane + idx] = p1;
+            Vs[2 * plane + idx] = p2;
+            Vs[3 * plane + idx] = p3;
+        } else {
+            Vt[idx] = acc;
+        }
     }
+}
+
+__global__ __launch_bounds__(256) void k_vvvv_dress(SysDev s, const cd *t1, cd *Vt) {
+    dress_body<false>(s, t1, Vt, nullptr, 0);
+}
+__global__ __launch_bounds__(256) void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt, int64_t plane) {
+    dress_body<true>(s, t1, nullptr, Vt, plane);
 }
 
 // ------------------------------------------------------------------ ring intermediate seed
@@ -440,6 +507,7 @@ __global__ void k_ring_z(SysDev s, const cd *t1, cd *Z) {
         cd acc = s.ooov[blk3(N, km, kb, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv + e];
         acc = make_double2(-acc.x, -acc.y);
         const cd *g = s.oovvT + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
+        #pragma unroll 8
         for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], g[(int64_t)f * nv]);
         Z[idx] = acc;
     }
@@ -459,8 +527,10 @@ __global__ void k_ring_w0(SysDev s, const cd *t1, const cd *Z, cd *WR) {
         int64_t bb = blk3(N, km, kb, ke);
         cd acc = s.ovvoT[bb * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv + e];
         const cd *g = s.ovvvT + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
+        #pragma unroll 8
         for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], g[(int64_t)f * nv]);
         const cd *z = Z + bb * o3v + (int64_t)m * no * no * nv + (int64_t)j * nv + e;
+        #pragma unroll 8
         for (int nn = 0; nn < no; ++nn)
             acc = csub(acc, cmul(t1[((int64_t)kb * no + nn) * nv + b], z[(int64_t)nn * no * nv]));
         WR[idx] = acc;
@@ -479,6 +549,7 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
         int kj = kcv(s.kc, N, ka, kb, ki);
         const cd *g = s.ovvoT + blk * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv;
         cd acc = make_double2(0.0, 0.0);
+        #pragma unroll 8
         for (int e = 0; e < nv; ++e) cfma(acc, t1[((int64_t)ki * no + i) * nv + e], g[e]);
         cd h = s.ooov[blk3(N, ki, kj, ka) * o3v + (((int64_t)i * no + j) * no + m) * nv + b];
         acc.x += 0.5 * h.x;
@@ -508,19 +579,23 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
         cd acc = make_double2(0.0, 0.0);
         // -sum_m t_m^a Q(m,i,j,b)
         const cd *qq = Q + blk3(N, ka, kb, ki) * o3v + ((int64_t)i * no + j) * nv + b;
+        #pragma unroll 8
         for (int m = 0; m < no; ++m) cfma(acc, t1[((int64_t)ka * no + m) * nv + a], qq[(int64_t)m * no * no * nv]);
         acc = make_double2(-acc.x, -acc.y);
         // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
         cd y = make_double2(0.0, 0.0);
         const cd *g = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
+        #pragma unroll 8
         for (int c = 0; c < nv; ++c) cfma(y, t1[((int64_t)ki * no + i) * nv + c], cconj(g[(int64_t)c * nv * nv]));
         // +1/2 sum_f t_ij^af Fvt[kb](b,f)  - 1/2 sum_n t_in^ab Fot[kj](n,j)
         const int64_t tb = blk3(N, ki, kj, ka) * s.d.t2blk();
         const cd *ta = t2 + tb + (((int64_t)i * no + j) * nv + a) * nv;
         const cd *fb = Fvt + ((int64_t)kb * nv + b) * nv;
         cd w = make_double2(0.0, 0.0);
+        #pragma unroll 8
         for (int f = 0; f < nv; ++f) cfma(w, ta[f], fb[f]);
         const cd *tn = t2 + tb + ((int64_t)i * no * nv + a) * nv + b;
+        #pragma unroll 8
         for (int n = 0; n < no; ++n) cfma(y, tn[(int64_t)n * nv * nv], Fot[((int64_t)kj * no + n) * no + j]);
         acc.x += 0.5 * (w.x - y.x);
         acc.y += 0.5 * (w.y - y.y);
@@ -658,7 +733,7 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     LAUNCH(k_fov, N * no * nv, s, t1, w.Fov);
     if (f_blocks_fit(s.d)) {
-        hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t1, t2, w.Poo, w.Pvv);
+        hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_foo_partial, N * N * N * no * no, s, t1, t2, w.Poo);
@@ -676,6 +751,12 @@ void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
     hipLaunchKernelGGL(k_vvvv_dress, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, int64_t plane, hipStream_t st) {
+    const int64_t N = s.d.N, nv = s.d.nv;
+    hipLaunchKernelGGL(k_vvvv_dress_split, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt, plane);
     CK_CHECK(hipGetLastError());
 }
 
@@ -709,7 +790,7 @@ void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
     if (r1_blocks_fit(s.d)) {
-        hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t2, P1, P1 + np);
+        hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(RB_NT), 0, st, s, t2, P1, P1 + np);
         CK_CHECK(hipGetLastError());
         LAUNCH(k_r1, N * no * nv, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
     } else {
