@@ -53,11 +53,11 @@ struct System {
     int32_t *dkc = nullptr;
     int64_t *dtab = nullptr;
     std::vector<cd *> dvec, derr;
-    // mixed precision: split-BF16 operands (four planes each) of the five products
+    // mixed precision: split-BF16 operands (four bf16 per element) of the five products
     bool mixed = false;
     uint16_t *sp_tau = nullptr, *sp_tauT = nullptr, *sp_t2 = nullptr, *sp_WT = nullptr, *sp_WR = nullptr,
              *sp_Vt = nullptr, *sp_oovv = nullptr;
-    int64_t pl_t2 = 0, pl_o4 = 0, pl_v4 = 0;
+    int64_t pl_t2 = 0, pl_o4 = 0, pl_v4 = 0;  // element counts of the split operands, padded
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -262,10 +262,10 @@ void carve(System &S, Carver &c) {
         c.take(S.tauT, S.n2());
         c.take(S.Vt, N3 * cls[5]);
     } else {
-        auto plane = [](int64_t n) { return (n + 63) / 64 * 64; };
-        S.pl_t2 = plane(S.n2());
-        S.pl_o4 = plane(N3 * cls[0]);
-        S.pl_v4 = plane(N3 * cls[5]);
+        auto padded = [](int64_t n) { return (n + 63) / 64 * 64; };
+        S.pl_t2 = padded(S.n2());
+        S.pl_o4 = padded(N3 * cls[0]);
+        S.pl_v4 = padded(N3 * cls[5]);
         c.take(S.sp_tau, 4 * S.pl_t2);
         c.take(S.sp_tauT, 4 * S.pl_t2);
         c.take(S.sp_t2, 4 * S.pl_t2);
@@ -348,16 +348,12 @@ void bind_ops(System &S) {
     if (!S.mixed) return;
     const uint16_t *SA[5] = {S.sp_tau, S.sp_tau, S.sp_WT, S.sp_t2, S.sp_t2};
     const uint16_t *SB[5] = {S.sp_oovv, S.sp_Vt, S.sp_tauT, S.sp_oovv, S.sp_WR};
-    const int64_t PA[5] = {S.pl_t2, S.pl_t2, S.pl_o4, S.pl_t2, S.pl_t2};
-    const int64_t PB[5] = {S.pl_t2, S.pl_v4, S.pl_t2, S.pl_t2, S.pl_t2};
     for (int i = 0; i < 5; ++i) {
         const ck::GemmOps<cd> &o = S.g[i].op;
         ck::SplitOps &s = S.sg[i];
         s.A = SA[i];
         s.B = SB[i];
         s.zeros = reinterpret_cast<const uint16_t *>(S.zeros);
-        s.a_plane = PA[i];
-        s.b_plane = PB[i];
         s.C = o.C;
         s.a_row = o.a_row; s.a_k = o.a_k; s.b_col = o.b_col; s.b_k = o.b_k; s.c_row = o.c_row; s.c_col = o.c_col;
         s.G = o.G; s.M = o.M; s.N = o.N; s.K = o.K; s.alpha = o.alpha; s.beta = o.beta;
@@ -415,9 +411,9 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
     } else {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, nullptr, st);
-        ck::launch_split(S.n2(), S.tau, S.sp_tau, S.pl_t2, st);
-        ck::launch_split_transpose(S.d, S.tau, S.sp_tauT, S.pl_t2, st);
-        ck::launch_split(S.n2(), S.t2(), S.sp_t2, S.pl_t2, st);
+        ck::launch_split(S.n2(), S.tau, S.sp_tau, st);
+        ck::launch_split_transpose(S.d, S.tau, S.sp_tauT, st);
+        ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
     }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
     ck::launch_wmnij_init(s, S.t1(), S.WT, st);
@@ -425,13 +421,12 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     if (!S.mixed) {
         ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
     } else {
-        ck::launch_split((int64_t)S.d.N * S.d.N * S.d.N * S.d.no * S.d.no * S.d.no * S.d.no, S.WT, S.sp_WT,
-                         S.pl_o4, st);
-        ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, S.pl_v4, st);
+        ck::launch_split((int64_t)S.d.N * S.d.N * S.d.N * S.d.no * S.d.no * S.d.no * S.d.no, S.WT, S.sp_WT, st);
+        ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, st);
     }
     ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
-    if (S.mixed) ck::launch_split(S.n2(), S.WR, S.sp_WR, S.pl_t2, st);
+    if (S.mixed) ck::launch_split(S.n2(), S.WR, S.sp_WR, st);
     run_gemm(c, S, 4);  // X += t2 W_mbej
     ck::launch_assemble_r2(s, S.X, S.r2(), st);
     run_gemm(c, S, 1);  // particle-particle ladder
@@ -586,7 +581,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
                 ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
                 ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
-                if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
+                if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, ctx->stream);
                 S.inputs = true;
             }
         }
@@ -624,7 +619,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
         ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
         ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
-        if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, S.pl_t2, ctx->stream);
+        if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, ctx->stream);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
@@ -886,15 +881,15 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
             ck::gemm_f64_reference(op, nullptr);
         } else if (reference == 2) {
             // split-BF16 operands of A and B, product on the bf16 MFMA kernel
-            auto plane = [](int64_t n) { return (n + 63) / 64 * 64; };
-            int64_t pa = plane((int64_t)na), pb = plane((int64_t)nb);
+            auto padded = [](int64_t n) { return (n + 63) / 64 * 64; };
+            int64_t pa = padded((int64_t)na), pb = padded((int64_t)nb);
             uint16_t *sA = nullptr, *sB = nullptr;
             CK_CHECK(hipMalloc(&sA, 4 * pa * sizeof(uint16_t)));
             CK_CHECK(hipMalloc(&sB, 4 * pb * sizeof(uint16_t)));
-            ck::launch_split((int64_t)na, dA, sA, pa, nullptr);
-            ck::launch_split((int64_t)nb, dB, sB, pb, nullptr);
+            ck::launch_split((int64_t)na, dA, sA, nullptr);
+            ck::launch_split((int64_t)nb, dB, sB, nullptr);
             ck::SplitOps so{};
-            so.A = sA; so.B = sB; so.a_plane = pa; so.b_plane = pb; so.C = dC;
+            so.A = sA; so.B = sB; so.C = dC;
             so.zeros = reinterpret_cast<const uint16_t *>(dZ);
             so.a_row = op.a_row; so.a_k = op.a_k; so.b_col = op.b_col; so.b_k = op.b_k;
             so.c_row = op.c_row; so.c_col = op.c_col;

@@ -83,6 +83,40 @@ struct GemmOps {
     double alpha, beta;
 };
 
+// Tile order of the grouped GEMMs.  Workgroups are dealt to the eight XCDs round robin
+// in launch order and each XCD has its own L2, so each XCD is given one contiguous run of
+// logical tiles, and each run is walked group_m row tiles at a time: the workgroups
+// resident together on an XCD then share a few A row panels and B column panels in its
+// L2 instead of each fetching its own pair.  The grid is gemm_tile_grid(...) workgroups
+// along x; a workgroup with valid == false has no tile and exits.
+struct GemmTile {
+    int g, mt, nt;
+    bool valid;
+};
+constexpr int XCDS = 8;
+inline dim3 gemm_tile_grid(int tiles_m, int tiles_n, int G) {
+    const int64_t t = (int64_t)tiles_m * tiles_n * G;
+    return dim3((unsigned)((t + XCDS - 1) / XCDS * XCDS));
+}
+__device__ inline GemmTile gemm_tile(int tiles_m, int tiles_n, int G, int group_m) {
+    const int64_t per_group = (int64_t)tiles_m * tiles_n;
+    const int64_t total = per_group * G;
+    const int64_t per_xcd = (total + XCDS - 1) / XCDS;
+    const int64_t L = (int64_t)(blockIdx.x % XCDS) * per_xcd + blockIdx.x / XCDS;
+    GemmTile r;
+    r.valid = L < total;
+    const int64_t Lc = r.valid ? L : 0;
+    r.g = (int)(Lc / per_group);
+    const int64_t t = Lc % per_group;
+    const int64_t width = (int64_t)group_m * tiles_n;  // tiles in one band of group_m rows
+    const int first = (int)(t / width) * group_m;
+    const int rows = min(tiles_m - first, group_m);
+    const int64_t u = t % width;
+    r.mt = first + (int)(u % rows);
+    r.nt = (int)(u / rows);
+    return r;
+}
+
 void gemm_f64(const GemmOps<cd> &op, hipStream_t s);
 void gemm_f64_reference(const GemmOps<cd> &op, hipStream_t s);
 

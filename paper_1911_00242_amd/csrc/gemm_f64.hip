@@ -33,9 +33,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
     __shared__ cd Bs[2][BK][BN + 1];
 
     const int tid = threadIdx.x;
-    const int g = blockIdx.z;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int M = op.M, N = op.N, K = op.K;
+    const GemmTile tile = gemm_tile((M + BM - 1) / BM, (N + BN - 1) / BN, op.G, 8);
+    if (!tile.valid) return;
+    const int g = tile.g;
+    const int m0 = tile.mt * BM, n0 = tile.nt * BN;
     const int kl = tid % BK;        // this thread's k lane within a stage
     const int rl = tid / BK;        // first row/col handled by this thread
 
@@ -196,7 +198,7 @@ __global__ void k_gemm_f64_reference(GemmOps<cd> op) {
 void gemm_f64(const GemmOps<cd> &op, hipStream_t s) {
     if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
     constexpr int BM = 64, BN = 64, BK = 16;
-    dim3 grid((op.N + BN - 1) / BN, (op.M + BM - 1) / BM, op.G);
+    const dim3 grid = gemm_tile_grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, op.G);
     hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, 2, 2>), grid, dim3(256), 0, s, op);
     CK_CHECK(hipGetLastError());
 }

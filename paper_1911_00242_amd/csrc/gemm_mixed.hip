@@ -1,7 +1,7 @@
 // Split-BF16 grouped complex GEMM for the mixed-precision path (CDNA4 bf16 MFMA).
 //
-// Same contractions and offset tables as the FP64 kernel; operands are stored as four
-// bf16 planes per complex element, plane-major: (re_hi, re_lo, im_hi, im_lo), where
+// Same contractions and offset tables as the FP64 kernel; operands are stored split
+// (mixed.h): four bf16 values per complex element (re_hi, re_lo, im_hi, im_lo), where
 // hi = bf16(x) and lo = bf16(x - hi), both rounded to nearest even, so hi + lo carries
 // 16 significant bits (|x - hi - lo| <= 2^-17 |x|).  A real product is taken as
 // hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is dropped), accumulated in
@@ -10,9 +10,11 @@
 // FP64 output with FP64 arithmetic.
 //
 // Tile: 128 x 128 complex outputs per 256-thread workgroup (2 x 2 waves of 64 x 64 =
-// 2 x 2 MFMA tiles of 32 x 32), 16 complex k per stage, LDS double buffered with
-// register staging.  Global loads move 16 bytes (8 consecutive k of one plane) when the
-// k offsets form aligned runs of 8 (FAST), else element by element.
+// 2 x 2 MFMA tiles of 32 x 32), 16 complex k per stage, LDS double buffered; global loads
+// run two stages ahead through two sets of staging registers, and LDS traffic is
+// interleaved with the MFMAs (see k_gemm_split).  In the fast case (aligned runs of 8 k)
+// eight lanes copy one row's stage, 128 contiguous bytes of split storage, so every load
+// instruction reads whole cache lines; otherwise elements are gathered one by one.
 #include "common.h"
 #include "mixed.h"
 
@@ -20,6 +22,9 @@ namespace ck {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+// 16-byte staging chunk as a native vector (a copy of HIP's uint4 struct becomes a memcpy
+// that keeps a register array in memory)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline uint16_t bf16_rne(float f) {
     uint32_t u = __builtin_bit_cast(uint32_t, f);
@@ -35,21 +40,27 @@ __device__ inline void split2(double x, uint16_t &hi, uint16_t &lo) {
 }
 
 // ------------------------------------------------------------------ conversions
-__global__ void k_split(int64_t n, const cd *src, uint16_t *dst, int64_t plane) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        cd x = src[i];
-        uint16_t a, b, c, d;
-        split2(x.x, a, b);
-        split2(x.y, c, d);
-        dst[i] = a;
-        dst[plane + i] = b;
-        dst[2 * plane + i] = c;
-        dst[3 * plane + i] = d;
+__global__ void k_split(int64_t n, const cd *src, uint16_t *dst) {
+    const int64_t nch = (n + 7) / 8;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t v[4][8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t e = c * 8 + j;
+            const cd x = e < n ? src[e] : make_double2(0.0, 0.0);
+            split2(x.x, v[0][j], v[1][j]);
+            split2(x.y, v[2][j], v[3][j]);
+        }
+        uint4 *o = (uint4 *)(dst + c * 32);
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            o[p] = make_uint4(v[p][0] | (uint32_t)v[p][1] << 16, v[p][2] | (uint32_t)v[p][3] << 16,
+                              v[p][4] | (uint32_t)v[p][5] << 16, v[p][6] | (uint32_t)v[p][7] << 16);
     }
 }
 
-// per momentum block (o^2 x v^2) -> split planes of the (v^2 x o^2) transpose
-__global__ void k_split_transpose(Dims d, const cd *src, uint16_t *dst, int64_t plane) {
+// per momentum block (o^2 x v^2) -> split storage of the (v^2 x o^2) transpose
+__global__ void k_split_transpose(Dims d, const cd *src, uint16_t *dst) {
     __shared__ cd tile[32][33];
     const int R = d.no * d.no, C = d.nv * d.nv;
     const int tr = (R + 31) / 32, tc = (C + 31) / 32;
@@ -72,201 +83,301 @@ __global__ void k_split_transpose(Dims d, const cd *src, uint16_t *dst, int64_t 
             uint16_t a, b, e, f;
             split2(x.x, a, b);
             split2(x.y, e, f);
-            dst[i] = a;
-            dst[plane + i] = b;
-            dst[2 * plane + i] = e;
-            dst[3 * plane + i] = f;
+            dst[split_index(i, 0)] = a;
+            dst[split_index(i, 1)] = b;
+            dst[split_index(i, 2)] = e;
+            dst[split_index(i, 3)] = f;
         }
     }
 }
 
-void launch_split(int64_t n, const cd *src, uint16_t *dst, int64_t plane, hipStream_t st) {
-    int64_t b = std::min<int64_t>((n + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(k_split, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, n, src, dst, plane);
+void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st) {
+    int64_t b = std::min<int64_t>(((n + 7) / 8 + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_split, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, n, src, dst);
     CK_CHECK(hipGetLastError());
 }
 
-void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, int64_t plane, hipStream_t st) {
+void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, hipStream_t st) {
     int R = d.no * d.no, C = d.nv * d.nv;
     dim3 g((unsigned)((int64_t)((R + 31) / 32) * ((C + 31) / 32) * d.N * d.N * d.N));
-    hipLaunchKernelGGL(k_split_transpose, g, dim3(256), 0, st, d, src, dst, plane);
+    hipLaunchKernelGGL(k_split_transpose, g, dim3(256), 0, st, d, src, dst);
     CK_CHECK(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ the GEMM
 // Eight consecutive k of one row of one plane, element by element (zeros out of range).
-__device__ inline uint4 gather8(const uint16_t *base, const int64_t *ktab, const uint16_t *zeros, int g, int K,
-                                int kb, bool rok, int64_t row, int64_t plane_off) {
+__device__ inline u32x4 gather8(const uint16_t *base, const int64_t *ktab, const uint16_t *zeros, int g, int K,
+                                int kb, bool rok, int64_t row, int p) {
     uint32_t v[4];
 #pragma unroll
     for (int j = 0; j < 8; j += 2) {
         const int k = kb + j;
-        const uint16_t *x0 = (rok && k < K) ? base + plane_off + row + ktab[(int64_t)g * K + min(k, K - 1)] : zeros;
-        const uint16_t *x1 = (rok && k + 1 < K) ? base + plane_off + row + ktab[(int64_t)g * K + min(k + 1, K - 1)] : zeros;
+        const uint16_t *x0 =
+            (rok && k < K) ? base + split_index(row + ktab[(int64_t)g * K + min(k, K - 1)], p) : zeros;
+        const uint16_t *x1 =
+            (rok && k + 1 < K) ? base + split_index(row + ktab[(int64_t)g * K + min(k + 1, K - 1)], p) : zeros;
         v[j / 2] = (uint32_t)*x0 | (uint32_t)*x1 << 16;
     }
-    return make_uint4(v[0], v[1], v[2], v[3]);
+    return u32x4{v[0], v[1], v[2], v[3]};
 }
 
+// One of the twelve MFMAs of a 32 x 32 complex tile step: A, B are the four planes
+// (re_hi, re_lo, im_hi, im_lo) of the lane's fragments, NA = (-im_hi, -im_lo) of A.
+// The real and imaginary chains alternate so that consecutive MFMAs are independent.
+template <int k>
+__device__ __forceinline__ void mfma_step(f32x16 &cr, f32x16 &ci, bf16x8 a0, bf16x8 a1, bf16x8 a2, bf16x8 a3,
+                                          bf16x8 na0, bf16x8 na1, bf16x8 b0, bf16x8 b1, bf16x8 b2, bf16x8 b3) {
+    // re += Ar*Br - Ai*Bi ; im += Ar*Bi + Ai*Br, each real product as hi*hi + hi*lo + lo*hi
+    if constexpr (k == 0) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, cr, 0, 0, 0);
+    if constexpr (k == 1) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b2, ci, 0, 0, 0);
+    if constexpr (k == 2) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, cr, 0, 0, 0);
+    if constexpr (k == 3) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b3, ci, 0, 0, 0);
+    if constexpr (k == 4) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, cr, 0, 0, 0);
+    if constexpr (k == 5) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, ci, 0, 0, 0);
+    if constexpr (k == 6) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na0, b2, cr, 0, 0, 0);
+    if constexpr (k == 7) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b0, ci, 0, 0, 0);
+    if constexpr (k == 8) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na0, b3, cr, 0, 0, 0);
+    if constexpr (k == 9) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b1, ci, 0, 0, 0);
+    if constexpr (k == 10) cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na1, b2, cr, 0, 0, 0);
+    if constexpr (k == 11) ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, b0, ci, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 negate_bf16x8(bf16x8 a) {
+    uint4 u = __builtin_bit_cast(uint4, a);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+// Tile: 128 x 128 complex outputs per 256-thread workgroup; wave (wm, wn) owns the 64 x 64
+// quadrant, i.e. 2 x 2 MFMA tiles (i, j) of 32 x 32, with fragments a_i (its rows) and b_j
+// (its columns).  One k stage of 16 complex values is software pipelined so that the
+// MFMA pipe of each wave never waits on memory:
+//   tile (0,0): a_0 b_0, meanwhile LDS reads of a_1, b_1 and the global loads of stage
+//               k+2 into one set of staging registers;
+//   tile (0,1): a_0 b_1, meanwhile the LDS writes of stage k+1 (loaded one stage ago,
+//               other staging set) into the other LDS buffer;
+//   barrier;
+//   tile (1,0): a_1 b_0, meanwhile LDS reads of a_0, b_0 of stage k+1;
+//   tile (1,1): a_1 b_1.
+// Every slot is one MFMA plus a few memory operations, fenced by sched_barrier so the
+// compiler keeps this order.  One barrier per stage suffices: the buffer written in tile
+// (0,1) of stage k was last read in tile (0,0) of stage k-1 and tile (1,0) of stage k-2,
+// both before the barrier of stage k-1, and it is first read in tile (1,0) of stage k,
+// after the barrier of stage k.
 template <bool FAST>
 __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
-    constexpr int BM = 128, BN = 128, BK = 16, PADK = BK + 8;
-    constexpr int PLANE = 128 * PADK;  // bf16 elements per plane in one LDS buffer
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][4 * PLANE];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][4 * PLANE];
+    constexpr int BM = 128, BN = 128, BK = 16;
+    // LDS row: one row's stage as in split storage (two chunks of 8 k, four planes each,
+    // 128 bytes) plus 16 bytes of pad, so that 16 lanes reading 16 consecutive rows hit
+    // distinct banks
+    constexpr int RS = 72;  // bf16 per LDS row
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * RS];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * RS];
 
     const int tid = threadIdx.x;
-    const int g = blockIdx.z;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int M = op.M, N = op.N, K = op.K;
-    // loader: thread -> (row = tid/2, chunk of 8 k = tid%2), all four planes.  Loads are
-    // branch free from clamped, always valid addresses; out-of-range rows and k are
-    // zeroed when the staged registers are written to LDS, so the compiler can keep the
-    // loads in flight across the MFMA work of the current stage.
-    const int lrow = tid >> 1, lkc = tid & 1;
-    const int am = m0 + lrow, bn = n0 + lrow;
-    const bool aok = am < M, bok = bn < N;
-    const int64_t arow = op.a_row[(int64_t)g * M + (aok ? am : M - 1)];
-    const int64_t bcol = op.b_col[(int64_t)g * N + (bok ? bn : N - 1)];
+    const GemmTile tile = gemm_tile((M + BM - 1) / BM, (N + BN - 1) / BN, op.G, 8);
+    if (!tile.valid) return;
+    const int g = tile.g;
+    const int m0 = tile.mt * BM, n0 = tile.nt * BN;
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int l32 = lane & 31, lh = lane >> 5;
+    // loader: lane -> 16-byte piece lq = lane % 8 of one row's stage (chunk lc = lq / 4,
+    // plane lp = lq % 4), rows lr + 8i (i = 0..3) of both A and B, so eight lanes copy one
+    // row's 128 bytes.  Loads are branch free from clamped, always valid addresses
+    // (out-of-range rows and k read the zero buffer), so no data-dependent select sits
+    // between a load and its LDS store.
+    const int lq = lane & 7, lc = lq >> 2, lp = lq & 3;
+    const int lr = wave * 32 + (lane >> 3);
+    const int64_t *a_rows = op.a_row + (int64_t)g * M, *b_cols = op.b_col + (int64_t)g * N;
+#define CK_ROW(i)                                                                    \
+    const int am##i = m0 + lr + 8 * (i), bn##i = n0 + lr + 8 * (i);                  \
+    const bool aok##i = am##i < M, bok##i = bn##i < N;                               \
+    const int64_t arow##i = a_rows[aok##i ? am##i : M - 1], bcol##i = b_cols[bok##i ? bn##i : N - 1];
+    CK_ROW(0)
+    CK_ROW(1)
+    CK_ROW(2)
+    CK_ROW(3)
+#undef CK_ROW
+    // LDS element offsets of this lane's fragment rows (8 consecutive k of row lane % 32,
+    // chunk lane / 32) and of this thread's first staging piece
+    const int fa0 = (wm * 64 + l32) * RS + lh * 32, fa1 = fa0 + 32 * RS;
+    const int fb0 = (wn * 64 + l32) * RS + lh * 32, fb1 = fb0 + 32 * RS;
+    const int sto = lr * RS + lq * 8;
 
-    f32x16 accr[2][2], acci[2][2];
+    f32x16 c00r, c00i, c01r, c01i, c10r, c10i, c11r, c11i;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                accr[i][j][r] = 0.f;
-                acci[i][j][r] = 0.f;
-            }
-
-    // Staged chunk of the next stage (registers), and the k-table offsets of the stage
-    // after it.  Every iteration loads (out-of-range chunks read the zero buffer), so no
-    // data-dependent select sits between a load and its LDS store.
-    uint4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
-    int64_t ak_cur = 0, bk_cur = 0;
+    for (int r = 0; r < 16; ++r) {
+        c00r[r] = c00i[r] = c01r[r] = c01i[r] = 0.f;
+        c10r[r] = c10i[r] = c11r[r] = c11i[r] = 0.f;
+    }
+    bf16x8 A0[2][4], B0[2][4];  // a_0, b_0 of the current stage [parity], of the next [!parity]
+    bf16x8 A1[4], B1[4];        // a_1, b_1 of the current stage
+    bf16x8 NA0[2], NA1[2];
+    u32x4 sa[2][4], sb[2][4];   // staging sets: this thread's pieces of A and B of one stage
+    int64_t ak_cur = 0, bk_cur = 0, ak_nxt = 0, bk_nxt = 0;
     // FAST implies K % 8 == 0 and K >= 8: clamp to the last whole 8-run so a 16-byte load
     // never leaves the operand; otherwise clamp to the last k
     const int kclamp = FAST ? K - 8 : K - 1;
+
+#define CK_SLOT __builtin_amdgcn_sched_barrier(0)
+#define CK_MF(k, CR, CI, A, NA, B) \
+    mfma_step<k>(CR, CI, A[0], A[1], A[2], A[3], NA[0], NA[1], B[0], B[1], B[2], B[3])
+#define CK_NEG(A, NA)                   \
+    {                                   \
+        NA[0] = negate_bf16x8(A[2]);    \
+        NA[1] = negate_bf16x8(A[3]);    \
+    }
 #define CK_KOFS(k0, ak, bk)                                          \
     {                                                                \
-        const int kb_ = min((k0) + lkc * 8, kclamp);                 \
+        const int kb_ = min((k0) + lc * 8, kclamp);                  \
         ak = op.a_k[(int64_t)g * K + kb_];                           \
         bk = op.b_k[(int64_t)g * K + kb_];                           \
     }
-#define CK_LOAD(k0)                                                                                   \
-    {                                                                                                 \
-        const int kb_ = (k0) + lkc * 8;                                                               \
-        if (FAST) {                                                                                   \
-            const uint16_t *pa_ = (kb_ < K && aok) ? op.A + arow + ak_cur : op.zeros;                 \
-            const uint16_t *pb_ = (kb_ < K && bok) ? op.B + bcol + bk_cur : op.zeros;                 \
-            const int64_t sa_ = (kb_ < K && aok) ? op.a_plane : 0, sb_ = (kb_ < K && bok) ? op.b_plane : 0; \
-            sa0 = *(const uint4 *)(pa_);                                                              \
-            sa1 = *(const uint4 *)(pa_ + sa_);                                                        \
-            sa2 = *(const uint4 *)(pa_ + 2 * sa_);                                                    \
-            sa3 = *(const uint4 *)(pa_ + 3 * sa_);                                                    \
-            sb0 = *(const uint4 *)(pb_);                                                              \
-            sb1 = *(const uint4 *)(pb_ + sb_);                                                        \
-            sb2 = *(const uint4 *)(pb_ + 2 * sb_);                                                    \
-            sb3 = *(const uint4 *)(pb_ + 3 * sb_);                                                    \
-        } else {                                                                                      \
-            sa0 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 0);                            \
-            sa1 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, op.a_plane);                   \
-            sa2 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 2 * op.a_plane);               \
-            sa3 = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok, arow, 3 * op.a_plane);               \
-            sb0 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 0);                            \
-            sb1 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, op.b_plane);                   \
-            sb2 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 2 * op.b_plane);               \
-            sb3 = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok, bcol, 3 * op.b_plane);               \
-        }                                                                                             \
+    // row lr + 8i of A or B, stage k0, into staging set S.  Separate names for the A and
+    // B sets (no pointer select between them) keep the staging arrays in registers.
+#define CK_LOADA(k0, S, i)                                                                              \
+    {                                                                                                  \
+        const int kb_ = (k0) + lc * 8;                                                                 \
+        if (FAST) {                                                                                    \
+            const bool ok_ = kb_ < K && aok##i;                                                        \
+            const uint16_t *src_ = ok_ ? op.A + (((arow##i + ak_cur) >> 3) << 5) + lp * 8 : op.zeros;  \
+            sa[S][i] = *(const u32x4 *)src_;                                                           \
+        } else {                                                                                       \
+            sa[S][i] = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok##i, arow##i, lp);                \
+        }                                                                                              \
     }
-#define CK_STORE(buf)                                                     \
-    {                                                                     \
-        uint16_t *a_ = &As[buf][lrow * PADK + lkc * 8];                   \
-        uint16_t *b_ = &Bs[buf][lrow * PADK + lkc * 8];                   \
-        *(uint4 *)(a_) = sa0;                                             \
-        *(uint4 *)(a_ + PLANE) = sa1;                                     \
-        *(uint4 *)(a_ + 2 * PLANE) = sa2;                                 \
-        *(uint4 *)(a_ + 3 * PLANE) = sa3;                                 \
-        *(uint4 *)(b_) = sb0;                                             \
-        *(uint4 *)(b_ + PLANE) = sb1;                                     \
-        *(uint4 *)(b_ + 2 * PLANE) = sb2;                                 \
-        *(uint4 *)(b_ + 3 * PLANE) = sb3;                                 \
+#define CK_LOADB(k0, S, i)                                                                              \
+    {                                                                                                  \
+        const int kb_ = (k0) + lc * 8;                                                                 \
+        if (FAST) {                                                                                    \
+            const bool ok_ = kb_ < K && bok##i;                                                        \
+            const uint16_t *src_ = ok_ ? op.B + (((bcol##i + bk_cur) >> 3) << 5) + lp * 8 : op.zeros;  \
+            sb[S][i] = *(const u32x4 *)src_;                                                           \
+        } else {                                                                                       \
+            sb[S][i] = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok##i, bcol##i, lp);                \
+        }                                                                                              \
+    }
+#define CK_STOREA(buf, S, i) *(u32x4 *)(&As[buf][sto + (i) * 8 * RS]) = sa[S][i]
+#define CK_STOREB(buf, S, i) *(u32x4 *)(&Bs[buf][sto + (i) * 8 * RS]) = sb[S][i]
+#define CK_RDA(dst, buf, off, p) dst = *(const bf16x8 *)(&As[buf][(off) + (p) * 8])
+#define CK_RDB(dst, buf, off, p) dst = *(const bf16x8 *)(&Bs[buf][(off) + (p) * 8])
+
+    // one pipelined stage KT held in LDS buffer BUF (literal 0 or 1); staging set BUF
+    // receives stage KT+2, set BUF^1 holds stage KT+1
+#define CK_STAGE(KT, BUF)                                                                              \
+    {                                                                                                  \
+        CK_NEG(A0[BUF], NA0);                                                                       \
+        /* tile (0,0) */                                                                               \
+        CK_MF(0, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[0], BUF, fb1, 0); CK_SLOT;          \
+        CK_MF(1, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[1], BUF, fb1, 1); CK_SLOT;          \
+        CK_MF(2, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[2], BUF, fb1, 2); CK_SLOT;          \
+        CK_MF(3, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[3], BUF, fb1, 3); CK_SLOT;          \
+        CK_MF(4, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[0], BUF, fa1, 0); CK_SLOT;          \
+        CK_MF(5, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[1], BUF, fa1, 1); CK_SLOT;          \
+        CK_MF(6, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[2], BUF, fa1, 2); CK_SLOT;          \
+        CK_MF(7, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[3], BUF, fa1, 3); CK_SLOT;          \
+        CK_MF(8, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_KOFS(((KT) + 3) * BK, ak_nxt, bk_nxt); CK_SLOT; \
+        CK_MF(9, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                               \
+        CK_LOADA(((KT) + 2) * BK, BUF, 0); CK_LOADA(((KT) + 2) * BK, BUF, 1); CK_SLOT;           \
+        CK_MF(10, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                              \
+        CK_LOADA(((KT) + 2) * BK, BUF, 2); CK_LOADA(((KT) + 2) * BK, BUF, 3);                    \
+        CK_LOADB(((KT) + 2) * BK, BUF, 0); CK_SLOT;                                                 \
+        CK_MF(11, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                              \
+        CK_LOADB(((KT) + 2) * BK, BUF, 1); CK_LOADB(((KT) + 2) * BK, BUF, 2);                    \
+        CK_LOADB(((KT) + 2) * BK, BUF, 3); CK_SLOT;                                                 \
+        /* tile (0,1) */                                                                               \
+        CK_MF(0, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;    \
+        CK_MF(1, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;    \
+        CK_MF(2, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;    \
+        CK_MF(3, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;    \
+        CK_MF(4, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;    \
+        CK_MF(5, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;    \
+        CK_MF(6, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;    \
+        CK_MF(7, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;    \
+        CK_MF(8, c01r, c01i, A0[BUF], NA0, B1); CK_NEG(A1, NA1); CK_SLOT;                       \
+        CK_MF(9, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                           \
+        CK_MF(10, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                          \
+        CK_MF(11, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                          \
+        __syncthreads();                                                                               \
+        CK_SLOT;                                                                                       \
+        /* tile (1,0) */                                                                               \
+        CK_MF(0, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][0], (BUF) ^ 1, fa0, 0); CK_SLOT; \
+        CK_MF(1, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][0], (BUF) ^ 1, fb0, 0); CK_SLOT; \
+        CK_MF(2, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][1], (BUF) ^ 1, fa0, 1); CK_SLOT; \
+        CK_MF(3, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][1], (BUF) ^ 1, fb0, 1); CK_SLOT; \
+        CK_MF(4, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][2], (BUF) ^ 1, fa0, 2); CK_SLOT; \
+        CK_MF(5, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][2], (BUF) ^ 1, fb0, 2); CK_SLOT; \
+        CK_MF(6, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][3], (BUF) ^ 1, fa0, 3); CK_SLOT; \
+        CK_MF(7, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][3], (BUF) ^ 1, fb0, 3); CK_SLOT; \
+        CK_MF(8, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                           \
+        CK_MF(9, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                           \
+        CK_MF(10, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                          \
+        CK_MF(11, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                          \
+        /* tile (1,1) */                                                                               \
+        CK_MF(0, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(1, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(2, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(3, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(4, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(5, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(6, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(7, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(8, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(9, c11r, c11i, A1, NA1, B1);                                                         \
+        CK_MF(10, c11r, c11i, A1, NA1, B1);                                                        \
+        CK_MF(11, c11r, c11i, A1, NA1, B1);                                                        \
+        CK_SLOT;                                                                                       \
+        ak_cur = ak_nxt;                                                                               \
+        bk_cur = bk_nxt;                                                                               \
     }
 
     const int nk = (K + BK - 1) / BK;
-    if (K > 0) {
+    if (nk > 0) {
+        // prologue: stage 0 into LDS buffer 0 and its a_0, b_0 into registers; stage 1 into
+        // staging set 1; k offsets of stage 2 ready
         CK_KOFS(0, ak_cur, bk_cur);
-        CK_LOAD(0);
-        CK_STORE(0);
+        CK_LOADA(0, 0, 0); CK_LOADA(0, 0, 1); CK_LOADA(0, 0, 2); CK_LOADA(0, 0, 3);
+        CK_LOADB(0, 0, 0); CK_LOADB(0, 0, 1); CK_LOADB(0, 0, 2); CK_LOADB(0, 0, 3);
+        CK_STOREA(0, 0, 0); CK_STOREA(0, 0, 1); CK_STOREA(0, 0, 2); CK_STOREA(0, 0, 3);
+        CK_STOREB(0, 0, 0); CK_STOREB(0, 0, 1); CK_STOREB(0, 0, 2); CK_STOREB(0, 0, 3);
         CK_KOFS(BK, ak_cur, bk_cur);
-    }
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        int64_t ak_nxt, bk_nxt;
-        // next stage's data (zeros past the end) and the k offsets of the one after it,
-        // issued ahead of the MFMA work they overlap with
-        CK_LOAD((kt + 1) * BK);
-        CK_KOFS((kt + 2) * BK, ak_nxt, bk_nxt);
-        __builtin_amdgcn_sched_barrier(0);
-        // fragments: lane holds 8 consecutive k of row (lane % 32), k offset 8 * (lane / 32)
-        bf16x8 a[2][4], b[2][4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                a[i][p] = *(const bf16x8 *)(&As[buf][p * PLANE + (wm * 64 + i * 32 + l32) * PADK + lh * 8]);
-                b[i][p] = *(const bf16x8 *)(&Bs[buf][p * PLANE + (wn * 64 + i * 32 + l32) * PADK + lh * 8]);
-            }
-        // -A_im for the real part
-        bf16x8 na[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                uint4 u = __builtin_bit_cast(uint4, a[i][2 + p]);
-                u.x ^= 0x80008000u;
-                u.y ^= 0x80008000u;
-                u.z ^= 0x80008000u;
-                u.w ^= 0x80008000u;
-                na[i][p] = __builtin_bit_cast(bf16x8, u);
-            }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                f32x16 cr = accr[i][j], ci = acci[i][j];
-                // re += Ar*Br - Ai*Bi
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na[i][0], b[j][2], cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na[i][0], b[j][3], cr, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(na[i][1], b[j][2], cr, 0, 0, 0);
-                // im += Ar*Bi + Ai*Br
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][3], ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][2], ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][1], ci, 0, 0, 0);
-                ci = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][3], b[j][0], ci, 0, 0, 0);
-                accr[i][j] = cr;
-                acci[i][j] = ci;
-            }
-        __builtin_amdgcn_sched_barrier(0);
-        CK_STORE(buf ^ 1);  // buf ^ 1 was last read before the previous barrier
-        ak_cur = ak_nxt;
-        bk_cur = bk_nxt;
+        CK_LOADA(BK, 1, 0); CK_LOADA(BK, 1, 1); CK_LOADA(BK, 1, 2); CK_LOADA(BK, 1, 3);
+        CK_LOADB(BK, 1, 0); CK_LOADB(BK, 1, 1); CK_LOADB(BK, 1, 2); CK_LOADB(BK, 1, 3);
+        CK_KOFS(2 * BK, ak_cur, bk_cur);
         __syncthreads();
+        // (constant indices only: a loop index here would let the compiler move the
+        // register arrays to LDS)
+        CK_RDA(A0[0][0], 0, fa0, 0); CK_RDA(A0[0][1], 0, fa0, 1); CK_RDA(A0[0][2], 0, fa0, 2); CK_RDA(A0[0][3], 0, fa0, 3);
+        CK_RDB(B0[0][0], 0, fb0, 0); CK_RDB(B0[0][1], 0, fb0, 1); CK_RDB(B0[0][2], 0, fb0, 2); CK_RDB(B0[0][3], 0, fb0, 3);
+        // unrolled by two so that every register set has a fixed role in each half; one
+        // exit, so the accumulators keep their registers across the halves
+        int kt = 0;
+        for (; kt + 1 < nk; kt += 2) {
+            CK_STAGE(kt, 0);
+            CK_STAGE(kt + 1, 1);
+        }
+        if (kt < nk) CK_STAGE(kt, 0);
     }
+#undef CK_SLOT
+#undef CK_MF
+#undef CK_NEG
 #undef CK_KOFS
-#undef CK_LOAD
-#undef CK_STORE
+#undef CK_LOADA
+#undef CK_LOADB
+#undef CK_STOREA
+#undef CK_STOREB
+#undef CK_RDA
+#undef CK_RDB
+#undef CK_STAGE
+
+    f32x16 accr[2][2] = {{c00r, c01r}, {c10r, c11r}};
+    f32x16 acci[2][2] = {{c00i, c01i}, {c10i, c11i}};
 
     // epilogue: 32x32 f32 output, register r of a lane holds row 8*(r/4) + 4*(lane/32) + r%4
     // of column lane%32
@@ -296,7 +407,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 
 void gemm_split(const SplitOps &op, hipStream_t s) {
     if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
-    dim3 grid((op.N + 127) / 128, (op.M + 127) / 128, op.G);
+    const dim3 grid = gemm_tile_grid((op.M + 127) / 128, (op.N + 127) / 128, op.G);
     if (op.fast)
         hipLaunchKernelGGL(k_gemm_split<true>, grid, dim3(256), 0, s, op);
     else

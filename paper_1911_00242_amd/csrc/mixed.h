@@ -4,14 +4,20 @@
 
 namespace ck {
 
-// Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps.  A and B
-// hold four bf16 planes (re_hi, re_lo, im_hi, im_lo) at plane strides a_plane, b_plane
-// (elements); C is complex128.  fast = 1 when every aligned group of 8 k indices is
-// contiguous and 16-byte aligned in both operands (then loads move 8 k at once).
+// Split-BF16 storage: every complex element x becomes four bf16 values (re_hi, re_lo,
+// im_hi, im_lo), hi = bf16(x), lo = bf16(x - hi).  They are stored chunk interleaved:
+// elements 8c .. 8c+7 of an operand occupy 64 contiguous bytes, plane p at bytes
+// 16p .. 16p+15, so the 16-byte loads of the GEMM read whole 128-byte lines for two
+// consecutive chunks.  An operand of n elements takes 4 * round_up(n, 8) bf16 values.
+__host__ __device__ inline int64_t split_index(int64_t e, int p) { return ((e >> 3) << 5) + (p << 3) + (e & 7); }
+
+// Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element
+// offsets into the unsplit operand, mapped through split_index).  C is complex128.
+// fast = 1 when every aligned group of 8 k indices is contiguous and starts at a multiple
+// of 8 in both operands (then loads move 8 k of one plane at once).
 struct SplitOps {
     const uint16_t *A, *B;
     const uint16_t *zeros;  // >= 16 bytes of zeros: the load address of out-of-range chunks
-    int64_t a_plane, b_plane;
     cd *C;
     const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
     int G, M, N, K;
@@ -20,11 +26,11 @@ struct SplitOps {
 };
 
 void gemm_split(const SplitOps &op, hipStream_t s);
-// dst planes of n elements each (plane stride `plane`) from complex128 src
-void launch_split(int64_t n, const cd *src, uint16_t *dst, int64_t plane, hipStream_t st);
-// split planes of the per-block (o^2 x v^2) -> (v^2 x o^2) transpose of src
-void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, int64_t plane, hipStream_t st);
-// T1-dressed <ab||ef> written as split planes
-void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, int64_t plane, hipStream_t st);
+// split storage of n complex128 elements (pad of the last chunk zeroed)
+void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st);
+// split storage of the per-block (o^2 x v^2) -> (v^2 x o^2) transpose of src
+void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, hipStream_t st);
+// T1-dressed <ab||ef> written in split storage
+void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st);
 
 }  // namespace ck

@@ -414,7 +414,7 @@ __host__ __device__ inline bool dress_fits(const Dims &d) {
 }
 
 template <bool SPLIT>
-__device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs, int64_t plane) {
+__device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs) {
     __shared__ cd G1[DR_G1];
     __shared__ cd TB[DR_T1];
     __shared__ cd TA[64];
@@ -451,10 +451,10 @@ __device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_
             uint16_t p0, p1, p2, p3;
             split_rne2(acc.x, p0, p1);
             split_rne2(acc.y, p2, p3);
-            Vs[idx] = p0;
-            Vs[plane + idx] = p1;
-            Vs[2 * plane + idx] = p2;
-            Vs[3 * plane + idx] = p3;
+            Vs[split_index(idx, 0)] = p0;
+            Vs[split_index(idx, 1)] = p1;
+            Vs[split_index(idx, 2)] = p2;
+            Vs[split_index(idx, 3)] = p3;
         } else {
             Vt[idx] = acc;
         }
@@ -462,10 +462,10 @@ __device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_
 }
 
 __global__ __launch_bounds__(256) void k_vvvv_dress(SysDev s, const cd *t1, cd *Vt) {
-    dress_body<false>(s, t1, Vt, nullptr, 0);
+    dress_body<false>(s, t1, Vt, nullptr);
 }
-__global__ __launch_bounds__(256) void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt, int64_t plane) {
-    dress_body<true>(s, t1, nullptr, Vt, plane);
+__global__ __launch_bounds__(256) void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt) {
+    dress_body<true>(s, t1, nullptr, Vt);
 }
 
 // ------------------------------------------------------------------ ring intermediate seed
@@ -754,9 +754,9 @@ void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
     CK_CHECK(hipGetLastError());
 }
 
-void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, int64_t plane, hipStream_t st) {
+void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
-    hipLaunchKernelGGL(k_vvvv_dress_split, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt, plane);
+    hipLaunchKernelGGL(k_vvvv_dress_split, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt);
     CK_CHECK(hipGetLastError());
 }
 
