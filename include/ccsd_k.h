@@ -90,7 +90,11 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
 /* One evaluation of (R1, R2) (eqs. ori_EqSingle, ori_EqDouble) for system sys.
  * t1/t2: host amplitudes to evaluate at (they become the system's current amplitudes);
  * NULL = the current device amplitudes.  r1/r2: host buffers for the result, or NULL to
- * keep it on the device only. */
+ * keep it on the device only.  t2 must be antisymmetric, t_{ij}^{ab} = -t_{ji}^{ab} =
+ * -t_{ij}^{ba} (with the momenta exchanged alike), as every CCSD amplitude is: several
+ * terms of the T2 equation are combined under one P(ij)P(ab) using that symmetry, so for
+ * other input the result differs from the equation by terms that vanish on antisymmetric
+ * amplitudes.  Amplitudes produced by ccsd_k_iterate keep the symmetry. */
 int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1,
                     double *r2);
 

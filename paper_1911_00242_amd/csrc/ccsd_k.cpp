@@ -355,6 +355,8 @@ void bind_ops(System &S) {
         s.B = SB[i];
         s.zeros = reinterpret_cast<const uint16_t *>(S.zeros);
         s.C = o.C;
+        // W_mnij and W_mbej are only consumed as split operands: their products write split
+        s.Cs = i == 0 ? S.sp_WT : i == 3 ? S.sp_WR : nullptr;
         s.a_row = o.a_row; s.a_k = o.a_k; s.b_col = o.b_col; s.b_k = o.b_k; s.c_row = o.c_row; s.c_col = o.c_col;
         s.G = o.G; s.M = o.M; s.N = o.N; s.K = o.K; s.alpha = o.alpha; s.beta = o.beta;
         s.fast = fast_ok(S, i) ? 1 : 0;
@@ -409,6 +411,8 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     stage_begin(c, all, ST_RES);
     if (!S.mixed) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
+    } else if (ck::tau_split_ok(S.d)) {
+        ck::launch_tau_split(S.d, S.dkc, S.t1(), S.t2(), S.sp_tau, S.sp_tauT, S.sp_t2, st);
     } else {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, nullptr, st);
         ck::launch_split(S.n2(), S.tau, S.sp_tau, st);
@@ -417,16 +421,11 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
     ck::launch_wmnij_init(s, S.t1(), S.WT, st);
-    run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>
-    if (!S.mixed) {
-        ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
-    } else {
-        ck::launch_split((int64_t)S.d.N * S.d.N * S.d.N * S.d.no * S.d.no * S.d.no * S.d.no, S.WT, S.sp_WT, st);
-        ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, st);
-    }
+    run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>  (mixed: written split)
+    if (!S.mixed) ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+    else ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, st);
     ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
-    run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
-    if (S.mixed) ck::launch_split(S.n2(), S.WR, S.sp_WR, st);
+    run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>  (mixed: written split)
     run_gemm(c, S, 4);  // X += t2 W_mbej
     ck::launch_assemble_r2(s, S.X, S.r2(), st);
     run_gemm(c, S, 1);  // particle-particle ladder

@@ -26,19 +26,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // that keeps a register array in memory)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ inline uint16_t bf16_rne(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__host__ __device__ inline float bf16_to_f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
-
-__device__ inline void split2(double x, uint16_t &hi, uint16_t &lo) {
-    hi = bf16_rne((float)x);
-    lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
-}
-
 // ------------------------------------------------------------------ conversions
 __global__ void k_split(int64_t n, const cd *src, uint16_t *dst) {
     const int64_t nch = (n + 7) / 8;
@@ -94,6 +81,86 @@ __global__ void k_split_transpose(Dims d, const cd *src, uint16_t *dst) {
 void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st) {
     int64_t b = std::min<int64_t>(((n + 7) / 8 + 255) / 256, 1 << 20);
     hipLaunchKernelGGL(k_split, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, n, src, dst);
+    CK_CHECK(hipGetLastError());
+}
+
+// tau = t2 + d(ka,ki) t_i^a t_j^b - d(kb,ki) t_i^b t_j^a, written with t2 itself and the
+// per-block transpose of tau in split storage, from one read of t2.  Per momentum block
+// (o^2 x v^2 row-major): a workgroup per 32 x 64 tile, a thread per (row, 8-column
+// chunk), so every split store is one 64-byte chunk; the transpose goes through LDS,
+// a thread per (column, 8-row chunk).
+__device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
+    uint16_t h[4][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        split2(x[j].x, h[0][j], h[1][j]);
+        split2(x[j].y, h[2][j], h[3][j]);
+    }
+    uint4 *o = (uint4 *)(dst + split_index(e0, 0));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        o[p] = make_uint4(h[p][0] | (uint32_t)h[p][1] << 16, h[p][2] | (uint32_t)h[p][3] << 16,
+                          h[p][4] | (uint32_t)h[p][5] << 16, h[p][6] | (uint32_t)h[p][7] << 16);
+}
+
+__global__ __launch_bounds__(256) void k_tau_split(Dims d, const int32_t *kc, const cd *t1, const cd *t2,
+                                                   uint16_t *tau_s, uint16_t *tauT_s, uint16_t *t2_s) {
+    __shared__ cd tile[32][64 + 1];
+    const int N = d.N, no = d.no, nv = d.nv, R = no * no, C = nv * nv;
+    const int tr = (R + 31) / 32, tc = C / 64 + (C % 64 ? 1 : 0);
+    const int64_t blk = blockIdx.x / (tr * tc);
+    const int t = (int)(blockIdx.x % (tr * tc));
+    const int r0 = (t / tc) * 32, c0 = (t % tc) * 64;
+    const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+    const int kb = kc[((int64_t)ki * N + kj) * N + ka];
+    const int64_t ob = blk * (int64_t)R * C;
+    {
+        const int y = threadIdx.x >> 3, cc = c0 + (threadIdx.x & 7) * 8;
+        const int r = r0 + y;
+        if (r < R && cc < C) {
+            const int i = r / no, j = r % no;
+            const int64_t e0 = ob + (int64_t)r * C + cc;
+            cd x[8], u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int a = (cc + q) / nv, b = (cc + q) % nv;
+                x[q] = t2[e0 + q];
+                u[q] = x[q];
+                if (ka == ki) {
+                    const cd p = cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + j) * nv + b]);
+                    u[q].x += p.x;
+                    u[q].y += p.y;
+                }
+                if (kb == ki) {
+                    const cd p = cmul(t1[((int64_t)ki * no + i) * nv + b], t1[((int64_t)kj * no + j) * nv + a]);
+                    u[q].x -= p.x;
+                    u[q].y -= p.y;
+                }
+                tile[y][(threadIdx.x & 7) * 8 + q] = u[q];
+            }
+            put_chunk(t2_s, e0, x);
+            put_chunk(tau_s, e0, u);
+        }
+    }
+    __syncthreads();
+    {
+        const int c = c0 + (threadIdx.x & 63), y0 = (threadIdx.x >> 6) * 8, r = r0 + y0;
+        if (c < C && r < R) {
+            cd u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = tile[y0 + q][threadIdx.x & 63];
+            put_chunk(tauT_s, ob + (int64_t)c * R + r, u);
+        }
+    }
+}
+
+bool tau_split_ok(const Dims &d) { return (d.no * d.no) % 8 == 0 && (d.nv * d.nv) % 8 == 0; }
+
+void launch_tau_split(const Dims &d, const int32_t *kc, const cd *t1, const cd *t2, uint16_t *tau_s,
+                      uint16_t *tauT_s, uint16_t *t2_s, hipStream_t st) {
+    const int R = d.no * d.no, C = d.nv * d.nv;
+    const int64_t tiles = (int64_t)((R + 31) / 32) * ((C + 63) / 64) * d.N * d.N * d.N;
+    hipLaunchKernelGGL(k_tau_split, dim3((unsigned)tiles), dim3(256), 0, st, d, kc, t1, t2, tau_s, tauT_s, t2_s);
     CK_CHECK(hipGetLastError());
 }
 
@@ -198,7 +265,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 #define CK_ROW(i)                                                                    \
     const int am##i = m0 + lr + 8 * (i), bn##i = n0 + lr + 8 * (i);                  \
     const bool aok##i = am##i < M, bok##i = bn##i < N;                               \
-    const int64_t arow##i = a_rows[aok##i ? am##i : M - 1], bcol##i = b_cols[bok##i ? bn##i : N - 1];
+    const int64_t arow##i = a_rows[aok##i ? am##i : M - 1], bcol##i = b_cols[bok##i ? bn##i : N - 1]; \
+    /* fast case: offsets are multiples of 8, so split_index(e, lp) = 4 e + 8 lp */            \
+    const uint16_t *abase##i = op.A + arow##i * 4 + lp * 8, *bbase##i = op.B + bcol##i * 4 + lp * 8;
     CK_ROW(0)
     CK_ROW(1)
     CK_ROW(2)
@@ -246,7 +315,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         const int kb_ = (k0) + lc * 8;                                                                 \
         if (FAST) {                                                                                    \
             const bool ok_ = kb_ < K && aok##i;                                                        \
-            const uint16_t *src_ = ok_ ? op.A + (((arow##i + ak_cur) >> 3) << 5) + lp * 8 : op.zeros;  \
+            const uint16_t *src_ = ok_ ? abase##i + ak_cur * 4 : op.zeros;                              \
             sa[S][i] = *(const u32x4 *)src_;                                                           \
         } else {                                                                                       \
             sa[S][i] = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok##i, arow##i, lp);                \
@@ -257,7 +326,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         const int kb_ = (k0) + lc * 8;                                                                 \
         if (FAST) {                                                                                    \
             const bool ok_ = kb_ < K && bok##i;                                                        \
-            const uint16_t *src_ = ok_ ? op.B + (((bcol##i + bk_cur) >> 3) << 5) + lp * 8 : op.zeros;  \
+            const uint16_t *src_ = ok_ ? bbase##i + bk_cur * 4 : op.zeros;                              \
             sb[S][i] = *(const u32x4 *)src_;                                                           \
         } else {                                                                                       \
             sb[S][i] = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok##i, bcol##i, lp);                \
@@ -393,14 +462,25 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
                 if (m >= M) continue;
-                cd *p = op.C + op.c_row[(int64_t)g * M + m] + ccol;
+                const int64_t e = op.c_row[(int64_t)g * M + m] + ccol;
+                cd *p = op.C + e;
                 cd v = make_double2(alpha * (double)accr[i][j][r], alpha * (double)acci[i][j][r]);
                 if (beta != 0.0) {
                     cd o = *p;
                     v.x = fma(beta, o.x, v.x);
                     v.y = fma(beta, o.y, v.y);
                 }
-                *p = v;
+                if (op.Cs) {
+                    uint16_t h0, h1, h2, h3;
+                    split2(v.x, h0, h1);
+                    split2(v.y, h2, h3);
+                    op.Cs[split_index(e, 0)] = h0;
+                    op.Cs[split_index(e, 1)] = h1;
+                    op.Cs[split_index(e, 2)] = h2;
+                    op.Cs[split_index(e, 3)] = h3;
+                } else {
+                    *p = v;
+                }
             }
         }
 }

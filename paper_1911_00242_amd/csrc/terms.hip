@@ -51,18 +51,6 @@ __device__ inline cd tau_el(const cd *t1, const cd *t2, int64_t idx, int ki, int
     return v;
 }
 
-// hi = RNE_bf16(x), lo = RNE_bf16(x - hi): the split-BF16 pair of the mixed path
-__device__ inline uint16_t rne_bf16(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ inline void split_rne2(double x, uint16_t &hi, uint16_t &lo) {
-    hi = rne_bf16((float)x);
-    lo = rne_bf16((float)(x - (double)__builtin_bit_cast(float, (uint32_t)hi << 16)));
-}
-
 // ------------------------------------------------------------------ tau and its transpose
 __global__ void k_tau(Dims d, const int32_t *kc, const cd *t1, const cd *t2, cd *tau) {
     const int N = d.N, no = d.no, nv = d.nv;
@@ -228,12 +216,123 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     }
 }
 
+// Register-blocked form of k_f_blocks for n_occ <= OM, n_vir <= VM: 256 threads per
+// block, the n-slab of the next iteration loaded into registers while the current one is
+// used from LDS.  Fvv: a thread owns a 2 x 2 (a, e) tile and a quarter of the m range;
+// Foo: a thread owns a 2 x 2 (m, i) tile and one sixteenth of the (e, f) range; each LDS
+// read feeds two multiply-adds.  Partial sums are combined through LDS at the end.
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
+    static_assert(OM % 8 == 0 && VM % 16 == 0, "tiling");
+    constexpr int VP = VM + 1, SL = OM * VM * VP;
+    constexpr int PER = OM * VM * VM / 256;  // slab elements staged per thread
+    __shared__ cd TS[SL], GS[SL];            // taut(x, n, e, f), <x n||e f> at (x * VM + e) * VP + f
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int tid = threadIdx.x;
+    const int64_t blk = blockIdx.x;
+    const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
+    const int kb = kcv(s.kc, N, p, q, r);
+    const int64_t base = blk * s.d.t2blk();
+    cd pt[PER], pg[PER];
+#define FB_LOAD(n)                                                                              \
+    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
+        const int x = tid + 256 * u;                                                            \
+        const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
+        if (row < no && e < nv && f < nv) {                                                     \
+            const int64_t gi = base + (((int64_t)row * no + (n)) * nv + e) * nv + f;            \
+            pt[u] = tau_el(t1, t2, gi, p, q, r, kb, row, (n), e, f, no, nv, 0.5);                \
+            pg[u] = s.oovv[gi];                                                                 \
+        } else {                                                                                \
+            pt[u] = pg[u] = make_double2(0.0, 0.0);                                             \
+        }                                                                                       \
+    }
+#define FB_STORE()                                                                              \
+    _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
+        const int x = tid + 256 * u;                                                            \
+        const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
+        TS[(row * VM + e) * VP + f] = pt[u];                                                    \
+        GS[(row * VM + e) * VP + f] = pg[u];                                                    \
+    }
+    // Fvv roles: tile (a0, e0), m quarter
+    const int vs = tid / 64, vt = tid % 64;
+    const int a0 = 2 * (vt / (VM / 2) % (VM / 2)), e0 = 2 * (vt % (VM / 2));
+    // (VM = 16: 64 tiles of 2 x 2 cover 16 x 16)
+    // Foo roles: tile (m0, i0), (e, f) sixteenth
+    const int os = tid / 16, ot = tid % 16;
+    const int m0 = 2 * (ot / 4), i0 = 2 * (ot % 4);  // OM = 8: 16 tiles of 2 x 2
+    cd v00 = {0, 0}, v01 = {0, 0}, v10 = {0, 0}, v11 = {0, 0};
+    cd o00 = {0, 0}, o01 = {0, 0}, o10 = {0, 0}, o11 = {0, 0};
+    FB_LOAD(0)
+    FB_STORE()
+    __syncthreads();
+    for (int n = 0; n < no; ++n) {
+        if (n + 1 < no) FB_LOAD(n + 1)
+        // Fvv(a,e) += sum_{m in quarter, f} taut(m,n,a,f) <mn||ef>
+#pragma unroll
+        for (int mm = 0; mm < OM / 4; ++mm) {
+            const int m = vs * (OM / 4) + mm;
+#pragma unroll 4
+            for (int f = 0; f < VM; ++f) {
+                const cd ta0 = TS[(m * VM + a0) * VP + f], ta1 = TS[(m * VM + a0 + 1) * VP + f];
+                const cd ge0 = GS[(m * VM + e0) * VP + f], ge1 = GS[(m * VM + e0 + 1) * VP + f];
+                cfma(v00, ta0, ge0);
+                cfma(v01, ta0, ge1);
+                cfma(v10, ta1, ge0);
+                cfma(v11, ta1, ge1);
+            }
+        }
+        // Foo(m,i) += sum_{(e,f) in sixteenth} taut(i,n,e,f) <mn||ef>
+#pragma unroll 4
+        for (int k = 0; k < VM * VM / 16; ++k) {
+            const int ef = os * (VM * VM / 16) + k, e = ef / VM, f = ef % VM;
+            const cd ti0 = TS[(i0 * VM + e) * VP + f], ti1 = TS[((i0 + 1) * VM + e) * VP + f];
+            const cd gm0 = GS[(m0 * VM + e) * VP + f], gm1 = GS[((m0 + 1) * VM + e) * VP + f];
+            cfma(o00, ti0, gm0);
+            cfma(o01, ti1, gm0);
+            cfma(o10, ti0, gm1);
+            cfma(o11, ti1, gm1);
+        }
+        __syncthreads();
+        if (n + 1 < no) {
+            FB_STORE()
+        }
+        __syncthreads();
+    }
+#undef FB_LOAD
+#undef FB_STORE
+    // combine the partial sums (LDS reused)
+    cd *ro = TS, *rv = GS;
+    ro[os * 64 + ot * 4 + 0] = o00;
+    ro[os * 64 + ot * 4 + 1] = o01;
+    ro[os * 64 + ot * 4 + 2] = o10;
+    ro[os * 64 + ot * 4 + 3] = o11;
+    rv[vs * 256 + vt * 4 + 0] = v00;
+    rv[vs * 256 + vt * 4 + 1] = v01;
+    rv[vs * 256 + vt * 4 + 2] = v10;
+    rv[vs * 256 + vt * 4 + 3] = v11;
+    __syncthreads();
+    if (tid < 64) {
+        cd sum = {0, 0};
+        for (int k = 0; k < 16; ++k) sum = cadd(sum, ro[k * 64 + tid]);
+        const int t = tid / 4, c = tid % 4;
+        const int m = 2 * (t / 4) + c / 2, i = 2 * (t % 4) + c % 2;
+        if (m < no && i < no) Poo[blk * no * no + (int64_t)m * no + i] = cscale(sum, 0.5);
+    }
+    {
+        cd sum = {0, 0};
+        for (int k = 0; k < 4; ++k) sum = cadd(sum, rv[k * 256 + tid]);
+        const int t = tid / 4, c = tid % 4;
+        const int a = 2 * (t / (VM / 2)) + c / 2, e = 2 * (t % (VM / 2)) + c % 2;
+        if (a < nv && e < nv) Pvv[(((int64_t)r * N + p) * N + q) * nv * nv + (int64_t)a * nv + e] = cscale(sum, -0.5);
+    }
+}
+
 // The two t2-integral sums of the T1 equation read the same t2 block [p,q,r]; one
 // workgroup per block stages t2(:, n, :, :), <n q, a p||ef> and <m p, n q||i r, f> through
 // LDS one n-slab at a time and forms
 //   P1[p][q][r](i,a) += -1/2 sum_{n,e,f} t2(i,n,e,f) <n q, a p || e r, f>   (k = p)
 //   P1[r][p][q](i,a) += -1/2 sum_{m,n,f} t2(m,n,a,f) <m p, n q || i r, f>   (k = r)
-// written to two partial arrays that k_r1 adds.
+// written to two partial arrays that k_r1_wave adds.
 constexpr int RB_T = 2176, RB_G = 4352, RB_H = 1152;
 inline bool r1_blocks_fit(const Dims &d) {
     return (int64_t)d.no * d.nv * (d.nv + 1) <= RB_T && (int64_t)d.nv * (d.nv * d.nv + 1) <= RB_G &&
@@ -296,6 +395,106 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
         cd sum = make_double2(0.0, 0.0);
         for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
         P1b[(((int64_t)r * N + p) * N + q) * nout + tid] = cscale(sum, -0.5);
+    }
+}
+
+// Register-blocked form of k_r1_blocks for n_occ <= OM, n_vir <= VM: 256 threads per
+// block, looping over n with the t2 slab t2(x, n, e, f) and the <m p, n q||i r, f> slab
+// staged in LDS (the next n prefetched into registers).  For P1a a thread owns one a and
+// a sixteenth of (e, f) and streams <n q, a p||e r, f> from global memory once, for every
+// i; for P1b a thread owns one (i, a) and half of the m range.
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
+    static_assert(OM == 8 && VM == 16, "thread roles assume n_occ <= 8, n_vir <= 16");
+    constexpr int VP = VM + 1;
+    constexpr int TSL = OM * VM * VP, HSL = OM * OM * VP;
+    constexpr int PT = OM * VM * VM / 256, PH = OM * OM * VM / 256;
+    __shared__ cd TS[TSL];  // t2(x, n, e, f) at (x * VM + e) * VP + f
+    __shared__ cd HS[HSL];  // <m p, n q||i r, f> at (m * OM + i) * VP + f
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int tid = threadIdx.x;
+    const int64_t blk = blockIdx.x;
+    const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
+    const int64_t tb = blk * s.d.t2blk();
+    const int64_t ov3 = (int64_t)no * nv * nv * nv, o3v = (int64_t)no * no * no * nv;
+    const cd *gb = s.ovvv + blk3(N, q, p, r) * ov3;  // (n, a, e, f)
+    const cd *hb = s.ooov + blk * o3v;              // (m, n, i, f)
+    cd pt[PT], ph[PH];
+#define RB_LOAD(n)                                                                          \
+    _Pragma("unroll") for (int u = 0; u < PT; ++u) {                                        \
+        const int x = tid + 256 * u, row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;    \
+        pt[u] = (row < no && e < nv && f < nv) ? t2[tb + (((int64_t)row * no + (n)) * nv + e) * nv + f] \
+                                               : make_double2(0.0, 0.0);                    \
+    }                                                                                       \
+    _Pragma("unroll") for (int u = 0; u < PH; ++u) {                                        \
+        const int x = tid + 256 * u, m = x / (OM * VM), i = (x / VM) % OM, f = x % VM;      \
+        ph[u] = (m < no && i < no && f < nv) ? hb[(((int64_t)m * no + (n)) * no + i) * nv + f] \
+                                             : make_double2(0.0, 0.0);                      \
+    }
+#define RB_STORE()                                                                          \
+    _Pragma("unroll") for (int u = 0; u < PT; ++u) {                                        \
+        const int x = tid + 256 * u, row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;    \
+        TS[(row * VM + e) * VP + f] = pt[u];                                                \
+    }                                                                                       \
+    _Pragma("unroll") for (int u = 0; u < PH; ++u) {                                        \
+        const int x = tid + 256 * u, m = x / (OM * VM), i = (x / VM) % OM, f = x % VM;      \
+        HS[(m * OM + i) * VP + f] = ph[u];                                                  \
+    }
+    // P1a roles
+    const int aa = tid / 16, ks = tid % 16;
+    // P1b roles
+    const int bi = (tid % 128) / VM, ba = tid % VM, bh = tid / 128;
+    cd acc[OM];
+#pragma unroll
+    for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
+    cd accb = make_double2(0.0, 0.0);
+    RB_LOAD(0)
+    RB_STORE()
+    __syncthreads();
+    for (int n = 0; n < no; ++n) {
+        if (n + 1 < no) RB_LOAD(n + 1)
+        // P1a(i, a) += sum_{ef} t2(i,n,e,f) <n a||e f>, this thread's (e, f) = ks + 16 u
+        if (aa < nv) {
+            const cd *g = gb + ((int64_t)n * nv + aa) * nv * nv;
+#pragma unroll 4
+            for (int u = 0; u < VM * VM / 16; ++u) {
+                const int ef = ks + 16 * u, e = ef / VM, f = ef % VM;
+                if (e < nv && f < nv) {
+                    const cd gv = g[e * nv + f];
+#pragma unroll
+                    for (int i = 0; i < OM; ++i) cfma(acc[i], TS[(i * VM + e) * VP + f], gv);
+                }
+            }
+        }
+        // P1b(i, a) += sum_{m in half, f} t2(m,n,a,f) <mn||if>
+#pragma unroll
+        for (int mm = 0; mm < OM / 2; ++mm) {
+            const int m = bh * (OM / 2) + mm;
+#pragma unroll 4
+            for (int f = 0; f < VM; ++f) cfma(accb, TS[(m * VM + ba) * VP + f], HS[(m * OM + bi) * VP + f]);
+        }
+        __syncthreads();
+        if (n + 1 < no) {
+            RB_STORE()
+        }
+        __syncthreads();
+    }
+#undef RB_LOAD
+#undef RB_STORE
+    cd *ra = TS, *rb = HS;  // partial sums (LDS reused)
+#pragma unroll
+    for (int i = 0; i < OM; ++i) ra[(aa * 16 + ks) * OM + i] = acc[i];
+    rb[bh * 128 + (tid % 128)] = accb;
+    __syncthreads();
+    if (tid < 128) {
+        const int i = tid / VM, a = tid % VM;
+        cd sa = make_double2(0.0, 0.0);
+        for (int k = 0; k < 16; ++k) sa = cadd(sa, ra[(a * 16 + k) * OM + i]);
+        const cd sb = cadd(rb[tid], rb[128 + tid]);
+        if (i < no && a < nv) {
+            P1a[blk * no * nv + (int64_t)i * nv + a] = cscale(sa, -0.5);
+            P1b[(((int64_t)r * N + p) * N + q) * no * nv + (int64_t)i * nv + a] = cscale(sb, -0.5);
+        }
     }
 }
 
@@ -391,6 +590,14 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
     }
 }
 
+// Blocked form for n_occ <= OM, n_vir <= VM: one workgroup per (ki, kj, km, m) stages
+// <mn||ie> for all (n, i, e) (ki block) and for all (n, j, e) (kj block), <mn||ij> and
+// both t1 blocks in LDS, so every ooov / oooo element is read once with contiguous loads;
+// a thread owns (n, i) and two j.  LDS rows are padded to n_vir + 1 and ordered so that
+// the lanes of a wave (consecutive n, then i) read distinct banks.
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT);
+
 // ------------------------------------------------------------------ XCD-aware block order
 // Workgroup w runs on XCD w % 8; give each XCD a contiguous range of logical blocks so
 // that neighbouring blocks, which share operand rows, meet in the same L2.  Launch
@@ -404,68 +611,101 @@ __device__ inline int64_t xcd_block(int64_t n) {
 // ------------------------------------------------------------------ T1-dressed <ab||ef>
 // Vt[ka][kb][ke](a,b,e,f) = <ab||ef> - P(ab) sum_m t_{m kb}^{b} <a ka, m kb || e f>
 //   = <ab||ef> + t_m^b <m kb, a ka||ef> - t_m^a <m ka, b kb||ef>
-// One workgroup per (ka, kb, ke, a), XCD-contiguous order.  The <m kb, a ka||ef> rows of
-// its a (o x v^2, reused for every b) and t_{m kb}^b, t_{m ka}^a are staged in LDS, so an
-// element costs one <ab||ef> and o <m ka, b kb||ef> global reads; neighbouring a share the
-// latter block in L2.
+// For fixed (ka, kb, ke, e) this is a rank-o update of the v x v x v slab (a, b, f):
+// one workgroup per (ka, kb, ke, e), XCD-contiguous order.  G1(m,a,f) = <m kb, a ka||e f>
+// (shared by every b) and t_{m ka}^a go through LDS; a thread owns (b, f), keeps
+// <m ka, b kb||e f> and t_{m kb}^b for all m in registers and runs over a.  Every
+// <ab||ef> and <mb||ef> element is read once per use, all reads are runs of v.
 constexpr int DR_G1 = 2048, DR_T1 = 512;
 __host__ __device__ inline bool dress_fits(const Dims &d) {
     return (int64_t)d.no * d.nv * d.nv <= DR_G1 && d.no * d.nv <= DR_T1;
 }
+// register arrays of OM (>= n_occ) entries; OM = 0 selects the plain global-memory path
+inline int dress_om(const Dims &d) {
+    if (!dress_fits(d)) return 0;
+    return d.no <= 8 ? 8 : d.no <= 16 ? 16 : d.no <= 32 ? 32 : 0;
+}
 
-template <bool SPLIT>
-__device__ inline void dress_body(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs) {
+template <bool SPLIT, int OM>
+__global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd *Vt, uint16_t *Vs) {
     __shared__ cd G1[DR_G1];
-    __shared__ cd TB[DR_T1];
-    __shared__ cd TA[64];
+    __shared__ cd TA[DR_T1];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
     const int64_t nblk = (int64_t)N * N * N * nv;
     const int64_t L = xcd_block(nblk);
     if (L >= nblk) return;
-    const int a = (int)(L % nv);
+    const int e = (int)(L % nv);
     const int64_t blk = L / nv;
     const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
-    const bool lds = dress_fits(s.d);
-    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)a * vv;
-    const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3;
+    // <m kb, a ka || e f> at (m, a, f) and <m ka, b kb || e f> at (m, b, f)
+    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
+    const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
+    const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
+    const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
+    const int64_t ob = blk * v4 + (int64_t)e * nv;
+    constexpr bool lds = OM > 0;
     if (lds) {
-        for (int x = threadIdx.x; x < no * vv; x += blockDim.x) G1[x] = g1b[(int64_t)(x / vv) * v3 + x % vv];
-        for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TB[x] = t1[(int64_t)kb * no * nv + x];
-        for (int x = threadIdx.x; x < no; x += blockDim.x) TA[x] = t1[((int64_t)ka * no + x) * nv + a];
+        for (int x = threadIdx.x; x < no * vv; x += blockDim.x) {
+            const int m = x / vv, af = x % vv;  // (a, f) = (af / nv, af % nv)
+            G1[x] = g1b[(int64_t)m * v3 + (int64_t)(af / nv) * vv + af % nv];
+        }
+        for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TA[x] = ta[x];
         __syncthreads();
     }
-    for (int64_t e = threadIdx.x; e < v3; e += blockDim.x) {
-        const int ef = (int)(e % vv), b = (int)(e / vv);
-        const int64_t idx = blk * v4 + (int64_t)a * v3 + e;
-        cd acc = s.vvvv[idx];
-#pragma unroll 8
-        for (int m = 0; m < no; ++m) {
-            const cd g1 = lds ? G1[m * vv + ef] : g1b[(int64_t)m * v3 + ef];
-            const cd tb = lds ? TB[m * nv + b] : t1[((int64_t)kb * no + m) * nv + b];
-            const cd ta = lds ? TA[m] : t1[((int64_t)ka * no + m) * nv + a];
-            cfma(acc, tb, g1);
-            acc = csub(acc, cmul(ta, g2b[(int64_t)m * v3 + (int64_t)b * vv + ef]));
-        }
-        if (SPLIT) {
-            uint16_t p0, p1, p2, p3;
-            split_rne2(acc.x, p0, p1);
-            split_rne2(acc.y, p2, p3);
-            Vs[split_index(idx, 0)] = p0;
-            Vs[split_index(idx, 1)] = p1;
-            Vs[split_index(idx, 2)] = p2;
-            Vs[split_index(idx, 3)] = p3;
+    for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
+        const int b = bf / nv, f = bf % nv;
+        if constexpr (lds) {
+            cd g2[OM > 0 ? OM : 1], t1b[OM > 0 ? OM : 1];
+#pragma unroll
+            for (int m = 0; m < OM; ++m) {
+                g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
+                t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
+            }
+            for (int a = 0; a < nv; ++a) {
+                const int64_t idx = ob + (int64_t)a * v3 + (int64_t)b * vv + f;
+                cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+#pragma unroll
+                for (int m = 0; m < OM; ++m) {
+                    if (m < no) {
+                        cfma(acc, t1b[m], G1[(m * nv + a) * nv + f]);
+                        acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
+                    }
+                }
+                if (SPLIT) {
+                    uint16_t p0, p1, p2, p3;
+                    split2(acc.x, p0, p1);
+                    split2(acc.y, p2, p3);
+                    Vs[split_index(idx, 0)] = p0;
+                    Vs[split_index(idx, 1)] = p1;
+                    Vs[split_index(idx, 2)] = p2;
+                    Vs[split_index(idx, 3)] = p3;
+                } else {
+                    Vt[idx] = acc;
+                }
+            }
         } else {
-            Vt[idx] = acc;
+            for (int a = 0; a < nv; ++a) {
+                const int64_t idx = ob + (int64_t)a * v3 + (int64_t)b * vv + f;
+                cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+                for (int m = 0; m < no; ++m) {
+                    cfma(acc, tb[m * nv + b], g1b[(int64_t)m * v3 + (int64_t)a * vv + f]);
+                    acc = csub(acc, cmul(ta[m * nv + a], g2b[(int64_t)m * v3 + (int64_t)b * vv + f]));
+                }
+                if (SPLIT) {
+                    uint16_t p0, p1, p2, p3;
+                    split2(acc.x, p0, p1);
+                    split2(acc.y, p2, p3);
+                    Vs[split_index(idx, 0)] = p0;
+                    Vs[split_index(idx, 1)] = p1;
+                    Vs[split_index(idx, 2)] = p2;
+                    Vs[split_index(idx, 3)] = p3;
+                } else {
+                    Vt[idx] = acc;
+                }
+            }
         }
     }
-}
-
-__global__ __launch_bounds__(256) void k_vvvv_dress(SysDev s, const cd *t1, cd *Vt) {
-    dress_body<false>(s, t1, Vt, nullptr);
-}
-__global__ __launch_bounds__(256) void k_vvvv_dress_split(SysDev s, const cd *t1, uint16_t *Vt) {
-    dress_body<true>(s, t1, nullptr, Vt);
 }
 
 // ------------------------------------------------------------------ ring intermediate seed
@@ -558,6 +798,123 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
     }
 }
 
+// Blocked forms of the three seeds above for n_occ <= OM, n_vir <= VM: one workgroup per
+// (momentum block, m), XCD-contiguous order.  Each thread keeps the integral row it
+// contracts (over f or e) in registers and produces the outputs of every j (or i), so
+// every <oo||vv>, <ov||vv> and <ov||vo> element is read once instead of n_occ times.
+template <int OM, int VM>
+__global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd *Z) {
+    __shared__ cd T1J[OM * VM];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o3v = (int64_t)no * no * no * nv;
+    const int64_t nblk = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int m = (int)(L % no);
+    const int64_t blk = L / no;
+    const int ke = (int)(blk % N), kb = (int)((blk / N) % N), km = (int)(blk / ((int64_t)N * N));
+    const int kj = kcv(s.kc, N, km, kb, ke);
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1J[x] = t1[(int64_t)kj * no * nv + x];
+    __syncthreads();
+    const int ne = threadIdx.x;
+    if (ne >= no * nv) return;
+    const int nn = ne / nv, e = ne % nv;
+    const cd *g = s.oovvT + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
+    cd gr[VM];
+#pragma unroll
+    for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
+    const cd *h = s.ooov + blk3(N, km, kb, kj) * o3v + ((int64_t)m * no + nn) * no * nv + e;
+    cd *z = Z + blk * o3v + ((int64_t)m * no + nn) * no * nv + e;
+    for (int j = 0; j < no; ++j) {
+        // <mn||ej> = -<mn||je>
+        const cd x = h[(int64_t)j * nv];
+        cd acc = make_double2(-x.x, -x.y);
+#pragma unroll
+        for (int f = 0; f < VM; ++f)
+            if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
+        z[(int64_t)j * nv] = acc;
+    }
+}
+
+template <int OM, int VM>
+__global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, const cd *Z, cd *WR) {
+    __shared__ cd ZS[OM * OM * VM];  // Z(m, n, j, e) of this m at (n * no + j) * nv + e
+    __shared__ cd T1J[OM * VM];      // t1[kj](j, f)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t ov = (int64_t)no * nv, blkq = ov * ov;
+    const int64_t o3v = (int64_t)no * no * no * nv, ov3 = (int64_t)no * nv * nv * nv;
+    const int64_t nblk = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int m = (int)(L % no);
+    const int64_t blk = L / no;  // (q, kj, km)
+    const int km = (int)(blk % N), kj = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
+    const int kb = kcv(s.kc, N, kj, 0, q), ke = kcv(s.kc, N, km, 0, q);
+    const int64_t bb = blk3(N, km, kb, ke);
+    const cd *zb = Z + bb * o3v + (int64_t)m * no * no * nv;
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) ZS[x] = zb[x];
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1J[x] = t1[(int64_t)kj * no * nv + x];
+    __syncthreads();
+    const int be = threadIdx.x;
+    if (be >= nv * nv) return;
+    const int b = be / nv, e = be % nv;
+    const cd *g = s.ovvvT + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
+    cd gr[VM], tb[OM];
+#pragma unroll
+    for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int n = 0; n < OM; ++n) tb[n] = n < no ? t1[((int64_t)kb * no + n) * nv + b] : make_double2(0.0, 0.0);
+    const cd *w0 = s.ovvoT + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
+    cd *wr = WR + blk * blkq + (int64_t)b * ov + (int64_t)m * nv + e;
+    for (int j = 0; j < no; ++j) {
+        cd acc = w0[(int64_t)j * nv];
+#pragma unroll
+        for (int f = 0; f < VM; ++f)
+            if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
+#pragma unroll
+        for (int n = 0; n < OM; ++n)
+            if (n < no) acc = csub(acc, cmul(tb[n], ZS[(n * no + j) * nv + e]));
+        wr[(int64_t)j * nv * ov] = acc;
+    }
+}
+
+template <int OM, int VM>
+__global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd *Q) {
+    __shared__ cd GS[VM * OM * (VM + 1)];  // <m b||e j> of this m at (b * no + j) * (nv + 1) + e
+    __shared__ cd T1I[OM * VM];            // t1[ki](i, e)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vp = nv + 1;
+    const int64_t o3v = (int64_t)no * no * no * nv;
+    const int64_t nblk = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int m = (int)(L % no);
+    const int64_t blk = L / no;
+    const int ki = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
+    const int kj = kcv(s.kc, N, ka, kb, ki);
+    const cd *gb = s.ovvoT + blk * s.d.t2blk() + (int64_t)m * nv * no * nv;
+    for (int x = threadIdx.x; x < nv * no * nv; x += blockDim.x) GS[(x / nv) * vp + x % nv] = gb[x];
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
+    __syncthreads();
+    const int jb = threadIdx.x;
+    if (jb >= no * nv) return;
+    const int j = jb / nv, b = jb % nv;
+    cd gr[VM];
+#pragma unroll
+    for (int e = 0; e < VM; ++e) gr[e] = e < nv ? GS[(b * no + j) * vp + e] : make_double2(0.0, 0.0);
+    const cd *h = s.ooov + blk3(N, ki, kj, ka) * o3v + ((int64_t)j * no + m) * nv + b;
+    cd *qo = Q + blk * o3v + (int64_t)m * no * no * nv + jb;
+    for (int i = 0; i < no; ++i) {
+        cd acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < VM; ++e)
+            if (e < nv) cfma(acc, T1I[i * nv + e], gr[e]);
+        const cd x = h[(int64_t)i * no * no * nv];
+        acc.x += 0.5 * x.x;
+        acc.y -= 0.5 * x.y;
+        qo[(int64_t)i * no * nv] = acc;
+    }
+}
+
 // X[q][ki][kj](i,a,j,b), k_a = k_i + q, k_b = k_j - q: everything of the T2 equation that is
 // neither the driver nor a ladder, arranged so that one P(ij)P(ab) produces it:
 //   - t_i^e t_m^a <mb||ej>                       (ring, the t2 W_mbej part is added by GEMM)
@@ -600,6 +957,102 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
         acc.x += 0.5 * (w.x - y.x);
         acc.y += 0.5 * (w.y - y.y);
         X[idx] = acc;
+    }
+}
+
+// The same X seed in two blocked passes for n_occ <= OM, n_vir <= VM (XCD-contiguous
+// workgroup order).  The <ov||vv> term wants every integral element read once (a thread
+// per (j, b) keeps <j c||a b> over c in registers and runs over i); the Q, Fvt and Fot
+// terms want the Q and t2 slabs of one i staged once.
+//   pass 1, a workgroup per (q, ki, kj, a):  X = -1/2 sum_c t_i^c conj(<j kj, c ki||a ka, b kb>)
+//   pass 2, a workgroup per (q, ki, kj, i):  X += -sum_m t_m^a Q(m,i,j,b)
+//                                              + 1/2 sum_f t_ij^af Fvt(b,f) - 1/2 sum_n t_in^ab Fot(n,j)
+template <int OM, int VM>
+__global__ __launch_bounds__(OM * VM) void k_xinit_ovvv_t(SysDev s, const cd *t1, cd *X) {
+    __shared__ cd T1I[OM * VM];  // t1[ki](i, c)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t ov = (int64_t)no * nv, ov3 = ov * nv * nv;
+    const int64_t nblk = (int64_t)N * N * N * nv;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int a = (int)(L % nv);
+    const int64_t blk = L / nv;  // (q, ki, kj)
+    const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
+    const int ka = kcv(s.kc, N, ki, q, 0);
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
+    __syncthreads();
+    const int jb = threadIdx.x;
+    if (jb >= no * nv) return;
+    const int j = jb / nv, b = jb % nv;
+    const cd *gb = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
+    cd g[VM];
+#pragma unroll
+    for (int c = 0; c < VM; ++c) g[c] = c < nv ? cconj(gb[(int64_t)c * nv * nv]) : make_double2(0.0, 0.0);
+    cd *xb = X + blk * ov * ov + (int64_t)a * ov + jb;
+    for (int i = 0; i < no; ++i) {
+        cd y = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < VM; ++c)
+            if (c < nv) cfma(y, T1I[i * nv + c], g[c]);
+        xb[(int64_t)i * nv * ov] = make_double2(-0.5 * y.x, -0.5 * y.y);
+    }
+}
+
+template <int OM, int VM>
+__global__ __launch_bounds__(2 * OM * VM) void k_xinit_rest_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
+                                                             const cd *Fot, const cd *Fvt, cd *X) {
+    // rows padded to nv + 1 so that lanes differing in (j, b) or a hit distinct banks
+    __shared__ cd T2S[OM * VM * (VM + 1)];  // t2(i, n, a, b) of this i at (n * nv + a) * (nv + 1) + b
+    __shared__ cd QS[OM * OM * VM];         // Q(m, i, j, b) of this i at (m * no + j) * nv + b
+    __shared__ cd T1A[OM * VM];             // t1[ka](m, a)
+    __shared__ cd FV[VM * VM];              // Fvt[kb](b, f) at f * nv + b
+    __shared__ cd FO[OM * OM];              // Fot[kj](n, j)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vp = nv + 1;
+    const int64_t ov = (int64_t)no * nv, o3v = ov * no * no;
+    const int64_t nblk = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int i = (int)(L % no);
+    const int64_t blk = L / no;  // (q, ki, kj)
+    const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
+    const int ka = kcv(s.kc, N, ki, q, 0), kb = kcv(s.kc, N, kj, 0, q);
+    const cd *tb = t2 + blk3(N, ki, kj, ka) * s.d.t2blk() + (int64_t)i * no * nv * nv;
+    for (int x = threadIdx.x; x < no * nv * nv; x += blockDim.x) T2S[(x / nv) * vp + x % nv] = tb[x];
+    const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + (int64_t)i * no * nv;
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {
+        const int m = x / (no * nv), jb = x % (no * nv);
+        QS[x] = qb[(int64_t)m * no * no * nv + jb];
+    }
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1A[x] = t1[(int64_t)ka * no * nv + x];
+    for (int x = threadIdx.x; x < nv * nv; x += blockDim.x) FV[(x % nv) * nv + x / nv] = Fvt[(int64_t)kb * nv * nv + x];
+    for (int x = threadIdx.x; x < no * no; x += blockDim.x) FO[x] = Fot[(int64_t)kj * no * no + x];
+    __syncthreads();
+    const int jb = threadIdx.x % (OM * VM), half = threadIdx.x / (OM * VM);
+    if (jb >= no * nv) return;
+    const int j = jb / nv, b = jb % nv;
+    cd qr[OM], fo[OM];
+#pragma unroll
+    for (int m = 0; m < OM; ++m) {
+        qr[m] = m < no ? QS[(m * no + j) * nv + b] : make_double2(0.0, 0.0);
+        fo[m] = m < no ? FO[m * no + j] : make_double2(0.0, 0.0);
+    }
+    cd *xb = X + blk * ov * ov + (int64_t)i * nv * ov + jb;
+    const int a0 = half * ((nv + 1) / 2), a1 = half ? nv : (nv + 1) / 2;
+    for (int a = a0; a < a1; ++a) {
+        cd acc = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < OM; ++m)
+            if (m < no) {
+                cfma(acc, T1A[m * nv + a], qr[m]);
+                cfma(y, T2S[(m * nv + a) * vp + b], fo[m]);
+            }
+#pragma unroll
+        for (int f = 0; f < VM; ++f)
+            if (f < nv) cfma(w, T2S[(j * nv + a) * vp + f], FV[f * nv + b]);
+        cd x = xb[(int64_t)a * ov];
+        x.x += -acc.x + 0.5 * (w.x - y.x);
+        x.y += -acc.y + 0.5 * (w.y - y.y);
+        xb[(int64_t)a * ov] = x;
     }
 }
 
@@ -684,32 +1137,52 @@ __global__ void k_r1_partial(SysDev s, const cd *t2, cd *P1) {
 
 // r1 = conj(f_ia) + t_i^c Fvv(a,c) - t_r^a Foo(r,i) + sum_kn t2[k,kn,k](i,n,a,f) Fov[kn](n,f)
 //      + sum_kn t_r^c <a k, r kn||i k, c kn> + sum_kx P1
-__global__ void k_r1(SysDev s, const cd *t1, const cd *t2, const cd *Foo, const cd *Fvv, const cd *Fov,
-                     const cd *P1, int nparts, cd *r1) {
+// One 64-lane wave per output (k, i, a): the N_k-long sums over kn and
+// the N_k^2 partial sums are spread over the lanes (consecutive lanes read consecutive
+// elements) and combined by a wave reduction, so the kernel is not limited by a few
+// hundred threads each running the whole sum.
+__device__ inline cd wave_sum(cd v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_r1_wave(SysDev s, const cd *t1, const cd *t2, const cd *Foo, const cd *Fvv,
+                                                const cd *Fov, const cd *P1, int nparts, cd *r1) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
-    GRID_STRIDE(idx, (int64_t)N * no * nv) {
-        int a = (int)(idx % nv), i = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
-        cd acc = cconj(s.fock[((int64_t)k * n + i) * n + no + a]);
-        for (int c = 0; c < nv; ++c)
-            cfma(acc, t1[((int64_t)k * no + i) * nv + c], Fvv[((int64_t)k * nv + a) * nv + c]);
+    const int64_t idx = blockIdx.x;
+    const int a = (int)(idx % nv), i = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
+    const int lane = threadIdx.x;
+    const int ov = no * nv;
+    cd acc = make_double2(0.0, 0.0);
+    // sum_{kn, n, f} t_{i k, n kn}^{a k, f kn} F(n kn, f kn)
+    for (int u = lane; u < N * ov; u += 64) {
+        const int kn = u / ov, nn = (u / nv) % no, f = u % nv;
+        const cd *t = t2 + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)i * no * nv * nv + (int64_t)a * nv;
+        cfma(acc, t[(int64_t)nn * nv * nv + f], Fov[((int64_t)kn * no + nn) * nv + f]);
+    }
+    // sum_{kn, r, c} t_{r kn}^{c kn} <r kn, a k || c kn, i k>   (ovvo block [kn,k,kn])
+    for (int u = lane; u < N * ov; u += 64) {
+        const int kn = u / ov, r = (u / nv) % no, c = u % nv;
+        const cd *g = s.ovvo + blk3(N, kn, k, kn) * s.d.t2blk() + (int64_t)a * nv * no + i;
+        cfma(acc, t1[((int64_t)kn * no + r) * nv + c], g[(int64_t)r * nv * nv * no + (int64_t)c * no]);
+    }
+    // the per-block partial sums
+    const int64_t np = (int64_t)N * N * N * no * nv;
+    for (int u = lane; u < nparts * N * N; u += 64) {
+        const int pp = u / (N * N), kk = u % (N * N);
+        acc = cadd(acc, P1[pp * np + (((int64_t)k * N * N + kk) * no + i) * nv + a]);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        cd v = cconj(s.fock[((int64_t)k * n + i) * n + no + a]);
+        for (int c = 0; c < nv; ++c) cfma(v, t1[((int64_t)k * no + i) * nv + c], Fvv[((int64_t)k * nv + a) * nv + c]);
         for (int r = 0; r < no; ++r)
-            acc = csub(acc, cmul(t1[((int64_t)k * no + r) * nv + a], Foo[((int64_t)k * no + r) * no + i]));
-        for (int kn = 0; kn < N; ++kn) {
-            const cd *t = t2 + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)i * no * nv * nv + (int64_t)a * nv;
-            for (int nn = 0; nn < no; ++nn)
-                for (int f = 0; f < nv; ++f)
-                    cfma(acc, t[(int64_t)nn * nv * nv + f], Fov[((int64_t)kn * no + nn) * nv + f]);
-            // <a k, r kn || i k, c kn> = <r kn, a k || c kn, i k>  (ovvo block [kn,k,kn])
-            const cd *g = s.ovvo + blk3(N, kn, k, kn) * s.d.t2blk() + (int64_t)a * nv * no + i;
-            for (int r = 0; r < no; ++r)
-                for (int c = 0; c < nv; ++c)
-                    cfma(acc, t1[((int64_t)kn * no + r) * nv + c], g[(int64_t)r * nv * nv * no + (int64_t)c * no]);
-        }
-        const int64_t np = (int64_t)N * N * N * no * nv;
-        for (int pp = 0; pp < nparts; ++pp)
-            for (int kk = 0; kk < N * N; ++kk)
-                acc = cadd(acc, P1[pp * np + (((int64_t)k * N * N + kk) * no + i) * nv + a]);
-        r1[idx] = acc;
+            v = csub(v, cmul(t1[((int64_t)k * no + r) * nv + a], Foo[((int64_t)k * no + r) * no + i]));
+        r1[idx] = cadd(v, acc);
     }
 }
 
@@ -732,7 +1205,11 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     LAUNCH(k_fov, N * no * nv, s, t1, w.Fov);
-    if (f_blocks_fit(s.d)) {
+    if (no <= 8 && nv <= 16) {
+        hipLaunchKernelGGL((k_f_blocks_t<8, 16>), dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t1, t2, w.Poo,
+                           w.Pvv);
+        CK_CHECK(hipGetLastError());
+    } else if (f_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
     } else {
@@ -743,20 +1220,87 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     LAUNCH(k_ftilde, N * no * no + N * nv * nv, s.d, t1, w.Foo, w.Fvv, w.Fov, w.Fot, w.Fvt);
 }
 
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT) {
+    static_assert(OM == 8, "thread roles assume n_occ <= 8");
+    constexpr int VP = VM + 1;
+    __shared__ cd A1[OM * OM * VP];  // <m km, n kn||i ki, e> at (i * OM + n) * VP + e
+    __shared__ cd A2[OM * OM * VP];  // <m km, n kn||j kj, e> at (j * OM + n) * VP + e
+    __shared__ cd T1I[OM * VP], T1J[OM * VP];
+    __shared__ cd O4[OM * OM * OM];  // <m km, n kn||i ki, j kj> at (n * OM + i) * OM + j
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o4 = (int64_t)no * no * no * no, o3v = (int64_t)no * no * no * nv;
+    const int64_t nblk = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int m = (int)(L % no);
+    const int64_t blk = L / no;
+    const int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+    const int kn = kcv(s.kc, N, ki, kj, km);
+    const cd *g1 = s.ooov + blk3(N, km, kn, ki) * o3v + (int64_t)m * no * no * nv;  // (n, i, e)
+    const cd *g2 = s.ooov + blk3(N, km, kn, kj) * o3v + (int64_t)m * no * no * nv;  // (n, j, e)
+    const cd *g0 = s.oooo + blk3(N, km, kn, ki) * o4 + (int64_t)m * no * no * no;    // (n, i, j)
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {
+        const int n = x / (no * nv), i = (x / nv) % no, e = x % nv;
+        A1[(i * OM + n) * VP + e] = g1[x];
+        A2[(i * OM + n) * VP + e] = g2[x];
+    }
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) {
+        T1I[(x / nv) * VP + x % nv] = t1[(int64_t)ki * no * nv + x];
+        T1J[(x / nv) * VP + x % nv] = t1[(int64_t)kj * no * nv + x];
+    }
+    for (int x = threadIdx.x; x < no * no * no; x += blockDim.x) {
+        const int n = x / (no * no), i = (x / no) % no, j = x % no;
+        O4[(n * OM + i) * OM + j] = g0[x];
+    }
+    __syncthreads();
+    const int n = threadIdx.x % OM, i = (threadIdx.x / OM) % OM, j0 = 2 * (threadIdx.x / (OM * OM));
+    if (n >= no || i >= no) return;
+    cd *wt = WT + blk * o4 + (int64_t)m * no + n;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+        const int j = j0 + jj;
+        if (j >= no) continue;
+        cd acc = O4[(n * OM + i) * OM + j];
+#pragma unroll
+        for (int e = 0; e < VM; ++e)
+            if (e < nv) {
+                cfma(acc, T1J[j * VP + e], A1[(i * OM + n) * VP + e]);
+                acc = csub(acc, cmul(T1I[i * VP + e], A2[(j * OM + n) * VP + e]));
+            }
+        wt[((int64_t)i * no + j) * no * no] = acc;
+    }
+}
+
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
-    const int64_t N = s.d.N, no = s.d.no;
-    LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
+    const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
+    if (no <= 8 && nv <= 16) {
+        hipLaunchKernelGGL((k_wmnij_init_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, WT);
+        CK_CHECK(hipGetLastError());
+    } else {
+        LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
+    }
+}
+
+template <bool SPLIT>
+static void dress_launch(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs, hipStream_t st) {
+    const int64_t N = s.d.N, nv = s.d.nv;
+    const dim3 grid = xcd_grid(N * N * N * nv);
+    switch (dress_om(s.d)) {
+    case 8: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 8>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
+    case 16: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 16>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
+    case 32: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 32>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
+    default: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 0>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
+    }
 }
 
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
-    const int64_t N = s.d.N, nv = s.d.nv;
-    hipLaunchKernelGGL(k_vvvv_dress, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt);
+    dress_launch<false>(s, t1, Vt, nullptr, st);
     CK_CHECK(hipGetLastError());
 }
 
 void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st) {
-    const int64_t N = s.d.N, nv = s.d.nv;
-    hipLaunchKernelGGL(k_vvvv_dress_split, xcd_grid(N * N * N * nv), dim3(256), 0, st, s, t1, Vt);
+    dress_launch<true>(s, t1, nullptr, Vt, st);
     CK_CHECK(hipGetLastError());
 }
 
@@ -774,10 +1318,28 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
                       hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n3 = N * N * N;
-    LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
-    LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
-    LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
-    LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
+    if (no <= 8 && nv <= 16) {
+        const dim3 grid = xcd_grid(n3 * no);
+        hipLaunchKernelGGL((k_ring_z_t<8, 16>), grid, dim3(8 * 16), 0, st, s, t1, scratch);
+        CK_CHECK(hipGetLastError());
+        hipLaunchKernelGGL((k_ring_w0_t<8, 16>), grid, dim3(16 * 16), 0, st, s, t1, scratch, WR);
+        CK_CHECK(hipGetLastError());
+        hipLaunchKernelGGL((k_ring_q_t<8, 16>), grid, dim3(8 * 16), 0, st, s, t1, scratch);
+        CK_CHECK(hipGetLastError());
+    } else {
+        LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
+        LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
+    }
+    if (no <= 8 && nv <= 16) {
+        hipLaunchKernelGGL((k_xinit_ovvv_t<8, 16>), xcd_grid(n3 * nv), dim3(8 * 16), 0, st, s, t1, X);
+        CK_CHECK(hipGetLastError());
+        hipLaunchKernelGGL((k_xinit_rest_t<8, 16>), xcd_grid(n3 * no), dim3(2 * 8 * 16), 0, st, s, t1, t2, scratch,
+                           w.Fot, w.Fvt, X);
+        CK_CHECK(hipGetLastError());
+    } else {
+        LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
+    }
 }
 
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st) {
@@ -789,13 +1351,20 @@ void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st) {
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
-    if (r1_blocks_fit(s.d)) {
+    if (no <= 8 && nv <= 16) {
+        hipLaunchKernelGGL((k_r1_blocks_t<8, 16>), dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t2, P1, P1 + np);
+        CK_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
+        CK_CHECK(hipGetLastError());
+    } else if (r1_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(RB_NT), 0, st, s, t2, P1, P1 + np);
         CK_CHECK(hipGetLastError());
-        LAUNCH(k_r1, N * no * nv, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
+        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
+        CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_r1_partial, N * N * N * no * nv, s, t2, P1);
-        LAUNCH(k_r1, N * no * nv, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 1, r1);
+        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 1, r1);
+        CK_CHECK(hipGetLastError());
     }
 }
 
