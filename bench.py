@@ -27,15 +27,30 @@ METRIC = "T2 residual evals/s + TFLOP/s at N_k=27 (split-BF16 vs FP64, |ΔE|≤1
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s, MI355X
 
 
-def measured_traffic(key, source):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel source changed since the counters were taken."""
+# Sources whose text fixes a GEMM kernel's memory traffic: the kernel file and the
+# headers that define its tile order and operand storage.
+KERNEL_SOURCES = {
+    "pp_ladder_fp64": ["paper_1911_00242_amd/csrc/gemm_f64.hip", "paper_1911_00242_amd/csrc/common.h"],
+    "pp_ladder_mixed": ["paper_1911_00242_amd/csrc/gemm_mixed.hip", "paper_1911_00242_amd/csrc/common.h",
+                        "paper_1911_00242_amd/csrc/mixed.h"],
+}
+
+
+def source_hash(key):
     import hashlib
 
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES[key]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed since the counters were taken."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
-        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
-        return rec["hbm_bytes_per_launch"] if sha == rec["source_sha256_16"] else None
+        return rec["hbm_bytes_per_launch"] if source_hash(key) == rec["source_sha256_16"] else None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -154,10 +169,10 @@ def main():
     pp_cmacs = N4 * a.no ** 2 * a.nv ** 4
     if head == 0:
         pp_flops, peak, dtype = 8.0 * pp_cmacs, PEAK["fp64"], "f64"
-        traffic = measured_traffic("pp_ladder_fp64", "paper_1911_00242_amd/csrc/gemm_f64.hip")
+        traffic = measured_traffic("pp_ladder_fp64")
     else:
         pp_flops, peak, dtype = 24.0 * pp_cmacs, PEAK["bf16"], "bf16x3/f32acc+f64"
-        traffic = measured_traffic("pp_ladder_mixed", "paper_1911_00242_amd/csrc/gemm_mixed.hip")
+        traffic = measured_traffic("pp_ladder_mixed")
     if (grid, a.no, a.nv) != ((3, 3, 3), 8, 16):
         traffic = None
     pp_avg = pp_ms / max(pp_n, 1)
