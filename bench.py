@@ -114,15 +114,16 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
 
 
 def cpu_baseline(no, nv, N_target):
-    """The FP64 oracle on a bounded sample: one residual on a 3x1x1 mesh with the same
-    per-k block shapes, scaled to the target mesh by the N_k^4 algorithmic flop ratio."""
+    """The FP64 oracle on a bounded sample (about 10-20 s of CPU work): one residual on a
+    2x2x2 mesh with the same per-k block shapes, scaled to the target mesh by the N_k^4
+    algorithmic flop ratio."""
     import numpy as np
 
     import synth
     from oracle import ccsd_k as O
 
-    grid = (3, 1, 1)
-    f, eris = synth.system(303, grid, no, nv, scale=0.05 / 3)
+    grid = (2, 2, 2)
+    f, eris = synth.system(303, grid, no, nv, scale=0.05 / 8)
     t1, t2 = synth.test_amplitudes(1, grid, no, nv, scale=0.01)
     kc = O.kconserv(grid)
     t0 = time.perf_counter()
@@ -135,9 +136,9 @@ def cpu_baseline(no, nv, N_target):
         threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
     except Exception:
         pass
-    ratio = (N_target / 3.0) ** 4
+    ratio = (N_target / 8.0) ** 4
     return {"value": 1.0 / (dt * ratio), "unit": "evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one oracle residual on a 3x1x1 mesh with n_occ={no}, n_vir={nv} per k "
+            "sample": f"one oracle residual on a 2x2x2 mesh with n_occ={no}, n_vir={nv} per k "
                       f"({dt:.2f} s), scaled by the N_k^4 flop ratio {ratio:.0f} to N_k={N_target}",
             "sample_seconds": dt}
 
