@@ -119,6 +119,16 @@ int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const 
  * grouped products (8 per complex multiply-add) and of all other terms. */
 int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops);
 
+/* Shape of one grouped complex product as executed for system sys: G groups of an
+ * M x N x K product each (complex elements).  product: 0 particle-particle ladder,
+ * 1 hole-hole ladder, 2 W_mnij build, 3 W_mbej build, 4 ring product (the numbering of
+ * ccsd_k_timing_get).  In the mixed path the three ladder-family products run on
+ * canonical antisymmetric pairs (N and K, or N, of the full form roughly halved), so the
+ * executed shape is smaller than the algorithmic one counted by ccsd_k_flops.  Any output
+ * pointer may be NULL. */
+int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
+                         int64_t *K);
+
 /* Per-stage device timing with HIP events on the context's stream (0 = off).  Stages:
  * 0 particle-particle ladder, 1 hole-hole ladder, 2 W_mnij build, 3 ring W build,
  * 4 ring product, 5 the whole residual evaluation (all of the above and every other term). */

@@ -64,6 +64,7 @@ _lib_energy = _sig("ccsd_k_energy", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_get_amp = _sig("ccsd_k_get_amplitudes", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_set_amp = _sig("ccsd_k_set_amplitudes", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_flops = _sig("ccsd_k_flops", ctypes.c_int, [_p, _i32, _dp, _dp])
+_lib_shape = _sig("ccsd_k_product_shape", ctypes.c_int, [_p, _i32, _i32] + [ctypes.POINTER(_i64)] * 4)
 _lib_timing = _sig("ccsd_k_timing", ctypes.c_int, [_p, _i32])
 _lib_timing_get = _sig("ccsd_k_timing_get", ctypes.c_int, [_p, _i32, _dp, ctypes.POINTER(_i64)])
 _lib_free = _sig("ccsd_k_free", None, [_p])
@@ -72,7 +73,8 @@ _lib_err = _sig("ccsd_k_last_error", ctypes.c_char_p, [_p])
 
 SYMBOLS = ("ccsd_k_init", "ccsd_k_workspace_bytes", "ccsd_k_bind_workspace", "ccsd_k_set_inputs",
            "ccsd_k_residual", "ccsd_k_iterate", "ccsd_k_residual_norm", "ccsd_k_energy",
-           "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_timing",
+           "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_product_shape",
+           "ccsd_k_timing",
            "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_free", "ccsd_k_last_error")
 
 
@@ -171,6 +173,12 @@ def ccsd_k_flops(ctx, sys):
     return float(g.value), float(o.value)
 
 
+def ccsd_k_product_shape(ctx, sys, product):
+    out = [_i64() for _ in range(4)]
+    _check(_lib_shape(ctx, sys, product, *[ctypes.byref(x) for x in out]), ctx)
+    return tuple(int(x.value) for x in out)
+
+
 def ccsd_k_timing(ctx, enable: bool):
     return _check(_lib_timing(ctx, 1 if enable else 0), ctx)
 
@@ -259,6 +267,10 @@ class Context:
 
     def flops(self, sys=0):
         return ccsd_k_flops(self.ctx, sys)
+
+    def product_shape(self, product, sys=0):
+        """(G, M, N, K) of a grouped product as executed; product is a stage name or number."""
+        return ccsd_k_product_shape(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product)
 
     def timing(self, enable=True):
         ccsd_k_timing(self.ctx, enable)

@@ -31,6 +31,8 @@ struct Gemm {
     ck::GemmOps<cd> op;
     int stage;
     size_t tab[6];  // offsets (in int64 units) of a_row, a_k, b_col, b_k, c_row, c_col in the table blob
+    // packed products only: partner column, split-output row and column offsets (SIZE_MAX: none)
+    size_t c_col2 = SIZE_MAX, cs_row = SIZE_MAX, cs_col = SIZE_MAX;
 };
 
 struct System {
@@ -55,9 +57,15 @@ struct System {
     std::vector<cd *> dvec, derr;
     // mixed precision: split-BF16 operands (four bf16 per element) of the five products
     bool mixed = false;
-    uint16_t *sp_tau = nullptr, *sp_tauT = nullptr, *sp_t2 = nullptr, *sp_WT = nullptr, *sp_WR = nullptr,
-             *sp_Vt = nullptr, *sp_oovv = nullptr;
-    int64_t pl_t2 = 0, pl_o4 = 0, pl_v4 = 0;  // element counts of the split operands, padded
+    uint16_t *sp_t2 = nullptr, *sp_WR = nullptr, *sp_oovv = nullptr;
+    int64_t pl_t2 = 0;  // element count of the T2-shaped split operands, padded
+    // the ladder products run on antisymmetric pairs (pack.hip): canonical pair lists per
+    // group (host and device, int32), the packed products and their split operands
+    std::vector<int32_t> ptab;  // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v]
+    int PV = 0, PO = 0;
+    int32_t *dptab = nullptr;
+    Gemm gp[3];  // packed W_mnij, particle-particle and hole-hole products
+    uint16_t *pk_tau = nullptr, *pk_tauT = nullptr, *pk_Vt = nullptr, *pk_WT = nullptr, *pk_oovv = nullptr;
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -88,6 +96,10 @@ struct System {
         s.ovvvT = ovvvT;
         s.oovvT = oovvT;
         return s;
+    }
+    ck::PairTabs pairs() const {
+        const int64_t N = d.N;
+        return ck::PairTabs{dptab, dptab + N * PV, dptab + N * (PV + PO), PV, PO};
     }
 };
 
@@ -134,6 +146,119 @@ int kcons(const ck::Mesh &m, int kp, int kq, int kr) {
 }
 
 // ---------------------------------------------------------------- contraction tables
+// Canonical pairs of a group of total pair momentum K: (kx, x; ky, y), ky = K - kx, with
+// (kx, x) < (ky, y), listed by kx, x, y; every group padded to the same length (a multiple
+// of 16) so that the grouped products have one k extent.  Packed ladder products (mixed
+// path), each a quarter of its full form (antisymmetry, pack.hip):
+//   G1p: W_mnij += tau . <mn||ef>^T   rows (ki,i,j), cols canonical (km,m,n), k canonical (ke,e,f)
+//        (alpha 1 = 1/2 x 2 for the canonical k pairs); written split to pk_WT [K][row][PO]
+//   G2p: r2 += tau . Vt^T             rows (ki,i,j), cols canonical (ka,a,b), k canonical (ke,e,f)
+//   G3p: r2 += W_mnij . tauT          rows (ki,i,j), cols canonical (ka,a,b), k canonical (km,m,n)
+// G2p and G3p write the (a,b) column and its partner (b,a) with the opposite sign.
+void build_tables(System &S);
+void build_pair_tables(System &S) {
+    const int64_t N = S.d.N, o = S.d.no, v = S.d.nv;
+    const int64_t oo = o * o, vv = v * v, t2b = oo * vv, o4 = oo * oo, M = N * oo;
+    auto kc = [&](int64_t a, int64_t b, int64_t c) { return (int64_t)S.kc[(a * N + b) * N + c]; };
+    auto list = [&](int64_t K, int64_t w, std::vector<int32_t> &out) {
+        out.clear();
+        for (int64_t kx = 0; kx < N; ++kx) {
+            const int64_t ky = kc(K, 0, kx);
+            if (kx > ky) continue;
+            for (int64_t x = 0; x < w; ++x)
+                for (int64_t y = (kx == ky ? x + 1 : 0); y < w; ++y) out.push_back((int32_t)((kx * w + x) * w + y));
+        }
+    };
+    std::vector<std::vector<int32_t>> vl(N), ol(N);
+    size_t mv = 0, mo = 0;
+    for (int64_t K = 0; K < N; ++K) {
+        list(K, v, vl[K]);
+        list(K, o, ol[K]);
+        mv = std::max(mv, vl[K].size());
+        mo = std::max(mo, ol[K].size());
+    }
+    S.PV = (int)((mv + 15) / 16 * 16);
+    S.PO = (int)((mo + 15) / 16 * 16);
+    if (S.PV == 0) S.PV = 16;
+    if (S.PO == 0) S.PO = 16;
+    const int64_t PV = S.PV, PO = S.PO;
+    S.ptab.assign(N * PV + N * PO + N * N * vv, -1);
+    int32_t *vlist = S.ptab.data(), *olist = vlist + N * PV, *vpos = olist + N * PO;
+    for (int64_t K = 0; K < N; ++K) {
+        for (size_t p = 0; p < vl[K].size(); ++p) {
+            vlist[K * PV + p] = vl[K][p];
+            const int64_t kx = vl[K][p] / vv, xy = vl[K][p] % vv;
+            vpos[(K * N + kx) * vv + xy] = (int32_t)p;
+        }
+        for (size_t p = 0; p < ol[K].size(); ++p) olist[K * PO + p] = ol[K][p];
+    }
+    std::vector<int64_t> &T = S.tables;
+    auto put = [&](Gemm &g, int which, int64_t len, auto fn) {
+        g.tab[which] = T.size();
+        for (int64_t x = 0; x < len; ++x) T.push_back(fn(x));
+    };
+    Gemm &g1 = S.gp[0], &g2 = S.gp[1], &g3 = S.gp[2];
+    // c_row of W_mnij and r2 for row (ki,i,j) of group K
+    auto row_t2 = [&](int64_t K, int64_t x) {
+        int64_t ki = x / oo, ij = x % oo;
+        return ((ki * N + kc(K, 0, ki)) * N) * t2b + ij * vv;
+    };
+    auto row_wt = [&](int64_t K, int64_t x) {
+        int64_t ki = x / oo, ij = x % oo;
+        return ((ki * N + kc(K, 0, ki)) * N) * o4 + ij * oo;
+    };
+    // G1p
+    put(g1, 0, N * M, [&](int64_t x) { return x * PV; });  // tau_pk rows
+    put(g1, 1, N * PV, [&](int64_t x) { return x % PV; });
+    put(g1, 2, N * PO, [&](int64_t x) { return x * PV; });  // oovv_pk rows
+    g1.tab[3] = g1.tab[1];
+    put(g1, 4, N * M, [&](int64_t x) { return row_wt(x / M, x % M); });
+    put(g1, 5, N * PO, [&](int64_t x) {  // W_mnij column of canonical (km,m,n), -1 in the padding
+        const int32_t pr = olist[x];
+        if (pr < 0) return (int64_t)-1;
+        return (int64_t)(pr / oo) * o4 + pr % oo;
+    });
+    g1.cs_row = T.size();
+    for (int64_t x = 0; x < N * M; ++x) T.push_back(x * PO);
+    g1.cs_col = T.size();
+    for (int64_t x = 0; x < N * PO; ++x) T.push_back(x % PO);
+    g1.op.G = (int)N; g1.op.M = (int)M; g1.op.N = (int)PO; g1.op.K = (int)PV;
+    g1.op.alpha = 1.0; g1.op.beta = 1.0; g1.stage = ST_WMN;
+    // G2p
+    g2.tab[0] = g1.tab[0];
+    g2.tab[1] = g1.tab[1];
+    put(g2, 2, N * PV, [&](int64_t x) { return x * PV; });  // Vt_pk rows
+    g2.tab[3] = g1.tab[1];
+    put(g2, 4, N * M, [&](int64_t x) { return row_t2(x / M, x % M); });
+    put(g2, 5, N * PV, [&](int64_t x) {  // r2 column (ka,a,b)
+        const int32_t pr = vlist[x];
+        if (pr < 0) return (int64_t)-1;
+        return (int64_t)(pr / vv) * t2b + pr % vv;
+    });
+    g2.c_col2 = T.size();
+    for (int64_t x = 0; x < N * PV; ++x) {  // its partner (kb,b,a)
+        const int32_t pr = vlist[x];
+        if (pr < 0) {
+            T.push_back(-1);
+            continue;
+        }
+        const int64_t K = x / PV, ka = pr / vv, a = (pr / v) % v, b = pr % v;
+        T.push_back(kc(K, 0, ka) * t2b + b * v + a);
+    }
+    g2.op.G = (int)N; g2.op.M = (int)M; g2.op.N = (int)PV; g2.op.K = (int)PV;
+    g2.op.alpha = 1.0; g2.op.beta = 1.0; g2.stage = ST_PP;
+    // G3p
+    put(g3, 0, N * M, [&](int64_t x) { return x * PO; });  // pk_WT rows
+    put(g3, 1, N * PO, [&](int64_t x) { return x % PO; });
+    put(g3, 2, N * PV, [&](int64_t x) { return x * PO; });  // tauT_pk rows
+    g3.tab[3] = g3.tab[1];
+    g3.tab[4] = g2.tab[4];
+    g3.tab[5] = g2.tab[5];
+    g3.c_col2 = g2.c_col2;
+    g3.op.G = (int)N; g3.op.M = (int)M; g3.op.N = (int)PV; g3.op.K = (int)PO;
+    g3.op.alpha = 1.0; g3.op.beta = 1.0; g3.stage = ST_HH;
+}
+
 // Offsets in complex elements.  Group label: total pair momentum K for the ladder
 // family, momentum transfer q for the ring family.
 void build_tables(System &S) {
@@ -236,6 +361,7 @@ void build_tables(System &S) {
     put(g5, 5, N * Mph, [&](int64_t x) { int64_t y = x % Mph; return (y / ov) * ov * ov + y % ov; });
     g5.op.G = (int)N; g5.op.M = (int)Mph; g5.op.N = (int)Mph; g5.op.K = (int)Mph;
     g5.op.alpha = 1.0; g5.op.beta = 1.0; g5.stage = ST_RING;
+    if (S.mixed) build_pair_tables(S);
 }
 
 // ---------------------------------------------------------------- workspace plan
@@ -257,22 +383,23 @@ void carve(System &S, Carver &c) {
     for (int i = 0; i < 6; ++i) c.take(S.eri[i], N3 * cls[i]);
     c.take(S.amp, S.n1() + S.n2());
     c.take(S.res, S.n1() + S.n2());
-    c.take(S.tau, S.n2());
     if (!S.mixed) {
+        c.take(S.tau, S.n2());
         c.take(S.tauT, S.n2());
         c.take(S.Vt, N3 * cls[5]);
     } else {
-        auto padded = [](int64_t n) { return (n + 63) / 64 * 64; };
-        S.pl_t2 = padded(S.n2());
-        S.pl_o4 = padded(N3 * cls[0]);
-        S.pl_v4 = padded(N3 * cls[5]);
-        c.take(S.sp_tau, 4 * S.pl_t2);
-        c.take(S.sp_tauT, 4 * S.pl_t2);
+        // split storage: 4 bf16 per element
+        S.pl_t2 = (S.n2() + 63) / 64 * 64;
+        const int64_t M = N * o * o, PV = S.PV, PO = S.PO;
         c.take(S.sp_t2, 4 * S.pl_t2);
         c.take(S.sp_WR, 4 * S.pl_t2);
         c.take(S.sp_oovv, 4 * S.pl_t2);
-        c.take(S.sp_WT, 4 * S.pl_o4);
-        c.take(S.sp_Vt, 4 * S.pl_v4);
+        c.take(S.pk_tau, 4 * N * M * PV);
+        c.take(S.pk_tauT, 4 * N * PV * PO);
+        c.take(S.pk_Vt, 4 * N * PV * PV);
+        c.take(S.pk_WT, 4 * N * M * PO);
+        c.take(S.pk_oovv, 4 * N * PO * PV);
+        c.take(S.dptab, (int64_t)S.ptab.size());
     }
     c.take(S.WT, N3 * cls[0]);
     c.take(S.WR, N3 * o * v * o * v);
@@ -307,8 +434,7 @@ void carve(System &S, Carver &c) {
 
 // True when every aligned group of 8 k indices of both operands is a contiguous,
 // 16-byte aligned run in every group, and all row/column bases are 8-aligned.
-bool fast_ok(const System &S, int i) {
-    const Gemm &g = S.g[i];
+bool fast_ok(const System &S, const Gemm &g) {
     const int64_t G = g.op.G, M = g.op.M, N = g.op.N, K = g.op.K;
     if (K % 8) return false;
     const int64_t *T = S.tables.data();
@@ -346,20 +472,27 @@ void bind_ops(System &S) {
         g.op.zeros = S.zeros;
     }
     if (!S.mixed) return;
-    const uint16_t *SA[5] = {S.sp_tau, S.sp_tau, S.sp_WT, S.sp_t2, S.sp_t2};
-    const uint16_t *SB[5] = {S.sp_oovv, S.sp_Vt, S.sp_tauT, S.sp_oovv, S.sp_WR};
+    // the ladder family on packed pairs (gp), the ring family in full (g[3], g[4])
+    const Gemm *G[5] = {&S.gp[0], &S.gp[1], &S.gp[2], &S.g[3], &S.g[4]};
+    const uint16_t *SA[5] = {S.pk_tau, S.pk_tau, S.pk_WT, S.sp_t2, S.sp_t2};
+    const uint16_t *SB[5] = {S.pk_oovv, S.pk_Vt, S.pk_tauT, S.sp_oovv, S.sp_WR};
+    // W_mnij and W_mbej are only consumed as split operands: their products write split
+    uint16_t *CS[5] = {S.pk_WT, nullptr, nullptr, S.sp_WR, nullptr};
+    auto tab = [&](size_t off) { return off == SIZE_MAX ? nullptr : T + off; };
     for (int i = 0; i < 5; ++i) {
-        const ck::GemmOps<cd> &o = S.g[i].op;
+        const Gemm &g = *G[i];
         ck::SplitOps &s = S.sg[i];
+        s = ck::SplitOps{};
         s.A = SA[i];
         s.B = SB[i];
         s.zeros = reinterpret_cast<const uint16_t *>(S.zeros);
-        s.C = o.C;
-        // W_mnij and W_mbej are only consumed as split operands: their products write split
-        s.Cs = i == 0 ? S.sp_WT : i == 3 ? S.sp_WR : nullptr;
-        s.a_row = o.a_row; s.a_k = o.a_k; s.b_col = o.b_col; s.b_k = o.b_k; s.c_row = o.c_row; s.c_col = o.c_col;
-        s.G = o.G; s.M = o.M; s.N = o.N; s.K = o.K; s.alpha = o.alpha; s.beta = o.beta;
-        s.fast = fast_ok(S, i) ? 1 : 0;
+        s.C = C[i];  // same FP64 outputs as the full forms
+        s.Cs = CS[i];
+        s.a_row = T + g.tab[0]; s.a_k = T + g.tab[1]; s.b_col = T + g.tab[2]; s.b_k = T + g.tab[3];
+        s.c_row = T + g.tab[4]; s.c_col = T + g.tab[5];
+        s.c_col2 = tab(g.c_col2); s.cs_row = tab(g.cs_row); s.cs_col = tab(g.cs_col);
+        s.G = g.op.G; s.M = g.op.M; s.N = g.op.N; s.K = g.op.K; s.alpha = g.op.alpha; s.beta = g.op.beta;
+        s.fast = fast_ok(S, g) ? 1 : 0;
     }
 }
 
@@ -397,7 +530,7 @@ void collect_timing(ccsd_k_ctx *c) {
 
 void run_gemm(ccsd_k_ctx *c, System &S, int i) {
     EventPair ep{};
-    stage_begin(c, ep, S.g[i].stage);
+    stage_begin(c, ep, (S.mixed && i < 3 ? S.gp[i] : S.g[i]).stage);
     if (S.mixed) ck::gemm_split(S.sg[i], c->stream);
     else ck::gemm_f64(S.g[i].op, c->stream);
     stage_end(c, ep);
@@ -411,19 +544,15 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     stage_begin(c, all, ST_RES);
     if (!S.mixed) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
-    } else if (ck::tau_split_ok(S.d)) {
-        ck::launch_tau_split(S.d, S.dkc, S.t1(), S.t2(), S.sp_tau, S.sp_tauT, S.sp_t2, st);
     } else {
-        ck::launch_tau(s, S.t1(), S.t2(), S.tau, nullptr, st);
-        ck::launch_split(S.n2(), S.tau, S.sp_tau, st);
-        ck::launch_split_transpose(S.d, S.tau, S.sp_tauT, st);
         ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
+        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_tau, S.pk_tauT, st);
     }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
     ck::launch_wmnij_init(s, S.t1(), S.WT, st);
     run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>  (mixed: written split)
     if (!S.mixed) ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
-    else ck::launch_vvvv_dress_split(s, S.t1(), S.sp_Vt, st);
+    else ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_Vt, st);
     ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>  (mixed: written split)
     run_gemm(c, S, 4);  // X += t2 W_mbej
@@ -432,6 +561,12 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     run_gemm(c, S, 2);  // hole-hole ladder
     ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     stage_end(c, all);
+}
+
+// split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
+void static_split(System &S, hipStream_t st) {
+    ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, st);
+    ck::launch_oovv_pack(S.d, S.dkc, S.pairs(), S.eri[2], S.pk_oovv, st);
 }
 
 double read_scalar(ccsd_k_ctx *c, const double *dptr) {
@@ -570,6 +705,15 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
             CK_CHECK(hipMemsetAsync(S.amp, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.res, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.zeros, 0, 16 * sizeof(cd), ctx->stream));
+            if (S.mixed) {
+                CK_CHECK(hipMemcpyAsync(S.dptab, S.ptab.data(), S.ptab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                        ctx->stream));
+                // the padding of the packed W_mnij and dressed <ab||ef> is never written by their
+                // producers and must read as zero
+                CK_CHECK(hipMemsetAsync(S.pk_WT, 0, 4 * S.d.N * (int64_t)S.d.N * S.d.no * S.d.no * S.PO * sizeof(uint16_t),
+                                        ctx->stream));
+                CK_CHECK(hipMemsetAsync(S.pk_Vt, 0, 4 * S.d.N * (int64_t)S.PV * S.PV * sizeof(uint16_t), ctx->stream));
+            }
             bind_ops(S);
             if (S.desc.synthetic) {
                 static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
@@ -580,7 +724,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
                 ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
                 ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
-                if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, ctx->stream);
+                if (S.mixed) static_split(S, ctx->stream);
                 S.inputs = true;
             }
         }
@@ -618,7 +762,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
         ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
         ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
-        if (S.mixed) ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, ctx->stream);
+        if (S.mixed) static_split(S, ctx->stream);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
@@ -807,6 +951,21 @@ int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double 
                          + o * o * v * v * (v + o))          // W_mbej seed
                   + N3 * N * (o * o * o * v * v + o * o * v * v * v) * 2.0;  // F and R1 sums
     if (other_flops) *other_flops = 8.0 * small;
+    return CCSD_K_OK;
+}
+
+int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
+                         int64_t *K) {
+    if (!ctx || sys < 0 || sys >= (int32_t)ctx->sys.size() || product < 0 || product > 4) return CCSD_K_EINVAL;
+    const System &S = ctx->sys[sys];
+    // product numbering of the timing stages: 0 pp-ladder, 1 hh-ladder, 2 W_mnij, 3 ring W, 4 ring
+    static const int gi[5] = {1, 2, 0, 3, 4};
+    const int i = gi[product];
+    const ck::GemmOps<cd> &o = (S.mixed && i < 3 ? S.gp[i] : S.g[i]).op;
+    if (G) *G = o.G;
+    if (M) *M = o.M;
+    if (N) *N = o.N;
+    if (K) *K = o.K;
     return CCSD_K_OK;
 }
 

@@ -89,20 +89,6 @@ void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st) {
 // (o^2 x v^2 row-major): a workgroup per 32 x 64 tile, a thread per (row, 8-column
 // chunk), so every split store is one 64-byte chunk; the transpose goes through LDS,
 // a thread per (column, 8-row chunk).
-__device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
-    uint16_t h[4][8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        split2(x[j].x, h[0][j], h[1][j]);
-        split2(x[j].y, h[2][j], h[3][j]);
-    }
-    uint4 *o = (uint4 *)(dst + split_index(e0, 0));
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-        o[p] = make_uint4(h[p][0] | (uint32_t)h[p][1] << 16, h[p][2] | (uint32_t)h[p][3] << 16,
-                          h[p][4] | (uint32_t)h[p][5] << 16, h[p][6] | (uint32_t)h[p][7] << 16);
-}
-
 __global__ __launch_bounds__(256) void k_tau_split(Dims d, const int32_t *kc, const cd *t1, const cd *t2,
                                                    uint16_t *tau_s, uint16_t *tauT_s, uint16_t *t2_s) {
     __shared__ cd tile[32][64 + 1];
@@ -458,19 +444,24 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
             const int n = n0 + wn * 64 + j * 32 + l32;
             if (n >= N) continue;
             const int64_t ccol = op.c_col[(int64_t)g * N + n];
+            if (ccol < 0) continue;  // padding column of a packed pair list
+            const int64_t ccol2 = op.c_col2 ? op.c_col2[(int64_t)g * N + n] : -1;
+            const int64_t cscol = op.cs_col ? op.cs_col[(int64_t)g * N + n] : ccol;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
                 if (m >= M) continue;
-                const int64_t e = op.c_row[(int64_t)g * M + m] + ccol;
-                cd *p = op.C + e;
-                cd v = make_double2(alpha * (double)accr[i][j][r], alpha * (double)acci[i][j][r]);
+                const int64_t crow = op.c_row[(int64_t)g * M + m];
+                const double ar = alpha * (double)accr[i][j][r], ai = alpha * (double)acci[i][j][r];
+                cd *p = op.C + crow + ccol;
+                cd v = make_double2(ar, ai);
                 if (beta != 0.0) {
                     cd o = *p;
                     v.x = fma(beta, o.x, v.x);
                     v.y = fma(beta, o.y, v.y);
                 }
                 if (op.Cs) {
+                    const int64_t e = (op.cs_row ? op.cs_row[(int64_t)g * M + m] : crow) + cscol;
                     uint16_t h0, h1, h2, h3;
                     split2(v.x, h0, h1);
                     split2(v.y, h2, h3);
@@ -480,6 +471,16 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
                     op.Cs[split_index(e, 3)] = h3;
                 } else {
                     *p = v;
+                }
+                if (ccol2 >= 0) {
+                    cd *p2 = op.C + crow + ccol2;
+                    cd w = make_double2(-ar, -ai);
+                    if (beta != 0.0) {
+                        cd o = *p2;
+                        w.x = fma(beta, o.x, w.x);
+                        w.y = fma(beta, o.y, w.y);
+                    }
+                    *p2 = w;
                 }
             }
         }

@@ -25,18 +25,46 @@ __host__ __device__ inline void split2(double x, uint16_t &hi, uint16_t &lo) {
     lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
 }
 
+// eight consecutive elements e0 .. e0+7 (e0 a multiple of 8) as one 64-byte chunk
+__device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
+    uint16_t h[4][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        split2(x[j].x, h[0][j], h[1][j]);
+        split2(x[j].y, h[2][j], h[3][j]);
+    }
+    uint4 *o = (uint4 *)(dst + split_index(e0, 0));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        o[p] = make_uint4(h[p][0] | (uint32_t)h[p][1] << 16, h[p][2] | (uint32_t)h[p][3] << 16,
+                          h[p][4] | (uint32_t)h[p][5] << 16, h[p][6] | (uint32_t)h[p][7] << 16);
+}
+
+// Canonical pairs of each group of total pair momentum K (pack.hip): vlist[K*PV + p] =
+// (kx*nv + x)*nv + y for the p-th canonical virtual pair of group K, -1 in the padding;
+// olist likewise for occupied pairs (PO); vpos[(K*N + kx)*nv*nv + x*nv + y] = p, or -1
+// when (kx, x, y) is not canonical.  PV and PO are multiples of 16.
+struct PairTabs {
+    const int32_t *vlist, *olist, *vpos;
+    int PV, PO;
+};
+
 // Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element
 // offsets into the unsplit operand, mapped through split_index).  C is complex128.
 // fast = 1 when every aligned group of 8 k indices is contiguous and starts at a multiple
-// of 8 in both operands (then loads move 8 k of one plane at once).  With Cs set, the
-// result alpha*AB + beta*C is written in split storage to Cs (same element offsets) and C
-// is only read.
+// of 8 in both operands (then loads move 8 k of one plane at once).  A column with
+// c_col < 0 is padding and is not written.  With Cs set, the result alpha*AB + beta*C is
+// written in split storage to Cs at cs_row + cs_col (cs_row/cs_col = NULL: the C offsets)
+// and C is only read.  With c_col2 set, every column with c_col2 >= 0 also updates a
+// second element C[c_row + c_col2] <- beta*C - alpha*AB (the antisymmetric partner of a
+// packed pair column).
 struct SplitOps {
     const uint16_t *A, *B;
     const uint16_t *zeros;  // >= 16 bytes of zeros: the load address of out-of-range chunks
     cd *C;
     uint16_t *Cs;
     const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
+    const int64_t *c_col2, *cs_row, *cs_col;
     int G, M, N, K;
     double alpha, beta;
     int fast;
@@ -54,5 +82,13 @@ void launch_tau_split(const Dims &d, const int32_t *kc, const cd *t1, const cd *
                       uint16_t *tauT_s, uint16_t *t2_s, hipStream_t st);
 // T1-dressed <ab||ef> written in split storage
 void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st);
+// packed ladder operands in split storage (pack.hip): tau rows [K][(ki,i,j)][PV] and its
+// hole-hole form [K][PV][PO]; <mn||ef> as [K][PO][PV]; the dressed <ab||ef> as [K][PV][PV]
+bool dress_pack_ok(const Dims &d);
+void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
+                     uint16_t *tau_pk, uint16_t *tauT_pk, hipStream_t st);
+void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
+                      hipStream_t st);
+void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, hipStream_t st);
 
 }  // namespace ck

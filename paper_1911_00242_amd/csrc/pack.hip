@@ -1,0 +1,245 @@
+// Antisymmetric pair packing of the ladder operands (mixed-precision path).
+//
+// tau_{ij}^{ef}, <mn||ef>, the T1-dressed <ab||ef> and W_mnij are antisymmetric under the
+// exchange of the two members of a pair (with their momenta), and so is the
+// particle-particle / hole-hole ladder contribution to R_{ij}^{ab} in (a, b).  Within a
+// group of total pair momentum K, a pair (kx, x; ky, y), ky = K - kx, is canonical when
+// (kx, x) < (ky, y) in (momentum, orbital) order.  A sum over all pairs of a product of
+// two antisymmetric factors is twice the sum over canonical pairs (the diagonal terms
+// vanish), and a result antisymmetric in (a, b) is fixed by its canonical columns.  The
+// ladder products therefore run on packed operands, canonical pairs of every group in a
+// fixed order padded with zeros to a multiple of 16, and take a quarter of the work of
+// the full products.  Every packed operand is written here in split storage.
+#include "common.h"
+#include "mixed.h"
+
+namespace ck {
+
+// tau_pk[K][(ki,i,j)][p] = tau_{i ki, j kj}^{e ke, f kf} for canonical pair p = (ke, e, f)
+// of group K: a thread per 8 consecutive p of one row, one 64-byte chunk.
+__global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out) {
+    const int N = d.N, no = d.no, nv = d.nv, M = N * no * no;
+    const int nch = pt.PV / 8;
+    const int64_t total = (int64_t)N * M * nch;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(x % nch);
+        const int64_t row = x / nch;  // K * M + m
+        const int K = (int)(row / M), m = (int)(row % M);
+        const int ki = m / (no * no), i = (m / no) % no, j = m % no;
+        const int kj = kcv(kc, N, K, 0, ki);
+        cd v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int pr = pt.vlist[(int64_t)K * pt.PV + c * 8 + q];
+            if (pr < 0) {
+                v[q] = make_double2(0.0, 0.0);
+                continue;
+            }
+            const int ke = pr / (nv * nv), e = (pr / nv) % nv, f = pr % nv;
+            const int kf = kcv(kc, N, ki, kj, ke);
+            const int64_t idx = blk3(N, ki, kj, ke) * d.t2blk() + (((int64_t)i * no + j) * nv + e) * nv + f;
+            v[q] = tau_el(t1, t2, idx, ki, kj, ke, kf, i, j, e, f, no, nv, 1.0);
+        }
+        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+    }
+}
+
+// tauT_pk[K][p'][p] = tau_{m km, n kn}^{a ka, b kb} for canonical (ka, a, b) = p' of group K
+// and canonical (km, m, n) = p: the B operand of the hole-hole ladder.
+__global__ void k_tauT_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out) {
+    const int N = d.N, no = d.no, nv = d.nv;
+    const int nch = pt.PO / 8;
+    const int64_t total = (int64_t)N * pt.PV * nch;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(x % nch);
+        const int64_t row = x / nch;  // K * PV + p'
+        const int K = (int)(row / pt.PV);
+        const int pab = pt.vlist[row];
+        cd v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int pmn = pt.olist[(int64_t)K * pt.PO + c * 8 + q];
+            if (pab < 0 || pmn < 0) {
+                v[q] = make_double2(0.0, 0.0);
+                continue;
+            }
+            const int ka = pab / (nv * nv), a = (pab / nv) % nv, b = pab % nv;
+            const int km = pmn / (no * no), mm = (pmn / no) % no, nn = pmn % no;
+            const int kn = kcv(kc, N, K, 0, km), kb = kcv(kc, N, km, kn, ka);
+            const int64_t idx = blk3(N, km, kn, ka) * d.t2blk() + (((int64_t)mm * no + nn) * nv + a) * nv + b;
+            v[q] = tau_el(t1, t2, idx, km, kn, ka, kb, mm, nn, a, b, no, nv, 1.0);
+        }
+        put_chunk(out, row * pt.PO + (int64_t)c * 8, v);
+    }
+}
+
+// oovv_pk[K][p'][p] = <m km, n kn || e ke, f kf> for canonical (km, m, n) = p' and canonical
+// (ke, e, f) = p of group K: the B operand of the W_mnij product (static).
+__global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oovv, uint16_t *out) {
+    const int N = d.N, no = d.no, nv = d.nv;
+    const int nch = pt.PV / 8;
+    const int64_t total = (int64_t)N * pt.PO * nch;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(x % nch);
+        const int64_t row = x / nch;  // K * PO + p'
+        const int K = (int)(row / pt.PO);
+        const int pmn = pt.olist[row];
+        cd v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int pef = pt.vlist[(int64_t)K * pt.PV + c * 8 + q];
+            if (pmn < 0 || pef < 0) {
+                v[q] = make_double2(0.0, 0.0);
+                continue;
+            }
+            const int km = pmn / (no * no), mm = (pmn / no) % no, nn = pmn % no;
+            const int ke = pef / (nv * nv), e = (pef / nv) % nv, f = pef % nv;
+            const int kn = kcv(kc, N, K, 0, km);
+            v[q] = oovv[blk3(N, km, kn, ke) * d.t2blk() + (((int64_t)mm * no + nn) * nv + e) * nv + f];
+        }
+        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+    }
+}
+
+// Vt_pk[K][p'][p] = <ab||ef> + t_m^b <m kb, a ka||ef> - t_m^a <m ka, b kb||ef> for canonical
+// (ka, a, b) = p' and (ke, e, f) = p.  The same workgroup layout as the full dressing (one
+// workgroup per (ka, kb, ke, e), a thread per (b, f) running over a, <m kb, a ka||e f> in
+// LDS, <m ka, b kb||e f> over m in registers), restricted to the blocks and elements that
+// are canonical in both pairs: a quarter of the reads and writes of the full copy.
+// For n_occ <= OM, o v^2 <= 2048.
+template <int OM>
+__global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out) {
+    __shared__ cd G1[2048];
+    __shared__ cd TA[OM * 64];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
+    const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
+    const int64_t nblk = (int64_t)N * N * N * nv;
+    const int64_t per = (nblk + 7) / 8;
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int e = (int)(L % nv);
+    const int64_t blk = L / nv;
+    const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
+    const int kf = kcv(s.kc, N, ka, kb, ke), K = kcv(s.kc, N, ka, kb, 0);
+    // only blocks holding canonical (a, b) and (e, f) pairs
+    if (ka > kb || ke > kf) return;
+    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
+    const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
+    const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
+    const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
+    for (int x = threadIdx.x; x < no * vv; x += blockDim.x) {
+        const int m = x / vv, af = x % vv;
+        G1[x] = g1b[(int64_t)m * v3 + (int64_t)(af / nv) * vv + af % nv];
+    }
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TA[x] = ta[x];
+    __syncthreads();
+    const int32_t *vpos_ab = pt.vpos + ((int64_t)K * N + ka) * vv;
+    const int32_t *vpos_ef = pt.vpos + ((int64_t)K * N + ke) * vv + e * nv;
+    for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
+        const int b = bf / nv, f = bf % nv;
+        const int pef = vpos_ef[f];
+        if (pef < 0) continue;
+        cd g2[OM], t1b[OM];
+#pragma unroll
+        for (int m = 0; m < OM; ++m) {
+            g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
+            t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
+        }
+        for (int a = 0; a < nv; ++a) {
+            const int pab = vpos_ab[a * nv + b];
+            if (pab < 0) continue;
+            cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+#pragma unroll
+            for (int m = 0; m < OM; ++m)
+                if (m < no) {
+                    cfma(acc, t1b[m], G1[(m * nv + a) * nv + f]);
+                    acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
+                }
+            const int64_t o = ((int64_t)K * pt.PV + pab) * pt.PV + pef;
+            uint16_t h0, h1, h2, h3;
+            split2(acc.x, h0, h1);
+            split2(acc.y, h2, h3);
+            out[split_index(o, 0)] = h0;
+            out[split_index(o, 1)] = h1;
+            out[split_index(o, 2)] = h2;
+            out[split_index(o, 3)] = h3;
+        }
+    }
+}
+
+// Plain form for other sizes: a thread per 8 consecutive p of one p', every term from
+// global memory.
+__global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uint16_t *out) {
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
+    const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
+    const int nch = pt.PV / 8;
+    const int64_t total = (int64_t)N * pt.PV * nch;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(x % nch);
+        const int64_t row = x / nch;  // K * PV + p'
+        const int K = (int)(row / pt.PV);
+        const int pab = pt.vlist[row];
+        cd v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int pef = pt.vlist[(int64_t)K * pt.PV + c * 8 + q];
+            v[q] = make_double2(0.0, 0.0);
+            if (pab < 0 || pef < 0) continue;
+            const int ka = pab / vv, a = (pab / nv) % nv, b = pab % nv;
+            const int ke = pef / vv, e = (pef / nv) % nv, f = pef % nv;
+            const int kb = kcv(s.kc, N, K, 0, ka);
+            cd acc = s.vvvv[blk3(N, ka, kb, ke) * v4 + (((int64_t)a * nv + b) * nv + e) * nv + f];
+            const cd *g1 = s.ovvv + blk3(N, kb, ka, ke) * ov3 + ((int64_t)a * nv + e) * nv + f;
+            const cd *g2 = s.ovvv + blk3(N, ka, kb, ke) * ov3 + ((int64_t)b * nv + e) * nv + f;
+            for (int m = 0; m < no; ++m) {
+                cfma(acc, t1[((int64_t)kb * no + m) * nv + b], g1[(int64_t)m * v3]);
+                acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], g2[(int64_t)m * v3]));
+            }
+            v[q] = acc;
+        }
+        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+    }
+}
+
+static dim3 pack_grid(int64_t threads) {
+    int64_t b = (threads + 255) / 256;
+    if (b > (1 << 20)) b = 1 << 20;
+    return dim3((unsigned)(b < 1 ? 1 : b));
+}
+
+bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv * d.nv <= 2048 && d.nv <= 64; }
+
+void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
+                     uint16_t *tau_pk, uint16_t *tauT_pk, hipStream_t st) {
+    const int64_t N = d.N, M = (int64_t)N * d.no * d.no;
+    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * M * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk);
+    CK_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_tauT_pack, pack_grid(N * pt.PV * (pt.PO / 8)), dim3(256), 0, st, d, kc, pt, t1, t2,
+                       tauT_pk);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
+                      hipStream_t st) {
+    const int64_t N = d.N;
+    hipLaunchKernelGGL(k_oovv_pack, pack_grid(N * pt.PO * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, oovv, out);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, hipStream_t st) {
+    const int64_t N = s.d.N, nv = s.d.nv;
+    const int64_t n = N * N * N * nv;
+    const dim3 grid((unsigned)((n + 7) / 8 * 8));
+    if (!dress_pack_ok(s.d))
+        hipLaunchKernelGGL(k_vvvv_dress_pack_plain, pack_grid(N * pt.PV * (pt.PV / 8)), dim3(256), 0, st, s, pt, t1,
+                           out);
+    else if (s.d.no <= 8)
+        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out);
+    else if (s.d.no <= 16)
+        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out);
+    else
+        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out);
+    CK_CHECK(hipGetLastError());
+}
+
+}  // namespace ck

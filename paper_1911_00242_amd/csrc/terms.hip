@@ -29,28 +29,6 @@ static inline dim3 grid_for(int64_t total) {
     return dim3((unsigned)b);
 }
 
-__device__ inline int kcv(const int32_t *kc, int N, int a, int b, int c) {
-    return kc[((int64_t)a * N + b) * N + c];
-}
-__device__ inline int64_t blk3(int N, int a, int b, int c) { return ((int64_t)a * N + b) * N + c; }
-
-// tau_{ij}^{ab} = t2 + fac * (d(ka,ki) t_i^a t_j^b - d(kb,ki) t_i^b t_j^a)
-__device__ inline cd tau_el(const cd *t1, const cd *t2, int64_t idx, int ki, int kj, int ka, int kb,
-                            int i, int j, int a, int b, int no, int nv, double fac) {
-    cd v = t2[idx];
-    if (ka == ki) {
-        cd p = cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + j) * nv + b]);
-        v.x += fac * p.x;
-        v.y += fac * p.y;
-    }
-    if (kb == ki) {
-        cd p = cmul(t1[((int64_t)ki * no + i) * nv + b], t1[((int64_t)kj * no + j) * nv + a]);
-        v.x -= fac * p.x;
-        v.y -= fac * p.y;
-    }
-    return v;
-}
-
 // ------------------------------------------------------------------ tau and its transpose
 __global__ void k_tau(Dims d, const int32_t *kc, const cd *t1, const cd *t2, cd *tau) {
     const int N = d.N, no = d.no, nv = d.nv;

@@ -91,3 +91,47 @@ def test_batch_plan_sums_systems():
     finally:
         for x in (a, b, ab):
             ck.ccsd_k_free(x)
+
+
+def _canonical_pairs(grid, w):
+    """Canonical pairs (kx, x) < (ky, y), ky = K - kx, of every group K, counted directly."""
+    import itertools
+
+    import numpy as np
+
+    from oracle import ccsd_k as O
+
+    kc = O.kconserv(grid)
+    N = int(np.prod(grid))
+    counts = []
+    for K in range(N):
+        n = 0
+        for kx in range(N):
+            ky = kc[K, 0, kx]
+            for x, y in itertools.product(range(w), range(w)):
+                n += (kx, x) < (ky, y)
+        counts.append(n)
+    return counts
+
+
+@pytest.mark.parametrize("grid,no,nv", [((3, 3, 3), 8, 16), ((2, 2, 2), 4, 8), ((2, 1, 1), 3, 5)])
+def test_product_shapes(grid, no, nv):
+    """FP64: the full grouped products; mixed: the ladder family on canonical pairs padded
+    to a multiple of 16 (a quarter of the work), the ring family in full."""
+    N = grid[0] * grid[1] * grid[2]
+    pv = -(-max(_canonical_pairs(grid, nv)) // 16) * 16
+    po = -(-max(_canonical_pairs(grid, no)) // 16) * 16
+    full = {0: (N, N * no * no, N * nv * nv, N * nv * nv), 1: (N, N * no * no, N * nv * nv, N * no * no),
+            2: (N, N * no * no, N * no * no, N * nv * nv), 3: (N, N * no * nv, N * no * nv, N * no * nv),
+            4: (N, N * no * nv, N * no * nv, N * no * nv)}
+    packed = dict(full)
+    packed[0] = (N, N * no * no, pv, pv)
+    packed[1] = (N, N * no * no, pv, po)
+    packed[2] = (N, N * no * no, po, pv)
+    for prec, want in ((ck.PREC_FP64, full), (ck.PREC_MIXED, packed)):
+        ctx = ck.ccsd_k_init([dict(grid=grid, no=no, nv=nv, precision=prec)], None)
+        try:
+            for p in range(5):
+                assert ck.ccsd_k_product_shape(ctx, 0, p) == want[p], (prec, p)
+        finally:
+            ck.ccsd_k_free(ctx)
