@@ -30,17 +30,20 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s, MI35
 # Sources whose text fixes a GEMM kernel's memory traffic: the kernel file and the
 # headers that define its tile order and operand storage.
 KERNEL_SOURCES = {
-    "pp_ladder_fp64": ["paper_1911_00242_amd/csrc/gemm_f64.hip", "paper_1911_00242_amd/csrc/common.h"],
-    "pp_ladder_mixed": ["paper_1911_00242_amd/csrc/gemm_mixed.hip", "paper_1911_00242_amd/csrc/common.h",
-                        "paper_1911_00242_amd/csrc/mixed.h"],
+    "fp64": ["paper_1911_00242_amd/csrc/gemm_f64.hip", "paper_1911_00242_amd/csrc/common.h"],
+    "mixed": ["paper_1911_00242_amd/csrc/gemm_mixed.hip", "paper_1911_00242_amd/csrc/common.h",
+              "paper_1911_00242_amd/csrc/mixed.h"],
 }
+PRODUCT_KERNEL = {"pp_ladder": "particle-particle ladder grouped GEMM", "hh_ladder": "hole-hole ladder grouped GEMM",
+                  "w_mnij": "W_mnij grouped GEMM", "w_mbej": "W_mbej grouped GEMM",
+                  "ring": "ring product grouped GEMM"}
 
 
 def source_hash(key):
     import hashlib
 
     h = hashlib.sha256()
-    for src in KERNEL_SOURCES[key]:
+    for src in KERNEL_SOURCES[key.rsplit("_", 1)[1]]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     return h.hexdigest()[:16]
 
@@ -170,19 +173,29 @@ def main():
     ms = 1000.0 * r["seconds"] / a.steps
     value = 1000.0 / ms
     tflops = r["exec_flops"] / (ms / 1000.0) / 1e12
-    pp_ms, pp_n = r["stages"]["pp_ladder"]
-    G, M, Nn, K = r["shapes"]["pp_ladder"]
-    pp_cmacs = float(G) * M * Nn * K  # complex multiply-adds of one pp-ladder launch as executed
-    if head == 0:
-        pp_flops, peak, dtype = 8.0 * pp_cmacs, PEAK["fp64"], "f64"
-        traffic = measured_traffic("pp_ladder_fp64")
-    else:
-        pp_flops, peak, dtype = 24.0 * pp_cmacs, PEAK["bf16"], "bf16x3/f32acc+f64"
-        traffic = measured_traffic("pp_ladder_mixed")
-    if (grid, a.no, a.nv) != ((3, 3, 3), 8, 16):
-        traffic = None
-    pp_avg = pp_ms / max(pp_n, 1)
-    achieved = pp_flops / (pp_avg / 1000.0) / 1e12 if pp_n else None
+    path = "fp64" if head == 0 else "mixed"
+    peak, dtype, per_cmac = ((PEAK["fp64"], "f64", 8.0) if head == 0 else
+                             (PEAK["bf16"], "bf16x3/f32acc+f64", 24.0))
+
+    def roofline(name):
+        """The product's executed work per launch (per_cmac flops per complex multiply-add:
+        8 for FP64, 24 = 3 bf16 products x 4 real products x 2 for split-BF16) over its
+        average launch time from HIP events on the library's stream."""
+        tot_ms, n = r["stages"][name]
+        G, M, Nn, K = r["shapes"][name]
+        if not n or not G:
+            return None
+        avg = tot_ms / n
+        achieved = per_cmac * G * M * Nn * K / (avg / 1000.0) / 1e12
+        traffic = measured_traffic(f"{name}_{path}") if (grid, a.no, a.nv) == ((3, 3, 3), 8, 16) else None
+        return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
+                "kernel": PRODUCT_KERNEL[name] + (" (both ladders, packed pairs)" if head == 1 and name == "pp_ladder"
+                                                   else ""),
+                "avg_launch_ms": avg, "shape": {"groups": G, "M": M, "N": Nn, "K": K}}
+
+    products = [k for k in PRODUCT_KERNEL if r["stages"][k][1]]
+    dominant = max(products, key=lambda k: r["stages"][k][0])
     line = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -192,11 +205,8 @@ def main():
                    "grid": list(grid), "n_occ": a.no, "n_vir": a.nv, "seed": a.seed},
         "tflops": tflops,
         "tflops_algorithmic": r["gemm_flops"] / (ms / 1000.0) / 1e12,
-        "pp_ladder_shape": {"groups": G, "M": M, "N": Nn, "K": K},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": (achieved / peak) if achieved else None,
-                     "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
-                     "kernel": "particle-particle ladder grouped GEMM", "avg_launch_ms": pp_avg},
+        "roofline": roofline(dominant),
+        "roofline_ladder": roofline("pp_ladder"),
         "stages_ms_per_step": {k: v[0] / a.steps for k, v in r["stages"].items()},
         "energy": [r["energy"].real, r["energy"].imag],
     }

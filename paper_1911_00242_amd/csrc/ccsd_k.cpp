@@ -64,8 +64,11 @@ struct System {
     std::vector<int32_t> ptab;  // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v]
     int PV = 0, PO = 0;
     int32_t *dptab = nullptr;
-    Gemm gp[3];  // packed W_mnij, particle-particle and hole-hole products
-    uint16_t *pk_tau = nullptr, *pk_tauT = nullptr, *pk_Vt = nullptr, *pk_WT = nullptr, *pk_oovv = nullptr;
+    Gemm gp[2];  // packed W_mnij product; both ladders as one packed product
+    // packed split operands, rows PV + PO elements long:
+    //   pk_A [K][(ki,i,j)]: tau over canonical (ke,e,f) | W_mnij over canonical (km,m,n)
+    //   pk_B [K][canonical (ka,a,b)]: dressed <ab||ef> over (ke,e,f) | tau over (km,m,n)
+    uint16_t *pk_A = nullptr, *pk_B = nullptr, *pk_oovv = nullptr;
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -151,10 +154,12 @@ int kcons(const ck::Mesh &m, int kp, int kq, int kr) {
 // of 16) so that the grouped products have one k extent.  Packed ladder products (mixed
 // path), each a quarter of its full form (antisymmetry, pack.hip):
 //   G1p: W_mnij += tau . <mn||ef>^T   rows (ki,i,j), cols canonical (km,m,n), k canonical (ke,e,f)
-//        (alpha 1 = 1/2 x 2 for the canonical k pairs); written split to pk_WT [K][row][PO]
-//   G2p: r2 += tau . Vt^T             rows (ki,i,j), cols canonical (ka,a,b), k canonical (ke,e,f)
-//   G3p: r2 += W_mnij . tauT          rows (ki,i,j), cols canonical (ka,a,b), k canonical (km,m,n)
-// G2p and G3p write the (a,b) column and its partner (b,a) with the opposite sign.
+//        (alpha 1 = 1/2 x 2 for the canonical k pairs); written split into the W_mnij part
+//        of pk_A
+//   G23p: r2 += tau . Vt^T + W_mnij . tauT   rows (ki,i,j), cols canonical (ka,a,b),
+//        k = canonical (ke,e,f) then canonical (km,m,n): both ladders as one product on
+//        the concatenated rows of pk_A and pk_B, whose epilogue writes the (a,b) column
+//        and its partner (b,a) with the opposite sign.
 void build_tables(System &S);
 void build_pair_tables(System &S) {
     const int64_t N = S.d.N, o = S.d.no, v = S.d.nv;
@@ -197,7 +202,8 @@ void build_pair_tables(System &S) {
         g.tab[which] = T.size();
         for (int64_t x = 0; x < len; ++x) T.push_back(fn(x));
     };
-    Gemm &g1 = S.gp[0], &g2 = S.gp[1], &g3 = S.gp[2];
+    Gemm &g1 = S.gp[0], &g2 = S.gp[1];
+    const int64_t R = PV + PO;  // row length of pk_A and pk_B
     // c_row of W_mnij and r2 for row (ki,i,j) of group K
     auto row_t2 = [&](int64_t K, int64_t x) {
         int64_t ki = x / oo, ij = x % oo;
@@ -208,7 +214,7 @@ void build_pair_tables(System &S) {
         return ((ki * N + kc(K, 0, ki)) * N) * o4 + ij * oo;
     };
     // G1p
-    put(g1, 0, N * M, [&](int64_t x) { return x * PV; });  // tau_pk rows
+    put(g1, 0, N * M, [&](int64_t x) { return x * R; });  // tau part of pk_A
     put(g1, 1, N * PV, [&](int64_t x) { return x % PV; });
     put(g1, 2, N * PO, [&](int64_t x) { return x * PV; });  // oovv_pk rows
     g1.tab[3] = g1.tab[1];
@@ -218,17 +224,17 @@ void build_pair_tables(System &S) {
         if (pr < 0) return (int64_t)-1;
         return (int64_t)(pr / oo) * o4 + pr % oo;
     });
-    g1.cs_row = T.size();
-    for (int64_t x = 0; x < N * M; ++x) T.push_back(x * PO);
+    g1.cs_row = T.size();  // W_mnij part of pk_A
+    for (int64_t x = 0; x < N * M; ++x) T.push_back(x * R + PV);
     g1.cs_col = T.size();
     for (int64_t x = 0; x < N * PO; ++x) T.push_back(x % PO);
     g1.op.G = (int)N; g1.op.M = (int)M; g1.op.N = (int)PO; g1.op.K = (int)PV;
     g1.op.alpha = 1.0; g1.op.beta = 1.0; g1.stage = ST_WMN;
-    // G2p
+    // G23p
     g2.tab[0] = g1.tab[0];
-    g2.tab[1] = g1.tab[1];
-    put(g2, 2, N * PV, [&](int64_t x) { return x * PV; });  // Vt_pk rows
-    g2.tab[3] = g1.tab[1];
+    put(g2, 1, N * R, [&](int64_t x) { return x % R; });
+    put(g2, 2, N * PV, [&](int64_t x) { return x * R; });  // pk_B rows
+    g2.tab[3] = g2.tab[1];
     put(g2, 4, N * M, [&](int64_t x) { return row_t2(x / M, x % M); });
     put(g2, 5, N * PV, [&](int64_t x) {  // r2 column (ka,a,b)
         const int32_t pr = vlist[x];
@@ -245,18 +251,8 @@ void build_pair_tables(System &S) {
         const int64_t K = x / PV, ka = pr / vv, a = (pr / v) % v, b = pr % v;
         T.push_back(kc(K, 0, ka) * t2b + b * v + a);
     }
-    g2.op.G = (int)N; g2.op.M = (int)M; g2.op.N = (int)PV; g2.op.K = (int)PV;
+    g2.op.G = (int)N; g2.op.M = (int)M; g2.op.N = (int)PV; g2.op.K = (int)R;
     g2.op.alpha = 1.0; g2.op.beta = 1.0; g2.stage = ST_PP;
-    // G3p
-    put(g3, 0, N * M, [&](int64_t x) { return x * PO; });  // pk_WT rows
-    put(g3, 1, N * PO, [&](int64_t x) { return x % PO; });
-    put(g3, 2, N * PV, [&](int64_t x) { return x * PO; });  // tauT_pk rows
-    g3.tab[3] = g3.tab[1];
-    g3.tab[4] = g2.tab[4];
-    g3.tab[5] = g2.tab[5];
-    g3.c_col2 = g2.c_col2;
-    g3.op.G = (int)N; g3.op.M = (int)M; g3.op.N = (int)PV; g3.op.K = (int)PO;
-    g3.op.alpha = 1.0; g3.op.beta = 1.0; g3.stage = ST_HH;
 }
 
 // Offsets in complex elements.  Group label: total pair momentum K for the ladder
@@ -394,10 +390,8 @@ void carve(System &S, Carver &c) {
         c.take(S.sp_t2, 4 * S.pl_t2);
         c.take(S.sp_WR, 4 * S.pl_t2);
         c.take(S.sp_oovv, 4 * S.pl_t2);
-        c.take(S.pk_tau, 4 * N * M * PV);
-        c.take(S.pk_tauT, 4 * N * PV * PO);
-        c.take(S.pk_Vt, 4 * N * PV * PV);
-        c.take(S.pk_WT, 4 * N * M * PO);
+        c.take(S.pk_A, 4 * N * M * (PV + PO));
+        c.take(S.pk_B, 4 * N * PV * (PV + PO));
         c.take(S.pk_oovv, 4 * N * PO * PV);
         c.take(S.dptab, (int64_t)S.ptab.size());
     }
@@ -472,12 +466,13 @@ void bind_ops(System &S) {
         g.op.zeros = S.zeros;
     }
     if (!S.mixed) return;
-    // the ladder family on packed pairs (gp), the ring family in full (g[3], g[4])
-    const Gemm *G[5] = {&S.gp[0], &S.gp[1], &S.gp[2], &S.g[3], &S.g[4]};
-    const uint16_t *SA[5] = {S.pk_tau, S.pk_tau, S.pk_WT, S.sp_t2, S.sp_t2};
-    const uint16_t *SB[5] = {S.pk_oovv, S.pk_Vt, S.pk_tauT, S.sp_oovv, S.sp_WR};
+    // the ladder family on packed pairs (gp: W_mnij, then both ladders as one product; slot
+    // 2, the separate hole-hole product, is unused), the ring family in full (g[3], g[4])
+    const Gemm *G[5] = {&S.gp[0], &S.gp[1], &S.gp[1], &S.g[3], &S.g[4]};
+    const uint16_t *SA[5] = {S.pk_A, S.pk_A, S.pk_A, S.sp_t2, S.sp_t2};
+    const uint16_t *SB[5] = {S.pk_oovv, S.pk_B, S.pk_B, S.sp_oovv, S.sp_WR};
     // W_mnij and W_mbej are only consumed as split operands: their products write split
-    uint16_t *CS[5] = {S.pk_WT, nullptr, nullptr, S.sp_WR, nullptr};
+    uint16_t *CS[5] = {S.pk_A, nullptr, nullptr, S.sp_WR, nullptr};
     auto tab = [&](size_t off) { return off == SIZE_MAX ? nullptr : T + off; };
     for (int i = 0; i < 5; ++i) {
         const Gemm &g = *G[i];
@@ -530,7 +525,7 @@ void collect_timing(ccsd_k_ctx *c) {
 
 void run_gemm(ccsd_k_ctx *c, System &S, int i) {
     EventPair ep{};
-    stage_begin(c, ep, (S.mixed && i < 3 ? S.gp[i] : S.g[i]).stage);
+    stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage);
     if (S.mixed) ck::gemm_split(S.sg[i], c->stream);
     else ck::gemm_f64(S.g[i].op, c->stream);
     stage_end(c, ep);
@@ -546,19 +541,20 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
     } else {
         ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
-        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_tau, S.pk_tauT, st);
+        const int64_t R = S.PV + S.PO;
+        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
     }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
     ck::launch_wmnij_init(s, S.t1(), S.WT, st);
     run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>  (mixed: written split)
     if (!S.mixed) ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
-    else ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_Vt, st);
+    else ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, S.PV + S.PO, st);
     ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>  (mixed: written split)
     run_gemm(c, S, 4);  // X += t2 W_mbej
     ck::launch_assemble_r2(s, S.X, S.r2(), st);
-    run_gemm(c, S, 1);  // particle-particle ladder
-    run_gemm(c, S, 2);  // hole-hole ladder
+    run_gemm(c, S, 1);  // particle-particle ladder (mixed: both ladders)
+    if (!S.mixed) run_gemm(c, S, 2);  // hole-hole ladder
     ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     stage_end(c, all);
 }
@@ -710,9 +706,9 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                                         ctx->stream));
                 // the padding of the packed W_mnij and dressed <ab||ef> is never written by their
                 // producers and must read as zero
-                CK_CHECK(hipMemsetAsync(S.pk_WT, 0, 4 * S.d.N * (int64_t)S.d.N * S.d.no * S.d.no * S.PO * sizeof(uint16_t),
-                                        ctx->stream));
-                CK_CHECK(hipMemsetAsync(S.pk_Vt, 0, 4 * S.d.N * (int64_t)S.PV * S.PV * sizeof(uint16_t), ctx->stream));
+                const int64_t R = S.PV + S.PO, M = (int64_t)S.d.N * S.d.no * S.d.no;
+                CK_CHECK(hipMemsetAsync(S.pk_A, 0, 4 * S.d.N * M * R * sizeof(uint16_t), ctx->stream));
+                CK_CHECK(hipMemsetAsync(S.pk_B, 0, 4 * S.d.N * (int64_t)S.PV * R * sizeof(uint16_t), ctx->stream));
             }
             bind_ops(S);
             if (S.desc.synthetic) {
@@ -961,7 +957,14 @@ int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, in
     // product numbering of the timing stages: 0 pp-ladder, 1 hh-ladder, 2 W_mnij, 3 ring W, 4 ring
     static const int gi[5] = {1, 2, 0, 3, 4};
     const int i = gi[product];
-    const ck::GemmOps<cd> &o = (S.mixed && i < 3 ? S.gp[i] : S.g[i]).op;
+    if (S.mixed && i == 2) {  // the hole-hole ladder runs inside the particle-particle product
+        if (G) *G = 0;
+        if (M) *M = 0;
+        if (N) *N = 0;
+        if (K) *K = 0;
+        return CCSD_K_OK;
+    }
+    const ck::GemmOps<cd> &o = (S.mixed && i < 2 ? S.gp[i] : S.g[i]).op;
     if (G) *G = o.G;
     if (M) *M = o.M;
     if (N) *N = o.N;

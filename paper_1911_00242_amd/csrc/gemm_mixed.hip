@@ -27,133 +27,40 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ conversions
-__global__ void k_split(int64_t n, const cd *src, uint16_t *dst) {
+// A workgroup converts 256 chunks (2048 elements) at a time: coalesced loads of
+// consecutive elements, the bf16 halves staged per plane in LDS, then one 64-byte chunk
+// store per thread.
+__global__ __launch_bounds__(256) void k_split(int64_t n, const cd *src, uint16_t *dst) {
+    __shared__ __attribute__((aligned(16))) uint16_t S[4][2048];
+    const int t = threadIdx.x;
     const int64_t nch = (n + 7) / 8;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += (int64_t)gridDim.x * blockDim.x) {
-        uint16_t v[4][8];
+    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < nch; c0 += (int64_t)gridDim.x * 256) {
+        const int64_t e0 = c0 * 8;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int64_t e = c * 8 + j;
+            const int64_t e = e0 + t + 256 * j;
             const cd x = e < n ? src[e] : make_double2(0.0, 0.0);
-            split2(x.x, v[0][j], v[1][j]);
-            split2(x.y, v[2][j], v[3][j]);
+            uint16_t h0, h1, h2, h3;
+            split2(x.x, h0, h1);
+            split2(x.y, h2, h3);
+            S[0][t + 256 * j] = h0;
+            S[1][t + 256 * j] = h1;
+            S[2][t + 256 * j] = h2;
+            S[3][t + 256 * j] = h3;
         }
-        uint4 *o = (uint4 *)(dst + c * 32);
+        __syncthreads();
+        if (c0 + t < nch) {
+            uint4 *o = (uint4 *)(dst + (c0 + t) * 32);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-            o[p] = make_uint4(v[p][0] | (uint32_t)v[p][1] << 16, v[p][2] | (uint32_t)v[p][3] << 16,
-                              v[p][4] | (uint32_t)v[p][5] << 16, v[p][6] | (uint32_t)v[p][7] << 16);
-    }
-}
-
-// per momentum block (o^2 x v^2) -> split storage of the (v^2 x o^2) transpose
-__global__ void k_split_transpose(Dims d, const cd *src, uint16_t *dst) {
-    __shared__ cd tile[32][33];
-    const int R = d.no * d.no, C = d.nv * d.nv;
-    const int tr = (R + 31) / 32, tc = (C + 31) / 32;
-    int64_t blk = blockIdx.x / (tr * tc);
-    int t = (int)(blockIdx.x % (tr * tc));
-    int r0 = (t / tc) * 32, c0 = (t % tc) * 32;
-    const cd *s = src + blk * d.t2blk();
-    int64_t ob = blk * d.t2blk();
-    int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
-    for (int y = ty; y < 32; y += 8) {
-        int r = r0 + y, c = c0 + tx;
-        if (r < R && c < C) tile[y][tx] = s[(int64_t)r * C + c];
-    }
-    __syncthreads();
-    for (int y = ty; y < 32; y += 8) {
-        int c = c0 + y, r = r0 + tx;
-        if (r < R && c < C) {
-            cd x = tile[tx][y];
-            int64_t i = ob + (int64_t)c * R + r;
-            uint16_t a, b, e, f;
-            split2(x.x, a, b);
-            split2(x.y, e, f);
-            dst[split_index(i, 0)] = a;
-            dst[split_index(i, 1)] = b;
-            dst[split_index(i, 2)] = e;
-            dst[split_index(i, 3)] = f;
+            for (int p = 0; p < 4; ++p) o[p] = *(const uint4 *)&S[p][8 * t];
         }
+        __syncthreads();
     }
 }
 
 void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st) {
-    int64_t b = std::min<int64_t>(((n + 7) / 8 + 255) / 256, 1 << 20);
+    int64_t b = std::min<int64_t>(((n + 7) / 8 + 255) / 256, 1 << 16);
     hipLaunchKernelGGL(k_split, dim3((unsigned)std::max<int64_t>(b, 1)), dim3(256), 0, st, n, src, dst);
-    CK_CHECK(hipGetLastError());
-}
-
-// tau = t2 + d(ka,ki) t_i^a t_j^b - d(kb,ki) t_i^b t_j^a, written with t2 itself and the
-// per-block transpose of tau in split storage, from one read of t2.  Per momentum block
-// (o^2 x v^2 row-major): a workgroup per 32 x 64 tile, a thread per (row, 8-column
-// chunk), so every split store is one 64-byte chunk; the transpose goes through LDS,
-// a thread per (column, 8-row chunk).
-__global__ __launch_bounds__(256) void k_tau_split(Dims d, const int32_t *kc, const cd *t1, const cd *t2,
-                                                   uint16_t *tau_s, uint16_t *tauT_s, uint16_t *t2_s) {
-    __shared__ cd tile[32][64 + 1];
-    const int N = d.N, no = d.no, nv = d.nv, R = no * no, C = nv * nv;
-    const int tr = (R + 31) / 32, tc = C / 64 + (C % 64 ? 1 : 0);
-    const int64_t blk = blockIdx.x / (tr * tc);
-    const int t = (int)(blockIdx.x % (tr * tc));
-    const int r0 = (t / tc) * 32, c0 = (t % tc) * 64;
-    const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
-    const int kb = kc[((int64_t)ki * N + kj) * N + ka];
-    const int64_t ob = blk * (int64_t)R * C;
-    {
-        const int y = threadIdx.x >> 3, cc = c0 + (threadIdx.x & 7) * 8;
-        const int r = r0 + y;
-        if (r < R && cc < C) {
-            const int i = r / no, j = r % no;
-            const int64_t e0 = ob + (int64_t)r * C + cc;
-            cd x[8], u[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int a = (cc + q) / nv, b = (cc + q) % nv;
-                x[q] = t2[e0 + q];
-                u[q] = x[q];
-                if (ka == ki) {
-                    const cd p = cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + j) * nv + b]);
-                    u[q].x += p.x;
-                    u[q].y += p.y;
-                }
-                if (kb == ki) {
-                    const cd p = cmul(t1[((int64_t)ki * no + i) * nv + b], t1[((int64_t)kj * no + j) * nv + a]);
-                    u[q].x -= p.x;
-                    u[q].y -= p.y;
-                }
-                tile[y][(threadIdx.x & 7) * 8 + q] = u[q];
-            }
-            put_chunk(t2_s, e0, x);
-            put_chunk(tau_s, e0, u);
-        }
-    }
-    __syncthreads();
-    {
-        const int c = c0 + (threadIdx.x & 63), y0 = (threadIdx.x >> 6) * 8, r = r0 + y0;
-        if (c < C && r < R) {
-            cd u[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) u[q] = tile[y0 + q][threadIdx.x & 63];
-            put_chunk(tauT_s, ob + (int64_t)c * R + r, u);
-        }
-    }
-}
-
-bool tau_split_ok(const Dims &d) { return (d.no * d.no) % 8 == 0 && (d.nv * d.nv) % 8 == 0; }
-
-void launch_tau_split(const Dims &d, const int32_t *kc, const cd *t1, const cd *t2, uint16_t *tau_s,
-                      uint16_t *tauT_s, uint16_t *t2_s, hipStream_t st) {
-    const int R = d.no * d.no, C = d.nv * d.nv;
-    const int64_t tiles = (int64_t)((R + 31) / 32) * ((C + 63) / 64) * d.N * d.N * d.N;
-    hipLaunchKernelGGL(k_tau_split, dim3((unsigned)tiles), dim3(256), 0, st, d, kc, t1, t2, tau_s, tauT_s, t2_s);
-    CK_CHECK(hipGetLastError());
-}
-
-void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, hipStream_t st) {
-    int R = d.no * d.no, C = d.nv * d.nv;
-    dim3 g((unsigned)((int64_t)((R + 31) / 32) * ((C + 31) / 32) * d.N * d.N * d.N));
-    hipLaunchKernelGGL(k_split_transpose, g, dim3(256), 0, st, d, src, dst);
     CK_CHECK(hipGetLastError());
 }
 

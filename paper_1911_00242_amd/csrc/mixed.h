@@ -73,22 +73,15 @@ struct SplitOps {
 void gemm_split(const SplitOps &op, hipStream_t s);
 // split storage of n complex128 elements (pad of the last chunk zeroed)
 void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st);
-// split storage of the per-block (o^2 x v^2) -> (v^2 x o^2) transpose of src
-void launch_split_transpose(const Dims &d, const cd *src, uint16_t *dst, hipStream_t st);
-// tau from (t1, t2) straight to split storage: tau, its per-block transpose, and t2 itself;
-// needs n_occ^2 and n_vir^2 to be multiples of 8 (tau_split_ok)
-bool tau_split_ok(const Dims &d);
-void launch_tau_split(const Dims &d, const int32_t *kc, const cd *t1, const cd *t2, uint16_t *tau_s,
-                      uint16_t *tauT_s, uint16_t *t2_s, hipStream_t st);
-// T1-dressed <ab||ef> written in split storage
-void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st);
-// packed ladder operands in split storage (pack.hip): tau rows [K][(ki,i,j)][PV] and its
-// hole-hole form [K][PV][PO]; <mn||ef> as [K][PO][PV]; the dressed <ab||ef> as [K][PV][PV]
+// packed ladder operands in split storage (pack.hip), rows ld elements apart: tau rows
+// [K][(ki,i,j)][PV] and its hole-hole form [K][PV][PO]; <mn||ef> as [K][PO][PV]; the
+// dressed <ab||ef> as [K][PV][PV]
 bool dress_pack_ok(const Dims &d);
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
-                     uint16_t *tau_pk, uint16_t *tauT_pk, hipStream_t st);
+                     uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st);
 void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
                       hipStream_t st);
-void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, hipStream_t st);
+void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
+                            hipStream_t st);
 
 }  // namespace ck

@@ -16,8 +16,10 @@
 namespace ck {
 
 // tau_pk[K][(ki,i,j)][p] = tau_{i ki, j kj}^{e ke, f kf} for canonical pair p = (ke, e, f)
-// of group K: a thread per 8 consecutive p of one row, one 64-byte chunk.
-__global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out) {
+// of group K (rows ld elements apart): a thread per 8 consecutive p of one row, one
+// 64-byte chunk.
+__global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out,
+                           int64_t ld) {
     const int N = d.N, no = d.no, nv = d.nv, M = N * no * no;
     const int nch = pt.PV / 8;
     const int64_t total = (int64_t)N * M * nch;
@@ -40,13 +42,15 @@ __global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1,
             const int64_t idx = blk3(N, ki, kj, ke) * d.t2blk() + (((int64_t)i * no + j) * nv + e) * nv + f;
             v[q] = tau_el(t1, t2, idx, ki, kj, ke, kf, i, j, e, f, no, nv, 1.0);
         }
-        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+        put_chunk(out, row * ld + (int64_t)c * 8, v);
     }
 }
 
 // tauT_pk[K][p'][p] = tau_{m km, n kn}^{a ka, b kb} for canonical (ka, a, b) = p' of group K
-// and canonical (km, m, n) = p: the B operand of the hole-hole ladder.
-__global__ void k_tauT_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out) {
+// and canonical (km, m, n) = p (rows ld elements apart): the B operand of the hole-hole
+// ladder.
+__global__ void k_tauT_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out,
+                            int64_t ld) {
     const int N = d.N, no = d.no, nv = d.nv;
     const int nch = pt.PO / 8;
     const int64_t total = (int64_t)N * pt.PV * nch;
@@ -69,7 +73,7 @@ __global__ void k_tauT_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1
             const int64_t idx = blk3(N, km, kn, ka) * d.t2blk() + (((int64_t)mm * no + nn) * nv + a) * nv + b;
             v[q] = tau_el(t1, t2, idx, km, kn, ka, kb, mm, nn, a, b, no, nv, 1.0);
         }
-        put_chunk(out, row * pt.PO + (int64_t)c * 8, v);
+        put_chunk(out, row * ld + (int64_t)c * 8, v);
     }
 }
 
@@ -108,7 +112,8 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // are canonical in both pairs: a quarter of the reads and writes of the full copy.
 // For n_occ <= OM, o v^2 <= 2048.
 template <int OM>
-__global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out) {
+__global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
+                                                         int64_t ld) {
     __shared__ cd G1[2048];
     __shared__ cd TA[OM * 64];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
                     cfma(acc, t1b[m], G1[(m * nv + a) * nv + f]);
                     acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
                 }
-            const int64_t o = ((int64_t)K * pt.PV + pab) * pt.PV + pef;
+            const int64_t o = ((int64_t)K * pt.PV + pab) * ld + pef;
             uint16_t h0, h1, h2, h3;
             split2(acc.x, h0, h1);
             split2(acc.y, h2, h3);
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
 
 // Plain form for other sizes: a thread per 8 consecutive p of one p', every term from
 // global memory.
-__global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uint16_t *out) {
+__global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uint16_t *out, int64_t ld) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
     const int nch = pt.PV / 8;
@@ -197,7 +202,7 @@ __global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uin
             }
             v[q] = acc;
         }
-        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+        put_chunk(out, row * ld + (int64_t)c * 8, v);
     }
 }
 
@@ -210,12 +215,13 @@ static dim3 pack_grid(int64_t threads) {
 bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv * d.nv <= 2048 && d.nv <= 64; }
 
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
-                     uint16_t *tau_pk, uint16_t *tauT_pk, hipStream_t st) {
+                     uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st) {
     const int64_t N = d.N, M = (int64_t)N * d.no * d.no;
-    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * M * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk);
+    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * M * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk,
+                       ld_tau);
     CK_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_tauT_pack, pack_grid(N * pt.PV * (pt.PO / 8)), dim3(256), 0, st, d, kc, pt, t1, t2,
-                       tauT_pk);
+                       tauT_pk, ld_tauT);
     CK_CHECK(hipGetLastError());
 }
 
@@ -226,19 +232,20 @@ void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, cons
     CK_CHECK(hipGetLastError());
 }
 
-void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, hipStream_t st) {
+void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
+                            hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
     const int64_t n = N * N * N * nv;
     const dim3 grid((unsigned)((n + 7) / 8 * 8));
     if (!dress_pack_ok(s.d))
         hipLaunchKernelGGL(k_vvvv_dress_pack_plain, pack_grid(N * pt.PV * (pt.PV / 8)), dim3(256), 0, st, s, pt, t1,
-                           out);
+                           out, ld);
     else if (s.d.no <= 8)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
     else if (s.d.no <= 16)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
     else
-        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
     CK_CHECK(hipGetLastError());
 }
 

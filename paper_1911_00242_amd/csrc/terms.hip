@@ -604,8 +604,8 @@ inline int dress_om(const Dims &d) {
     return d.no <= 8 ? 8 : d.no <= 16 ? 16 : d.no <= 32 ? 32 : 0;
 }
 
-template <bool SPLIT, int OM>
-__global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd *Vt, uint16_t *Vs) {
+template <int OM>
+__global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd *Vt) {
     __shared__ cd G1[DR_G1];
     __shared__ cd TA[DR_T1];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
@@ -650,17 +650,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd
                         acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
                     }
                 }
-                if (SPLIT) {
-                    uint16_t p0, p1, p2, p3;
-                    split2(acc.x, p0, p1);
-                    split2(acc.y, p2, p3);
-                    Vs[split_index(idx, 0)] = p0;
-                    Vs[split_index(idx, 1)] = p1;
-                    Vs[split_index(idx, 2)] = p2;
-                    Vs[split_index(idx, 3)] = p3;
-                } else {
-                    Vt[idx] = acc;
-                }
+                Vt[idx] = acc;
             }
         } else {
             for (int a = 0; a < nv; ++a) {
@@ -670,17 +660,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd
                     cfma(acc, tb[m * nv + b], g1b[(int64_t)m * v3 + (int64_t)a * vv + f]);
                     acc = csub(acc, cmul(ta[m * nv + a], g2b[(int64_t)m * v3 + (int64_t)b * vv + f]));
                 }
-                if (SPLIT) {
-                    uint16_t p0, p1, p2, p3;
-                    split2(acc.x, p0, p1);
-                    split2(acc.y, p2, p3);
-                    Vs[split_index(idx, 0)] = p0;
-                    Vs[split_index(idx, 1)] = p1;
-                    Vs[split_index(idx, 2)] = p2;
-                    Vs[split_index(idx, 3)] = p3;
-                } else {
-                    Vt[idx] = acc;
-                }
+                Vt[idx] = acc;
             }
         }
     }
@@ -1260,25 +1240,15 @@ void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
     }
 }
 
-template <bool SPLIT>
-static void dress_launch(const SysDev &s, const cd *t1, cd *Vt, uint16_t *Vs, hipStream_t st) {
+void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
     const dim3 grid = xcd_grid(N * N * N * nv);
     switch (dress_om(s.d)) {
-    case 8: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 8>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
-    case 16: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 16>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
-    case 32: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 32>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
-    default: hipLaunchKernelGGL((k_vvvv_dress_t<SPLIT, 0>), grid, dim3(256), 0, st, s, t1, Vt, Vs); break;
+    case 8: hipLaunchKernelGGL((k_vvvv_dress_t<8>), grid, dim3(256), 0, st, s, t1, Vt); break;
+    case 16: hipLaunchKernelGGL((k_vvvv_dress_t<16>), grid, dim3(256), 0, st, s, t1, Vt); break;
+    case 32: hipLaunchKernelGGL((k_vvvv_dress_t<32>), grid, dim3(256), 0, st, s, t1, Vt); break;
+    default: hipLaunchKernelGGL((k_vvvv_dress_t<0>), grid, dim3(256), 0, st, s, t1, Vt); break;
     }
-}
-
-void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
-    dress_launch<false>(s, t1, Vt, nullptr, st);
-    CK_CHECK(hipGetLastError());
-}
-
-void launch_vvvv_dress_split(const SysDev &s, const cd *t1, uint16_t *Vt, hipStream_t st) {
-    dress_launch<true>(s, t1, nullptr, Vt, st);
     CK_CHECK(hipGetLastError());
 }
 
