@@ -61,8 +61,8 @@ struct System {
     int64_t pl_t2 = 0;  // element count of the T2-shaped split operands, padded
     // the ladder products run on antisymmetric pairs (pack.hip): canonical pair lists per
     // group (host and device, int32), the packed products and their split operands
-    std::vector<int32_t> ptab;  // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v]
-    int PV = 0, PO = 0;
+    std::vector<int32_t> ptab;  // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v] | dblk
+    int PV = 0, PO = 0, ndblk = 0;
     int32_t *dptab = nullptr;
     Gemm gp[2];  // packed W_mnij product; both ladders as one packed product
     // packed split operands, rows PV + PO elements long:
@@ -102,7 +102,9 @@ struct System {
     }
     ck::PairTabs pairs() const {
         const int64_t N = d.N;
-        return ck::PairTabs{dptab, dptab + N * PV, dptab + N * (PV + PO), PV, PO};
+        const int64_t nv = d.nv;
+        return ck::PairTabs{dptab, dptab + N * PV, dptab + N * (PV + PO), dptab + N * (PV + PO) + N * N * nv * nv,
+                            PV, PO, ndblk};
     }
 };
 
@@ -187,7 +189,14 @@ void build_pair_tables(System &S) {
     if (S.PV == 0) S.PV = 16;
     if (S.PO == 0) S.PO = 16;
     const int64_t PV = S.PV, PO = S.PO;
+    std::vector<int32_t> dblk;
+    for (int64_t ka = 0; ka < N; ++ka)
+        for (int64_t kb = ka; kb < N; ++kb)
+            for (int64_t ke = 0; ke < N; ++ke)
+                if (ke <= kc(ka, kb, ke)) dblk.push_back((int32_t)((ka * N + kb) * N + ke));
+    S.ndblk = (int)dblk.size();
     S.ptab.assign(N * PV + N * PO + N * N * vv, -1);
+    S.ptab.insert(S.ptab.end(), dblk.begin(), dblk.end());
     int32_t *vlist = S.ptab.data(), *olist = vlist + N * PV, *vpos = olist + N * PO;
     for (int64_t K = 0; K < N; ++K) {
         for (size_t p = 0; p < vl[K].size(); ++p) {

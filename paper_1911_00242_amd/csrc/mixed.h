@@ -43,10 +43,12 @@ __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
 // Canonical pairs of each group of total pair momentum K (pack.hip): vlist[K*PV + p] =
 // (kx*nv + x)*nv + y for the p-th canonical virtual pair of group K, -1 in the padding;
 // olist likewise for occupied pairs (PO); vpos[(K*N + kx)*nv*nv + x*nv + y] = p, or -1
-// when (kx, x, y) is not canonical.  PV and PO are multiples of 16.
+// when (kx, x, y) is not canonical.  PV and PO are multiples of 16.  dblk lists the ndblk
+// momentum blocks (ka*N + kb)*N + ke with ka <= kb and ke <= kf, the only ones holding
+// canonical (a,b) and (e,f) pairs.
 struct PairTabs {
-    const int32_t *vlist, *olist, *vpos;
-    int PV, PO;
+    const int32_t *vlist, *olist, *vpos, *dblk;
+    int PV, PO, ndblk;
 };
 
 // Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element

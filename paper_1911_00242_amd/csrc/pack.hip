@@ -109,7 +109,8 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // (ka, a, b) = p' and (ke, e, f) = p.  The same workgroup layout as the full dressing (one
 // workgroup per (ka, kb, ke, e), a thread per (b, f) running over a, <m kb, a ka||e f> in
 // LDS, <m ka, b kb||e f> over m in registers), restricted to the blocks and elements that
-// are canonical in both pairs: a quarter of the reads and writes of the full copy.
+// are canonical in both pairs: a quarter of the reads and writes of the full copy.  The
+// grid covers only those blocks (pt.dblk), so the work is spread evenly over the XCDs.
 // For n_occ <= OM, o v^2 <= 2048.
 template <int OM>
 __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
@@ -118,16 +119,14 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
     __shared__ cd TA[OM * 64];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
-    const int64_t nblk = (int64_t)N * N * N * nv;
+    const int64_t nblk = (int64_t)pt.ndblk * nv;
     const int64_t per = (nblk + 7) / 8;
     const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (L >= nblk) return;
     const int e = (int)(L % nv);
-    const int64_t blk = L / nv;
+    const int64_t blk = pt.dblk[L / nv];
     const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
-    const int kf = kcv(s.kc, N, ka, kb, ke), K = kcv(s.kc, N, ka, kb, 0);
-    // only blocks holding canonical (a, b) and (e, f) pairs
-    if (ka > kb || ke > kf) return;
+    const int K = kcv(s.kc, N, ka, kb, 0);
     const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
     const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
     const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
@@ -235,7 +234,7 @@ void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, cons
 void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
                             hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
-    const int64_t n = N * N * N * nv;
+    const int64_t n = (int64_t)pt.ndblk * nv;
     const dim3 grid((unsigned)((n + 7) / 8 * 8));
     if (!dress_pack_ok(s.d))
         hipLaunchKernelGGL(k_vvvv_dress_pack_plain, pack_grid(N * pt.PV * (pt.PV / 8)), dim3(256), 0, st, s, pt, t1,

@@ -480,45 +480,59 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
 // Fvv[k](a,e) = f_ae - 1/2 f_me t_m^a + sum_{km} t_m^f <a k,m km||e k,f km> + sum_km Pvv
 // and the combinations used by the T2 equation:
 // Fvt[k](b,f) = Fvv(b,f) - 1/2 t_r^b Fov(r,f),  Fot[k](n,j) = Foo(n,j) + 1/2 t_j^c Fov(n,c)
-__global__ void k_foo_fvv(SysDev s, const cd *t1, const cd *Fov, const cd *Poo, const cd *Pvv,
-                          cd *Foo, cd *Fvv) {
+// One 64-lane wave per output element: the N_k-long sums over the extra momentum and the
+// N_k^2 per-block partial sums are spread over the lanes and combined by a wave reduction.
+__device__ inline cd wave_sum(cd v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd *Fov, const cd *Poo,
+                                                const cd *Pvv, cd *Foo, cd *Fvv) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
-    const int64_t noo = (int64_t)N * no * no, nvv = (int64_t)N * nv * nv;
-    GRID_STRIDE(idx, noo + nvv) {
-        if (idx < noo) {
-            int i = (int)(idx % no), m = (int)((idx / no) % no), k = (int)(idx / ((int64_t)no * no));
+    const int64_t noo = (int64_t)N * no * no;
+    const int64_t idx = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int ov = no * nv;
+    cd acc = make_double2(0.0, 0.0);
+    if (idx < noo) {
+        const int i = (int)(idx % no), m = (int)((idx / no) % no), k = (int)(idx / ((int64_t)no * no));
+        // sum_{kn, n, e} t_{n kn}^{e kn} <m k, n kn || i k, e kn>
+        for (int u = lane; u < N * ov; u += 64) {
+            const int kn = u / ov, nn = (u / nv) % no, e = u % nv;
+            const cd *g = s.ooov + blk3(N, k, kn, k) * ((int64_t)no * no * no * nv);
+            cfma(acc, t1[((int64_t)kn * no + nn) * nv + e], g[(((int64_t)m * no + nn) * no + i) * nv + e]);
+        }
+        for (int u = lane; u < N * N; u += 64) acc = cadd(acc, Poo[(((int64_t)k * N * N + u) * no + m) * no + i]);
+        acc = wave_sum(acc);
+        if (lane == 0) {
             const cd *fk = s.fock + (int64_t)k * n * n;
-            cd acc = fk[m * n + i];
             cd h = make_double2(0.0, 0.0);
             for (int c = 0; c < nv; ++c) cfma(h, fk[m * n + no + c], t1[((int64_t)k * no + i) * nv + c]);
-            acc = cadd(acc, cscale(h, 0.5));
-            for (int kn = 0; kn < N; ++kn) {
-                const cd *g = s.ooov + blk3(N, k, kn, k) * ((int64_t)no * no * no * nv);
-                for (int nn = 0; nn < no; ++nn)
-                    for (int e = 0; e < nv; ++e)
-                        cfma(acc, t1[((int64_t)kn * no + nn) * nv + e], g[(((int64_t)m * no + nn) * no + i) * nv + e]);
-            }
-            for (int kk = 0; kk < N * N; ++kk) acc = cadd(acc, Poo[(((int64_t)k * N * N + kk) * no + m) * no + i]);
-            Foo[idx] = acc;
-        } else {
-            int64_t r = idx - noo;
-            int e = (int)(r % nv), a = (int)((r / nv) % nv), k = (int)(r / ((int64_t)nv * nv));
+            Foo[idx] = cadd(cadd(fk[m * n + i], cscale(h, 0.5)), acc);
+        }
+    } else {
+        const int64_t r = idx - noo;
+        const int e = (int)(r % nv), a = (int)((r / nv) % nv), k = (int)(r / ((int64_t)nv * nv));
+        // sum_{km, m, f} t_{m km}^{f km} <a k, m km || e k, f km>, the integral read as
+        // -<m km, a k || e k, f km> (ovvv block [km,k,k])
+        for (int u = lane; u < N * ov; u += 64) {
+            const int km = u / ov, m = (u / nv) % no, f = u % nv;
+            const cd *g = s.ovvv + blk3(N, km, k, k) * ((int64_t)no * nv * nv * nv);
+            cfma(acc, t1[((int64_t)km * no + m) * nv + f], g[(((int64_t)m * nv + a) * nv + e) * nv + f]);
+        }
+        acc = make_double2(-acc.x, -acc.y);
+        for (int u = lane; u < N * N; u += 64) acc = cadd(acc, Pvv[(((int64_t)k * N * N + u) * nv + a) * nv + e]);
+        acc = wave_sum(acc);
+        if (lane == 0) {
             const cd *fk = s.fock + (int64_t)k * n * n;
-            cd acc = fk[(no + a) * n + no + e];
             cd h = make_double2(0.0, 0.0);
             for (int m = 0; m < no; ++m) cfma(h, fk[m * n + no + e], t1[((int64_t)k * no + m) * nv + a]);
-            acc = csub(acc, cscale(h, 0.5));
-            for (int km = 0; km < N; ++km) {
-                // <a k, m km || e k, f km> = -<m km, a k || e k, f km>  (ovvv block [km,k,k])
-                const cd *g = s.ovvv + blk3(N, km, k, k) * ((int64_t)no * nv * nv * nv);
-                cd u = make_double2(0.0, 0.0);
-                for (int m = 0; m < no; ++m)
-                    for (int f = 0; f < nv; ++f)
-                        cfma(u, t1[((int64_t)km * no + m) * nv + f], g[(((int64_t)m * nv + a) * nv + e) * nv + f]);
-                acc = csub(acc, u);
-            }
-            for (int kk = 0; kk < N * N; ++kk) acc = cadd(acc, Pvv[(((int64_t)k * N * N + kk) * nv + a) * nv + e]);
-            Fvv[r] = acc;
+            Fvv[r] = cadd(csub(fk[(no + a) * n + no + e], cscale(h, 0.5)), acc);
         }
     }
 }
@@ -1099,15 +1113,6 @@ __global__ void k_r1_partial(SysDev s, const cd *t2, cd *P1) {
 // the N_k^2 partial sums are spread over the lanes (consecutive lanes read consecutive
 // elements) and combined by a wave reduction, so the kernel is not limited by a few
 // hundred threads each running the whole sum.
-__device__ inline cd wave_sum(cd v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        v.x += __shfl_xor(v.x, o, 64);
-        v.y += __shfl_xor(v.y, o, 64);
-    }
-    return v;
-}
-
 __global__ __launch_bounds__(64) void k_r1_wave(SysDev s, const cd *t1, const cd *t2, const cd *Foo, const cd *Fvv,
                                                 const cd *Fov, const cd *P1, int nparts, cd *r1) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
@@ -1174,7 +1179,9 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
         LAUNCH(k_foo_partial, N * N * N * no * no, s, t1, t2, w.Poo);
         LAUNCH(k_fvv_partial, N * N * N * nv * nv, s, t1, t2, w.Pvv);
     }
-    LAUNCH(k_foo_fvv, N * no * no + N * nv * nv, s, t1, w.Fov, w.Poo, w.Pvv, w.Foo, w.Fvv);
+    hipLaunchKernelGGL(k_foo_fvv, dim3((unsigned)(N * no * no + N * nv * nv)), dim3(64), 0, st, s, t1, w.Fov, w.Poo,
+                       w.Pvv, w.Foo, w.Fvv);
+    CK_CHECK(hipGetLastError());
     LAUNCH(k_ftilde, N * no * no + N * nv * nv, s.d, t1, w.Foo, w.Fvv, w.Fov, w.Fot, w.Fvt);
 }
 
