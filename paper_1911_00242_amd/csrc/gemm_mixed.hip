@@ -114,19 +114,19 @@ __device__ __forceinline__ bf16x8 negate_bf16x8(bf16x8 a) {
 // Tile: 128 x 128 complex outputs per 256-thread workgroup; wave (wm, wn) owns the 64 x 64
 // quadrant, i.e. 2 x 2 MFMA tiles (i, j) of 32 x 32, with fragments a_i (its rows) and b_j
 // (its columns).  One k stage of 16 complex values is software pipelined so that the
-// MFMA pipe of each wave never waits on memory:
-//   tile (0,0): a_0 b_0, meanwhile LDS reads of a_1, b_1 and the global loads of stage
-//               k+2 into one set of staging registers;
-//   tile (0,1): a_0 b_1, meanwhile the LDS writes of stage k+1 (loaded one stage ago,
-//               other staging set) into the other LDS buffer;
+// MFMA pipe of each wave never waits on memory; all four fragments of a stage are in
+// registers when it starts (read during the previous stage), and its 48 MFMAs run
+// round robin over the four tiles, so eight accumulator chains are in flight:
+//   first half: the global loads of stage k+2 into one set of staging registers, then
+//               the LDS writes of stage k+1 (loaded one stage ago, other set) into the
+//               other LDS buffer;
 //   barrier;
-//   tile (1,0): a_1 b_0, meanwhile LDS reads of a_0, b_0 of stage k+1;
-//   tile (1,1): a_1 b_1.
-// Every slot is one MFMA plus a few memory operations, fenced by sched_barrier so the
-// compiler keeps this order.  One barrier per stage suffices: the buffer written in tile
-// (0,1) of stage k was last read in tile (0,0) of stage k-1 and tile (1,0) of stage k-2,
-// both before the barrier of stage k-1, and it is first read in tile (1,0) of stage k,
-// after the barrier of stage k.
+//   second half: the LDS reads of all fragments of stage k+1 into the other register set.
+// Every slot is one MFMA plus at most one memory operation, fenced by sched_barrier so
+// the compiler keeps this order.  One barrier per stage suffices: the buffer written in
+// the first half of stage k was last read in the second half of stage k-2, before the
+// barrier of stage k-1, and it is read in the second half of stage k, after the barrier
+// of stage k.
 template <bool FAST>
 __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
     constexpr int BM = 128, BN = 128, BK = 16;
@@ -178,9 +178,8 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         c00r[r] = c00i[r] = c01r[r] = c01i[r] = 0.f;
         c10r[r] = c10i[r] = c11r[r] = c11i[r] = 0.f;
     }
-    bf16x8 A0[2][4], B0[2][4];  // a_0, b_0 of the current stage [parity], of the next [!parity]
-    bf16x8 A1[4], B1[4];        // a_1, b_1 of the current stage
-    bf16x8 NA0[2], NA1[2];
+    bf16x8 FA[2][2][4], FB[2][2][4];  // [set][fragment row i / column j][plane]: current, next stage
+    bf16x8 NA[2][2];                   // -A_im of the current set, per fragment row
     u32x4 sa[2][4], sb[2][4];   // staging sets: this thread's pieces of A and B of one stage
     int64_t ak_cur = 0, bk_cur = 0, ak_nxt = 0, bk_nxt = 0;
     // FAST implies K % 8 == 0 and K >= 8: clamp to the last whole 8-run so a 16-byte load
@@ -230,73 +229,64 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 #define CK_RDA(dst, buf, off, p) dst = *(const bf16x8 *)(&As[buf][(off) + (p) * 8])
 #define CK_RDB(dst, buf, off, p) dst = *(const bf16x8 *)(&Bs[buf][(off) + (p) * 8])
 
-    // one pipelined stage KT held in LDS buffer BUF (literal 0 or 1); staging set BUF
-    // receives stage KT+2, set BUF^1 holds stage KT+1
-#define CK_STAGE(KT, BUF)                                                                              \
-    {                                                                                                  \
-        CK_NEG(A0[BUF], NA0);                                                                       \
-        /* tile (0,0) */                                                                               \
-        CK_MF(0, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[0], BUF, fb1, 0); CK_SLOT;          \
-        CK_MF(1, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[1], BUF, fb1, 1); CK_SLOT;          \
-        CK_MF(2, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[2], BUF, fb1, 2); CK_SLOT;          \
-        CK_MF(3, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDB(B1[3], BUF, fb1, 3); CK_SLOT;          \
-        CK_MF(4, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[0], BUF, fa1, 0); CK_SLOT;          \
-        CK_MF(5, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[1], BUF, fa1, 1); CK_SLOT;          \
-        CK_MF(6, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[2], BUF, fa1, 2); CK_SLOT;          \
-        CK_MF(7, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_RDA(A1[3], BUF, fa1, 3); CK_SLOT;          \
-        CK_MF(8, c00r, c00i, A0[BUF], NA0, B0[BUF]); CK_KOFS(((KT) + 3) * BK, ak_nxt, bk_nxt); CK_SLOT; \
-        CK_MF(9, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                               \
-        CK_LOADA(((KT) + 2) * BK, BUF, 0); CK_LOADA(((KT) + 2) * BK, BUF, 1); CK_SLOT;           \
-        CK_MF(10, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                              \
-        CK_LOADA(((KT) + 2) * BK, BUF, 2); CK_LOADA(((KT) + 2) * BK, BUF, 3);                    \
-        CK_LOADB(((KT) + 2) * BK, BUF, 0); CK_SLOT;                                                 \
-        CK_MF(11, c00r, c00i, A0[BUF], NA0, B0[BUF]);                                              \
-        CK_LOADB(((KT) + 2) * BK, BUF, 1); CK_LOADB(((KT) + 2) * BK, BUF, 2);                    \
-        CK_LOADB(((KT) + 2) * BK, BUF, 3); CK_SLOT;                                                 \
-        /* tile (0,1) */                                                                               \
-        CK_MF(0, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;    \
-        CK_MF(1, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;    \
-        CK_MF(2, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;    \
-        CK_MF(3, c01r, c01i, A0[BUF], NA0, B1); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;    \
-        CK_MF(4, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;    \
-        CK_MF(5, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;    \
-        CK_MF(6, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;    \
-        CK_MF(7, c01r, c01i, A0[BUF], NA0, B1); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;    \
-        CK_MF(8, c01r, c01i, A0[BUF], NA0, B1); CK_NEG(A1, NA1); CK_SLOT;                       \
-        CK_MF(9, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                           \
-        CK_MF(10, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                          \
-        CK_MF(11, c01r, c01i, A0[BUF], NA0, B1); CK_SLOT;                                          \
-        __syncthreads();                                                                               \
-        CK_SLOT;                                                                                       \
-        /* tile (1,0) */                                                                               \
-        CK_MF(0, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][0], (BUF) ^ 1, fa0, 0); CK_SLOT; \
-        CK_MF(1, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][0], (BUF) ^ 1, fb0, 0); CK_SLOT; \
-        CK_MF(2, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][1], (BUF) ^ 1, fa0, 1); CK_SLOT; \
-        CK_MF(3, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][1], (BUF) ^ 1, fb0, 1); CK_SLOT; \
-        CK_MF(4, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][2], (BUF) ^ 1, fa0, 2); CK_SLOT; \
-        CK_MF(5, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][2], (BUF) ^ 1, fb0, 2); CK_SLOT; \
-        CK_MF(6, c10r, c10i, A1, NA1, B0[BUF]); CK_RDA(A0[(BUF) ^ 1][3], (BUF) ^ 1, fa0, 3); CK_SLOT; \
-        CK_MF(7, c10r, c10i, A1, NA1, B0[BUF]); CK_RDB(B0[(BUF) ^ 1][3], (BUF) ^ 1, fb0, 3); CK_SLOT; \
-        CK_MF(8, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                           \
-        CK_MF(9, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                           \
-        CK_MF(10, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                          \
-        CK_MF(11, c10r, c10i, A1, NA1, B0[BUF]); CK_SLOT;                                          \
-        /* tile (1,1) */                                                                               \
-        CK_MF(0, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(1, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(2, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(3, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(4, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(5, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(6, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(7, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(8, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(9, c11r, c11i, A1, NA1, B1);                                                         \
-        CK_MF(10, c11r, c11i, A1, NA1, B1);                                                        \
-        CK_MF(11, c11r, c11i, A1, NA1, B1);                                                        \
-        CK_SLOT;                                                                                       \
-        ak_cur = ak_nxt;                                                                               \
-        bk_cur = bk_nxt;                                                                               \
+    // one pipelined stage KT held in LDS buffer BUF (literal 0 or 1), its fragments in
+    // register set BUF; staging set BUF receives stage KT+2, set BUF^1 holds stage KT+1
+#define CK_STAGE(KT, BUF)                                                                                             \
+    {                                                                                                                 \
+        CK_NEG(FA[BUF][0], NA[0]);                                                                                    \
+        CK_NEG(FA[BUF][1], NA[1]);                                                                                    \
+        CK_MF(0, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_KOFS(((KT) + 3) * BK, ak_nxt, bk_nxt); CK_SLOT;       \
+        CK_MF(0, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADA(((KT) + 2) * BK, BUF, 0); CK_SLOT;              \
+        CK_MF(0, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADA(((KT) + 2) * BK, BUF, 1); CK_SLOT;              \
+        CK_MF(0, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADA(((KT) + 2) * BK, BUF, 2); CK_SLOT;              \
+        CK_MF(1, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADA(((KT) + 2) * BK, BUF, 3); CK_SLOT;              \
+        CK_MF(1, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADB(((KT) + 2) * BK, BUF, 0); CK_SLOT;              \
+        CK_MF(1, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADB(((KT) + 2) * BK, BUF, 1); CK_SLOT;              \
+        CK_MF(1, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADB(((KT) + 2) * BK, BUF, 2); CK_SLOT;              \
+        CK_MF(2, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADB(((KT) + 2) * BK, BUF, 3); CK_SLOT;              \
+        CK_MF(2, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                 \
+        CK_MF(2, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                 \
+        CK_MF(2, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                 \
+        CK_MF(3, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_SLOT;                                                 \
+        CK_MF(3, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                 \
+        CK_MF(3, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                 \
+        CK_MF(3, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;             \
+        CK_MF(4, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;             \
+        CK_MF(4, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;             \
+        CK_MF(4, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;             \
+        CK_MF(4, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;             \
+        CK_MF(5, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;             \
+        CK_MF(5, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;             \
+        CK_MF(5, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;             \
+        CK_MF(5, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                 \
+        __syncthreads();                                                                                              \
+        CK_SLOT;                                                                                                      \
+        CK_MF(6, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][0][0], (BUF) ^ 1, fa0, 0); CK_SLOT; \
+        CK_MF(6, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][0][0], (BUF) ^ 1, fb0, 0); CK_SLOT; \
+        CK_MF(6, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][1][0], (BUF) ^ 1, fa1, 0); CK_SLOT; \
+        CK_MF(6, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][1][0], (BUF) ^ 1, fb1, 0); CK_SLOT; \
+        CK_MF(7, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][0][1], (BUF) ^ 1, fa0, 1); CK_SLOT; \
+        CK_MF(7, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][0][1], (BUF) ^ 1, fb0, 1); CK_SLOT; \
+        CK_MF(7, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][1][1], (BUF) ^ 1, fa1, 1); CK_SLOT; \
+        CK_MF(7, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][1][1], (BUF) ^ 1, fb1, 1); CK_SLOT; \
+        CK_MF(8, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][0][2], (BUF) ^ 1, fa0, 2); CK_SLOT; \
+        CK_MF(8, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][0][2], (BUF) ^ 1, fb0, 2); CK_SLOT; \
+        CK_MF(8, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][1][2], (BUF) ^ 1, fa1, 2); CK_SLOT; \
+        CK_MF(8, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][1][2], (BUF) ^ 1, fb1, 2); CK_SLOT; \
+        CK_MF(9, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][0][3], (BUF) ^ 1, fa0, 3); CK_SLOT; \
+        CK_MF(9, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][0][3], (BUF) ^ 1, fb0, 3); CK_SLOT; \
+        CK_MF(9, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_RDA(FA[(BUF) ^ 1][1][3], (BUF) ^ 1, fa1, 3); CK_SLOT; \
+        CK_MF(9, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_RDB(FB[(BUF) ^ 1][1][3], (BUF) ^ 1, fb1, 3); CK_SLOT; \
+        CK_MF(10, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_SLOT;                                                \
+        CK_MF(10, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                \
+        CK_MF(10, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                \
+        CK_MF(10, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                \
+        CK_MF(11, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_SLOT;                                                \
+        CK_MF(11, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                \
+        CK_MF(11, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                \
+        CK_MF(11, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                \
+        ak_cur = ak_nxt;                                                                                              \
+        bk_cur = bk_nxt;                                                                                              \
     }
 
     const int nk = (K + BK - 1) / BK;
@@ -315,8 +305,10 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         __syncthreads();
         // (constant indices only: a loop index here would let the compiler move the
         // register arrays to LDS)
-        CK_RDA(A0[0][0], 0, fa0, 0); CK_RDA(A0[0][1], 0, fa0, 1); CK_RDA(A0[0][2], 0, fa0, 2); CK_RDA(A0[0][3], 0, fa0, 3);
-        CK_RDB(B0[0][0], 0, fb0, 0); CK_RDB(B0[0][1], 0, fb0, 1); CK_RDB(B0[0][2], 0, fb0, 2); CK_RDB(B0[0][3], 0, fb0, 3);
+        CK_RDA(FA[0][0][0], 0, fa0, 0); CK_RDA(FA[0][0][1], 0, fa0, 1); CK_RDA(FA[0][0][2], 0, fa0, 2); CK_RDA(FA[0][0][3], 0, fa0, 3);
+        CK_RDA(FA[0][1][0], 0, fa1, 0); CK_RDA(FA[0][1][1], 0, fa1, 1); CK_RDA(FA[0][1][2], 0, fa1, 2); CK_RDA(FA[0][1][3], 0, fa1, 3);
+        CK_RDB(FB[0][0][0], 0, fb0, 0); CK_RDB(FB[0][0][1], 0, fb0, 1); CK_RDB(FB[0][0][2], 0, fb0, 2); CK_RDB(FB[0][0][3], 0, fb0, 3);
+        CK_RDB(FB[0][1][0], 0, fb1, 0); CK_RDB(FB[0][1][1], 0, fb1, 1); CK_RDB(FB[0][1][2], 0, fb1, 2); CK_RDB(FB[0][1][3], 0, fb1, 3);
         // unrolled by two so that every register set has a fixed role in each half; one
         // exit, so the accumulators keep their registers across the halves
         int kt = 0;

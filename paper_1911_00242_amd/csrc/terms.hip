@@ -1008,9 +1008,21 @@ __global__ __launch_bounds__(2 * OM * VM) void k_xinit_rest_t(SysDev s, const cd
         qr[m] = m < no ? QS[(m * no + j) * nv + b] : make_double2(0.0, 0.0);
         fo[m] = m < no ? FO[m * no + j] : make_double2(0.0, 0.0);
     }
+    // Fvt[kb](b, f) over f, used for every a
+    cd fv[VM];
+#pragma unroll
+    for (int f = 0; f < VM; ++f) fv[f] = f < nv ? FV[f * nv + b] : make_double2(0.0, 0.0);
     cd *xb = X + blk * ov * ov + (int64_t)i * nv * ov + jb;
+    constexpr int AH = (VM + 1) / 2;  // a values per thread
     const int a0 = half * ((nv + 1) / 2), a1 = half ? nv : (nv + 1) / 2;
-    for (int a = a0; a < a1; ++a) {
+    // the X values this thread updates, loaded up front
+    cd xo[AH];
+#pragma unroll
+    for (int u = 0; u < AH; ++u) xo[u] = a0 + u < a1 ? xb[(int64_t)(a0 + u) * ov] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < AH; ++u) {
+        const int a = a0 + u;
+        if (a >= a1) continue;
         cd acc = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
 #pragma unroll
         for (int m = 0; m < OM; ++m)
@@ -1020,8 +1032,8 @@ __global__ __launch_bounds__(2 * OM * VM) void k_xinit_rest_t(SysDev s, const cd
             }
 #pragma unroll
         for (int f = 0; f < VM; ++f)
-            if (f < nv) cfma(w, T2S[(j * nv + a) * vp + f], FV[f * nv + b]);
-        cd x = xb[(int64_t)a * ov];
+            if (f < nv) cfma(w, T2S[(j * nv + a) * vp + f], fv[f]);
+        cd x = xo[u];
         x.x += -acc.x + 0.5 * (w.x - y.x);
         x.y += -acc.y + 0.5 * (w.y - y.y);
         xb[(int64_t)a * ov] = x;
