@@ -123,7 +123,7 @@ int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double 
  * M x N x K product each (complex elements).  product: 0 particle-particle ladder,
  * 1 hole-hole ladder, 2 W_mnij build, 3 W_mbej build, 4 ring product (the numbering of
  * ccsd_k_timing_get).  In the mixed path the three ladder-family products run on
- * canonical antisymmetric pairs (N and K, or N, of the full form roughly halved), so the
+ * canonical antisymmetric pairs (M, N and K of the full form each roughly halved), so the
  * executed shape is smaller than the algorithmic one counted by ccsd_k_flops, and the
  * hole-hole ladder runs inside the particle-particle product (its k pairs appended), so
  * product 1 reports a zero shape and product 0 the combined one.  Any output pointer may

@@ -61,14 +61,16 @@ struct System {
     int64_t pl_t2 = 0;  // element count of the T2-shaped split operands, padded
     // the ladder products run on antisymmetric pairs (pack.hip): canonical pair lists per
     // group (host and device, int32), the packed products and their split operands
-    std::vector<int32_t> ptab;  // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v] | dblk
-    int PV = 0, PO = 0, ndblk = 0;
+    // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v] | opos [N][N][o][o] | dblk | ablk
+    std::vector<int32_t> ptab;
+    int PV = 0, PO = 0, ndblk = 0, nablk = 0;
     int32_t *dptab = nullptr;
     Gemm gp[2];  // packed W_mnij product; both ladders as one packed product
     // packed split operands, rows PV + PO elements long:
-    //   pk_A [K][(ki,i,j)]: tau over canonical (ke,e,f) | W_mnij over canonical (km,m,n)
+    //   pk_A [K][canonical (ki,i,j)]: tau over canonical (ke,e,f) | W_mnij over canonical (km,m,n)
     //   pk_B [K][canonical (ka,a,b)]: dressed <ab||ef> over (ke,e,f) | tau over (km,m,n)
     uint16_t *pk_A = nullptr, *pk_B = nullptr, *pk_oovv = nullptr;
+    cd *Lp = nullptr;  // [K][canonical (ki,i,j)][canonical (ka,a,b)]: both ladders' contribution to R2
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -103,8 +105,10 @@ struct System {
     ck::PairTabs pairs() const {
         const int64_t N = d.N;
         const int64_t nv = d.nv;
-        return ck::PairTabs{dptab, dptab + N * PV, dptab + N * (PV + PO), dptab + N * (PV + PO) + N * N * nv * nv,
-                            PV, PO, ndblk};
+        const int64_t no = d.no;
+        const int32_t *vpos = dptab + N * (PV + PO), *opos = vpos + N * N * nv * nv;
+        const int32_t *dblk = opos + N * N * no * no;
+        return ck::PairTabs{dptab, dptab + N * PV, vpos, opos, dblk, dblk + ndblk, PV, PO, ndblk, nablk};
     }
 };
 
@@ -154,18 +158,19 @@ int kcons(const ck::Mesh &m, int kp, int kq, int kr) {
 // Canonical pairs of a group of total pair momentum K: (kx, x; ky, y), ky = K - kx, with
 // (kx, x) < (ky, y), listed by kx, x, y; every group padded to the same length (a multiple
 // of 16) so that the grouped products have one k extent.  Packed ladder products (mixed
-// path), each a quarter of its full form (antisymmetry, pack.hip):
-//   G1p: W_mnij += tau . <mn||ef>^T   rows (ki,i,j), cols canonical (km,m,n), k canonical (ke,e,f)
-//        (alpha 1 = 1/2 x 2 for the canonical k pairs); written split into the W_mnij part
-//        of pk_A
-//   G23p: r2 += tau . Vt^T + W_mnij . tauT   rows (ki,i,j), cols canonical (ka,a,b),
+// path), on canonical pairs in rows, columns and k alike (antisymmetry, pack.hip): an
+// eighth of the full form's work each.
+//   G1p: W_mnij += tau . <mn||ef>^T   rows canonical (ki,i,j), cols canonical (km,m,n),
+//        k canonical (ke,e,f) (alpha 1 = 1/2 x 2 for the canonical k pairs); written split
+//        into the W_mnij part of pk_A
+//   G23p: L = tau . Vt^T + W_mnij . tauT   rows canonical (ki,i,j), cols canonical (ka,a,b),
 //        k = canonical (ke,e,f) then canonical (km,m,n): both ladders as one product on
-//        the concatenated rows of pk_A and pk_B, whose epilogue writes the (a,b) column
-//        and its partner (b,a) with the opposite sign.
+//        the concatenated rows of pk_A and pk_B, written (beta 0) to the packed Lp; the
+//        assembly of R2 expands it to all four orientations of the two pairs.
 void build_tables(System &S);
 void build_pair_tables(System &S) {
     const int64_t N = S.d.N, o = S.d.no, v = S.d.nv;
-    const int64_t oo = o * o, vv = v * v, t2b = oo * vv, o4 = oo * oo, M = N * oo;
+    const int64_t oo = o * o, vv = v * v, o4 = oo * oo;
     auto kc = [&](int64_t a, int64_t b, int64_t c) { return (int64_t)S.kc[(a * N + b) * N + c]; };
     auto list = [&](int64_t K, int64_t w, std::vector<int32_t> &out) {
         out.clear();
@@ -195,16 +200,29 @@ void build_pair_tables(System &S) {
             for (int64_t ke = 0; ke < N; ++ke)
                 if (ke <= kc(ka, kb, ke)) dblk.push_back((int32_t)((ka * N + kb) * N + ke));
     S.ndblk = (int)dblk.size();
-    S.ptab.assign(N * PV + N * PO + N * N * vv, -1);
+    // R2 blocks (ki, kj, ka) that represent their orbit under (ki <-> kj) and (ka <-> kb):
+    // ki <= kj and ka <= kb (the assembly writes the other members)
+    std::vector<int32_t> ablk;
+    for (int64_t ki = 0; ki < N; ++ki)
+        for (int64_t kj = ki; kj < N; ++kj)
+            for (int64_t ka = 0; ka < N; ++ka)
+                if (ka <= kc(ki, kj, ka)) ablk.push_back((int32_t)((ki * N + kj) * N + ka));
+    S.nablk = (int)ablk.size();
+    S.ptab.assign(N * PV + N * PO + N * N * vv + N * N * oo, -1);
     S.ptab.insert(S.ptab.end(), dblk.begin(), dblk.end());
-    int32_t *vlist = S.ptab.data(), *olist = vlist + N * PV, *vpos = olist + N * PO;
+    S.ptab.insert(S.ptab.end(), ablk.begin(), ablk.end());
+    int32_t *vlist = S.ptab.data(), *olist = vlist + N * PV, *vpos = olist + N * PO, *opos = vpos + N * N * vv;
     for (int64_t K = 0; K < N; ++K) {
         for (size_t p = 0; p < vl[K].size(); ++p) {
             vlist[K * PV + p] = vl[K][p];
             const int64_t kx = vl[K][p] / vv, xy = vl[K][p] % vv;
             vpos[(K * N + kx) * vv + xy] = (int32_t)p;
         }
-        for (size_t p = 0; p < ol[K].size(); ++p) olist[K * PO + p] = ol[K][p];
+        for (size_t p = 0; p < ol[K].size(); ++p) {
+            olist[K * PO + p] = ol[K][p];
+            const int64_t kx = ol[K][p] / oo, xy = ol[K][p] % oo;
+            opos[(K * N + kx) * oo + xy] = (int32_t)p;
+        }
     }
     std::vector<int64_t> &T = S.tables;
     auto put = [&](Gemm &g, int which, int64_t len, auto fn) {
@@ -213,55 +231,38 @@ void build_pair_tables(System &S) {
     };
     Gemm &g1 = S.gp[0], &g2 = S.gp[1];
     const int64_t R = PV + PO;  // row length of pk_A and pk_B
-    // c_row of W_mnij and r2 for row (ki,i,j) of group K
-    auto row_t2 = [&](int64_t K, int64_t x) {
-        int64_t ki = x / oo, ij = x % oo;
-        return ((ki * N + kc(K, 0, ki)) * N) * t2b + ij * vv;
-    };
-    auto row_wt = [&](int64_t K, int64_t x) {
-        int64_t ki = x / oo, ij = x % oo;
+    // W_mnij row of canonical (ki,i,j) = pr of group K, -1 for the padding (no output)
+    auto row_wt = [&](int64_t K, int32_t pr) {
+        if (pr < 0) return (int64_t)-1;
+        int64_t ki = pr / oo, ij = pr % oo;
         return ((ki * N + kc(K, 0, ki)) * N) * o4 + ij * oo;
     };
     // G1p
-    put(g1, 0, N * M, [&](int64_t x) { return x * R; });  // tau part of pk_A
+    put(g1, 0, N * PO, [&](int64_t x) { return x * R; });  // tau part of pk_A
     put(g1, 1, N * PV, [&](int64_t x) { return x % PV; });
     put(g1, 2, N * PO, [&](int64_t x) { return x * PV; });  // oovv_pk rows
     g1.tab[3] = g1.tab[1];
-    put(g1, 4, N * M, [&](int64_t x) { return row_wt(x / M, x % M); });
+    put(g1, 4, N * PO, [&](int64_t x) { return row_wt(x / PO, olist[x]); });
     put(g1, 5, N * PO, [&](int64_t x) {  // W_mnij column of canonical (km,m,n), -1 in the padding
         const int32_t pr = olist[x];
         if (pr < 0) return (int64_t)-1;
         return (int64_t)(pr / oo) * o4 + pr % oo;
     });
     g1.cs_row = T.size();  // W_mnij part of pk_A
-    for (int64_t x = 0; x < N * M; ++x) T.push_back(x * R + PV);
+    for (int64_t x = 0; x < N * PO; ++x) T.push_back(x * R + PV);
     g1.cs_col = T.size();
     for (int64_t x = 0; x < N * PO; ++x) T.push_back(x % PO);
-    g1.op.G = (int)N; g1.op.M = (int)M; g1.op.N = (int)PO; g1.op.K = (int)PV;
+    g1.op.G = (int)N; g1.op.M = (int)PO; g1.op.N = (int)PO; g1.op.K = (int)PV;
     g1.op.alpha = 1.0; g1.op.beta = 1.0; g1.stage = ST_WMN;
     // G23p
     g2.tab[0] = g1.tab[0];
     put(g2, 1, N * R, [&](int64_t x) { return x % R; });
     put(g2, 2, N * PV, [&](int64_t x) { return x * R; });  // pk_B rows
     g2.tab[3] = g2.tab[1];
-    put(g2, 4, N * M, [&](int64_t x) { return row_t2(x / M, x % M); });
-    put(g2, 5, N * PV, [&](int64_t x) {  // r2 column (ka,a,b)
-        const int32_t pr = vlist[x];
-        if (pr < 0) return (int64_t)-1;
-        return (int64_t)(pr / vv) * t2b + pr % vv;
-    });
-    g2.c_col2 = T.size();
-    for (int64_t x = 0; x < N * PV; ++x) {  // its partner (kb,b,a)
-        const int32_t pr = vlist[x];
-        if (pr < 0) {
-            T.push_back(-1);
-            continue;
-        }
-        const int64_t K = x / PV, ka = pr / vv, a = (pr / v) % v, b = pr % v;
-        T.push_back(kc(K, 0, ka) * t2b + b * v + a);
-    }
-    g2.op.G = (int)N; g2.op.M = (int)M; g2.op.N = (int)PV; g2.op.K = (int)R;
-    g2.op.alpha = 1.0; g2.op.beta = 1.0; g2.stage = ST_PP;
+    put(g2, 4, N * PO, [&](int64_t x) { return olist[x] < 0 ? (int64_t)-1 : x * PV; });  // Lp rows
+    put(g2, 5, N * PV, [&](int64_t x) { return vlist[x] < 0 ? (int64_t)-1 : x % PV; });
+    g2.op.G = (int)N; g2.op.M = (int)PO; g2.op.N = (int)PV; g2.op.K = (int)R;
+    g2.op.alpha = 1.0; g2.op.beta = 0.0; g2.stage = ST_PP;
 }
 
 // Offsets in complex elements.  Group label: total pair momentum K for the ladder
@@ -395,13 +396,14 @@ void carve(System &S, Carver &c) {
     } else {
         // split storage: 4 bf16 per element
         S.pl_t2 = (S.n2() + 63) / 64 * 64;
-        const int64_t M = N * o * o, PV = S.PV, PO = S.PO;
+        const int64_t PV = S.PV, PO = S.PO;
         c.take(S.sp_t2, 4 * S.pl_t2);
         c.take(S.sp_WR, 4 * S.pl_t2);
         c.take(S.sp_oovv, 4 * S.pl_t2);
-        c.take(S.pk_A, 4 * N * M * (PV + PO));
+        c.take(S.pk_A, 4 * N * PO * (PV + PO));
         c.take(S.pk_B, 4 * N * PV * (PV + PO));
         c.take(S.pk_oovv, 4 * N * PO * PV);
+        c.take(S.Lp, N * PO * PV);
         c.take(S.dptab, (int64_t)S.ptab.size());
     }
     c.take(S.WT, N3 * cls[0]);
@@ -422,7 +424,7 @@ void carve(System &S, Carver &c) {
     c.take(S.zeros, 16);
     c.take(S.eo, N * o);
     c.take(S.ev, N * v);
-    c.take(S.red, 16 * ck::RED_BLOCKS);
+    c.take(S.red, 16 * (int64_t)ck::UPD_BLOCKS);
     c.take(S.redout, 32);
     c.take(S.dkc, N3);
     c.take(S.dtab, (int64_t)S.tables.size());
@@ -490,7 +492,7 @@ void bind_ops(System &S) {
         s.A = SA[i];
         s.B = SB[i];
         s.zeros = reinterpret_cast<const uint16_t *>(S.zeros);
-        s.C = C[i];  // same FP64 outputs as the full forms
+        s.C = i == 1 || i == 2 ? S.Lp : C[i];  // the ladders write the packed Lp
         s.Cs = CS[i];
         s.a_row = T + g.tab[0]; s.a_k = T + g.tab[1]; s.b_col = T + g.tab[2]; s.b_k = T + g.tab[3];
         s.c_row = T + g.tab[4]; s.c_col = T + g.tab[5];
@@ -561,9 +563,14 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
     run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>  (mixed: written split)
     run_gemm(c, S, 4);  // X += t2 W_mbej
-    ck::launch_assemble_r2(s, S.X, S.r2(), st);
-    run_gemm(c, S, 1);  // particle-particle ladder (mixed: both ladders)
-    if (!S.mixed) run_gemm(c, S, 2);  // hole-hole ladder
+    if (!S.mixed) {
+        ck::launch_assemble_r2(s, S.X, S.r2(), st);
+        run_gemm(c, S, 1);  // particle-particle ladder
+        run_gemm(c, S, 2);  // hole-hole ladder
+    } else {
+        run_gemm(c, S, 1);  // both ladders on canonical pairs, into Lp
+        ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2(), st);
+    }
     ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     stage_end(c, all);
 }
@@ -715,8 +722,8 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                                         ctx->stream));
                 // the padding of the packed W_mnij and dressed <ab||ef> is never written by their
                 // producers and must read as zero
-                const int64_t R = S.PV + S.PO, M = (int64_t)S.d.N * S.d.no * S.d.no;
-                CK_CHECK(hipMemsetAsync(S.pk_A, 0, 4 * S.d.N * M * R * sizeof(uint16_t), ctx->stream));
+                const int64_t R = S.PV + S.PO;
+                CK_CHECK(hipMemsetAsync(S.pk_A, 0, 4 * S.d.N * (int64_t)S.PO * R * sizeof(uint16_t), ctx->stream));
                 CK_CHECK(hipMemsetAsync(S.pk_B, 0, 4 * S.d.N * (int64_t)S.PV * R * sizeof(uint16_t), ctx->stream));
             }
             bind_ops(S);
@@ -837,12 +844,11 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 }
                 int slot = S->diis_head;
                 cd *err = S->derr[slot];
-                ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), err, err + S->n1(), ctx->stream);
-                ck::launch_copy(S->n1() + S->n2(), S->amp, S->dvec[slot], ctx->stream);
                 int held = std::min(S->diis_n + 1, m);
                 std::vector<const cd *> ys(held);
                 for (int j = 0; j < held; ++j) ys[j] = S->derr[j];
-                ck::launch_dots(S->n1() + S->n2(), err, ys.data(), held, S->red, S->redout, ctx->stream);
+                ck::launch_update_diis(sd, S->amp, S->res, err, S->dvec[slot], ys.data(), held, slot, S->red,
+                                       S->redout, ctx->stream);
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             for (System *S : upd) {

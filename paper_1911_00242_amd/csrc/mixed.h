@@ -47,8 +47,8 @@ __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
 // momentum blocks (ka*N + kb)*N + ke with ka <= kb and ke <= kf, the only ones holding
 // canonical (a,b) and (e,f) pairs.
 struct PairTabs {
-    const int32_t *vlist, *olist, *vpos, *dblk;
-    int PV, PO, ndblk;
+    const int32_t *vlist, *olist, *vpos, *opos, *dblk, *ablk;
+    int PV, PO, ndblk, nablk;
 };
 
 // Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element
@@ -83,6 +83,9 @@ void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const
                      uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st);
 void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
                       hipStream_t st);
+// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2,
+                             hipStream_t st);
 void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
                             hipStream_t st);
 

@@ -15,25 +15,27 @@
 
 namespace ck {
 
-// tau_pk[K][(ki,i,j)][p] = tau_{i ki, j kj}^{e ke, f kf} for canonical pair p = (ke, e, f)
-// of group K (rows ld elements apart): a thread per 8 consecutive p of one row, one
-// 64-byte chunk.
+// tau_pk[K][p'][p] = tau_{i ki, j kj}^{e ke, f kf} for canonical (ki, i, j) = p' and canonical
+// (ke, e, f) = p of group K (rows ld elements apart; the padding rows are written as zeros):
+// a thread per 8 consecutive p of one row, one 64-byte chunk.
 __global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out,
                            int64_t ld) {
-    const int N = d.N, no = d.no, nv = d.nv, M = N * no * no;
+    const int N = d.N, no = d.no, nv = d.nv;
     const int nch = pt.PV / 8;
-    const int64_t total = (int64_t)N * M * nch;
+    const int64_t total = (int64_t)N * pt.PO * nch;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(x % nch);
-        const int64_t row = x / nch;  // K * M + m
-        const int K = (int)(row / M), m = (int)(row % M);
-        const int ki = m / (no * no), i = (m / no) % no, j = m % no;
+        const int64_t row = x / nch;  // K * PO + p'
+        const int K = (int)(row / pt.PO);
+        const int pij = pt.olist[row];
+        const int pq = pij < 0 ? 0 : pij;  // a padding row decodes as pair 0 and writes zeros
+        const int ki = pq / (no * no), i = (pq / no) % no, j = pq % no;
         const int kj = kcv(kc, N, K, 0, ki);
         cd v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int pr = pt.vlist[(int64_t)K * pt.PV + c * 8 + q];
-            if (pr < 0) {
+            if (pr < 0 || pij < 0) {
                 v[q] = make_double2(0.0, 0.0);
                 continue;
             }
@@ -215,8 +217,8 @@ bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv * 
 
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
                      uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st) {
-    const int64_t N = d.N, M = (int64_t)N * d.no * d.no;
-    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * M * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk,
+    const int64_t N = d.N;
+    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * pt.PO * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk,
                        ld_tau);
     CK_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_tauT_pack, pack_grid(N * pt.PV * (pt.PO / 8)), dim3(256), 0, st, d, kc, pt, t1, t2,
@@ -245,6 +247,116 @@ void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, u
         hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
     else
         hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
+    CK_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ R2 assembly
+// r2 = <ab||ij>* + P(ij)P(ab) X + L, with L the ladders' packed result Lp[K][p'][p]
+// (canonical (ki, i, j) = p', canonical (ka, a, b) = p) expanded by antisymmetry:
+// L(ij, ab) = s_ij s_ab Lp[canonical ij][canonical ab], s = -1 for a pair in the
+// non-canonical order, 0 for a pair of two equal members.
+//
+// The four R2 blocks B1 = (ki, kj, ka; i, j), B2 = (kj, ki, ka; j, i), B3 = (ki, kj, kb; i, j)
+// and B4 = (kj, ki, kb; j, i) use the same four v x v slabs of X,
+//   Xa = X(ki, kj, ka; i, j), Xb = X(kj, ki, ka; j, i), Xc = X(ki, kj, kb; i, j),
+//   Xd = X(kj, ki, kb; j, i),
+// each straight and transposed, so one workgroup takes the whole orbit: the slabs are read
+// once into LDS and every member is written with the two-pair formula
+//   B(a, b) = (x1 + x4) - (x2 + x3),  x1 = own slab (a, b), x2 = the ij partner's (a, b),
+//   x3 = the ab partner's (b, a), x4 = the (ij, ab) partner's (b, a),
+// exactly as a workgroup per block would (the members are exact negatives and transposes
+// of each other).  Workgroups run over the orbit representatives pt.ablk (ki <= kj,
+// ka <= kb) times the (i, j) with i <= j when ki == kj; members that coincide with the
+// representative (ki == kj and i == j, or ka == kb) are not written twice.
+constexpr int ASMP_VMAX = 31;  // four padded slabs within 64 KB of dynamic LDS
+
+__device__ inline cd asm_lab(const cd *Lrow, const int32_t *vposK, int vv, int nv, int kx, int x, int ky, int y) {
+    if (kx < ky || (kx == ky && x < y)) return Lrow[vposK[(int64_t)kx * vv + x * nv + y]];
+    if (kx == ky && x == y) return make_double2(0.0, 0.0);
+    const cd l = Lrow[vposK[(int64_t)ky * vv + y * nv + x]];
+    return make_double2(-l.x, -l.y);
+}
+
+__global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt, const cd *X, const cd *Lp, cd *r2) {
+    extern __shared__ cd XS[];  // four slabs, rows padded to nv + 1 (LDS form only)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, vp = nv + 1;
+    const int64_t ov = (int64_t)no * nv, ov2 = ov * ov, bs = s.d.t2blk();
+    const int64_t nblk = (int64_t)pt.nablk * no * no;
+    const int64_t per = (nblk + 7) / 8;
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int j = (int)(L % no), i = (int)((L / no) % no);
+    const int blk = pt.ablk[L / ((int64_t)no * no)];
+    const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
+    if (ki == kj && i > j) return;
+    const int kb = kcv(s.kc, N, ki, kj, ka), K = kcv(s.kc, N, ki, kj, 0);
+    const bool own_ij = ki == kj && i == j, own_ab = ka == kb;
+    // slab (x at k1, y at k2; a-slot momentum k3): X[q = k3 - k1][k1][k2](x, ., y, .)
+    auto slab = [&](int k1, int k2, int k3, int x, int y) {
+        const int q = kcv(s.kc, N, k3, 0, k1);
+        return X + (((int64_t)q * N + k1) * N + k2) * ov2 + (int64_t)x * nv * ov + (int64_t)y * nv;
+    };
+    const cd *sa = slab(ki, kj, ka, i, j), *sb = slab(kj, ki, ka, j, i);
+    const cd *sc = slab(ki, kj, kb, i, j), *sd = slab(kj, ki, kb, j, i);
+    const bool lds = nv <= ASMP_VMAX;
+    cd *Xa = XS, *Xb = XS + nv * vp, *Xc = XS + 2 * nv * vp, *Xd = XS + 3 * nv * vp;
+    if (lds) {
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / nv, b = e % nv;
+            const int64_t g = (int64_t)a * ov + b;
+            Xa[a * vp + b] = sa[g];
+            Xb[a * vp + b] = sb[g];
+            Xc[a * vp + b] = sc[g];
+            Xd[a * vp + b] = sd[g];
+        }
+        __syncthreads();
+    }
+    auto at = [&](const cd *sm, const cd *sg, int a, int b) {
+        return lds ? sm[a * vp + b] : sg[(int64_t)a * ov + b];
+    };
+    const int po = own_ij ? -1 : pt.opos[((int64_t)K * N + ki) * no * no + i * no + j];
+    const cd *Lrow = Lp + ((int64_t)K * pt.PO + (po < 0 ? 0 : po)) * pt.PV;
+    const int32_t *vposK = pt.vpos + (int64_t)K * N * vv;
+    const int64_t o1 = blk3(N, ki, kj, ka) * bs + ((int64_t)i * no + j) * vv;
+    const int64_t o2 = blk3(N, kj, ki, ka) * bs + ((int64_t)j * no + i) * vv;
+    const int64_t o3 = blk3(N, ki, kj, kb) * bs + ((int64_t)i * no + j) * vv;
+    const int64_t o4 = blk3(N, kj, ki, kb) * bs + ((int64_t)j * no + i) * vv;
+    for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+        const int a = e / nv, b = e % nv;
+        const cd l1 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, ka, a, kb, b);
+        {  // B1 and B2
+            const cd x1 = at(Xa, sa, a, b), x2 = at(Xb, sb, a, b), x3 = at(Xc, sc, b, a), x4 = at(Xd, sd, b, a);
+            const cd d1 = cconj(s.oovv[o1 + e]);
+            const cd p1 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
+            r2[o1 + e] = make_double2((d1.x + p1.x) + l1.x, (d1.y + p1.y) + l1.y);
+            if (!own_ij) {
+                const cd d2 = cconj(s.oovv[o2 + e]);
+                const cd p2 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
+                r2[o2 + e] = make_double2((d2.x + p2.x) - l1.x, (d2.y + p2.y) - l1.y);
+            }
+        }
+        if (!own_ab) {  // B3 and B4: the a slot at kb
+            const cd l3 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, kb, a, ka, b);
+            const cd x1 = at(Xc, sc, a, b), x2 = at(Xd, sd, a, b), x3 = at(Xa, sa, b, a), x4 = at(Xb, sb, b, a);
+            const cd d3 = cconj(s.oovv[o3 + e]);
+            const cd p3 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
+            r2[o3 + e] = make_double2((d3.x + p3.x) + l3.x, (d3.y + p3.y) + l3.y);
+            if (!own_ij) {
+                const cd d4 = cconj(s.oovv[o4 + e]);
+                const cd p4 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
+                r2[o4 + e] = make_double2((d4.x + p4.x) - l3.x, (d4.y + p4.y) - l3.y);
+            }
+        }
+    }
+}
+
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2,
+                             hipStream_t st) {
+    const int64_t no = s.d.no, nv = s.d.nv;
+    const int64_t n = (int64_t)pt.nablk * no * no;
+    if (n == 0) return;
+    const size_t lds = nv <= ASMP_VMAX ? (size_t)4 * nv * (nv + 1) * sizeof(cd) : 0;
+    hipLaunchKernelGGL(k_assemble_r2_pack, dim3((unsigned)((n + 7) / 8 * 8)), dim3(256), lds, st, s, pt, X, Lp, r2);
     CK_CHECK(hipGetLastError());
 }
 

@@ -112,6 +112,13 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
     CK_CHECK(hipGetLastError());
 }
 
+struct PtrPack {
+    const cd *p[16];
+};
+struct CoefPack {
+    double c[16];
+};
+
 __global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n1 = s.d.t1(), n2 = s.d.t2();
@@ -144,41 +151,63 @@ void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, 
     CK_CHECK(hipGetLastError());
 }
 
-struct PtrPack {
-    const cd *p[16];
-};
-struct CoefPack {
-    double c[16];
-};
-
-__global__ void k_dots(int64_t n, const cd *x, PtrPack y, int m, double *partials) {
+// The DIIS step of one iteration in one pass: e = D^-1 R, t <- t + e, err = e, hist = t
+// (the new amplitudes' history copy), and the partial sums of Re <e, y_j> for the m held
+// error vectors (y[self] is err itself, whose product is taken from e before it is stored).
+// A fixed grid of UPD_BLOCKS workgroups and a fixed summation order, so the dots are
+// deterministic.  The grid is larger than RED_BLOCKS because this pass streams 4 + m
+// vectors and needs the memory parallelism; the t2 index is split once per element into a
+// momentum block and a 32-bit offset inside it.
+__global__ __launch_bounds__(256) void k_update_diis(SysDev s, cd *t, const cd *r, cd *err, cd *hist, PtrPack y,
+                                                     int m, int self, double *partials) {
     __shared__ double sh[16][256];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
     double v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = 0.0;
-    GRID_STRIDE(i, n) {
-        cd a = x[i];
+    GRID_STRIDE(idx, n1 + n2) {
+        double D;
+        if (idx < n1) {
+            const int x = (int)idx;
+            const int a = x % nv, i = (x / nv) % no, k = x / (no * nv);
+            D = s.eo[k * no + i] - s.ev[k * nv + a];
+        } else {
+            const int64_t blk = (idx - n1) / bs;
+            const int x = (int)(idx - n1 - blk * bs);
+            const int b = x % nv, a = (x / nv) % nv, j = (x / (nv * nv)) % no, i = x / (nv * nv * no);
+            const int kb3 = (int)blk;
+            const int ka = kb3 % N, kj = (kb3 / N) % N, ki = kb3 / (N * N);
+            const int kb = s.kc[kb3];  // kc is indexed by the block triple (ki, kj, ka)
+            D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
+        }
+        const cd rv = r[idx];
+        const cd e = make_double2(rv.x / D, rv.y / D);
+        const cd tn = cadd(t[idx], e);
+        t[idx] = tn;
+        hist[idx] = tn;
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             if (j < m) {
-                cd b = y.p[j][i];
-                v[j] = fma(a.x, b.x, fma(a.y, b.y, v[j]));
+                const cd b = j == self ? e : y.p[j][idx];
+                v[j] = fma(e.x, b.x, fma(e.y, b.y, v[j]));
             }
+        err[idx] = e;
     }
     block_sum<16>(v, sh);
     if (threadIdx.x == 0)
-        for (int j = 0; j < m; ++j) partials[(int64_t)j * RED_BLOCKS + blockIdx.x] = v[j];
+        for (int j = 0; j < m; ++j) partials[(int64_t)j * UPD_BLOCKS + blockIdx.x] = v[j];
 }
 
-void launch_dots(int64_t n, const cd *x, const cd *const *y, int m, double *partials, double *out,
-                 hipStream_t st) {
+void launch_update_diis(const SysDev &s, cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
+                        int self, double *partials, double *out, hipStream_t st) {
     PtrPack pk{};
     for (int j = 0; j < m; ++j) pk.p[j] = y[j];
-    hipLaunchKernelGGL(k_dots, dim3(RED_BLOCKS), dim3(256), 0, st, n, x, pk, m, partials);
+    hipLaunchKernelGGL(k_update_diis, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r, err, hist, pk, m, self, partials);
     CK_CHECK(hipGetLastError());
     for (int j = 0; j < m; ++j) {
-        hipLaunchKernelGGL(k_final_sum<1>, dim3(1), dim3(256), 0, st, partials + (int64_t)j * RED_BLOCKS,
-                           RED_BLOCKS, out + j);
+        hipLaunchKernelGGL(k_final_sum<1>, dim3(1), dim3(256), 0, st, partials + (int64_t)j * UPD_BLOCKS,
+                           UPD_BLOCKS, out + j);
         CK_CHECK(hipGetLastError());
     }
 }
@@ -206,20 +235,6 @@ void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd 
     CK_CHECK(hipGetLastError());
 }
 
-__global__ void k_copy(int64_t n, const cd *src, cd *dst) {
-    GRID_STRIDE(i, n) dst[i] = src[i];
-}
-__global__ void k_add(int64_t n, const cd *a, const cd *b, cd *dst) {
-    GRID_STRIDE(i, n) dst[i] = cadd(a[i], b[i]);
-}
-void launch_copy(int64_t n, const cd *src, cd *dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy, grid_for(n), dim3(256), 0, st, n, src, dst);
-    CK_CHECK(hipGetLastError());
-}
-void launch_add(int64_t n, const cd *a, const cd *b, cd *dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_add, grid_for(n), dim3(256), 0, st, n, a, b, dst);
-    CK_CHECK(hipGetLastError());
-}
 
 __global__ void k_diag(Dims d, const cd *fock, double *eo, double *ev) {
     const int n = d.no + d.nv;

@@ -29,6 +29,7 @@ void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *
 
 // reductions (deterministic: fixed grid, fixed-order partial sums) -------------------
 constexpr int RED_BLOCKS = 1024;
+constexpr int UPD_BLOCKS = 4096;  // grid of the DIIS update pass (its partials: m * UPD_BLOCKS)
 // out[0] = sum |r1|^2 + |r2|^2 ; partials must hold RED_BLOCKS doubles
 void launch_norm2(const Dims &d, const cd *r1, const cd *r2, double *partials, double *out, hipStream_t st);
 // out[0..1] = complex correlation energy; partials must hold 2*RED_BLOCKS doubles
@@ -36,14 +37,12 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
 // t += r / D, and (optionally) err = r / D
 void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
                    hipStream_t st);
-// out[j] = Re <x, y_j> over n complex elements, j < m ; partials must hold m*RED_BLOCKS doubles
-void launch_dots(int64_t n, const cd *x, const cd *const *y, int m, double *partials, double *out,
-                 hipStream_t st);
+// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D, t += e, err = e,
+// hist = t, and out[j] = Re <e, y_j> for j < m (y[self] is err); partials: m*UPD_BLOCKS
+void launch_update_diis(const SysDev &s, cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
+                        int self, double *partials, double *out, hipStream_t st);
 // dst = sum_j c[j] * src_j over n complex elements (m <= 16)
 void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st);
-// copies and fills
-void launch_copy(int64_t n, const cd *src, cd *dst, hipStream_t st);
-void launch_add(int64_t n, const cd *a, const cd *b, cd *dst, hipStream_t st);  // dst = a + b
 
 // device synthetic inputs (same recipe as the host generator) ------------------------
 void launch_synth_fock(const Mesh &m, int no, int nv, uint64_t seed, cd *fock, hipStream_t st);

@@ -932,112 +932,87 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
     }
 }
 
-// The same X seed in two blocked passes for n_occ <= OM, n_vir <= VM (XCD-contiguous
-// workgroup order).  The <ov||vv> term wants every integral element read once (a thread
-// per (j, b) keeps <j c||a b> over c in registers and runs over i); the Q, Fvt and Fot
-// terms want the Q and t2 slabs of one i staged once.
-//   pass 1, a workgroup per (q, ki, kj, a):  X = -1/2 sum_c t_i^c conj(<j kj, c ki||a ka, b kb>)
-//   pass 2, a workgroup per (q, ki, kj, i):  X += -sum_m t_m^a Q(m,i,j,b)
-//                                              + 1/2 sum_f t_ij^af Fvt(b,f) - 1/2 sum_n t_in^ab Fot(n,j)
+// The same X seed in one blocked pass for n_occ <= OM, n_vir <= VM: a workgroup per
+// (q, ki, kj, a) in XCD-contiguous order, a thread per (j, b) holding the no values of X at
+// (i, a, j, b) for every i.  Every <ov||vv> and t2 element is read once (t2 of this a goes
+// through LDS, with each (i, n) run of b contiguous); the Q slab of (ka, kb, ki) is shared by
+// the nv workgroups of one (q, ki, kj), which run next to each other on one XCD, so it comes
+// from L2 after the first.  The coefficients -1, -1/2, 1/2, -1/2 of the four terms are folded
+// into the staged factors (exact scalings), so one accumulator per i takes all of them.
 template <int OM, int VM>
-__global__ __launch_bounds__(OM * VM) void k_xinit_ovvv_t(SysDev s, const cd *t1, cd *X) {
-    __shared__ cd T1I[OM * VM];  // t1[ki](i, c)
+__global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
+                                                    const cd *Fot, const cd *Fvt, cd *X) {
+    __shared__ cd T2S[OM * OM * VM];  // t2[ki,kj,ka](i, n, a, b) of this a at (i * no + n) * nv + b
+    __shared__ cd FV[VM * VM];        // 1/2 Fvt[kb](b, f) at f * nv + b
+    __shared__ cd FO[OM * OM];        // -1/2 Fot[kj](n, j)
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t ov = (int64_t)no * nv, ov3 = ov * nv * nv;
+    const int64_t ov = (int64_t)no * nv, ov3 = ov * nv * nv, o3v = ov * no * no;
     const int64_t nblk = (int64_t)N * N * N * nv;
     const int64_t L = xcd_block(nblk);
     if (L >= nblk) return;
     const int a = (int)(L % nv);
     const int64_t blk = L / nv;  // (q, ki, kj)
     const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
-    const int ka = kcv(s.kc, N, ki, q, 0);
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
+    const int ka = kcv(s.kc, N, ki, q, 0), kb = kcv(s.kc, N, kj, 0, q);
+    const cd *tb = t2 + blk3(N, ki, kj, ka) * s.d.t2blk() + (int64_t)a * nv;
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x)
+        T2S[x] = tb[(int64_t)(x / nv) * nv * nv + x % nv];
+    for (int x = threadIdx.x; x < nv * nv; x += blockDim.x)
+        FV[(x % nv) * nv + x / nv] = cscale(Fvt[(int64_t)kb * nv * nv + x], 0.5);
+    for (int x = threadIdx.x; x < no * no; x += blockDim.x) FO[x] = cscale(Fot[(int64_t)kj * no * no + x], -0.5);
     __syncthreads();
     const int jb = threadIdx.x;
     if (jb >= no * nv) return;
     const int j = jb / nv, b = jb % nv;
+    cd acc[OM];
+#pragma unroll
+    for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
+    // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
+    // (t1 is read at wave-uniform addresses, so through the scalar cache, not LDS)
     const cd *gb = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
-    cd g[VM];
+    const cd *t1i = t1 + (int64_t)ki * no * nv;
 #pragma unroll
-    for (int c = 0; c < VM; ++c) g[c] = c < nv ? cconj(gb[(int64_t)c * nv * nv]) : make_double2(0.0, 0.0);
-    cd *xb = X + blk * ov * ov + (int64_t)a * ov + jb;
-    for (int i = 0; i < no; ++i) {
-        cd y = make_double2(0.0, 0.0);
+    for (int c = 0; c < VM; ++c) {
+        if (c >= nv) break;
+        const cd gv = gb[(int64_t)c * nv * nv];
+        const cd g = make_double2(-0.5 * gv.x, 0.5 * gv.y);  // -1/2 conj(<..>)
 #pragma unroll
-        for (int c = 0; c < VM; ++c)
-            if (c < nv) cfma(y, T1I[i * nv + c], g[c]);
-        xb[(int64_t)i * nv * ov] = make_double2(-0.5 * y.x, -0.5 * y.y);
+        for (int i = 0; i < OM; ++i)
+            if (i < no) cfma(acc[i], t1i[i * nv + c], g);
     }
-}
-
-template <int OM, int VM>
-__global__ __launch_bounds__(2 * OM * VM) void k_xinit_rest_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
-                                                             const cd *Fot, const cd *Fvt, cd *X) {
-    // rows padded to nv + 1 so that lanes differing in (j, b) or a hit distinct banks
-    __shared__ cd T2S[OM * VM * (VM + 1)];  // t2(i, n, a, b) of this i at (n * nv + a) * (nv + 1) + b
-    __shared__ cd QS[OM * OM * VM];         // Q(m, i, j, b) of this i at (m * no + j) * nv + b
-    __shared__ cd T1A[OM * VM];             // t1[ka](m, a)
-    __shared__ cd FV[VM * VM];              // Fvt[kb](b, f) at f * nv + b
-    __shared__ cd FO[OM * OM];              // Fot[kj](n, j)
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vp = nv + 1;
-    const int64_t ov = (int64_t)no * nv, o3v = ov * no * no;
-    const int64_t nblk = (int64_t)N * N * N * no;
-    const int64_t L = xcd_block(nblk);
-    if (L >= nblk) return;
-    const int i = (int)(L % no);
-    const int64_t blk = L / no;  // (q, ki, kj)
-    const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
-    const int ka = kcv(s.kc, N, ki, q, 0), kb = kcv(s.kc, N, kj, 0, q);
-    const cd *tb = t2 + blk3(N, ki, kj, ka) * s.d.t2blk() + (int64_t)i * no * nv * nv;
-    for (int x = threadIdx.x; x < no * nv * nv; x += blockDim.x) T2S[(x / nv) * vp + x % nv] = tb[x];
-    const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + (int64_t)i * no * nv;
-    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {
-        const int m = x / (no * nv), jb = x % (no * nv);
-        QS[x] = qb[(int64_t)m * no * no * nv + jb];
-    }
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1A[x] = t1[(int64_t)ka * no * nv + x];
-    for (int x = threadIdx.x; x < nv * nv; x += blockDim.x) FV[(x % nv) * nv + x / nv] = Fvt[(int64_t)kb * nv * nv + x];
-    for (int x = threadIdx.x; x < no * no; x += blockDim.x) FO[x] = Fot[(int64_t)kj * no * no + x];
-    __syncthreads();
-    const int jb = threadIdx.x % (OM * VM), half = threadIdx.x / (OM * VM);
-    if (jb >= no * nv) return;
-    const int j = jb / nv, b = jb % nv;
-    cd qr[OM], fo[OM];
+    // -sum_m t_m^a Q(m, i, j, b)
+    const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + jb;
 #pragma unroll
     for (int m = 0; m < OM; ++m) {
-        qr[m] = m < no ? QS[(m * no + j) * nv + b] : make_double2(0.0, 0.0);
-        fo[m] = m < no ? FO[m * no + j] : make_double2(0.0, 0.0);
+        if (m >= no) break;
+        const cd tv = t1[((int64_t)ka * no + m) * nv + a];
+        const cd tm = make_double2(-tv.x, -tv.y);
+#pragma unroll
+        for (int i = 0; i < OM; ++i)
+            if (i < no) cfma(acc[i], tm, qb[(int64_t)(m * no + i) * ov]);
     }
-    // Fvt[kb](b, f) over f, used for every a
-    cd fv[VM];
+    // +1/2 sum_f t_ij^af Fvt[kb](b, f)
 #pragma unroll
-    for (int f = 0; f < VM; ++f) fv[f] = f < nv ? FV[f * nv + b] : make_double2(0.0, 0.0);
-    cd *xb = X + blk * ov * ov + (int64_t)i * nv * ov + jb;
-    constexpr int AH = (VM + 1) / 2;  // a values per thread
-    const int a0 = half * ((nv + 1) / 2), a1 = half ? nv : (nv + 1) / 2;
-    // the X values this thread updates, loaded up front
-    cd xo[AH];
+    for (int f = 0; f < VM; ++f) {
+        if (f >= nv) break;
+        const cd fv = FV[f * nv + b];
 #pragma unroll
-    for (int u = 0; u < AH; ++u) xo[u] = a0 + u < a1 ? xb[(int64_t)(a0 + u) * ov] : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int u = 0; u < AH; ++u) {
-        const int a = a0 + u;
-        if (a >= a1) continue;
-        cd acc = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int m = 0; m < OM; ++m)
-            if (m < no) {
-                cfma(acc, T1A[m * nv + a], qr[m]);
-                cfma(y, T2S[(m * nv + a) * vp + b], fo[m]);
-            }
-#pragma unroll
-        for (int f = 0; f < VM; ++f)
-            if (f < nv) cfma(w, T2S[(j * nv + a) * vp + f], fv[f]);
-        cd x = xo[u];
-        x.x += -acc.x + 0.5 * (w.x - y.x);
-        x.y += -acc.y + 0.5 * (w.y - y.y);
-        xb[(int64_t)a * ov] = x;
+        for (int i = 0; i < OM; ++i)
+            if (i < no) cfma(acc[i], T2S[(i * no + j) * nv + f], fv);
     }
+    // -1/2 sum_n t_in^ab Fot[kj](n, j)
+#pragma unroll
+    for (int n = 0; n < OM; ++n) {
+        if (n >= no) break;
+        const cd fo = FO[n * no + j];
+#pragma unroll
+        for (int i = 0; i < OM; ++i)
+            if (i < no) cfma(acc[i], T2S[(i * no + n) * nv + b], fo);
+    }
+    cd *xb = X + blk * ov * ov + (int64_t)a * ov + jb;
+#pragma unroll
+    for (int i = 0; i < OM; ++i)
+        if (i < no) xb[(int64_t)i * nv * ov] = acc[i];
 }
 
 // ------------------------------------------------------------------ T2 assembly
@@ -1299,10 +1274,8 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
     }
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_xinit_ovvv_t<8, 16>), xcd_grid(n3 * nv), dim3(8 * 16), 0, st, s, t1, X);
-        CK_CHECK(hipGetLastError());
-        hipLaunchKernelGGL((k_xinit_rest_t<8, 16>), xcd_grid(n3 * no), dim3(2 * 8 * 16), 0, st, s, t1, t2, scratch,
-                           w.Fot, w.Fvt, X);
+        hipLaunchKernelGGL((k_xinit_t<8, 16>), xcd_grid(n3 * nv), dim3(8 * 16), 0, st, s, t1, t2, scratch, w.Fot,
+                           w.Fvt, X);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);

@@ -117,8 +117,8 @@ def _canonical_pairs(grid, w):
 @pytest.mark.parametrize("grid,no,nv", [((3, 3, 3), 8, 16), ((2, 2, 2), 4, 8), ((2, 1, 1), 3, 5)])
 def test_product_shapes(grid, no, nv):
     """FP64: the full grouped products; mixed: the ladder family on canonical pairs padded
-    to a multiple of 16 (a quarter of the work), the two ladders as one product, the ring
-    family in full."""
+    to a multiple of 16 in rows, columns and k (an eighth of the work), the two ladders as
+    one product, the ring family in full."""
     N = grid[0] * grid[1] * grid[2]
     pv = -(-max(_canonical_pairs(grid, nv)) // 16) * 16
     po = -(-max(_canonical_pairs(grid, no)) // 16) * 16
@@ -126,9 +126,9 @@ def test_product_shapes(grid, no, nv):
             2: (N, N * no * no, N * no * no, N * nv * nv), 3: (N, N * no * nv, N * no * nv, N * no * nv),
             4: (N, N * no * nv, N * no * nv, N * no * nv)}
     packed = dict(full)
-    packed[0] = (N, N * no * no, pv, pv + po)  # both ladders in one product
+    packed[0] = (N, po, pv, pv + po)  # both ladders in one product
     packed[1] = (0, 0, 0, 0)
-    packed[2] = (N, N * no * no, po, pv)
+    packed[2] = (N, po, po, pv)
     for prec, want in ((ck.PREC_FP64, full), (ck.PREC_MIXED, packed)):
         ctx = ck.ccsd_k_init([dict(grid=grid, no=no, nv=nv, precision=prec)], None)
         try:
