@@ -935,14 +935,19 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 // The same X seed in one blocked pass for n_occ <= OM, n_vir <= VM: a workgroup per
 // (q, ki, kj, a) in XCD-contiguous order, a thread per (j, b) holding the no values of X at
 // (i, a, j, b) for every i.  Every <ov||vv> and t2 element is read once (t2 of this a goes
-// through LDS, with each (i, n) run of b contiguous); the Q slab of (ka, kb, ki) is shared by
-// the nv workgroups of one (q, ki, kj), which run next to each other on one XCD, so it comes
-// from L2 after the first.  The coefficients -1, -1/2, 1/2, -1/2 of the four terms are folded
-// into the staged factors (exact scalings), so one accumulator per i takes all of them.
+// through LDS, with each (i, n) run of b contiguous, half of the i at a time so that more
+// workgroups fit on a CU; its loads are issued before the integral terms and land in LDS
+// after them); the Q slab of (ka, kb, ki) is shared by the nv workgroups of one (q, ki, kj),
+// which run next to each other on one XCD, so it comes from L2 after the first.  t1 is read
+// at wave-uniform addresses (scalar loads).  The coefficients -1, -1/2, 1/2, -1/2 of the four
+// terms are folded into one factor of each product (exact scalings), so one accumulator per
+// i takes all of them.
 template <int OM, int VM>
 __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
                                                     const cd *Fot, const cd *Fvt, cd *X) {
-    __shared__ cd T2S[OM * OM * VM];  // t2[ki,kj,ka](i, n, a, b) of this a at (i * no + n) * nv + b
+    constexpr int IH = (OM + 1) / 2;  // i values per LDS phase
+    constexpr int NT = OM * VM;       // threads
+    __shared__ cd T2S[IH * OM * VM];  // t2[ki,kj,ka](i0 + il, n, a, b) at (il * no + n) * nv + b
     __shared__ cd FV[VM * VM];        // 1/2 Fvt[kb](b, f) at f * nv + b
     __shared__ cd FO[OM * OM];        // -1/2 Fot[kj](n, j)
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
@@ -955,60 +960,90 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
     const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
     const int ka = kcv(s.kc, N, ki, q, 0), kb = kcv(s.kc, N, kj, 0, q);
     const cd *tb = t2 + blk3(N, ki, kj, ka) * s.d.t2blk() + (int64_t)a * nv;
-    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x)
-        T2S[x] = tb[(int64_t)(x / nv) * nv * nv + x % nv];
+    const int nh = IH * no * nv;  // staged elements per phase
+    cd st[IH];
+    auto load_half = [&](int i0) {
+#pragma unroll
+        for (int u = 0; u < IH; ++u) {
+            const int x = threadIdx.x + u * NT, il = x / (no * nv), i = i0 + il;
+            st[u] = x < nh && i < no ? tb[((int64_t)i * no + (x / nv) % no) * nv * nv + x % nv] : make_double2(0.0, 0.0);
+        }
+    };
+    auto store_half = [&]() {
+#pragma unroll
+        for (int u = 0; u < IH; ++u) {
+            const int x = threadIdx.x + u * NT;
+            if (x < nh) T2S[x] = st[u];
+        }
+    };
+    load_half(0);
     for (int x = threadIdx.x; x < nv * nv; x += blockDim.x)
         FV[(x % nv) * nv + x / nv] = cscale(Fvt[(int64_t)kb * nv * nv + x], 0.5);
     for (int x = threadIdx.x; x < no * no; x += blockDim.x) FO[x] = cscale(Fot[(int64_t)kj * no * no + x], -0.5);
-    __syncthreads();
     const int jb = threadIdx.x;
-    if (jb >= no * nv) return;
-    const int j = jb / nv, b = jb % nv;
+    const bool act = jb < no * nv;
+    const int j = act ? jb / nv : 0, b = act ? jb % nv : 0;
     cd acc[OM];
 #pragma unroll
     for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
-    // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
-    // (t1 is read at wave-uniform addresses, so through the scalar cache, not LDS)
-    const cd *gb = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
-    const cd *t1i = t1 + (int64_t)ki * no * nv;
+    if (act) {
+        // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
+        const cd *gb = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
+        const cd *t1i = t1 + (int64_t)ki * no * nv;
 #pragma unroll
-    for (int c = 0; c < VM; ++c) {
-        if (c >= nv) break;
-        const cd gv = gb[(int64_t)c * nv * nv];
-        const cd g = make_double2(-0.5 * gv.x, 0.5 * gv.y);  // -1/2 conj(<..>)
+        for (int c = 0; c < VM; ++c) {
+            if (c >= nv) break;
+            const cd gv = gb[(int64_t)c * nv * nv];
+            const cd g = make_double2(-0.5 * gv.x, 0.5 * gv.y);  // -1/2 conj(<..>)
 #pragma unroll
-        for (int i = 0; i < OM; ++i)
-            if (i < no) cfma(acc[i], t1i[i * nv + c], g);
+            for (int i = 0; i < OM; ++i)
+                if (i < no) cfma(acc[i], t1i[i * nv + c], g);
+        }
+        // -sum_m t_m^a Q(m, i, j, b)
+        const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + jb;
+#pragma unroll
+        for (int m = 0; m < OM; ++m) {
+            if (m >= no) break;
+            const cd tv = t1[((int64_t)ka * no + m) * nv + a];
+            const cd tm = make_double2(-tv.x, -tv.y);
+#pragma unroll
+            for (int i = 0; i < OM; ++i)
+                if (i < no) cfma(acc[i], tm, qb[(int64_t)(m * no + i) * ov]);
+        }
     }
-    // -sum_m t_m^a Q(m, i, j, b)
-    const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + jb;
+    store_half();
 #pragma unroll
-    for (int m = 0; m < OM; ++m) {
-        if (m >= no) break;
-        const cd tv = t1[((int64_t)ka * no + m) * nv + a];
-        const cd tm = make_double2(-tv.x, -tv.y);
+    for (int p = 0; p < 2; ++p) {
+        const int i0 = p * IH;
+        if (i0 >= no) break;
+        if (p > 0) {
+            load_half(i0);
+            __syncthreads();  // every read of the previous phase is done
+            store_half();
+        }
+        __syncthreads();
+        if (act) {
+            // +1/2 sum_f t_ij^af Fvt[kb](b, f)
 #pragma unroll
-        for (int i = 0; i < OM; ++i)
-            if (i < no) cfma(acc[i], tm, qb[(int64_t)(m * no + i) * ov]);
+            for (int f = 0; f < VM; ++f) {
+                if (f >= nv) break;
+                const cd fv = FV[f * nv + b];
+#pragma unroll
+                for (int il = 0; il < IH; ++il)
+                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + j) * nv + f], fv);
+            }
+            // -1/2 sum_n t_in^ab Fot[kj](n, j)
+#pragma unroll
+            for (int n = 0; n < OM; ++n) {
+                if (n >= no) break;
+                const cd fo = FO[n * no + j];
+#pragma unroll
+                for (int il = 0; il < IH; ++il)
+                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + n) * nv + b], fo);
+            }
+        }
     }
-    // +1/2 sum_f t_ij^af Fvt[kb](b, f)
-#pragma unroll
-    for (int f = 0; f < VM; ++f) {
-        if (f >= nv) break;
-        const cd fv = FV[f * nv + b];
-#pragma unroll
-        for (int i = 0; i < OM; ++i)
-            if (i < no) cfma(acc[i], T2S[(i * no + j) * nv + f], fv);
-    }
-    // -1/2 sum_n t_in^ab Fot[kj](n, j)
-#pragma unroll
-    for (int n = 0; n < OM; ++n) {
-        if (n >= no) break;
-        const cd fo = FO[n * no + j];
-#pragma unroll
-        for (int i = 0; i < OM; ++i)
-            if (i < no) cfma(acc[i], T2S[(i * no + n) * nv + b], fo);
-    }
+    if (!act) return;
     cd *xb = X + blk * ov * ov + (int64_t)a * ov + jb;
 #pragma unroll
     for (int i = 0; i < OM; ++i)
