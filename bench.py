@@ -10,8 +10,9 @@ T1 residual), its norm, the correlation energy, the update t <- t + R/D and DIIS
 Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line: value = residual evaluations per second of the headline path,
-with the dominant kernel's roofline (particle-particle ladder, HIP events on the
-library's stream) and the FP64 CPU oracle timed on a bounded sample on the host.
+with the roofline of the dominant grouped product (the one with the largest total time;
+HIP events on the library's stream) and of the ladder product, and the FP64 CPU oracle
+timed on a bounded sample on the host.
 """
 import argparse
 import json
@@ -122,9 +123,10 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
 
 
 def cpu_baseline(no, nv, N_target):
-    """The FP64 oracle on a bounded sample (about 10-20 s of CPU work): one residual on a
-    2x2x2 mesh with the same per-k block shapes, scaled to the target mesh by the N_k^4
-    algorithmic flop ratio."""
+    """The FP64 oracle on a bounded sample (about 10-25 s of CPU work): residuals on a
+    2x2x2 mesh with the same per-k block shapes, repeated until 10 s have passed (at most
+    four), the time per residual scaled to the target mesh by the N_k^4 algorithmic flop
+    ratio."""
     import numpy as np
 
     import synth
@@ -134,9 +136,12 @@ def cpu_baseline(no, nv, N_target):
     f, eris = synth.system(303, grid, no, nv, scale=0.05 / 8)
     t1, t2 = synth.test_amplitudes(1, grid, no, nv, scale=0.01)
     kc = O.kconserv(grid)
+    reps = 0
     t0 = time.perf_counter()
-    O.residual(f, eris, t1, t2, kc)
-    dt = time.perf_counter() - t0
+    while reps < 4 and (reps == 0 or time.perf_counter() - t0 < 10.0):
+        O.residual(f, eris, t1, t2, kc)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
     threads = 1
     try:
         from threadpoolctl import threadpool_info
@@ -146,9 +151,9 @@ def cpu_baseline(no, nv, N_target):
         pass
     ratio = (N_target / 8.0) ** 4
     return {"value": 1.0 / (dt * ratio), "unit": "evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one oracle residual on a 2x2x2 mesh with n_occ={no}, n_vir={nv} per k "
-                      f"({dt:.2f} s), scaled by the N_k^4 flop ratio {ratio:.0f} to N_k={N_target}",
-            "sample_seconds": dt}
+            "sample": f"{reps} oracle residual(s) on a 2x2x2 mesh with n_occ={no}, n_vir={nv} per k "
+                      f"({dt:.2f} s each), scaled by the N_k^4 flop ratio {ratio:.0f} to N_k={N_target}",
+            "sample_seconds": dt * reps}
 
 
 def main():

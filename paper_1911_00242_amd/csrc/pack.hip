@@ -2,14 +2,15 @@
 //
 // tau_{ij}^{ef}, <mn||ef>, the T1-dressed <ab||ef> and W_mnij are antisymmetric under the
 // exchange of the two members of a pair (with their momenta), and so is the
-// particle-particle / hole-hole ladder contribution to R_{ij}^{ab} in (a, b).  Within a
-// group of total pair momentum K, a pair (kx, x; ky, y), ky = K - kx, is canonical when
-// (kx, x) < (ky, y) in (momentum, orbital) order.  A sum over all pairs of a product of
-// two antisymmetric factors is twice the sum over canonical pairs (the diagonal terms
-// vanish), and a result antisymmetric in (a, b) is fixed by its canonical columns.  The
-// ladder products therefore run on packed operands, canonical pairs of every group in a
-// fixed order padded with zeros to a multiple of 16, and take a quarter of the work of
-// the full products.  Every packed operand is written here in split storage.
+// particle-particle / hole-hole ladder contribution to R_{ij}^{ab} in (i, j) and in (a, b).
+// Within a group of total pair momentum K, a pair (kx, x; ky, y), ky = K - kx, is canonical
+// when (kx, x) < (ky, y) in (momentum, orbital) order.  A sum over all pairs of a product
+// of two antisymmetric factors is twice the sum over canonical pairs (the diagonal terms
+// vanish), and a result antisymmetric in both pairs is fixed by its canonical rows and
+// columns.  The ladder products therefore run on packed operands, canonical pairs of every
+// group in a fixed order padded with zeros to a multiple of 16, and take an eighth of the
+// work of the full products; their result stays packed (Lp) until the R2 assembly expands
+// it.  Every packed operand is written here in split storage.
 #include "common.h"
 #include "mixed.h"
 
