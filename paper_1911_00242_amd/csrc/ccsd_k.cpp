@@ -54,7 +54,10 @@ struct System {
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
     int32_t *dkc = nullptr;
     int64_t *dtab = nullptr;
+    // DIIS history: amplitudes (FP64) and error vectors (FP64; complex64 on the mixed path,
+    // whose residual carries about 1e-7 relative error, so the overlaps lose nothing)
     std::vector<cd *> dvec, derr;
+    std::vector<ck::cf *> derr32;
     // mixed precision: split-BF16 operands (four bf16 per element) of the five products
     bool mixed = false;
     uint16_t *sp_t2 = nullptr, *sp_WR = nullptr, *sp_oovv = nullptr;
@@ -71,6 +74,7 @@ struct System {
     //   pk_B [K][canonical (ka,a,b)]: dressed <ab||ef> over (ke,e,f) | tau over (km,m,n)
     uint16_t *pk_A = nullptr, *pk_B = nullptr, *pk_oovv = nullptr;
     cd *Lp = nullptr;  // [K][canonical (ki,i,j)][canonical (ka,a,b)]: both ladders' contribution to R2
+    double *npart = nullptr;  // per-workgroup sums of |r2|^2 written by the R2 assembly
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -404,6 +408,7 @@ void carve(System &S, Carver &c) {
         c.take(S.pk_B, 4 * N * PV * (PV + PO));
         c.take(S.pk_oovv, 4 * N * PO * PV);
         c.take(S.Lp, N * PO * PV);
+        c.take(S.npart, ck::assemble_pack_blocks(S.d, S.pairs()));
         c.take(S.dptab, (int64_t)S.ptab.size());
     }
     c.take(S.WT, N3 * cls[0]);
@@ -430,10 +435,12 @@ void carve(System &S, Carver &c) {
     c.take(S.dtab, (int64_t)S.tables.size());
     int m = S.desc.diis_space;
     S.dvec.assign(m, nullptr);
-    S.derr.assign(m, nullptr);
+    S.derr.assign(S.mixed ? 0 : m, nullptr);
+    S.derr32.assign(S.mixed ? m : 0, nullptr);
     for (int i = 0; i < m; ++i) {
         c.take(S.dvec[i], S.n1() + S.n2());
-        c.take(S.derr[i], S.n1() + S.n2());
+        if (S.mixed) c.take(S.derr32[i], S.n1() + S.n2());
+        else c.take(S.derr[i], S.n1() + S.n2());
     }
 }
 
@@ -556,7 +563,7 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
     }
     ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
-    ck::launch_wmnij_init(s, S.t1(), S.WT, st);
+    ck::launch_wmnij_init(s, S.t1(), S.WT, S.mixed, st);
     run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>  (mixed: written split)
     if (!S.mixed) ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
     else ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, S.PV + S.PO, st);
@@ -569,10 +576,16 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         run_gemm(c, S, 2);  // hole-hole ladder
     } else {
         run_gemm(c, S, 1);  // both ladders on canonical pairs, into Lp
-        ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2(), st);
+        ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2(), S.npart, st);
     }
     ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     stage_end(c, all);
+}
+
+// ||R||^2 into S.redout[0] after residual_device (the mixed assembly left partial sums)
+void launch_norm(ccsd_k_ctx *c, System &S) {
+    if (S.mixed) ck::launch_norm_pack(S.d, S.pairs(), S.npart, S.r1(), S.redout, c->stream);
+    else ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, c->stream);
 }
 
 // split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
@@ -791,7 +804,7 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
         if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         residual_device(ctx, S);
-        ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, ctx->stream);
+        launch_norm(ctx, S);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
         if (r1) CK_CHECK(hipMemcpyAsync(r1, S.r1(), S.n1() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
         if (r2) CK_CHECK(hipMemcpyAsync(r2, S.r2(), S.n2() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
@@ -821,7 +834,7 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
             if (active.empty()) break;
             for (System *S : active) {
                 residual_device(ctx, *S);
-                ck::launch_norm2(S->d, S->r1(), S->r2(), S->red, S->redout, ctx->stream);
+                launch_norm(ctx, *S);
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             done = it + 1;
@@ -843,12 +856,16 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                     continue;
                 }
                 int slot = S->diis_head;
-                cd *err = S->derr[slot];
                 int held = std::min(S->diis_n + 1, m);
-                std::vector<const cd *> ys(held);
-                for (int j = 0; j < held; ++j) ys[j] = S->derr[j];
-                ck::launch_update_diis(sd, S->amp, S->res, err, S->dvec[slot], ys.data(), held, slot, S->red,
-                                       S->redout, ctx->stream);
+                if (S->mixed) {
+                    std::vector<const ck::cf *> ys(S->derr32.begin(), S->derr32.begin() + held);
+                    ck::launch_update_diis(sd, S->amp, S->res, S->derr32[slot], S->dvec[slot], ys.data(), held, slot,
+                                           S->red, S->redout, ctx->stream);
+                } else {
+                    std::vector<const cd *> ys(S->derr.begin(), S->derr.begin() + held);
+                    ck::launch_update_diis(sd, S->amp, S->res, S->derr[slot], S->dvec[slot], ys.data(), held, slot,
+                                           S->red, S->redout, ctx->stream);
+                }
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             for (System *S : upd) {
@@ -861,15 +878,20 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 for (int j = 0; j < held; ++j) S->B[slot * m + j] = S->B[j * m + slot] = dots[j];
                 S->diis_n = held;
                 S->diis_head = (slot + 1) % m;
-                if (held < 2) continue;
-                // the held slots in FIFO order do not matter for the solution
+                // the new amplitudes are in dvec[slot]: extrapolate into amp, or copy them
+                // (a combination with the single coefficient 1, exact) when there is no
+                // extrapolation; the held slots in FIFO order do not matter for the solution
                 std::vector<double> Bs((size_t)held * held), coef;
                 for (int i = 0; i < held; ++i)
                     for (int j = 0; j < held; ++j) Bs[i * held + j] = S->B[i * m + j];
-                if (!diis_solve(Bs, held, coef)) continue;
-                std::vector<const cd *> src(held);
-                for (int j = 0; j < held; ++j) src[j] = S->dvec[j];
-                ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), held, S->amp, ctx->stream);
+                std::vector<const cd *> src;
+                if (held >= 2 && diis_solve(Bs, held, coef)) {
+                    for (int j = 0; j < held; ++j) src.push_back(S->dvec[j]);
+                } else {
+                    src.push_back(S->dvec[slot]);
+                    coef.assign(1, 1.0);
+                }
+                ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), (int)src.size(), S->amp, ctx->stream);
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             collect_timing(ctx);

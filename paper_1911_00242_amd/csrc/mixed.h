@@ -83,9 +83,14 @@ void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const
                      uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st);
 void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
                       hipStream_t st);
-// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry
-void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2,
+// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry;
+// npart (assemble_pack_blocks doubles) receives per-workgroup sums of |r2|^2
+int64_t assemble_pack_blocks(const Dims &d, const PairTabs &pt);
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2, double *npart,
                              hipStream_t st);
+// out[0] = sum |r1|^2 + sum |r2|^2 from the assembly's partial sums (fixed order)
+void launch_norm_pack(const Dims &d, const PairTabs &pt, const double *npart, const cd *r1, double *out,
+                      hipStream_t st);
 void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
                             hipStream_t st);
 

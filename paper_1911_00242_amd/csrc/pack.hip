@@ -278,18 +278,37 @@ __device__ inline cd asm_lab(const cd *Lrow, const int32_t *vposK, int vv, int n
     return make_double2(-l.x, -l.y);
 }
 
-__global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt, const cd *X, const cd *Lp, cd *r2) {
+// Sum of |x|^2 over the workgroup (256 threads), in a fixed order; the result is valid in
+// thread 0.
+__device__ inline double asm_block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// npart[blockIdx.x] receives the sum of |r2|^2 over the elements this workgroup writes (0
+// for a workgroup without an orbit), so that the residual norm needs no second pass over R2.
+__global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt, const cd *X, const cd *Lp, cd *r2,
+                                                          double *npart) {
     extern __shared__ cd XS[];  // four slabs, rows padded to nv + 1 (LDS form only)
+    __shared__ double NS[256];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, vp = nv + 1;
     const int64_t ov = (int64_t)no * nv, ov2 = ov * ov, bs = s.d.t2blk();
     const int64_t nblk = (int64_t)pt.nablk * no * no;
     const int64_t per = (nblk + 7) / 8;
     const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (L >= nblk) return;
-    const int j = (int)(L % no), i = (int)((L / no) % no);
-    const int blk = pt.ablk[L / ((int64_t)no * no)];
+    const int64_t Lc = L < nblk ? L : 0;
+    const int j = (int)(Lc % no), i = (int)((Lc / no) % no);
+    const int blk = pt.ablk[Lc / ((int64_t)no * no)];
     const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
-    if (ki == kj && i > j) return;
+    if (L >= nblk || (ki == kj && i > j)) {
+        if (threadIdx.x == 0) npart[blockIdx.x] = 0.0;
+        return;
+    }
     const int kb = kcv(s.kc, N, ki, kj, ka), K = kcv(s.kc, N, ki, kj, 0);
     const bool own_ij = ki == kj && i == j, own_ab = ka == kb;
     // slab (x at k1, y at k2; a-slot momentum k3): X[q = k3 - k1][k1][k2](x, ., y, .)
@@ -322,6 +341,11 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
     const int64_t o2 = blk3(N, kj, ki, ka) * bs + ((int64_t)j * no + i) * vv;
     const int64_t o3 = blk3(N, ki, kj, kb) * bs + ((int64_t)i * no + j) * vv;
     const int64_t o4 = blk3(N, kj, ki, kb) * bs + ((int64_t)j * no + i) * vv;
+    double nsq = 0.0;
+    auto put = [&](int64_t o, cd v) {
+        r2[o] = v;
+        nsq = fma(v.x, v.x, fma(v.y, v.y, nsq));
+    };
     for (int e = threadIdx.x; e < vv; e += blockDim.x) {
         const int a = e / nv, b = e % nv;
         const cd l1 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, ka, a, kb, b);
@@ -329,11 +353,11 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
             const cd x1 = at(Xa, sa, a, b), x2 = at(Xb, sb, a, b), x3 = at(Xc, sc, b, a), x4 = at(Xd, sd, b, a);
             const cd d1 = cconj(s.oovv[o1 + e]);
             const cd p1 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
-            r2[o1 + e] = make_double2((d1.x + p1.x) + l1.x, (d1.y + p1.y) + l1.y);
+            put(o1 + e, make_double2((d1.x + p1.x) + l1.x, (d1.y + p1.y) + l1.y));
             if (!own_ij) {
                 const cd d2 = cconj(s.oovv[o2 + e]);
                 const cd p2 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
-                r2[o2 + e] = make_double2((d2.x + p2.x) - l1.x, (d2.y + p2.y) - l1.y);
+                put(o2 + e, make_double2((d2.x + p2.x) - l1.x, (d2.y + p2.y) - l1.y));
             }
         }
         if (!own_ab) {  // B3 and B4: the a slot at kb
@@ -341,23 +365,61 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
             const cd x1 = at(Xc, sc, a, b), x2 = at(Xd, sd, a, b), x3 = at(Xa, sa, b, a), x4 = at(Xb, sb, b, a);
             const cd d3 = cconj(s.oovv[o3 + e]);
             const cd p3 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
-            r2[o3 + e] = make_double2((d3.x + p3.x) + l3.x, (d3.y + p3.y) + l3.y);
+            put(o3 + e, make_double2((d3.x + p3.x) + l3.x, (d3.y + p3.y) + l3.y));
             if (!own_ij) {
                 const cd d4 = cconj(s.oovv[o4 + e]);
                 const cd p4 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
-                r2[o4 + e] = make_double2((d4.x + p4.x) - l3.x, (d4.y + p4.y) - l3.y);
+                put(o4 + e, make_double2((d4.x + p4.x) - l3.x, (d4.y + p4.y) - l3.y));
             }
         }
     }
+    const double tot = asm_block_sum(nsq, NS);
+    if (threadIdx.x == 0) npart[blockIdx.x] = tot;
 }
 
-void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2,
+// out = sum_b npart[b] + sum |r1|^2: one workgroup of 1024 threads, each with four
+// independent partial sums over a fixed strided subset (so that four loads are in flight),
+// combined in a fixed order and then by a fixed LDS tree
+__global__ __launch_bounds__(1024) void k_norm_final(const double *npart, int64_t nb, const cd *r1, int64_t n1,
+                                                     double *out) {
+    __shared__ double NS[1024];
+    const int t = threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t b0 = t; b0 < nb; b0 += 4 * 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t b = b0 + (int64_t)u * 1024;
+            if (b < nb) v[u] += npart[b];
+        }
+    }
+    for (int64_t x = t; x < n1; x += 1024) v[0] = fma(r1[x].x, r1[x].x, fma(r1[x].y, r1[x].y, v[0]));
+    NS[t] = (v[0] + v[1]) + (v[2] + v[3]);
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) NS[t] += NS[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[0] = NS[0];
+}
+
+int64_t assemble_pack_blocks(const Dims &d, const PairTabs &pt) {
+    const int64_t n = (int64_t)pt.nablk * d.no * d.no;
+    return (n + 7) / 8 * 8;
+}
+
+void launch_norm_pack(const Dims &d, const PairTabs &pt, const double *npart, const cd *r1, double *out,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(1024), 0, st, npart, assemble_pack_blocks(d, pt), r1, d.t1(), out);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2, double *npart,
                              hipStream_t st) {
-    const int64_t no = s.d.no, nv = s.d.nv;
-    const int64_t n = (int64_t)pt.nablk * no * no;
-    if (n == 0) return;
+    const int64_t nv = s.d.nv;
+    const int64_t nb = assemble_pack_blocks(s.d, pt);
+    if (nb == 0) return;
     const size_t lds = nv <= ASMP_VMAX ? (size_t)4 * nv * (nv + 1) * sizeof(cd) : 0;
-    hipLaunchKernelGGL(k_assemble_r2_pack, dim3((unsigned)((n + 7) / 8 * 8)), dim3(256), lds, st, s, pt, X, Lp, r2);
+    hipLaunchKernelGGL(k_assemble_r2_pack, dim3((unsigned)nb), dim3(256), lds, st, s, pt, X, Lp, r2, npart);
     CK_CHECK(hipGetLastError());
 }
 

@@ -112,12 +112,6 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
     CK_CHECK(hipGetLastError());
 }
 
-struct PtrPack {
-    const cd *p[16];
-};
-struct CoefPack {
-    double c[16];
-};
 
 __global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
@@ -151,15 +145,28 @@ void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, 
     CK_CHECK(hipGetLastError());
 }
 
-// The DIIS step of one iteration in one pass: e = D^-1 R, t <- t + e, err = e, hist = t
-// (the new amplitudes' history copy), and the partial sums of Re <e, y_j> for the m held
-// error vectors (y[self] is err itself, whose product is taken from e before it is stored).
+// The DIIS step of one iteration in one pass: e = D^-1 R, hist = t + e (the new amplitudes,
+// written only to their history slot: the extrapolation, or a copy when there is none,
+// writes t afterwards), err = e stored as E (complex128, or complex64 on the mixed path,
+// whose residual is itself accurate to about 1e-7 relative), and the partial sums of
+// Re <e, y_j> for the m held error vectors, all taken from the stored values (y[self] is
+// err itself, whose product is taken from e, rounded to E, before it is stored).
 // A fixed grid of UPD_BLOCKS workgroups and a fixed summation order, so the dots are
-// deterministic.  The grid is larger than RED_BLOCKS because this pass streams 4 + m
+// deterministic.  The grid is larger than RED_BLOCKS because this pass streams 3 + m
 // vectors and needs the memory parallelism; the t2 index is split once per element into a
 // momentum block and a 32-bit offset inside it.
-__global__ __launch_bounds__(256) void k_update_diis(SysDev s, cd *t, const cd *r, cd *err, cd *hist, PtrPack y,
-                                                     int m, int self, double *partials) {
+template <class E>
+struct ErrPack {
+    const E *p[16];
+};
+__device__ inline cd to_cd(cd x) { return x; }
+__device__ inline cd to_cd(cf x) { return make_double2((double)x.x, (double)x.y); }
+__device__ inline void from_cd(cd x, cd &y) { y = x; }
+__device__ inline void from_cd(cd x, cf &y) { y = make_float2((float)x.x, (float)x.y); }
+
+template <class E>
+__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r, E *err, cd *hist,
+                                                     ErrPack<E> y, int m, int self, double *partials) {
     __shared__ double sh[16][256];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
@@ -183,27 +190,30 @@ __global__ __launch_bounds__(256) void k_update_diis(SysDev s, cd *t, const cd *
         }
         const cd rv = r[idx];
         const cd e = make_double2(rv.x / D, rv.y / D);
-        const cd tn = cadd(t[idx], e);
-        t[idx] = tn;
-        hist[idx] = tn;
+        hist[idx] = cadd(t[idx], e);
+        E es;
+        from_cd(e, es);
+        const cd ed = to_cd(es);
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             if (j < m) {
-                const cd b = j == self ? e : y.p[j][idx];
-                v[j] = fma(e.x, b.x, fma(e.y, b.y, v[j]));
+                const cd b = j == self ? ed : to_cd(y.p[j][idx]);
+                v[j] = fma(ed.x, b.x, fma(ed.y, b.y, v[j]));
             }
-        err[idx] = e;
+        err[idx] = es;
     }
     block_sum<16>(v, sh);
     if (threadIdx.x == 0)
         for (int j = 0; j < m; ++j) partials[(int64_t)j * UPD_BLOCKS + blockIdx.x] = v[j];
 }
 
-void launch_update_diis(const SysDev &s, cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
-                        int self, double *partials, double *out, hipStream_t st) {
-    PtrPack pk{};
+template <class E>
+void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r, E *err, cd *hist, const E *const *y, int m,
+                          int self, double *partials, double *out, hipStream_t st) {
+    ErrPack<E> pk{};
     for (int j = 0; j < m; ++j) pk.p[j] = y[j];
-    hipLaunchKernelGGL(k_update_diis, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r, err, hist, pk, m, self, partials);
+    hipLaunchKernelGGL(k_update_diis<E>, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r, err, hist, pk, m, self,
+                       partials);
     CK_CHECK(hipGetLastError());
     for (int j = 0; j < m; ++j) {
         hipLaunchKernelGGL(k_final_sum<1>, dim3(1), dim3(256), 0, st, partials + (int64_t)j * UPD_BLOCKS,
@@ -211,6 +221,22 @@ void launch_update_diis(const SysDev &s, cd *t, const cd *r, cd *err, cd *hist, 
         CK_CHECK(hipGetLastError());
     }
 }
+
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
+                        int self, double *partials, double *out, hipStream_t st) {
+    launch_update_diis_t<cd>(s, t, r, err, hist, y, m, self, partials, out, st);
+}
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cf *err, cd *hist, const cf *const *y, int m,
+                        int self, double *partials, double *out, hipStream_t st) {
+    launch_update_diis_t<cf>(s, t, r, err, hist, y, m, self, partials, out, st);
+}
+
+struct PtrPack {
+    const cd *p[16];
+};
+struct CoefPack {
+    double c[16];
+};
 
 __global__ void k_lincomb(int64_t n, PtrPack src, CoefPack c, int m, cd *dst) {
     GRID_STRIDE(i, n) {

@@ -13,7 +13,9 @@ struct FWork {
 
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st);
-void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st);
+// canon: only the blocks with canonical rows and columns (ki <= kj, km <= kn) are written
+// (all that the packed W_mnij product reads); the plain fallback ignores it
+void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st);
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st);
 // ring seeds: W_mbej without its t2 part (WR) and X = every non-ladder, non-driver term
 // arranged for one P(ij)P(ab); needs the F combinations of w
@@ -37,9 +39,13 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
 // t += r / D, and (optionally) err = r / D
 void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
                    hipStream_t st);
-// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D, t += e, err = e,
-// hist = t, and out[j] = Re <e, y_j> for j < m (y[self] is err); partials: m*UPD_BLOCKS
-void launch_update_diis(const SysDev &s, cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
+// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D, hist = t + e
+// (t itself is not written), err = e (complex128 or complex64 storage), and
+// out[j] = Re <e, y_j> for j < m over the stored values (y[self] is err); partials:
+// m*UPD_BLOCKS
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
+                        int self, double *partials, double *out, hipStream_t st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cf *err, cd *hist, const cf *const *y, int m,
                         int self, double *partials, double *out, hipStream_t st);
 // dst = sum_j c[j] * src_j over n complex elements (m <= 16)
 void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st);

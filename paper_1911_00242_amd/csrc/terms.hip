@@ -588,7 +588,7 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
 // a thread owns (n, i) and two j.  LDS rows are padded to n_vir + 1 and ordered so that
 // the lanes of a wave (consecutive n, then i) read distinct banks.
 template <int OM, int VM>
-__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT);
+__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon);
 
 // ------------------------------------------------------------------ XCD-aware block order
 // Workgroup w runs on XCD w % 8; give each XCD a contiguous range of logical blocks so
@@ -852,9 +852,15 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
 
 template <int OM, int VM>
 __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd *Q) {
-    __shared__ cd GS[VM * OM * (VM + 1)];  // <m b||e j> of this m at (b * no + j) * (nv + 1) + e
-    __shared__ cd T1I[OM * VM];            // t1[ki](i, e)
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vp = nv + 1;
+    // The <m b||e j> slab of this m goes through LDS EP values of e at a time (so that
+    // many workgroups fit on a CU), at e * (no * nv + 1) + j * nv + b: a lane (j, b) reads
+    // consecutive words, and the staging writes (consecutive e) are one padded row apart.
+    // The next phase's slab is loaded into registers while the current one is used.
+    constexpr int EP = 4;
+    constexpr int NT = OM * VM;
+    __shared__ cd GS[EP * (OM * VM + 1)];
+    __shared__ cd T1I[OM * VM];  // t1[ki](i, e)
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, rp = no * nv + 1;
     const int64_t o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
     const int64_t L = xcd_block(nblk);
@@ -863,27 +869,59 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     const int64_t blk = L / no;
     const int ki = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
     const int kj = kcv(s.kc, N, ka, kb, ki);
-    const cd *gb = s.ovvoT + blk * s.d.t2blk() + (int64_t)m * nv * no * nv;
-    for (int x = threadIdx.x; x < nv * no * nv; x += blockDim.x) GS[(x / nv) * vp + x % nv] = gb[x];
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
-    __syncthreads();
-    const int jb = threadIdx.x;
-    if (jb >= no * nv) return;
-    const int j = jb / nv, b = jb % nv;
-    cd gr[VM];
+    const cd *gb = s.ovvoT + blk * s.d.t2blk() + (int64_t)m * nv * no * nv;  // (b, j, e)
+    const int nph = no * nv * EP;  // staged elements per phase
+    cd st[EP];
+    auto load_phase = [&](int e0) {
 #pragma unroll
-    for (int e = 0; e < VM; ++e) gr[e] = e < nv ? GS[(b * no + j) * vp + e] : make_double2(0.0, 0.0);
+        for (int u = 0; u < EP; ++u) {
+            const int x = threadIdx.x + u * NT;  // (bj, el) with el fastest
+            const int bj = x / EP, e = e0 + x % EP;
+            st[u] = x < nph && e < nv ? gb[(int64_t)bj * nv + e] : make_double2(0.0, 0.0);
+        }
+    };
+    auto store_phase = [&]() {
+#pragma unroll
+        for (int u = 0; u < EP; ++u) {
+            const int x = threadIdx.x + u * NT, bj = x / EP, el = x % EP;
+            if (x < nph) GS[el * rp + (bj % no) * nv + bj / no] = st[u];
+        }
+    };
+    load_phase(0);
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
+    const int jb = threadIdx.x;
+    const bool act = jb < no * nv;
+    cd acc[OM];
+#pragma unroll
+    for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int e0 = 0; e0 < nv; e0 += EP) {
+        if (e0 > 0) __syncthreads();  // every read of the previous phase is done
+        store_phase();
+        __syncthreads();
+        if (e0 + EP < nv) load_phase(e0 + EP);
+        if (act) {
+#pragma unroll
+            for (int el = 0; el < EP; ++el) {
+                if (e0 + el >= nv) break;
+                const cd g = GS[el * rp + jb];
+#pragma unroll
+                for (int i = 0; i < OM; ++i)
+                    if (i < no) cfma(acc[i], T1I[i * nv + e0 + el], g);
+            }
+        }
+    }
+    if (!act) return;
+    const int j = jb / nv, b = jb % nv;
     const cd *h = s.ooov + blk3(N, ki, kj, ka) * o3v + ((int64_t)j * no + m) * nv + b;
     cd *qo = Q + blk * o3v + (int64_t)m * no * no * nv + jb;
-    for (int i = 0; i < no; ++i) {
-        cd acc = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int e = 0; e < VM; ++e)
-            if (e < nv) cfma(acc, T1I[i * nv + e], gr[e]);
+    for (int i = 0; i < OM; ++i) {
+        if (i >= no) break;
         const cd x = h[(int64_t)i * no * no * nv];
-        acc.x += 0.5 * x.x;
-        acc.y -= 0.5 * x.y;
-        qo[(int64_t)i * no * nv] = acc;
+        cd v = acc[i];
+        v.x += 0.5 * x.x;
+        v.y -= 0.5 * x.y;
+        qo[(int64_t)i * no * nv] = v;
     }
 }
 
@@ -947,7 +985,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
                                                     const cd *Fot, const cd *Fvt, cd *X) {
     constexpr int IH = (OM + 1) / 2;  // i values per LDS phase
     constexpr int NT = OM * VM;       // threads
-    __shared__ cd T2S[IH * OM * VM];  // t2[ki,kj,ka](i0 + il, n, a, b) at (il * no + n) * nv + b
+    __shared__ cd T2S[IH * OM * (VM + 1)];  // t2[ki,kj,ka](i0 + il, n, a, b) at (il * no + n) * (nv + 1) + b
     __shared__ cd FV[VM * VM];        // 1/2 Fvt[kb](b, f) at f * nv + b
     __shared__ cd FO[OM * OM];        // -1/2 Fot[kj](n, j)
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
@@ -969,11 +1007,12 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
             st[u] = x < nh && i < no ? tb[((int64_t)i * no + (x / nv) % no) * nv * nv + x % nv] : make_double2(0.0, 0.0);
         }
     };
+    const int vp = nv + 1;  // padded rows: the lanes of different j read different banks
     auto store_half = [&]() {
 #pragma unroll
         for (int u = 0; u < IH; ++u) {
             const int x = threadIdx.x + u * NT;
-            if (x < nh) T2S[x] = st[u];
+            if (x < nh) T2S[(x / nv) * vp + x % nv] = st[u];
         }
     };
     load_half(0);
@@ -1030,7 +1069,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
                 const cd fv = FV[f * nv + b];
 #pragma unroll
                 for (int il = 0; il < IH; ++il)
-                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + j) * nv + f], fv);
+                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + j) * vp + f], fv);
             }
             // -1/2 sum_n t_in^ab Fot[kj](n, j)
 #pragma unroll
@@ -1039,7 +1078,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
                 const cd fo = FO[n * no + j];
 #pragma unroll
                 for (int il = 0; il < IH; ++il)
-                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + n) * nv + b], fo);
+                    if (i0 + il < no) cfma(acc[i0 + il], T2S[(il * no + n) * vp + b], fo);
             }
         }
     }
@@ -1208,7 +1247,7 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
 }
 
 template <int OM, int VM>
-__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT) {
+__global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon) {
     static_assert(OM == 8, "thread roles assume n_occ <= 8");
     constexpr int VP = VM + 1;
     __shared__ cd A1[OM * OM * VP];  // <m km, n kn||i ki, e> at (i * OM + n) * VP + e
@@ -1218,12 +1257,16 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o4 = (int64_t)no * no * no * no, o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
-    const int64_t L = xcd_block(nblk);
+    // canon: only blocks holding canonical (ki, i, j) rows and (km, m, n) columns (ki <= kj,
+    // km <= kn) are needed; the others exit, and plain launch order spreads the rest evenly
+    // over the XCDs
+    const int64_t L = canon ? (int64_t)blockIdx.x : xcd_block(nblk);
     if (L >= nblk) return;
     const int m = (int)(L % no);
     const int64_t blk = L / no;
     const int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
     const int kn = kcv(s.kc, N, ki, kj, km);
+    if (canon && (ki > kj || km > kn)) return;
     const cd *g1 = s.ooov + blk3(N, km, kn, ki) * o3v + (int64_t)m * no * no * nv;  // (n, i, e)
     const cd *g2 = s.ooov + blk3(N, km, kn, kj) * o3v + (int64_t)m * no * no * nv;  // (n, j, e)
     const cd *g0 = s.oooo + blk3(N, km, kn, ki) * o4 + (int64_t)m * no * no * no;    // (n, i, j)
@@ -1259,10 +1302,10 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
     }
 }
 
-void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
+void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_wmnij_init_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, WT);
+        hipLaunchKernelGGL((k_wmnij_init_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, WT, canon);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
