@@ -68,20 +68,6 @@ __global__ void k_block_transpose(Dims d, const cd *src, cd *dst) {
 
 // ------------------------------------------------------------------ F intermediates
 // Fov[k](m,e) = f_me + sum_{kn,n,f} t_n^f <m k, n kn || e k, f kn>
-__global__ void k_fov(SysDev s, const cd *t1, cd *Fov) {
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
-    GRID_STRIDE(idx, (int64_t)N * no * nv) {
-        int e = (int)(idx % nv), m = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
-        cd acc = s.fock[((int64_t)k * n + m) * n + no + e];
-        for (int kn = 0; kn < N; ++kn) {
-            const cd *g = s.oovv + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)m * no * nv * nv;
-            const cd *t = t1 + (int64_t)kn * no * nv;
-            for (int nn = 0; nn < no; ++nn)
-                for (int f = 0; f < nv; ++f) cfma(acc, t[nn * nv + f], g[((int64_t)nn * nv + e) * nv + f]);
-        }
-        Fov[idx] = acc;
-    }
-}
 
 // Partial sums of the tau-tilde terms of F_oo and F_vv, one per momentum block:
 //   Poo[k][kn][ke](m,i) = 1/2 sum_{n,e,f} taut[k,kn,ke](i,n,e,f) <m k, n kn || e ke, f kf>
@@ -202,9 +188,12 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
 template <int OM, int VM>
 __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
     static_assert(OM % 8 == 0 && VM % 16 == 0, "tiling");
-    constexpr int VP = VM + 1, SL = OM * VM * VP;
+    // taut(x, n, e, f) and <x n||e f> at x * RX + e * VP + f: rows padded to VP = VM + 1 and
+    // row blocks to RX = VM * VP + 1, so that the lanes of one 8-lane group read distinct
+    // banks in both role layouts below
+    constexpr int VP = VM + 1, RX = VM * VP + 1, SL = OM * RX;
     constexpr int PER = OM * VM * VM / 256;  // slab elements staged per thread
-    __shared__ cd TS[SL], GS[SL];            // taut(x, n, e, f), <x n||e f> at (x * VM + e) * VP + f
+    __shared__ cd TS[SL], GS[SL];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
@@ -228,12 +217,13 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
         const int x = tid + 256 * u;                                                            \
         const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
-        TS[(row * VM + e) * VP + f] = pt[u];                                                    \
-        GS[(row * VM + e) * VP + f] = pg[u];                                                    \
+        TS[row * RX + e * VP + f] = pt[u];                                                      \
+        GS[row * RX + e * VP + f] = pg[u];                                                      \
     }
-    // Fvv roles: tile (a0, e0), m quarter
+    // Fvv roles: outputs (a0 + 8 da, e0 + 8 de), m quarter; the eight lanes of a group share
+    // a0 (one broadcast row) and take eight consecutive e0
     const int vs = tid / 64, vt = tid % 64;
-    const int a0 = 2 * (vt / (VM / 2) % (VM / 2)), e0 = 2 * (vt % (VM / 2));
+    const int a0 = vt / (VM / 2), e0 = vt % (VM / 2);
     // (VM = 16: 64 tiles of 2 x 2 cover 16 x 16)
     // Foo roles: tile (m0, i0), (e, f) sixteenth
     const int os = tid / 16, ot = tid % 16;
@@ -251,8 +241,8 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
             const int m = vs * (OM / 4) + mm;
 #pragma unroll 4
             for (int f = 0; f < VM; ++f) {
-                const cd ta0 = TS[(m * VM + a0) * VP + f], ta1 = TS[(m * VM + a0 + 1) * VP + f];
-                const cd ge0 = GS[(m * VM + e0) * VP + f], ge1 = GS[(m * VM + e0 + 1) * VP + f];
+                const cd ta0 = TS[m * RX + a0 * VP + f], ta1 = TS[m * RX + (a0 + VM / 2) * VP + f];
+                const cd ge0 = GS[m * RX + e0 * VP + f], ge1 = GS[m * RX + (e0 + VM / 2) * VP + f];
                 cfma(v00, ta0, ge0);
                 cfma(v01, ta0, ge1);
                 cfma(v10, ta1, ge0);
@@ -263,8 +253,8 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
 #pragma unroll 4
         for (int k = 0; k < VM * VM / 16; ++k) {
             const int ef = os * (VM * VM / 16) + k, e = ef / VM, f = ef % VM;
-            const cd ti0 = TS[(i0 * VM + e) * VP + f], ti1 = TS[((i0 + 1) * VM + e) * VP + f];
-            const cd gm0 = GS[(m0 * VM + e) * VP + f], gm1 = GS[((m0 + 1) * VM + e) * VP + f];
+            const cd ti0 = TS[i0 * RX + e * VP + f], ti1 = TS[(i0 + 1) * RX + e * VP + f];
+            const cd gm0 = GS[m0 * RX + e * VP + f], gm1 = GS[(m0 + 1) * RX + e * VP + f];
             cfma(o00, ti0, gm0);
             cfma(o01, ti1, gm0);
             cfma(o10, ti0, gm1);
@@ -300,7 +290,7 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
         cd sum = {0, 0};
         for (int k = 0; k < 4; ++k) sum = cadd(sum, rv[k * 256 + tid]);
         const int t = tid / 4, c = tid % 4;
-        const int a = 2 * (t / (VM / 2)) + c / 2, e = 2 * (t % (VM / 2)) + c % 2;
+        const int a = t / (VM / 2) + (VM / 2) * (c / 2), e = t % (VM / 2) + (VM / 2) * (c % 2);
         if (a < nv && e < nv) Pvv[(((int64_t)r * N + p) * N + q) * nv * nv + (int64_t)a * nv + e] = cscale(sum, -0.5);
     }
 }
@@ -489,6 +479,24 @@ __device__ inline cd wave_sum(cd v) {
         v.y += __shfl_xor(v.y, o, 64);
     }
     return v;
+}
+
+// F_ov[k](m,e) = f_me + sum_{kn,n,f} t_{n kn}^{f kn} <m k, n kn || e k, f kn>: one wave per
+// output element, the lanes over (kn, n, f) (runs of n_vir contiguous integrals), then a
+// fixed-order wave reduction.
+__global__ __launch_bounds__(64) void k_fov(SysDev s, const cd *t1, cd *Fov) {
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv, ov = no * nv;
+    const int64_t idx = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int e = (int)(idx % nv), m = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
+    cd acc = make_double2(0.0, 0.0);
+    for (int u = lane; u < N * ov; u += 64) {
+        const int kn = u / ov, nn = (u / nv) % no, f = u % nv;
+        const cd *g = s.oovv + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)m * no * nv * nv;
+        cfma(acc, t1[(int64_t)u], g[((int64_t)nn * nv + e) * nv + f]);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) Fov[idx] = cadd(s.fock[((int64_t)k * n + m) * n + no + e], acc);
 }
 
 __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd *Fov, const cd *Poo,
@@ -1228,7 +1236,8 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
 
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
-    LAUNCH(k_fov, N * no * nv, s, t1, w.Fov);
+    hipLaunchKernelGGL(k_fov, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
+    CK_CHECK(hipGetLastError());
     if (no <= 8 && nv <= 16) {
         hipLaunchKernelGGL((k_f_blocks_t<8, 16>), dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t1, t2, w.Poo,
                            w.Pvv);
