@@ -185,7 +185,7 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
 // used from LDS.  Fvv: a thread owns a 2 x 2 (a, e) tile and a quarter of the m range;
 // Foo: a thread owns a 2 x 2 (m, i) tile and one sixteenth of the (e, f) range; each LDS
 // read feeds two multiply-adds.  Partial sums are combined through LDS at the end.
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
     static_assert(OM % 8 == 0 && VM % 16 == 0, "tiling");
     // taut(x, n, e, f) and <x n||e f> at x * RX + e * VP + f: rows padded to VP = VM + 1 and
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
     constexpr int VP = VM + 1, RX = VM * VP + 1, SL = OM * RX;
     constexpr int PER = OM * VM * VM / 256;  // slab elements staged per thread
     __shared__ cd TS[SL], GS[SL];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
 // staged in LDS (the next n prefetched into registers).  For P1a a thread owns one a and
 // a sixteenth of (e, f) and streams <n q, a p||e r, f> from global memory once, for every
 // i; for P1b a thread owns one (i, a) and half of the m range.
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
     static_assert(OM == 8 && VM == 16, "thread roles assume n_occ <= 8, n_vir <= 16");
     constexpr int VP = VM + 1;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     constexpr int PT = OM * VM * VM / 256, PH = OM * OM * VM / 256;
     __shared__ cd TS[TSL];  // t2(x, n, e, f) at (x * VM + e) * VP + f
     __shared__ cd HS[HSL];  // <m p, n q||i r, f> at (m * OM + i) * VP + f
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
@@ -595,7 +595,7 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
 // both t1 blocks in LDS, so every ooov / oooo element is read once with contiguous loads;
 // a thread owns (n, i) and two j.  LDS rows are padded to n_vir + 1 and ordered so that
 // the lanes of a wave (consecutive n, then i) read distinct banks.
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon);
 
 // ------------------------------------------------------------------ XCD-aware block order
@@ -782,10 +782,10 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
 // (momentum block, m), XCD-contiguous order.  Each thread keeps the integral row it
 // contracts (over f or e) in registers and produces the outputs of every j (or i), so
 // every <oo||vv>, <ov||vv> and <ov||vo> element is read once instead of n_occ times.
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd *Z) {
     __shared__ cd T1J[OM * VM];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
     const int64_t L = xcd_block(nblk);
@@ -816,11 +816,11 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd
     }
 }
 
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, const cd *Z, cd *WR) {
     __shared__ cd ZS[OM * OM * VM];  // Z(m, n, j, e) of this m at (n * no + j) * nv + e
     __shared__ cd T1J[OM * VM];      // t1[kj](j, f)
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t ov = (int64_t)no * nv, blkq = ov * ov;
     const int64_t o3v = (int64_t)no * no * no * nv, ov3 = (int64_t)no * nv * nv * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
     }
 }
 
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd *Q) {
     // The <m b||e j> slab of this m goes through LDS EP values of e at a time (so that
     // many workgroups fit on a CU), at e * (no * nv + 1) + j * nv + b: a lane (j, b) reads
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     constexpr int NT = OM * VM;
     __shared__ cd GS[EP * (OM * VM + 1)];
     __shared__ cd T1I[OM * VM];  // t1[ki](i, e)
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, rp = no * nv + 1;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv, rp = no * nv + 1;
     const int64_t o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
     const int64_t L = xcd_block(nblk);
@@ -988,7 +988,7 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 // at wave-uniform addresses (scalar loads).  The coefficients -1, -1/2, 1/2, -1/2 of the four
 // terms are folded into one factor of each product (exact scalings), so one accumulator per
 // i takes all of them.
-template <int OM, int VM>
+template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
                                                     const cd *Fot, const cd *Fvt, cd *X) {
     constexpr int IH = (OM + 1) / 2;  // i values per LDS phase
@@ -996,7 +996,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
     __shared__ cd T2S[IH * OM * (VM + 1)];  // t2[ki,kj,ka](i0 + il, n, a, b) at (il * no + n) * (nv + 1) + b
     __shared__ cd FV[VM * VM];        // 1/2 Fvt[kb](b, f) at f * nv + b
     __shared__ cd FO[OM * OM];        // -1/2 Fot[kj](n, j)
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t ov = (int64_t)no * nv, ov3 = ov * nv * nv, o3v = ov * no * no;
     const int64_t nblk = (int64_t)N * N * N * nv;
     const int64_t L = xcd_block(nblk);
@@ -1234,14 +1234,24 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
     CK_CHECK(hipGetLastError());
 }
 
+// the blocked side kernels at the workload's exact block shape (n_occ = 8, n_vir = 16) take
+// the sizes as constants: every bound check folds away and index divisions become shifts
+#define LAUNCH_T(K, grid, block, ...)                                                     \
+    do {                                                                                  \
+        if (s.d.no == 8 && s.d.nv == 16)                                                  \
+            hipLaunchKernelGGL((K<8, 16, true>), grid, block, 0, st, __VA_ARGS__);        \
+        else                                                                              \
+            hipLaunchKernelGGL((K<8, 16, false>), grid, block, 0, st, __VA_ARGS__);       \
+        CK_CHECK(hipGetLastError());                                                      \
+    } while (0)
+
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     hipLaunchKernelGGL(k_fov, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
     CK_CHECK(hipGetLastError());
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_f_blocks_t<8, 16>), dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t1, t2, w.Poo,
+        LAUNCH_T(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo,
                            w.Pvv);
-        CK_CHECK(hipGetLastError());
     } else if (f_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
@@ -1255,7 +1265,7 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     LAUNCH(k_ftilde, N * no * no + N * nv * nv, s.d, t1, w.Foo, w.Fvv, w.Fov, w.Fot, w.Fvt);
 }
 
-template <int OM, int VM>
+template <int OM, int VM, bool EX>
 __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon) {
     static_assert(OM == 8, "thread roles assume n_occ <= 8");
     constexpr int VP = VM + 1;
@@ -1263,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
     __shared__ cd A2[OM * OM * VP];  // <m km, n kn||j kj, e> at (j * OM + n) * VP + e
     __shared__ cd T1I[OM * VP], T1J[OM * VP];
     __shared__ cd O4[OM * OM * OM];  // <m km, n kn||i ki, j kj> at (n * OM + i) * OM + j
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t o4 = (int64_t)no * no * no * no, o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
     // canon: only blocks holding canonical (ki, i, j) rows and (km, m, n) columns (ki <= kj,
@@ -1314,8 +1324,7 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_wmnij_init_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, WT, canon);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_T(k_wmnij_init_t, xcd_grid(N * N * N * no), dim3(256), s, t1, WT, canon);
     } else {
         LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
     }
@@ -1349,21 +1358,17 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
     const int64_t n3 = N * N * N;
     if (no <= 8 && nv <= 16) {
         const dim3 grid = xcd_grid(n3 * no);
-        hipLaunchKernelGGL((k_ring_z_t<8, 16>), grid, dim3(8 * 16), 0, st, s, t1, scratch);
-        CK_CHECK(hipGetLastError());
-        hipLaunchKernelGGL((k_ring_w0_t<8, 16>), grid, dim3(16 * 16), 0, st, s, t1, scratch, WR);
-        CK_CHECK(hipGetLastError());
-        hipLaunchKernelGGL((k_ring_q_t<8, 16>), grid, dim3(8 * 16), 0, st, s, t1, scratch);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_T(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
+        LAUNCH_T(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
+        LAUNCH_T(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
     } else {
         LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
         LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
         LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
     }
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_xinit_t<8, 16>), xcd_grid(n3 * nv), dim3(8 * 16), 0, st, s, t1, t2, scratch, w.Fot,
+        LAUNCH_T(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot,
                            w.Fvt, X);
-        CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }
@@ -1379,8 +1384,7 @@ void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
     if (no <= 8 && nv <= 16) {
-        hipLaunchKernelGGL((k_r1_blocks_t<8, 16>), dim3((unsigned)(N * N * N)), dim3(256), 0, st, s, t2, P1, P1 + np);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_T(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
         hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
         CK_CHECK(hipGetLastError());
     } else if (r1_blocks_fit(s.d)) {

@@ -57,6 +57,8 @@ RES_CASES = [
     ((2, 2, 1), 3, 5, False),
     ((1, 1, 1), 5, 7, True),
     ((3, 1, 1), 1, 1, False),
+    # the block shape of the N_k=27 workload, which the blocked side kernels take as constants
+    ((2, 1, 1), 8, 16, False),
     # sizes past the register / LDS bounds of the blocked side kernels (other code paths)
     ((2, 1, 1), 10, 3, False),
     ((1, 1, 1), 17, 2, False),
