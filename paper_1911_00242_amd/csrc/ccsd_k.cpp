@@ -510,8 +510,9 @@ void bind_ops(System &S) {
 }
 
 // ---------------------------------------------------------------- timing
-void stage_begin(ccsd_k_ctx *c, EventPair &ep, int stage) {
+void stage_begin(ccsd_k_ctx *c, EventPair &ep, int stage, hipStream_t st = nullptr) {
     if (!c->timing) return;
+    if (!st) st = c->stream;
     if (c->pool.empty()) {
         EventPair p;
         CK_CHECK(hipEventCreate(&p.a));
@@ -521,11 +522,11 @@ void stage_begin(ccsd_k_ctx *c, EventPair &ep, int stage) {
     ep = c->pool.back();
     c->pool.pop_back();
     ep.stage = stage;
-    CK_CHECK(hipEventRecord(ep.a, c->stream));
+    CK_CHECK(hipEventRecord(ep.a, st));
 }
-void stage_end(ccsd_k_ctx *c, EventPair &ep) {
+void stage_end(ccsd_k_ctx *c, EventPair &ep, hipStream_t st = nullptr) {
     if (!c->timing) return;
-    CK_CHECK(hipEventRecord(ep.b, c->stream));
+    CK_CHECK(hipEventRecord(ep.b, st ? st : c->stream));
     c->pending.push_back(ep);
 }
 void collect_timing(ccsd_k_ctx *c) {
@@ -541,12 +542,13 @@ void collect_timing(ccsd_k_ctx *c) {
     c->pending.clear();
 }
 
-void run_gemm(ccsd_k_ctx *c, System &S, int i) {
+void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st = nullptr) {
+    if (!st) st = c->stream;
     EventPair ep{};
-    stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage);
-    if (S.mixed) ck::gemm_split(S.sg[i], c->stream);
-    else ck::gemm_f64(S.g[i].op, c->stream);
-    stage_end(c, ep);
+    stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage, st);
+    if (S.mixed) ck::gemm_split(S.sg[i], st);
+    else ck::gemm_f64(S.g[i].op, st);
+    stage_end(c, ep, st);
 }
 
 // One evaluation of (R1, R2) at the current amplitudes, left in S.res.
@@ -557,28 +559,32 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     stage_begin(c, all, ST_RES);
     if (!S.mixed) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
-    } else {
-        ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
-        const int64_t R = S.PV + S.PO;
-        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
-    }
-    ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
-    ck::launch_wmnij_init(s, S.t1(), S.WT, S.mixed, st);
-    run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>  (mixed: written split)
-    if (!S.mixed) ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
-    else ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, S.PV + S.PO, st);
-    ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
-    run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>  (mixed: written split)
-    run_gemm(c, S, 4);  // X += t2 W_mbej
-    if (!S.mixed) {
+        ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
+        ck::launch_wmnij_init(s, S.t1(), S.WT, false, st);
+        run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>
+        ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+        ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
+        run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
+        run_gemm(c, S, 4);  // X += t2 W_mbej
         ck::launch_assemble_r2(s, S.X, S.r2(), st);
         run_gemm(c, S, 1);  // particle-particle ladder
         run_gemm(c, S, 2);  // hole-hole ladder
+        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
+        const int64_t R = S.PV + S.PO;
+        ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
+        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
+        ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
+        ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
+        run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
+        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, st);
+        ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
+        run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>, written split
+        run_gemm(c, S, 4);  // X += t2 W_mbej
         run_gemm(c, S, 1);  // both ladders on canonical pairs, into Lp
         ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2(), S.npart, st);
+        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     }
-    ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     stage_end(c, all);
 }
 

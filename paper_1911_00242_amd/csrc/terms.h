@@ -28,6 +28,11 @@ void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st);
 // ovvv and oovv with their last two indices swapped (once per set of inputs)
 void launch_static_swaps(const SysDev &s, cd *ovvvT, cd *oovvT, hipStream_t st);
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
+// the two halves of launch_r1: the t2 x integral partial sums (which need no intermediate),
+// then R1 from t1, t2, F and those partials
+void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st);
+void launch_r1_final(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, const cd *P1, cd *r1,
+                     hipStream_t st);
 
 // reductions (deterministic: fixed grid, fixed-order partial sums) -------------------
 constexpr int RED_BLOCKS = 1024;

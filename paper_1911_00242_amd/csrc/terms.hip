@@ -1380,23 +1380,32 @@ void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st) {
     CK_CHECK(hipGetLastError());
 }
 
-void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st) {
+static bool r1_two_parts(const Dims &d) { return (d.no <= 8 && d.nv <= 16) || r1_blocks_fit(d); }
+
+void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
     if (no <= 8 && nv <= 16) {
         LAUNCH_T(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
-        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
-        CK_CHECK(hipGetLastError());
     } else if (r1_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(RB_NT), 0, st, s, t2, P1, P1 + np);
         CK_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 2, r1);
-        CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_r1_partial, N * N * N * no * nv, s, t2, P1);
-        hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1, 1, r1);
-        CK_CHECK(hipGetLastError());
     }
+}
+
+void launch_r1_final(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, const cd *P1, cd *r1,
+                     hipStream_t st) {
+    const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
+    hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1,
+                       r1_two_parts(s.d) ? 2 : 1, r1);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st) {
+    launch_r1_partials(s, t2, P1, st);
+    launch_r1_final(s, t1, t2, w, P1, r1, st);
 }
 
 }  // namespace ck
