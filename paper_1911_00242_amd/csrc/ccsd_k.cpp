@@ -17,6 +17,7 @@
 
 #include "common.h"
 #include "mixed.h"
+#include "pack.h"
 #include "terms.h"
 
 namespace {
@@ -75,6 +76,11 @@ struct System {
     uint16_t *pk_A = nullptr, *pk_B = nullptr, *pk_oovv = nullptr;
     cd *Lp = nullptr;  // [K][canonical (ki,i,j)][canonical (ka,a,b)]: both ladders' contribution to R2
     double *npart = nullptr;  // per-workgroup sums of |r2|^2 written by the R2 assembly
+    // the DIIS extrapolation of the mixed path also leaves the split copy of the new t2 and
+    // the energy partial sums at the new amplitudes; these flags say they match the
+    // current amplitudes (cleared by every other write of the amplitudes or the inputs)
+    double *epart = nullptr;
+    bool sp_ok = false, e_ok = false;
     ck::SplitOps sg[5];
     // host state
     int diis_n = 0, diis_head = 0;
@@ -409,6 +415,7 @@ void carve(System &S, Carver &c) {
         c.take(S.pk_oovv, 4 * N * PO * PV);
         c.take(S.Lp, N * PO * PV);
         c.take(S.npart, ck::assemble_pack_blocks(S.d, S.pairs()));
+        c.take(S.epart, 2 + 2 * (int64_t)ck::lincomb_t2_blocks(S.d));
         c.take(S.dptab, (int64_t)S.ptab.size());
     }
     c.take(S.WT, N3 * cls[0]);
@@ -572,7 +579,8 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
         const int64_t R = S.PV + S.PO;
-        ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
+        if (!S.sp_ok) ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
+        S.sp_ok = true;
         ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
         ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
@@ -587,6 +595,9 @@ void residual_device(ccsd_k_ctx *c, System &S) {
     }
     stage_end(c, all);
 }
+
+// every write of the amplitudes other than the mixed DIIS extrapolation
+void amplitudes_changed(System &S) { S.sp_ok = S.e_ok = false; }
 
 // ||R||^2 into S.redout[0] after residual_device (the mixed assembly left partial sums)
 void launch_norm(ccsd_k_ctx *c, System &S) {
@@ -734,6 +745,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
             CK_CHECK(hipMemcpyAsync(S.dtab, S.tables.data(), S.tables.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                                     ctx->stream));
             CK_CHECK(hipMemsetAsync(S.amp, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            amplitudes_changed(S);
             CK_CHECK(hipMemsetAsync(S.res, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.zeros, 0, 16 * sizeof(cd), ctx->stream));
             if (S.mixed) {
@@ -794,6 +806,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
         ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
         if (S.mixed) static_split(S, ctx->stream);
+        S.e_ok = false;
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
@@ -809,6 +822,7 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
     try {
         if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        if (t1 || t2) amplitudes_changed(S);
         residual_device(ctx, S);
         launch_norm(ctx, S);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
@@ -859,6 +873,7 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 int m = S->desc.diis_space;
                 if (m == 0) {
                     ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, ctx->stream);
+                    amplitudes_changed(*S);
                     continue;
                 }
                 int slot = S->diis_head;
@@ -897,7 +912,14 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                     src.push_back(S->dvec[slot]);
                     coef.assign(1, 1.0);
                 }
-                ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), (int)src.size(), S->amp, ctx->stream);
+                if (S->mixed) {
+                    ck::launch_lincomb_pack(S->dev(), src.data(), coef.data(), (int)src.size(), S->amp, S->sp_t2,
+                                            S->epart, ctx->stream);
+                    S->sp_ok = S->e_ok = true;
+                } else {
+                    ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), (int)src.size(), S->amp,
+                                       ctx->stream);
+                }
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             collect_timing(ctx);
@@ -931,7 +953,8 @@ int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
     System &S = ctx->sys[sys];
     double e[2] = {0.0, 0.0};
     try {
-        ck::launch_energy(S.dev(), S.t1(), S.t2(), S.red, S.redout, ctx->stream);
+        if (S.e_ok) ck::launch_energy_pack(S.d, S.epart, S.redout, ctx->stream);
+        else ck::launch_energy(S.dev(), S.t1(), S.t2(), S.red, S.redout, ctx->stream);
         CK_CHECK(hipMemcpyAsync(e, S.redout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &er) {
@@ -964,6 +987,7 @@ int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const 
     try {
         if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+        amplitudes_changed(S);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);

@@ -40,17 +40,6 @@ __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
                           h[p][4] | (uint32_t)h[p][5] << 16, h[p][6] | (uint32_t)h[p][7] << 16);
 }
 
-// Canonical pairs of each group of total pair momentum K (pack.hip): vlist[K*PV + p] =
-// (kx*nv + x)*nv + y for the p-th canonical virtual pair of group K, -1 in the padding;
-// olist likewise for occupied pairs (PO); vpos[(K*N + kx)*nv*nv + x*nv + y] = p, or -1
-// when (kx, x, y) is not canonical.  PV and PO are multiples of 16.  dblk lists the ndblk
-// momentum blocks (ka*N + kb)*N + ke with ka <= kb and ke <= kf, the only ones holding
-// canonical (a,b) and (e,f) pairs.
-struct PairTabs {
-    const int32_t *vlist, *olist, *vpos, *opos, *dblk, *ablk;
-    int PV, PO, ndblk, nablk;
-};
-
 // Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element
 // offsets into the unsplit operand, mapped through split_index).  C is complex128.
 // fast = 1 when every aligned group of 8 k indices is contiguous and starts at a multiple
@@ -75,23 +64,5 @@ struct SplitOps {
 void gemm_split(const SplitOps &op, hipStream_t s);
 // split storage of n complex128 elements (pad of the last chunk zeroed)
 void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st);
-// packed ladder operands in split storage (pack.hip), rows ld elements apart: tau rows
-// [K][(ki,i,j)][PV] and its hole-hole form [K][PV][PO]; <mn||ef> as [K][PO][PV]; the
-// dressed <ab||ef> as [K][PV][PV]
-bool dress_pack_ok(const Dims &d);
-void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
-                     uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st);
-void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
-                      hipStream_t st);
-// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry;
-// npart (assemble_pack_blocks doubles) receives per-workgroup sums of |r2|^2
-int64_t assemble_pack_blocks(const Dims &d, const PairTabs &pt);
-void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2, double *npart,
-                             hipStream_t st);
-// out[0] = sum |r1|^2 + sum |r2|^2 from the assembly's partial sums (fixed order)
-void launch_norm_pack(const Dims &d, const PairTabs &pt, const double *npart, const cd *r1, double *out,
-                      hipStream_t st);
-void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
-                            hipStream_t st);
 
 }  // namespace ck

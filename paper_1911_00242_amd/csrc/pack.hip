@@ -11,8 +11,11 @@
 // group in a fixed order padded with zeros to a multiple of 16, and take an eighth of the
 // work of the full products; their result stays packed (Lp) until the R2 assembly expands
 // it.  Every packed operand is written here in split storage.
+#include <algorithm>
+
 #include "common.h"
 #include "mixed.h"
+#include "pack.h"
 
 namespace ck {
 
@@ -420,6 +423,150 @@ void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, c
     if (nb == 0) return;
     const size_t lds = nv <= ASMP_VMAX ? (size_t)4 * nv * (nv + 1) * sizeof(cd) : 0;
     hipLaunchKernelGGL(k_assemble_r2_pack, dim3((unsigned)nb), dim3(256), lds, st, s, pt, X, Lp, r2, npart);
+    CK_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ DIIS extrapolation
+// t <- sum_j c_j src_j for the mixed path, split in two passes over the (t1 | t2) vector:
+// the t1 part (with the f_ia t_i^a term of the correlation energy), then the t2 part, which
+// also writes the split copy of t2 that the next residual's products read and the t2 terms
+// of the energy at the new amplitudes (they need the new t1, hence the order).  The energy
+// is 1/4 <ij||ab> t_ij^ab + 1/2 <ij||ab> t_i^a t_j^b (k_a = k_i) summed over every stored
+// element, plus sum f_ia t_i^a, exactly as the stand-alone energy pass.
+
+__device__ inline void blk_sum2(double &x, double &y, double (*sh)[256]) {
+    const int t = threadIdx.x;
+    sh[0][t] = x;
+    sh[1][t] = y;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    x = sh[0][0];
+    y = sh[1][0];
+}
+
+__global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, int m, cd *t, double *ep1) {
+    __shared__ double sh[2][256];
+    const int no = s.d.no, nv = s.d.nv, n = no + nv;
+    const int64_t n1 = s.d.t1();
+    double er = 0.0, ei = 0.0;
+    for (int64_t idx = threadIdx.x; idx < n1; idx += 256) {
+        cd acc = make_double2(0.0, 0.0);
+        for (int j = 0; j < m; ++j) {
+            const cd x = L.src[j][idx];
+            acc.x = fma(L.c[j], x.x, acc.x);
+            acc.y = fma(L.c[j], x.y, acc.y);
+        }
+        t[idx] = acc;
+        const int a = (int)(idx % nv), i = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
+        const cd p = cmul(s.fock[((int64_t)k * n + i) * n + no + a], acc);
+        er += p.x;
+        ei += p.y;
+    }
+    blk_sum2(er, ei, sh);
+    if (threadIdx.x == 0) {
+        ep1[0] = er;
+        ep1[1] = ei;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int m, cd *t, uint16_t *sp, double *ep2) {
+    __shared__ __attribute__((aligned(16))) uint16_t S[4][2048];
+    __shared__ double sh[2][256];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
+    const int64_t nch = (n2 + 7) / 8;
+    const int tid = threadIdx.x;
+    const cd *t1 = t;  // the new t1, written by k_lincomb_t1
+    double er = 0.0, ei = 0.0;
+    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < nch; c0 += (int64_t)gridDim.x * 256) {
+        const int64_t e0 = c0 * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t e = e0 + tid + 256 * q;
+            cd acc = make_double2(0.0, 0.0);
+            if (e < n2) {
+                for (int j = 0; j < m; ++j) {
+                    const cd x = L.src[j][n1 + e];
+                    acc.x = fma(L.c[j], x.x, acc.x);
+                    acc.y = fma(L.c[j], x.y, acc.y);
+                }
+                t[n1 + e] = acc;
+                const int64_t blk = e / bs;
+                const int x = (int)(e - blk * bs);
+                const int b = x % nv, a = (x / nv) % nv, jj = (x / (nv * nv)) % no, i = x / (nv * nv * no);
+                const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+                cd w = cscale(acc, 0.25);
+                if (ka == ki)
+                    w = cadd(w, cscale(cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + jj) * nv + b]), 0.5));
+                const cd p = cmul(s.oovv[e], w);
+                er += p.x;
+                ei += p.y;
+            }
+            uint16_t h0, h1, h2, h3;
+            split2(acc.x, h0, h1);
+            split2(acc.y, h2, h3);
+            S[0][tid + 256 * q] = h0;
+            S[1][tid + 256 * q] = h1;
+            S[2][tid + 256 * q] = h2;
+            S[3][tid + 256 * q] = h3;
+        }
+        __syncthreads();
+        if (c0 + tid < nch) {
+            uint4 *o = (uint4 *)(sp + (c0 + tid) * 32);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) o[p] = *(const uint4 *)&S[p][8 * tid];
+        }
+        __syncthreads();
+    }
+    blk_sum2(er, ei, sh);
+    if (tid == 0) {
+        ep2[blockIdx.x] = er;
+        ep2[gridDim.x + blockIdx.x] = ei;
+    }
+}
+
+// out[0..1] = ep1 + sum_b ep2 (fixed order)
+__global__ __launch_bounds__(256) void k_energy_final(const double *ep1, const double *ep2, int nb, double *out) {
+    __shared__ double sh[2][256];
+    double er = 0.0, ei = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        er += ep2[b];
+        ei += ep2[nb + b];
+    }
+    blk_sum2(er, ei, sh);
+    if (threadIdx.x == 0) {
+        out[0] = ep1[0] + er;
+        out[1] = ep1[1] + ei;
+    }
+}
+
+int lincomb_t2_blocks(const Dims &d) {
+    const int64_t nch = (d.t2() + 7) / 8;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((nch + 255) / 256, LINCOMB_T2_BLOCKS));
+}
+
+void launch_lincomb_pack(const SysDev &s, const cd *const *src, const double *c, int m, cd *t, uint16_t *sp,
+                         double *epart, hipStream_t st) {
+    LincombArgs L{};
+    for (int j = 0; j < m; ++j) {
+        L.src[j] = src[j];
+        L.c[j] = c[j];
+    }
+    hipLaunchKernelGGL(k_lincomb_t1, dim3(1), dim3(256), 0, st, s, L, m, t, epart);
+    CK_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_lincomb_t2, dim3((unsigned)lincomb_t2_blocks(s.d)), dim3(256), 0, st, s, L, m, t, sp,
+                       epart + 2);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_energy_pack(const Dims &d, const double *epart, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, epart, epart + 2, lincomb_t2_blocks(d), out);
     CK_CHECK(hipGetLastError());
 }
 

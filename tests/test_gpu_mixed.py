@@ -73,3 +73,23 @@ def test_mixed_converged_energy_matches_fp64():
     dt2 = np.abs(out[ck.PREC_MIXED][2] - ref["t2"]).max()
     print(f"mixed: |dE| = {de:.3e} Eh, max|dT2| = {dt2:.3e}, E = {ref['energy']}")
     assert de <= 1e-6 * abs(ref["energy"])
+
+
+def test_mixed_extrapolation_caches_match_fresh_passes():
+    """The mixed DIIS extrapolation also writes the split copy of t2 and the energy partial
+    sums; the residual and energy taken from them equal the ones from fresh passes over the
+    same amplitudes (residual bitwise, energy to rounding)."""
+    grid, no, nv = (2, 2, 1), 3, 5
+    f, eris = synth.system(606, grid, no, nv, scale=0.05 / 4)
+    with ck.Context([dict(grid=grid, no=no, nv=nv, precision=ck.PREC_MIXED, diis_space=4)]) as c:
+        c.set_inputs(0, f, eris)
+        c.iterate(5, 0.0)  # several extrapolations
+        e_cached = c.energy(0)
+        r1a, r2a = c.residual(0)  # split t2 from the extrapolation
+        t1, t2 = c.get_amplitudes(0)
+        c.set_amplitudes(0, t1, t2)  # invalidates both
+        e_fresh = c.energy(0)
+        r1b, r2b = c.residual(0)
+    assert abs(e_cached - e_fresh) <= 1e-12 * abs(e_fresh)
+    assert np.array_equal(r2a, r2b)
+    assert np.array_equal(r1a, r1b)
