@@ -33,7 +33,7 @@ struct Gemm {
     int stage;
     size_t tab[6];  // offsets (in int64 units) of a_row, a_k, b_col, b_k, c_row, c_col in the table blob
     // packed products only: partner column, split-output row and column offsets (SIZE_MAX: none)
-    size_t c_col2 = SIZE_MAX, cs_row = SIZE_MAX, cs_col = SIZE_MAX;
+    size_t cs_row = SIZE_MAX, cs_col = SIZE_MAX;
 };
 
 struct System {
@@ -510,7 +510,7 @@ void bind_ops(System &S) {
         s.Cs = CS[i];
         s.a_row = T + g.tab[0]; s.a_k = T + g.tab[1]; s.b_col = T + g.tab[2]; s.b_k = T + g.tab[3];
         s.c_row = T + g.tab[4]; s.c_col = T + g.tab[5];
-        s.c_col2 = tab(g.c_col2); s.cs_row = tab(g.cs_row); s.cs_col = tab(g.cs_col);
+        s.cs_row = tab(g.cs_row); s.cs_col = tab(g.cs_col);
         s.G = g.op.G; s.M = g.op.M; s.N = g.op.N; s.K = g.op.K; s.alpha = g.op.alpha; s.beta = g.op.beta;
         s.fast = fast_ok(S, g) ? 1 : 0;
     }

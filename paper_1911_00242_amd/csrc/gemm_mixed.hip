@@ -334,47 +334,49 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
     f32x16 acci[2][2] = {{c00i, c01i}, {c10i, c11i}};
 
     // epilogue: 32x32 f32 output, register r of a lane holds row 8*(r/4) + 4*(lane/32) + r%4
-    // of column lane%32.  Per fragment the row offsets and (beta != 0) the old values are
-    // all loaded before the first store: a store to C could alias a later load as far as the
-    // compiler knows, so interleaved load / store pairs would each wait a full memory latency.
+    // of column lane%32.  Per fragment row i the row offsets, and (beta != 0) the old values
+    // of both fragment columns, are all loaded before the first store: a store to C could
+    // alias a later load as far as the compiler knows, so interleaved load / store pairs
+    // would each wait a full memory latency.
     const double alpha = op.alpha, beta = op.beta;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        const int mb = m0 + wm * 64 + i * 32 + 4 * lh;
+        int64_t crow[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = mb + 8 * (r >> 2) + (r & 3);
+            crow[r] = m < M ? op.c_row[(int64_t)g * M + m] : -1;
+        }
+        int64_t ccol[2], cscol[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int n = n0 + wn * 64 + j * 32 + l32;
-            if (n >= N) continue;
-            const int64_t ccol = op.c_col[(int64_t)g * N + n];
-            if (ccol < 0) continue;  // padding column of a packed pair list
-            const int64_t ccol2 = op.c_col2 ? op.c_col2[(int64_t)g * N + n] : -1;
-            const int64_t cscol = op.cs_col ? op.cs_col[(int64_t)g * N + n] : ccol;
-            const int mb = m0 + wm * 64 + i * 32 + 4 * lh;
-            int64_t crow[16];
+            ccol[j] = n < N ? op.c_col[(int64_t)g * N + n] : -1;  // < 0: padding column
+            cscol[j] = (n < N && op.cs_col) ? op.cs_col[(int64_t)g * N + n] : ccol[j];
+        }
+        cd o[2][16];
+        if (beta != 0.0) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = mb + 8 * (r >> 2) + (r & 3);
-                crow[r] = m < M ? op.c_row[(int64_t)g * M + m] : -1;
-            }
-            cd o[16], o2[16];
-            if (beta != 0.0) {
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    o[r] = crow[r] >= 0 ? op.C[crow[r] + ccol] : make_double2(0.0, 0.0);
-                    o2[r] = crow[r] >= 0 && ccol2 >= 0 ? op.C[crow[r] + ccol2] : make_double2(0.0, 0.0);
-                }
-            }
+                for (int r = 0; r < 16; ++r)
+                    o[j][r] = crow[r] >= 0 && ccol[j] >= 0 ? op.C[crow[r] + ccol[j]] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (ccol[j] < 0) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 if (crow[r] < 0) continue;
-                const double ar = alpha * (double)accr[i][j][r], ai = alpha * (double)acci[i][j][r];
-                cd v = make_double2(ar, ai);
+                cd v = make_double2(alpha * (double)accr[i][j][r], alpha * (double)acci[i][j][r]);
                 if (beta != 0.0) {
-                    v.x = fma(beta, o[r].x, v.x);
-                    v.y = fma(beta, o[r].y, v.y);
+                    v.x = fma(beta, o[j][r].x, v.x);
+                    v.y = fma(beta, o[j][r].y, v.y);
                 }
                 if (op.Cs) {
                     const int m = mb + 8 * (r >> 2) + (r & 3);
-                    const int64_t e = (op.cs_row ? op.cs_row[(int64_t)g * M + m] : crow[r]) + cscol;
+                    const int64_t e = (op.cs_row ? op.cs_row[(int64_t)g * M + m] : crow[r]) + cscol[j];
                     uint16_t h0, h1, h2, h3;
                     split2(v.x, h0, h1);
                     split2(v.y, h2, h3);
@@ -383,18 +385,11 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
                     op.Cs[split_index(e, 2)] = h2;
                     op.Cs[split_index(e, 3)] = h3;
                 } else {
-                    op.C[crow[r] + ccol] = v;
-                }
-                if (ccol2 >= 0) {
-                    cd w = make_double2(-ar, -ai);
-                    if (beta != 0.0) {
-                        w.x = fma(beta, o2[r].x, w.x);
-                        w.y = fma(beta, o2[r].y, w.y);
-                    }
-                    op.C[crow[r] + ccol2] = w;
+                    op.C[crow[r] + ccol[j]] = v;
                 }
             }
         }
+    }
 }
 
 void gemm_split(const SplitOps &op, hipStream_t s) {

@@ -46,16 +46,14 @@ __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
 // of 8 in both operands (then loads move 8 k of one plane at once).  A column with
 // c_col < 0 is padding and is not written.  With Cs set, the result alpha*AB + beta*C is
 // written in split storage to Cs at cs_row + cs_col (cs_row/cs_col = NULL: the C offsets)
-// and C is only read.  With c_col2 set, every column with c_col2 >= 0 also updates a
-// second element C[c_row + c_col2] <- beta*C - alpha*AB (the antisymmetric partner of a
-// packed pair column).
+// and C is only read.
 struct SplitOps {
     const uint16_t *A, *B;
     const uint16_t *zeros;  // >= 16 bytes of zeros: the load address of out-of-range chunks
     cd *C;
     uint16_t *Cs;
     const int64_t *a_row, *a_k, *b_col, *b_k, *c_row, *c_col;
-    const int64_t *c_col2, *cs_row, *cs_col;
+    const int64_t *cs_row, *cs_col;
     int G, M, N, K;
     double alpha, beta;
     int fast;
