@@ -14,6 +14,11 @@
   and N_k*n_vir virtual orbitals (zeros where momentum is not conserved) has the same
   converged energy, which checks the k-block bookkeeping against the N_k = 1 code path.
 * Mutation: planting a sign error in one oracle term makes the brute-force pin fail.
+* Rearranged equations: the rearranged T1 and T2 equations of Sec. 3.3 (a second oracle,
+  ``oracle.rearranged``) equal the original ones; each reading of a Sec. 3.3 misprint is
+  needed for that.
+* Orbital rotation: the converged energy is the same in rotated occupied and virtual
+  orbitals (a Fock matrix with all couplings).
 """
 import numpy as np
 import pytest
@@ -216,3 +221,94 @@ def test_supercell_folding_matches_k_blocks():
     res_1 = O.solve(F, big, (1, 1, 1), max_iter=60, tol=1e-11)
     assert res_k["converged"] and res_1["converged"]
     assert abs(res_k["energy"] - res_1["energy"]) <= 1e-11
+
+
+@pytest.mark.parametrize("grid,no,nv", [((1, 1, 1), 2, 3), ((2, 1, 1), 2, 2), ((3, 1, 1), 2, 3), ((2, 2, 1), 1, 2)])
+def test_rearranged_equations_match_original(grid, no, nv):
+    """The rearranged equations of Sec. 3.3 (A-bar + A-check + A-tilde + A-hat and the
+    rearranged T1 equation) are an exact regrouping of Sec. 2: both oracles agree on random
+    antisymmetric amplitudes, random integrals and a Fock matrix with occupied-virtual
+    coupling.  This pins the readings of the Sec. 3.3 misprints (module docstring of
+    oracle.rearranged): reversing any of them breaks the equality."""
+    from oracle import rearranged as RA
+
+    N = int(np.prod(grid))
+    kc = O.kconserv(grid)
+    f, eris = synth.system(900 + N, grid, no, nv, scale=0.1)
+    f = _random_fock(np.random.default_rng(N + no), N, no, nv)
+    t1, t2 = synth.test_amplitudes(40 + N, grid, no, nv, scale=0.2)
+    R1, R2 = O.residual(f, eris, t1, t2, kc)
+    A1, A2 = RA.residual(f, eris, t1, t2, kc)
+    assert np.abs(A2 - R2).max() <= 1e-12 * np.abs(R2).max()
+    assert np.abs(A1 - R1).max() <= 1e-12 * np.abs(R1).max()
+
+
+@pytest.mark.parametrize("key,printed", [("K_SIGN_FOO", -1), ("ZETA_BAR", "ia"), ("AHAT_PAIR", "check")])
+def test_rearranged_misprint_readings_are_forced(monkeypatch, key, printed):
+    """Each reading of a Sec. 3.3 misprint is needed: with the printed form instead, the
+    rearranged equations no longer equal the original ones (on a 1-D N_k = 3 mesh, where
+    k and -k differ)."""
+    from oracle import rearranged as RA
+
+    grid, no, nv = (3, 1, 1), 2, 2
+    kc = O.kconserv(grid)
+    f, eris = synth.system(77, grid, no, nv, scale=0.1)
+    f = _random_fock(np.random.default_rng(5), 3, no, nv)
+    t1, t2 = synth.test_amplitudes(8, grid, no, nv, scale=0.2)
+    R1, R2 = O.residual(f, eris, t1, t2, kc)
+    monkeypatch.setitem(RA.READINGS, key, printed)
+    A1, A2 = RA.residual(f, eris, t1, t2, kc)
+    bad = max(np.abs(A2 - R2).max() / np.abs(R2).max(), np.abs(A1 - R1).max() / np.abs(R1).max())
+    assert bad > 1e-6
+
+
+def rotate_system(f, eris, kc, no, seed, angle=0.3):
+    """The same system in rotated orbitals: per k, a random unitary U_k mixing the occupied
+    orbitals among themselves and the virtual ones among themselves; f_k -> U_k^H f_k U_k and
+    <pq||rs> -> sum conj(U_p) conj(U_q) U_r U_s <..||..>, each factor at its own momentum.
+    Returns (f', eris')."""
+    N, n = f.shape[0], f.shape[1]
+    rng = np.random.default_rng(seed)
+    U = np.zeros((N, n, n), dtype=np.complex128)
+    for k in range(N):
+        for lo, hi in ((0, no), (no, n)):
+            m = hi - lo
+            h = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+            h = angle * (h + h.conj().T) / 2
+            w, v = np.linalg.eigh(h)
+            U[k, lo:hi, lo:hi] = (v * np.exp(1j * w)) @ v.conj().T
+    fr = np.stack([U[k].conj().T @ f[k] @ U[k] for k in range(N)])
+    E = O.Eris(eris, kc)
+    sl = {"o": slice(0, no), "v": slice(no, n)}
+    full = np.zeros((N, N, N, n, n, n, n), dtype=np.complex128)
+    for kp in range(N):
+        for kq in range(N):
+            for kr in range(N):
+                for a in "ov":
+                    for b in "ov":
+                        for c in "ov":
+                            for d in "ov":
+                                full[kp, kq, kr][sl[a], sl[b], sl[c], sl[d]] = E.block(a + b + c + d, kp, kq, kr)
+    rot = np.zeros_like(full)
+    for kp in range(N):
+        for kq in range(N):
+            for kr in range(N):
+                ks = kc[kp, kq, kr]
+                rot[kp, kq, kr] = np.einsum("ap,bq,cr,ds,abcd->pqrs", U[kp].conj(), U[kq].conj(), U[kr], U[ks],
+                                            full[kp, kq, kr], optimize=True)
+    return fr, _classes_from_full(rot, no)
+
+
+@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 2, 3), ((2, 2, 1), 1, 2)])
+def test_energy_invariant_under_orbital_rotation(grid, no, nv):
+    """The converged CCSD energy does not depend on the orbital basis within the occupied
+    and within the virtual space: the same system in rotated orbitals (a Fock matrix with
+    occupied-occupied and virtual-virtual off-diagonal elements) converges to the same E."""
+    kc = O.kconserv(grid)
+    f, eris = synth.system(31, grid, no, nv, scale=0.05)
+    fr, er = rotate_system(f, eris, kc, no, seed=3)
+    a = O.solve(f, eris, grid, max_iter=80, tol=1e-11, diis_space=6)
+    b = O.solve(fr, er, grid, max_iter=80, tol=1e-11, diis_space=6)
+    assert a["converged"] and b["converged"]
+    assert abs(fr[0] - f[0]).max() > 1e-3  # the rotation really changed the Fock matrix
+    assert abs(a["energy"] - b["energy"]) <= 1e-10 * max(1.0, abs(a["energy"]))
