@@ -117,7 +117,8 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // LDS, <m ka, b kb||e f> over m in registers), restricted to the blocks and elements that
 // are canonical in both pairs: a quarter of the reads and writes of the full copy.  The
 // grid covers only those blocks (pt.dblk), so the work is spread evenly over the XCDs.
-// For n_occ <= OM, o v^2 <= 2048.
+// <m kb, a ka||e f> is staged for as many a at a time as fit 2048 elements (all of them
+// when o v^2 <= 2048).  For n_occ <= OM and o v <= 2048.
 template <int OM>
 __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
                                                          int64_t ld) {
@@ -137,42 +138,48 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
     const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
     const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
     const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
-    for (int x = threadIdx.x; x < no * vv; x += blockDim.x) {
-        const int m = x / vv, af = x % vv;
-        G1[x] = g1b[(int64_t)m * v3 + (int64_t)(af / nv) * vv + af % nv];
-    }
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TA[x] = ta[x];
-    __syncthreads();
     const int32_t *vpos_ab = pt.vpos + ((int64_t)K * N + ka) * vv;
     const int32_t *vpos_ef = pt.vpos + ((int64_t)K * N + ke) * vv + e * nv;
-    for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
-        const int b = bf / nv, f = bf % nv;
-        const int pef = vpos_ef[f];
-        if (pef < 0) continue;
-        cd g2[OM], t1b[OM];
-#pragma unroll
-        for (int m = 0; m < OM; ++m) {
-            g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
-            t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
+    // a chunk of ac values of a: no * ac * nv <= 2048 and no * ac <= OM * 64
+    const int ac = min(nv, 2048 / (no * nv));
+    for (int a0 = 0; a0 < nv; a0 += ac) {
+        const int na = min(ac, nv - a0), anv = na * nv;
+        if (a0) __syncthreads();
+        for (int x = threadIdx.x; x < no * anv; x += blockDim.x) {
+            const int m = x / anv, af = x % anv;
+            G1[x] = g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv];
         }
-        for (int a = 0; a < nv; ++a) {
-            const int pab = vpos_ab[a * nv + b];
-            if (pab < 0) continue;
-            cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+        for (int x = threadIdx.x; x < no * na; x += blockDim.x) TA[x] = ta[(x / na) * nv + a0 + x % na];
+        __syncthreads();
+        for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
+            const int b = bf / nv, f = bf % nv;
+            const int pef = vpos_ef[f];
+            if (pef < 0) continue;
+            cd g2[OM], t1b[OM];
 #pragma unroll
-            for (int m = 0; m < OM; ++m)
-                if (m < no) {
-                    cfma(acc, t1b[m], G1[(m * nv + a) * nv + f]);
-                    acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
-                }
-            const int64_t o = ((int64_t)K * pt.PV + pab) * ld + pef;
-            uint16_t h0, h1, h2, h3;
-            split2(acc.x, h0, h1);
-            split2(acc.y, h2, h3);
-            out[split_index(o, 0)] = h0;
-            out[split_index(o, 1)] = h1;
-            out[split_index(o, 2)] = h2;
-            out[split_index(o, 3)] = h3;
+            for (int m = 0; m < OM; ++m) {
+                g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
+                t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
+            }
+            for (int a = 0; a < na; ++a) {
+                const int pab = vpos_ab[(a0 + a) * nv + b];
+                if (pab < 0) continue;
+                cd acc = vb[(int64_t)(a0 + a) * v3 + (int64_t)b * vv + f];
+#pragma unroll
+                for (int m = 0; m < OM; ++m)
+                    if (m < no) {
+                        cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
+                        acc = csub(acc, cmul(TA[m * na + a], g2[m]));
+                    }
+                const int64_t o = ((int64_t)K * pt.PV + pab) * ld + pef;
+                uint16_t h0, h1, h2, h3;
+                split2(acc.x, h0, h1);
+                split2(acc.y, h2, h3);
+                out[split_index(o, 0)] = h0;
+                out[split_index(o, 1)] = h1;
+                out[split_index(o, 2)] = h2;
+                out[split_index(o, 3)] = h3;
+            }
         }
     }
 }
@@ -217,7 +224,7 @@ static dim3 pack_grid(int64_t threads) {
     return dim3((unsigned)(b < 1 ? 1 : b));
 }
 
-bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv * d.nv <= 2048 && d.nv <= 64; }
+bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv <= 2048; }
 
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
                      uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st) {

@@ -614,11 +614,12 @@ __device__ inline int64_t xcd_block(int64_t n) {
 // For fixed (ka, kb, ke, e) this is a rank-o update of the v x v x v slab (a, b, f):
 // one workgroup per (ka, kb, ke, e), XCD-contiguous order.  G1(m,a,f) = <m kb, a ka||e f>
 // (shared by every b) and t_{m ka}^a go through LDS; a thread owns (b, f), keeps
-// <m ka, b kb||e f> and t_{m kb}^b for all m in registers and runs over a.  Every
-// <ab||ef> and <mb||ef> element is read once per use, all reads are runs of v.
+// <m ka, b kb||e f> and t_{m kb}^b for all m in registers and runs over a.  G1 holds as
+// many a at a time as fit DR_G1 elements (all of them when o v^2 <= DR_G1); <ab||ef> is
+// read once, <mb||ef> once per such chunk of a, all reads are runs of v.
 constexpr int DR_G1 = 2048, DR_T1 = 512;
 __host__ __device__ inline bool dress_fits(const Dims &d) {
-    return (int64_t)d.no * d.nv * d.nv <= DR_G1 && d.no * d.nv <= DR_T1;
+    return d.no <= 32 && (int64_t)d.no * d.nv <= DR_G1;
 }
 // register arrays of OM (>= n_occ) entries; OM = 0 selects the plain global-memory path
 inline int dress_om(const Dims &d) {
@@ -644,37 +645,44 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd
     const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
     const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
     const int64_t ob = blk * v4 + (int64_t)e * nv;
-    constexpr bool lds = OM > 0;
-    if (lds) {
-        for (int x = threadIdx.x; x < no * vv; x += blockDim.x) {
-            const int m = x / vv, af = x % vv;  // (a, f) = (af / nv, af % nv)
-            G1[x] = g1b[(int64_t)m * v3 + (int64_t)(af / nv) * vv + af % nv];
-        }
-        for (int x = threadIdx.x; x < no * nv; x += blockDim.x) TA[x] = ta[x];
-        __syncthreads();
-    }
-    for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
-        const int b = bf / nv, f = bf % nv;
-        if constexpr (lds) {
-            cd g2[OM > 0 ? OM : 1], t1b[OM > 0 ? OM : 1];
-#pragma unroll
-            for (int m = 0; m < OM; ++m) {
-                g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
-                t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
+    if constexpr (OM > 0) {
+        // <m kb, a ka||e f> staged for ac values of a at a time: no * ac * nv <= DR_G1 and
+        // no * ac <= DR_T1
+        const int ac = min(min(nv, DR_G1 / (no * nv)), DR_T1 / no);
+        for (int a0 = 0; a0 < nv; a0 += ac) {
+            const int na = min(ac, nv - a0), anv = na * nv;
+            if (a0) __syncthreads();
+            for (int x = threadIdx.x; x < no * anv; x += blockDim.x) {
+                const int m = x / anv, af = x % anv;
+                G1[x] = g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv];
             }
-            for (int a = 0; a < nv; ++a) {
-                const int64_t idx = ob + (int64_t)a * v3 + (int64_t)b * vv + f;
-                cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+            for (int x = threadIdx.x; x < no * na; x += blockDim.x) TA[x] = ta[(x / na) * nv + a0 + x % na];
+            __syncthreads();
+            for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
+                const int b = bf / nv, f = bf % nv;
+                cd g2[OM], t1b[OM];
 #pragma unroll
                 for (int m = 0; m < OM; ++m) {
-                    if (m < no) {
-                        cfma(acc, t1b[m], G1[(m * nv + a) * nv + f]);
-                        acc = csub(acc, cmul(TA[m * nv + a], g2[m]));
-                    }
+                    g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
+                    t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
                 }
-                Vt[idx] = acc;
+                for (int a = 0; a < na; ++a) {
+                    const int64_t idx = ob + (int64_t)(a0 + a) * v3 + (int64_t)b * vv + f;
+                    cd acc = vb[(int64_t)(a0 + a) * v3 + (int64_t)b * vv + f];
+#pragma unroll
+                    for (int m = 0; m < OM; ++m) {
+                        if (m < no) {
+                            cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
+                            acc = csub(acc, cmul(TA[m * na + a], g2[m]));
+                        }
+                    }
+                    Vt[idx] = acc;
+                }
             }
-        } else {
+        }
+    } else {
+        for (int bf = threadIdx.x; bf < vv; bf += blockDim.x) {
+            const int b = bf / nv, f = bf % nv;
             for (int a = 0; a < nv; ++a) {
                 const int64_t idx = ob + (int64_t)a * v3 + (int64_t)b * vv + f;
                 cd acc = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
