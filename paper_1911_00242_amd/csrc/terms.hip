@@ -118,10 +118,11 @@ __global__ void k_fvv_partial(SysDev s, const cd *t1, const cd *t2, cd *Pvv) {
 // time (rows (x, e) padded to n_vir+1) and forms
 //   Poo[p][q][r](m,i) = 1/2 sum_{n,e,f} taut(i,n,e,f) <mn||ef>     (k = p, kn = q, ke = r)
 //   Pvv[r][p][q](a,e) = -1/2 sum_{m,n,f} taut(m,n,a,f) <mn||ef>    (k = r, km = p, kn = q)
-constexpr int FB_SLAB = 2176;  // o * v * (v + 1) complex elements per staged slab (o=8, v=16)
-inline bool f_blocks_fit(const Dims &d) {
-    return (int64_t)d.no * d.nv * (d.nv + 1) <= FB_SLAB && d.no * d.no <= 1024 && d.nv * d.nv <= 1024;
-}
+// When a whole n-slab (o v (v+1) elements) does not fit FB_SLAB, the two sums take
+// separate passes: Poo over slabs of every row x and a range of e, Pvv over slabs of a
+// range of rows m and every e.
+constexpr int FB_SLAB = 2176;  // staged complex elements per operand
+inline bool f_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
 constexpr int FB_NT = 1024;
 __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
@@ -134,34 +135,65 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     const int kb = kcv(s.kc, N, p, q, r);
     const int64_t base = blk * s.d.t2blk();
     const int oo = no * no, parts = FB_NT / oo;
-    const int u = tid % oo, part = tid / oo;  // Foo output (m,i) = u, ef slice = part
+    const int u = tid % oo, part = tid / oo;  // Foo output (m,i) = u, slice = part
     const int um = u / no, ui = u % no;
-    const int ef0 = part < parts ? (int)((int64_t)part * vv / parts) : 0;
-    const int ef1 = part < parts ? (int)((int64_t)(part + 1) * vv / parts) : 0;
     const int vparts = FB_NT / vv;  // threads per Fvv output (v^2 <= FB_NT)
     const int vo = tid % vv, vpart = tid / vv;
     const int va = vo / nv, ve = vo % nv;
-    const int mf0 = vpart < vparts ? (int)((int64_t)vpart * no * nv / vparts) : 0;
-    const int mf1 = vpart < vparts ? (int)((int64_t)(vpart + 1) * no * nv / vparts) : 0;
-    cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0);
-    for (int n = 0; n < no; ++n) {
+    // slab of rows x0 .. x0+nx-1 and e0 .. e0+ne-1 of n: element (x, e, f) at
+    // ((x - x0) * ne + e - e0) * rs + f
+    auto stage = [&](int n, int x0, int nx, int e0, int ne) {
+        const int per = ne * nv;
 #pragma unroll 4
-        for (int x = tid; x < no * vv; x += FB_NT) {
-            const int row = x / vv, e = (x % vv) / nv, f = x % nv;
-            const int64_t gi = base + (((int64_t)row * no + n) * nv + e) * nv + f;
-            Ts[(row * nv + e) * rs + f] = tau_el(t1, t2, gi, p, q, r, kb, row, n, e, f, no, nv, 0.5);
-            Gs[(row * nv + e) * rs + f] = s.oovv[gi];
+        for (int x = tid; x < nx * per; x += FB_NT) {
+            const int row = x / per, e = (x % per) / nv, f = x % nv;
+            const int64_t gi = base + (((int64_t)(x0 + row) * no + n) * nv + e0 + e) * nv + f;
+            Ts[(row * ne + e) * rs + f] = tau_el(t1, t2, gi, p, q, r, kb, x0 + row, n, e0 + e, f, no, nv, 0.5);
+            Gs[(row * ne + e) * rs + f] = s.oovv[gi];
         }
-        __syncthreads();
-        for (int ef = ef0; ef < ef1; ++ef) {
-            const int e = ef / nv, f = ef % nv;
-            cfma(aoo, Ts[(ui * nv + e) * rs + f], Gs[(um * nv + e) * rs + f]);
+    };
+    auto slice = [](int pt, int np, int cnt, int &b0, int &b1) {
+        b0 = pt < np ? (int)((int64_t)pt * cnt / np) : 0;
+        b1 = pt < np ? (int)((int64_t)(pt + 1) * cnt / np) : 0;
+    };
+    const bool one = (int64_t)no * nv * rs <= FB_SLAB;  // both sums from one slab per n
+    const int ec = one ? nv : FB_SLAB / (no * rs);
+    cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0);
+    for (int n = 0; n < no; ++n)
+        for (int e0 = 0; e0 < nv; e0 += ec) {
+            const int ne = min(ec, nv - e0);
+            stage(n, 0, no, e0, ne);
+            __syncthreads();
+            int b0, b1;
+            slice(part, parts, ne * nv, b0, b1);
+            for (int ef = b0; ef < b1; ++ef) {
+                const int e = ef / nv, f = ef % nv;
+                cfma(aoo, Ts[(ui * ne + e) * rs + f], Gs[(um * ne + e) * rs + f]);
+            }
+            if (one) {
+                slice(vpart, vparts, no * nv, b0, b1);
+                for (int mf = b0; mf < b1; ++mf) {
+                    const int m = mf / nv, f = mf % nv;
+                    cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
+                }
+            }
+            __syncthreads();
         }
-        for (int mf = mf0; mf < mf1; ++mf) {
-            const int m = mf / nv, f = mf % nv;
-            cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
-        }
-        __syncthreads();
+    if (!one) {
+        const int mc = FB_SLAB / (nv * rs);
+        for (int n = 0; n < no; ++n)
+            for (int m0 = 0; m0 < no; m0 += mc) {
+                const int nm = min(mc, no - m0);
+                stage(n, m0, nm, 0, nv);
+                __syncthreads();
+                int b0, b1;
+                slice(vpart, vparts, nm * nv, b0, b1);
+                for (int mf = b0; mf < b1; ++mf) {
+                    const int m = mf / nv, f = mf % nv;
+                    cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
+                }
+                __syncthreads();
+            }
     }
     red[tid] = aoo;
     __syncthreads();
@@ -300,18 +332,17 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
 // LDS one n-slab at a time and forms
 //   P1[p][q][r](i,a) += -1/2 sum_{n,e,f} t2(i,n,e,f) <n q, a p || e r, f>   (k = p)
 //   P1[r][p][q](i,a) += -1/2 sum_{m,n,f} t2(m,n,a,f) <m p, n q || i r, f>   (k = r)
-// written to two partial arrays that k_r1_wave adds.
+// written to two partial arrays that k_r1_wave adds.  When the slabs of one n do not fit,
+// the two sums take separate passes: the first over slabs of a range of e (every i, a),
+// the second over slabs of a range of m (every a, i).
 constexpr int RB_T = 2176, RB_G = 4352, RB_H = 1152;
-inline bool r1_blocks_fit(const Dims &d) {
-    return (int64_t)d.no * d.nv * (d.nv + 1) <= RB_T && (int64_t)d.nv * (d.nv * d.nv + 1) <= RB_G &&
-           (int64_t)d.no * d.no * (d.nv + 1) <= RB_H && d.no * d.nv <= 1024;
-}
+inline bool r1_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
 constexpr int RB_NT = 1024;
 __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
     __shared__ cd Ts[RB_T], Gs[RB_G], Hs[RB_H];
     __shared__ cd red[RB_NT];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1, gs = vv + 1;
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
@@ -323,31 +354,67 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     const int parts = RB_NT / nout;             // threads per output
     const int part = tid / nout, oi = tid % nout;
     const int ii = oi / nv, aa = oi % nv;
-    const int ef0 = part < parts ? (int)((int64_t)part * vv / parts) : 0;
-    const int ef1 = part < parts ? (int)((int64_t)(part + 1) * vv / parts) : 0;
-    const int mf0 = part < parts ? (int)((int64_t)part * no * nv / parts) : 0;
-    const int mf1 = part < parts ? (int)((int64_t)(part + 1) * no * nv / parts) : 0;
-    cd accA = make_double2(0.0, 0.0), accB = make_double2(0.0, 0.0);
-    for (int n = 0; n < no; ++n) {
+    auto slice = [&](int cnt, int &b0, int &b1) {
+        b0 = part < parts ? (int)((int64_t)part * cnt / parts) : 0;
+        b1 = part < parts ? (int)((int64_t)(part + 1) * cnt / parts) : 0;
+    };
+    // t2(x, n, e, f) for rows x0 .. x0+nx-1 and e0 .. e0+ne-1 at ((x - x0) * ne + e - e0) * rs + f
+    auto stage_t = [&](int n, int x0, int nx, int e0, int ne) {
+        const int per = ne * nv;
 #pragma unroll 4
-        for (int x = tid; x < no * vv; x += RB_NT) {  // t2(x, n, e, f)
-            const int row = x / vv, e = (x % vv) / nv, f = x % nv;
-            Ts[(row * nv + e) * rs + f] = t2[tb + (((int64_t)row * no + n) * nv + e) * nv + f];
+        for (int x = tid; x < nx * per; x += RB_NT) {
+            const int row = x / per, e = (x % per) / nv, f = x % nv;
+            Ts[(row * ne + e) * rs + f] = t2[tb + (((int64_t)(x0 + row) * no + n) * nv + e0 + e) * nv + f];
         }
-#pragma unroll 4
-        for (int x = tid; x < nv * vv; x += RB_NT)  // <n q, a p || e r, f>: (a, ef)
-            Gs[(x / vv) * gs + x % vv] = s.ovvv[gb + (int64_t)n * nv * vv + x];
-        for (int x = tid; x < no * no * nv; x += RB_NT) {  // <m p, n q || i r, f>: (m, i, f)
+    };
+    // <m p, n q || i r, f> for m0 .. m0+nm-1 at ((m - m0) * no + i) * rs + f
+    auto stage_h = [&](int n, int m0, int nm) {
+        for (int x = tid; x < nm * no * nv; x += RB_NT) {
             const int m = x / (no * nv), i = (x / nv) % no, f = x % nv;
-            Hs[(m * no + i) * rs + f] = s.ooov[hb + (((int64_t)m * no + n) * no + i) * nv + f];
+            Hs[(m * no + i) * rs + f] = s.ooov[hb + (((int64_t)(m0 + m) * no + n) * no + i) * nv + f];
         }
-        __syncthreads();
-        for (int ef = ef0; ef < ef1; ++ef) cfma(accA, Ts[(ii * nv + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
-        for (int mf = mf0; mf < mf1; ++mf) {
-            const int m = mf / nv, f = mf % nv;
-            cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+    };
+    const bool one = (int64_t)no * nv * rs <= RB_T && (int64_t)nv * (vv + 1) <= RB_G && (int64_t)no * no * rs <= RB_H;
+    const int ec = one ? nv : min(RB_T / (no * rs), (RB_G / nv - 1) / nv);
+    cd accA = make_double2(0.0, 0.0), accB = make_double2(0.0, 0.0);
+    for (int n = 0; n < no; ++n)
+        for (int e0 = 0; e0 < nv; e0 += ec) {
+            const int ne = min(ec, nv - e0), per = ne * nv, gs = per + 1;
+            stage_t(n, 0, no, e0, ne);
+            // <n q, a p || e r, f> for e0 .. e0+ne-1: (a, (e - e0) * nv + f), rows padded to gs
+#pragma unroll 4
+            for (int x = tid; x < nv * per; x += RB_NT)
+                Gs[(x / per) * gs + x % per] = s.ovvv[gb + (int64_t)n * nv * vv + (int64_t)(x / per) * vv + e0 * nv + x % per];
+            if (one) stage_h(n, 0, no);
+            __syncthreads();
+            int b0, b1;
+            slice(per, b0, b1);
+            for (int ef = b0; ef < b1; ++ef) cfma(accA, Ts[(ii * ne + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
+            if (one) {
+                slice(no * nv, b0, b1);
+                for (int mf = b0; mf < b1; ++mf) {
+                    const int m = mf / nv, f = mf % nv;
+                    cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+    if (!one) {
+        const int mc = min(min(no, RB_T / (nv * rs)), RB_H / (no * rs));
+        for (int n = 0; n < no; ++n)
+            for (int m0 = 0; m0 < no; m0 += mc) {
+                const int nm = min(mc, no - m0);
+                stage_t(n, m0, nm, 0, nv);
+                stage_h(n, m0, nm);
+                __syncthreads();
+                int b0, b1;
+                slice(nm * nv, b0, b1);
+                for (int mf = b0; mf < b1; ++mf) {
+                    const int m = mf / nv, f = mf % nv;
+                    cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+                }
+                __syncthreads();
+            }
     }
     red[tid] = accA;
     __syncthreads();
@@ -1369,6 +1436,13 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         LAUNCH_T(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
         LAUNCH_T(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
         LAUNCH_T(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
+    } else if (no <= 8 && nv <= 32) {
+        const dim3 grid = xcd_grid(n3 * no);
+        hipLaunchKernelGGL((k_ring_z_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
+        CK_CHECK(hipGetLastError());
+        LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        hipLaunchKernelGGL((k_ring_q_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
+        CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
         LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
@@ -1377,6 +1451,10 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
     if (no <= 8 && nv <= 16) {
         LAUNCH_T(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot,
                            w.Fvt, X);
+    } else if (no <= 8 && nv <= 32) {
+        hipLaunchKernelGGL((k_xinit_t<8, 32, false>), xcd_grid(n3 * nv), dim3(8 * 32), 0, st, s, t1, t2, scratch,
+                           w.Fot, w.Fvt, X);
+        CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }

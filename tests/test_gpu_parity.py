@@ -63,6 +63,8 @@ RES_CASES = [
     ((2, 1, 1), 10, 3, False),
     ((1, 1, 1), 17, 2, False),
     ((1, 1, 1), 2, 34, False),
+    # n_vir between 16 and 32: chunked staging of the blocked F and R1 sums, 32-wide ring tiles
+    ((2, 1, 1), 5, 23, True),
 ]
 
 
