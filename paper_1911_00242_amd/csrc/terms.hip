@@ -855,8 +855,9 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
 
 // Blocked forms of the three seeds above for n_occ <= OM, n_vir <= VM: one workgroup per
 // (momentum block, m), XCD-contiguous order.  Each thread keeps the integral row it
-// contracts (over f or e) in registers and produces the outputs of every j (or i), so
-// every <oo||vv>, <ov||vv> and <ov||vo> element is read once instead of n_occ times.
+// contracts (over f or e) in registers (for n_vir > 16 the W0 seed keeps one accumulator
+// per j instead) and produces the outputs of every j (or i), so every <oo||vv>, <ov||vv>
+// and <ov||vo> element is read once instead of n_occ times.
 template <int OM, int VM, bool EX = false>
 __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd *Z) {
     __shared__ cd T1J[OM * VM];
@@ -914,23 +915,50 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
     if (be >= nv * nv) return;
     const int b = be / nv, e = be % nv;
     const cd *g = s.ovvvT + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
-    cd gr[VM], tb[OM];
-#pragma unroll
-    for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int n = 0; n < OM; ++n) tb[n] = n < no ? t1[((int64_t)kb * no + n) * nv + b] : make_double2(0.0, 0.0);
     const cd *w0 = s.ovvoT + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
     cd *wr = WR + blk * blkq + (int64_t)b * ov + (int64_t)m * nv + e;
-    for (int j = 0; j < no; ++j) {
-        cd acc = w0[(int64_t)j * nv];
+    if constexpr (VM <= 16) {
+        // the row <m b||f e> over f in registers, one j at a time
+        cd gr[VM], tb[OM];
 #pragma unroll
-        for (int f = 0; f < VM; ++f)
-            if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
+        for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int n = 0; n < OM; ++n)
-            if (n < no) acc = csub(acc, cmul(tb[n], ZS[(n * no + j) * nv + e]));
-        wr[(int64_t)j * nv * ov] = acc;
+        for (int n = 0; n < OM; ++n) tb[n] = n < no ? t1[((int64_t)kb * no + n) * nv + b] : make_double2(0.0, 0.0);
+        for (int j = 0; j < no; ++j) {
+            cd acc = w0[(int64_t)j * nv];
+#pragma unroll
+            for (int f = 0; f < VM; ++f)
+                if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
+#pragma unroll
+            for (int n = 0; n < OM; ++n)
+                if (n < no) acc = csub(acc, cmul(tb[n], ZS[(n * no + j) * nv + e]));
+            wr[(int64_t)j * nv * ov] = acc;
+        }
+        return;
     }
+    // wider rows: one accumulator per j, each <m b||f e> loaded once and used for every j
+    cd acc[OM];
+#pragma unroll
+    for (int j = 0; j < OM; ++j) acc[j] = j < no ? w0[(int64_t)j * nv] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int f = 0; f < VM; ++f) {
+        if (f >= nv) break;
+        const cd gv = g[(int64_t)f * nv];
+#pragma unroll
+        for (int j = 0; j < OM; ++j)
+            if (j < no) cfma(acc[j], T1J[j * nv + f], gv);
+    }
+#pragma unroll
+    for (int n = 0; n < OM; ++n) {
+        if (n >= no) break;
+        const cd tv = t1[((int64_t)kb * no + n) * nv + b];
+#pragma unroll
+        for (int j = 0; j < OM; ++j)
+            if (j < no) acc[j] = csub(acc[j], cmul(tv, ZS[(n * no + j) * nv + e]));
+    }
+#pragma unroll
+    for (int j = 0; j < OM; ++j)
+        if (j < no) wr[(int64_t)j * nv * ov] = acc[j];
 }
 
 template <int OM, int VM, bool EX = false>
@@ -1440,7 +1468,8 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         const dim3 grid = xcd_grid(n3 * no);
         hipLaunchKernelGGL((k_ring_z_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
         CK_CHECK(hipGetLastError());
-        LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        hipLaunchKernelGGL((k_ring_w0_t<8, 32, false>), grid, dim3(32 * 32), 0, st, s, t1, scratch, WR);
+        CK_CHECK(hipGetLastError());
         hipLaunchKernelGGL((k_ring_q_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
         CK_CHECK(hipGetLastError());
     } else {
