@@ -20,66 +20,102 @@
 namespace ck {
 
 // tau_pk[K][p'][p] = tau_{i ki, j kj}^{e ke, f kf} for canonical (ki, i, j) = p' and canonical
-// (ke, e, f) = p of group K (rows ld elements apart; the padding rows are written as zeros):
-// a thread per 8 consecutive p of one row, one 64-byte chunk.
-__global__ void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out,
-                           int64_t ld) {
-    const int N = d.N, no = d.no, nv = d.nv;
-    const int nch = pt.PV / 8;
-    const int64_t total = (int64_t)N * pt.PO * nch;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(x % nch);
-        const int64_t row = x / nch;  // K * PO + p'
-        const int K = (int)(row / pt.PO);
-        const int pij = pt.olist[row];
-        const int pq = pij < 0 ? 0 : pij;  // a padding row decodes as pair 0 and writes zeros
-        const int ki = pq / (no * no), i = (pq / no) % no, j = pq % no;
-        const int kj = kcv(kc, N, K, 0, ki);
-        cd v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int pr = pt.vlist[(int64_t)K * pt.PV + c * 8 + q];
-            if (pr < 0 || pij < 0) {
-                v[q] = make_double2(0.0, 0.0);
-                continue;
+// (ke, e, f) = p of group K (rows ld elements apart; the padding rows are written as zeros).
+// A thread per element, consecutive threads on consecutive p, so the reads of t2 and of the
+// pair list are contiguous across a wave; the workgroup's 256 elements (32 whole chunks:
+// PV is a multiple of 8) are put together in split storage in LDS and written as 16-byte
+// words.  EX: n_occ = 8, n_vir = 16 as constants.
+template <bool EX>
+__global__ __launch_bounds__(256) void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1,
+                                                  const cd *t2, uint16_t *out, int64_t ld) {
+    __shared__ __align__(16) uint16_t S[256 * 4];  // chunk-local split layout: chunk * 32 + plane * 8 + q
+    const int N = d.N, no = EX ? 8 : d.no, nv = EX ? 16 : d.nv;
+    const int64_t t2blk = (int64_t)no * no * nv * nv;
+    const int64_t total = (int64_t)N * pt.PO * pt.PV;
+    for (int64_t x0 = (int64_t)blockIdx.x * 256; x0 < total; x0 += (int64_t)gridDim.x * 256) {
+        const int64_t x = x0 + threadIdx.x;
+        cd v = make_double2(0.0, 0.0);
+        if (x < total) {
+            const int64_t row = x / pt.PV;  // K * PO + p'
+            const int col = (int)(x - row * pt.PV);
+            const int K = (int)(row / pt.PO);
+            const int pij = pt.olist[row];
+            const int pr = pt.vlist[(int64_t)K * pt.PV + col];
+            if (pij >= 0 && pr >= 0) {
+                const int ki = pij / (no * no), i = (pij / no) % no, j = pij % no;
+                const int kj = kcv(kc, N, K, 0, ki);
+                const int ke = pr / (nv * nv), e = (pr / nv) % nv, f = pr % nv;
+                const int kf = kcv(kc, N, ki, kj, ke);
+                const int64_t idx = blk3(N, ki, kj, ke) * t2blk + (((int64_t)i * no + j) * nv + e) * nv + f;
+                v = tau_el(t1, t2, idx, ki, kj, ke, kf, i, j, e, f, no, nv, 1.0);
             }
-            const int ke = pr / (nv * nv), e = (pr / nv) % nv, f = pr % nv;
-            const int kf = kcv(kc, N, ki, kj, ke);
-            const int64_t idx = blk3(N, ki, kj, ke) * d.t2blk() + (((int64_t)i * no + j) * nv + e) * nv + f;
-            v[q] = tau_el(t1, t2, idx, ki, kj, ke, kf, i, j, e, f, no, nv, 1.0);
         }
-        put_chunk(out, row * ld + (int64_t)c * 8, v);
+        uint16_t h0, h1, h2, h3;
+        split2(v.x, h0, h1);
+        split2(v.y, h2, h3);
+        const int ch = threadIdx.x >> 3, q = threadIdx.x & 7;
+        S[ch * 32 + q] = h0;
+        S[ch * 32 + 8 + q] = h1;
+        S[ch * 32 + 16 + q] = h2;
+        S[ch * 32 + 24 + q] = h3;
+        __syncthreads();
+        if (threadIdx.x < 128) {
+            const int c = threadIdx.x >> 2, p = threadIdx.x & 3;  // chunk, plane
+            const int64_t xc = x0 + c * 8;                        // first element of the chunk
+            if (xc < total) {
+                const int64_t row = xc / pt.PV;
+                const int64_t o = row * ld + (xc - row * pt.PV);
+                *(uint4 *)(out + split_index(o, p)) = *(const uint4 *)(S + c * 32 + p * 8);
+            }
+        }
+        __syncthreads();
     }
 }
 
-// tauT_pk[K][p'][p] = tau_{m km, n kn}^{a ka, b kb} for canonical (ka, a, b) = p' of group K
-// and canonical (km, m, n) = p (rows ld elements apart): the B operand of the hole-hole
-// ladder.
-__global__ void k_tauT_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1, const cd *t2, uint16_t *out,
-                            int64_t ld) {
-    const int N = d.N, no = d.no, nv = d.nv;
-    const int nch = pt.PO / 8;
-    const int64_t total = (int64_t)N * pt.PV * nch;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(x % nch);
-        const int64_t row = x / nch;  // K * PV + p'
-        const int K = (int)(row / pt.PV);
-        const int pab = pt.vlist[row];
-        cd v[8];
+// tauT_pk[K][p'][p] = tau_{m km, n kn}^{a ka, b kb} for canonical (ka, a, b) = p' and
+// canonical (km, m, n) = p: the B operand of the hole-hole ladder, which is the tau_pk of
+// the same group transposed (padding included).  A workgroup moves a 64 x 64 tile of split
+// storage through LDS, each element as one 8-byte unit of its four bf16 planes; both the
+// reads and the writes are whole 64-byte chunks.
+constexpr int TT = 64;
+__global__ __launch_bounds__(256) void k_tau_transpose(int PO, int PV, const uint16_t *src, int64_t lds,
+                                                       uint16_t *dst, int64_t ldd) {
+    __shared__ uint2 T[TT][TT + 1];  // [p' - m0][p - n0]
+    const int K = blockIdx.z, m0 = blockIdx.y * TT, n0 = blockIdx.x * TT;
+    for (int u = threadIdx.x; u < TT * (TT / 8); u += blockDim.x) {
+        const int r = u / (TT / 8), c = u % (TT / 8), row = m0 + r, col = n0 + c * 8;
+        if (row >= PO || col >= PV) continue;
+        const uint4 *s = (const uint4 *)(src + split_index(((int64_t)K * PO + row) * lds + col, 0));
+        uint32_t w[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint4 v = s[p];
+            w[p][0] = v.x, w[p][1] = v.y, w[p][2] = v.z, w[p][3] = v.w;
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int pmn = pt.olist[(int64_t)K * pt.PO + c * 8 + q];
-            if (pab < 0 || pmn < 0) {
-                v[q] = make_double2(0.0, 0.0);
-                continue;
-            }
-            const int ka = pab / (nv * nv), a = (pab / nv) % nv, b = pab % nv;
-            const int km = pmn / (no * no), mm = (pmn / no) % no, nn = pmn % no;
-            const int kn = kcv(kc, N, K, 0, km), kb = kcv(kc, N, km, kn, ka);
-            const int64_t idx = blk3(N, km, kn, ka) * d.t2blk() + (((int64_t)mm * no + nn) * nv + a) * nv + b;
-            v[q] = tau_el(t1, t2, idx, km, kn, ka, kb, mm, nn, a, b, no, nv, 1.0);
+            const int sh = (q & 1) * 16, k = q >> 1;
+            const uint32_t h0 = (w[0][k] >> sh) & 0xffffu, h1 = (w[1][k] >> sh) & 0xffffu;
+            const uint32_t h2 = (w[2][k] >> sh) & 0xffffu, h3 = (w[3][k] >> sh) & 0xffffu;
+            T[r][c * 8 + q] = make_uint2(h0 | h1 << 16, h2 | h3 << 16);
         }
-        put_chunk(out, row * ld + (int64_t)c * 8, v);
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < TT * (TT / 8); u += blockDim.x) {
+        const int r = u / (TT / 8), c = u % (TT / 8), row = n0 + r, col = m0 + c * 8;
+        if (row >= PV || col >= PO) continue;
+        uint2 e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = T[c * 8 + q][r];
+        uint4 *o = (uint4 *)(dst + split_index(((int64_t)K * PV + row) * ldd + col, 0));
+        o[0] = make_uint4((e[0].x & 0xffffu) | e[1].x << 16, (e[2].x & 0xffffu) | e[3].x << 16,
+                          (e[4].x & 0xffffu) | e[5].x << 16, (e[6].x & 0xffffu) | e[7].x << 16);
+        o[1] = make_uint4(e[0].x >> 16 | (e[1].x & 0xffff0000u), e[2].x >> 16 | (e[3].x & 0xffff0000u),
+                          e[4].x >> 16 | (e[5].x & 0xffff0000u), e[6].x >> 16 | (e[7].x & 0xffff0000u));
+        o[2] = make_uint4((e[0].y & 0xffffu) | e[1].y << 16, (e[2].y & 0xffffu) | e[3].y << 16,
+                          (e[4].y & 0xffffu) | e[5].y << 16, (e[6].y & 0xffffu) | e[7].y << 16);
+        o[3] = make_uint4(e[0].y >> 16 | (e[1].y & 0xffff0000u), e[2].y >> 16 | (e[3].y & 0xffff0000u),
+                          e[4].y >> 16 | (e[5].y & 0xffff0000u), e[6].y >> 16 | (e[7].y & 0xffff0000u));
     }
 }
 
@@ -229,11 +265,14 @@ bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv <=
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
                      uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st) {
     const int64_t N = d.N;
-    hipLaunchKernelGGL(k_tau_pack, pack_grid(N * pt.PO * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk,
-                       ld_tau);
+    const dim3 g = pack_grid(N * pt.PO * pt.PV);
+    if (d.no == 8 && d.nv == 16)
+        hipLaunchKernelGGL(k_tau_pack<true>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau);
+    else
+        hipLaunchKernelGGL(k_tau_pack<false>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau);
     CK_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_tauT_pack, pack_grid(N * pt.PV * (pt.PO / 8)), dim3(256), 0, st, d, kc, pt, t1, t2,
-                       tauT_pk, ld_tauT);
+    const dim3 gt((unsigned)((pt.PV + TT - 1) / TT), (unsigned)((pt.PO + TT - 1) / TT), (unsigned)N);
+    hipLaunchKernelGGL(k_tau_transpose, gt, dim3(256), 0, st, pt.PO, pt.PV, tau_pk, ld_tau, tauT_pk, ld_tauT);
     CK_CHECK(hipGetLastError());
 }
 
