@@ -50,6 +50,7 @@ struct System {
     cd *scr = nullptr, *P1 = nullptr;
     cd *ovvoT = nullptr;  // static ovvo, ovvv, oovv classes with their last two indices swapped
     cd *ovvvT = nullptr, *oovvT = nullptr;
+    ck::cf *ovvv_c = nullptr, *ovvvT_c = nullptr;  // mixed path: complex64 ovvv and ovvvT (no FP64 ovvvT)
     cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
@@ -110,6 +111,8 @@ struct System {
         s.ovvoT = ovvoT;
         s.ovvvT = ovvvT;
         s.oovvT = oovvT;
+        s.ovvv_c = ovvv_c;
+        s.ovvvT_c = ovvvT_c;
         return s;
     }
     ck::PairTabs pairs() const {
@@ -423,7 +426,12 @@ void carve(System &S, Carver &c) {
     c.take(S.X, N3 * o * v * o * v);
     c.take(S.scr, N3 * o * o * o * v);
     c.take(S.ovvoT, S.n2());
-    c.take(S.ovvvT, N3 * cls[4]);
+    if (S.mixed) {
+        c.take(S.ovvv_c, N3 * cls[4]);
+        c.take(S.ovvvT_c, N3 * cls[4]);
+    } else {
+        c.take(S.ovvvT, N3 * cls[4]);
+    }
     c.take(S.oovvT, S.n2());
     c.take(S.P1, 2 * N3 * o * v);
     c.take(S.fw.Fov, N * o * v);
@@ -766,7 +774,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                                          ctx->stream);
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
                 ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
-                ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
+                ck::launch_static_swaps(S.dev(), S.ovvvT, S.ovvv_c, S.ovvvT_c, S.oovvT, ctx->stream);
                 if (S.mixed) static_split(S, ctx->stream);
                 S.inputs = true;
             }
@@ -804,7 +812,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
             CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
         ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
-        ck::launch_static_swaps(S.dev(), S.ovvvT, S.oovvT, ctx->stream);
+        ck::launch_static_swaps(S.dev(), S.ovvvT, S.ovvv_c, S.ovvvT_c, S.oovvT, ctx->stream);
         if (S.mixed) static_split(S, ctx->stream);
         S.e_ok = false;
         CK_CHECK(hipStreamSynchronize(ctx->stream));

@@ -34,6 +34,12 @@ __host__ __device__ inline cd cadd(cd a, cd b) { return make_double2(a.x + b.x, 
 __host__ __device__ inline cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline cd cscale(cd a, double s) { return make_double2(a.x * s, a.y * s); }
 __host__ __device__ inline cd cconj(cd a) { return make_double2(a.x, -a.y); }
+// an element of a complex64 copy widened to complex128 (and the identity on complex128)
+__host__ __device__ inline cd to_cd(cd v) { return v; }
+__host__ __device__ inline cd to_cd(cf v) { return make_double2((double)v.x, (double)v.y); }
+// and back: y = x, rounded to complex64 for a complex64 y
+__host__ __device__ inline void from_cd(cd x, cd &y) { y = x; }
+__host__ __device__ inline void from_cd(cd x, cf &y) { y = make_float2((float)x.x, (float)x.y); }
 // a += b * c
 __host__ __device__ inline void cfma(cd &a, cd b, cd c) {
     a.x = fma(b.x, c.x, fma(-b.y, c.y, a.x));
@@ -64,7 +70,18 @@ struct SysDev {
     const cd *ovvoT;  // ovvo with the last two indices swapped: [km][kb][ke][m][b][j][e]
     const cd *ovvvT;  // ovvv with the last two indices swapped: [km][kb][ke][m][b][f][e]
     const cd *oovvT;  // oovv with the last two indices swapped: [km][kn][ke][m][n][f][e]
+    // Mixed-precision path only (null otherwise): complex64 copies of ovvv and ovvvT for
+    // the side terms that scale them by t1 or t2 (then ovvvT above is not kept).
+    const cf *ovvv_c, *ovvvT_c;
 };
+
+// The ovvv / ovvvT copy a kernel instantiated for element type IT reads.
+template <class IT> __device__ inline const IT *ovvv_of(const SysDev &s);
+template <> __device__ inline const cd *ovvv_of<cd>(const SysDev &s) { return s.ovvv; }
+template <> __device__ inline const cf *ovvv_of<cf>(const SysDev &s) { return s.ovvv_c; }
+template <class IT> __device__ inline const IT *ovvvT_of(const SysDev &s);
+template <> __device__ inline const cd *ovvvT_of<cd>(const SysDev &s) { return s.ovvvT; }
+template <> __device__ inline const cf *ovvvT_of<cf>(const SysDev &s) { return s.ovvvT_c; }
 
 // ---------------------------------------------------------------------------------
 // Grouped complex GEMM with gathered operands (all element offsets in complex units):

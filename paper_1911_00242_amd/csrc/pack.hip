@@ -170,8 +170,9 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
     const int64_t blk = pt.dblk[L / nv];
     const int ke = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
     const int K = kcv(s.kc, N, ka, kb, 0);
-    const cd *g1b = s.ovvv + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
-    const cd *g2b = s.ovvv + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
+    // the complex64 copy of ovvv: the t1 terms are rounded to bf16 pairs with <ab||ef> anyway
+    const cf *g1b = s.ovvv_c + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
+    const cf *g2b = s.ovvv_c + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
     const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
     const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
     const int32_t *vpos_ab = pt.vpos + ((int64_t)K * N + ka) * vv;
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
         if (a0) __syncthreads();
         for (int x = threadIdx.x; x < no * anv; x += blockDim.x) {
             const int m = x / anv, af = x % anv;
-            G1[x] = g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv];
+            G1[x] = to_cd(g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv]);
         }
         for (int x = threadIdx.x; x < no * na; x += blockDim.x) TA[x] = ta[(x / na) * nv + a0 + x % na];
         __syncthreads();
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
             cd g2[OM], t1b[OM];
 #pragma unroll
             for (int m = 0; m < OM; ++m) {
-                g2[m] = m < no ? g2b[(int64_t)m * v3 + (int64_t)b * vv + f] : make_double2(0.0, 0.0);
+                g2[m] = m < no ? to_cd(g2b[(int64_t)m * v3 + (int64_t)b * vv + f]) : make_double2(0.0, 0.0);
                 t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
             }
             for (int a = 0; a < na; ++a) {

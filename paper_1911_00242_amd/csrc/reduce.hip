@@ -159,10 +159,6 @@ template <class E>
 struct ErrPack {
     const E *p[16];
 };
-__device__ inline cd to_cd(cd x) { return x; }
-__device__ inline cd to_cd(cf x) { return make_double2((double)x.x, (double)x.y); }
-__device__ inline void from_cd(cd x, cd &y) { y = x; }
-__device__ inline void from_cd(cd x, cf &y) { y = make_float2((float)x.x, (float)x.y); }
 
 template <class E>
 __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r, E *err, cd *hist,

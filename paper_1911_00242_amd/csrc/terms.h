@@ -25,8 +25,9 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st);
 // the static ovvo class with its last two indices swapped (once per set of inputs)
 void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st);
-// ovvv and oovv with their last two indices swapped (once per set of inputs)
-void launch_static_swaps(const SysDev &s, cd *ovvvT, cd *oovvT, hipStream_t st);
+// ovvv and oovv with their last two indices swapped (once per set of inputs): ovvvT (FP64
+// path) or, when ovvv_c is non-null (mixed path), complex64 copies of ovvv and ovvvT; oovvT
+void launch_static_swaps(const SysDev &s, cd *ovvvT, cf *ovvv_c, cf *ovvvT_c, cd *oovvT, hipStream_t st);
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
 // the two halves of launch_r1: the t2 x integral partial sums (which need no intermediate),
 // then R1 from t1, t2, F and those partials

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
 // staged in LDS (the next n prefetched into registers).  For P1a a thread owns one a and
 // a sixteenth of (e, f) and streams <n q, a p||e r, f> from global memory once, for every
 // i; for P1b a thread owns one (i, a) and half of the m range.
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
     static_assert(OM == 8 && VM == 16, "thread roles assume n_occ <= 8, n_vir <= 16");
     constexpr int VP = VM + 1;
@@ -452,8 +452,8 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int64_t tb = blk * s.d.t2blk();
     const int64_t ov3 = (int64_t)no * nv * nv * nv, o3v = (int64_t)no * no * no * nv;
-    const cd *gb = s.ovvv + blk3(N, q, p, r) * ov3;  // (n, a, e, f)
-    const cd *hb = s.ooov + blk * o3v;              // (m, n, i, f)
+    const IT *gb = ovvv_of<IT>(s) + blk3(N, q, p, r) * ov3;  // (n, a, e, f)
+    const cd *hb = s.ooov + blk * o3v;                       // (m, n, i, f)
     cd pt[PT], ph[PH];
 #define RB_LOAD(n)                                                                          \
     _Pragma("unroll") for (int u = 0; u < PT; ++u) {                                        \
@@ -490,12 +490,12 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
         if (n + 1 < no) RB_LOAD(n + 1)
         // P1a(i, a) += sum_{ef} t2(i,n,e,f) <n a||e f>, this thread's (e, f) = ks + 16 u
         if (aa < nv) {
-            const cd *g = gb + ((int64_t)n * nv + aa) * nv * nv;
+            const IT *g = gb + ((int64_t)n * nv + aa) * nv * nv;
 #pragma unroll 4
             for (int u = 0; u < VM * VM / 16; ++u) {
                 const int ef = ks + 16 * u, e = ef / VM, f = ef % VM;
                 if (e < nv && f < nv) {
-                    const cd gv = g[e * nv + f];
+                    const cd gv = to_cd(g[e * nv + f]);
 #pragma unroll
                     for (int i = 0; i < OM; ++i) cfma(acc[i], TS[(i * VM + e) * VP + f], gv);
                 }
@@ -779,13 +779,18 @@ __global__ void k_ovvo_transpose(SysDev s, cd *ovvoT) {
 // Last-two-index swaps of the static ovvv and oovv classes, so that the contractions over
 // their last index below read along lanes:  ovvvT[..](m,b,f,e) = <mb||ef>,
 // oovvT[..](m,n,f,e) = <mn||ef>.
-__global__ void k_swap_last2(int64_t nblocks, int v, const cd *src, cd *dst) {
+// (OT = cf: rounded to complex64, the copy the mixed-precision path reads)
+template <class OT>
+__global__ void k_swap_last2(int64_t nblocks, int v, const cd *src, OT *dst) {
     const int64_t vv = (int64_t)v * v;
     GRID_STRIDE(idx, nblocks * vv) {
         const int64_t r = idx / vv;
         const int e = (int)(idx % v), f = (int)((idx / v) % v);
-        dst[idx] = src[r * vv + (int64_t)e * v + f];
+        from_cd(src[r * vv + (int64_t)e * v + f], dst[idx]);
     }
+}
+__global__ void k_to_c64(int64_t n, const cd *src, cf *dst) {
+    GRID_STRIDE(idx, n) from_cd(src[idx], dst[idx]);
 }
 
 // Z[km][kb][ke](m,n,j,e) = <m km, n kb || e ke, j kj> + sum_f t_j^f <m km, n kb || e ke, f kj>
@@ -809,6 +814,7 @@ __global__ void k_ring_z(SysDev s, const cd *t1, cd *Z) {
 }
 
 // WR[q][kj][km](j,b,m,e) = <mb||ej> + t_j^f <mb||ef> - t_n^b Z(m,n,j,e)   (t2 part by GEMM)
+template <class IT>
 __global__ void k_ring_w0(SysDev s, const cd *t1, const cd *Z, cd *WR) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t ov = (int64_t)no * nv, blkq = ov * ov;
@@ -821,9 +827,9 @@ __global__ void k_ring_w0(SysDev s, const cd *t1, const cd *Z, cd *WR) {
         int kb = kcv(s.kc, N, kj, 0, q), ke = kcv(s.kc, N, km, 0, q);
         int64_t bb = blk3(N, km, kb, ke);
         cd acc = s.ovvoT[bb * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv + e];
-        const cd *g = s.ovvvT + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
+        const IT *g = ovvvT_of<IT>(s) + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
         #pragma unroll 8
-        for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], g[(int64_t)f * nv]);
+        for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], to_cd(g[(int64_t)f * nv]));
         const cd *z = Z + bb * o3v + (int64_t)m * no * no * nv + (int64_t)j * nv + e;
         #pragma unroll 8
         for (int nn = 0; nn < no; ++nn)
@@ -892,7 +898,7 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd
     }
 }
 
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, const cd *Z, cd *WR) {
     __shared__ cd ZS[OM * OM * VM];  // Z(m, n, j, e) of this m at (n * no + j) * nv + e
     __shared__ cd T1J[OM * VM];      // t1[kj](j, f)
@@ -914,14 +920,14 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
     const int be = threadIdx.x;
     if (be >= nv * nv) return;
     const int b = be / nv, e = be % nv;
-    const cd *g = s.ovvvT + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
+    const IT *g = ovvvT_of<IT>(s) + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
     const cd *w0 = s.ovvoT + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
     cd *wr = WR + blk * blkq + (int64_t)b * ov + (int64_t)m * nv + e;
     if constexpr (VM <= 16) {
         // the row <m b||f e> over f in registers, one j at a time
         cd gr[VM], tb[OM];
 #pragma unroll
-        for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
+        for (int f = 0; f < VM; ++f) gr[f] = f < nv ? to_cd(g[(int64_t)f * nv]) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int n = 0; n < OM; ++n) tb[n] = n < no ? t1[((int64_t)kb * no + n) * nv + b] : make_double2(0.0, 0.0);
         for (int j = 0; j < no; ++j) {
@@ -943,7 +949,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
 #pragma unroll
     for (int f = 0; f < VM; ++f) {
         if (f >= nv) break;
-        const cd gv = g[(int64_t)f * nv];
+        const cd gv = to_cd(g[(int64_t)f * nv]);
 #pragma unroll
         for (int j = 0; j < OM; ++j)
             if (j < no) cfma(acc[j], T1J[j * nv + f], gv);
@@ -1091,7 +1097,7 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 // at wave-uniform addresses (scalar loads).  The coefficients -1, -1/2, 1/2, -1/2 of the four
 // terms are folded into one factor of each product (exact scalings), so one accumulator per
 // i takes all of them.
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
                                                     const cd *Fot, const cd *Fvt, cd *X) {
     constexpr int IH = (OM + 1) / 2;  // i values per LDS phase
@@ -1138,12 +1144,12 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
     for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
     if (act) {
         // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
-        const cd *gb = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
+        const IT *gb = ovvv_of<IT>(s) + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
         const cd *t1i = t1 + (int64_t)ki * no * nv;
 #pragma unroll
         for (int c = 0; c < VM; ++c) {
             if (c >= nv) break;
-            const cd gv = gb[(int64_t)c * nv * nv];
+            const cd gv = to_cd(gb[(int64_t)c * nv * nv]);
             const cd g = make_double2(-0.5 * gv.x, 0.5 * gv.y);  // -1/2 conj(<..>)
 #pragma unroll
             for (int i = 0; i < OM; ++i)
@@ -1348,6 +1354,32 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
         CK_CHECK(hipGetLastError());                                                      \
     } while (0)
 
+// the same with the element type of the ovvv copy a kernel reads (complex64 on the
+// mixed-precision path)
+#define LAUNCH_TI(K, grid, block, ...)                                                    \
+    do {                                                                                  \
+        if (s.ovvv_c) {                                                                   \
+            if (s.d.no == 8 && s.d.nv == 16)                                              \
+                hipLaunchKernelGGL((K<8, 16, true, cf>), grid, block, 0, st, __VA_ARGS__);  \
+            else                                                                          \
+                hipLaunchKernelGGL((K<8, 16, false, cf>), grid, block, 0, st, __VA_ARGS__); \
+        } else {                                                                          \
+            if (s.d.no == 8 && s.d.nv == 16)                                              \
+                hipLaunchKernelGGL((K<8, 16, true, cd>), grid, block, 0, st, __VA_ARGS__);  \
+            else                                                                          \
+                hipLaunchKernelGGL((K<8, 16, false, cd>), grid, block, 0, st, __VA_ARGS__); \
+        }                                                                                 \
+        CK_CHECK(hipGetLastError());                                                      \
+    } while (0)
+#define LAUNCH_32I(K, grid, block, ...)                                                   \
+    do {                                                                                  \
+        if (s.ovvv_c)                                                                     \
+            hipLaunchKernelGGL((K<8, 32, false, cf>), grid, block, 0, st, __VA_ARGS__);     \
+        else                                                                              \
+            hipLaunchKernelGGL((K<8, 32, false, cd>), grid, block, 0, st, __VA_ARGS__);     \
+        CK_CHECK(hipGetLastError());                                                      \
+    } while (0)
+
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     hipLaunchKernelGGL(k_fov, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
@@ -1449,10 +1481,15 @@ void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st) {
     LAUNCH(k_ovvo_transpose, s.d.t2(), s, ovvoT);
 }
 
-void launch_static_swaps(const SysDev &s, cd *ovvvT, cd *oovvT, hipStream_t st) {
+void launch_static_swaps(const SysDev &s, cd *ovvvT, cf *ovvv_c, cf *ovvvT_c, cd *oovvT, hipStream_t st) {
     const int64_t N3 = (int64_t)s.d.N * s.d.N * s.d.N, o = s.d.no, v = s.d.nv;
-    LAUNCH(k_swap_last2, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, ovvvT);
-    LAUNCH(k_swap_last2, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, oovvT);
+    if (ovvv_c) {
+        LAUNCH(k_to_c64, N3 * o * v * v * v, N3 * o * v * v * v, s.ovvv, ovvv_c);
+        LAUNCH(k_swap_last2<cf>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, ovvvT_c);
+    } else {
+        LAUNCH(k_swap_last2<cd>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, ovvvT);
+    }
+    LAUNCH(k_swap_last2<cd>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, oovvT);
 }
 
 void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
@@ -1462,28 +1499,27 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
     if (no <= 8 && nv <= 16) {
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_T(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
-        LAUNCH_T(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
+        LAUNCH_TI(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
         LAUNCH_T(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
     } else if (no <= 8 && nv <= 32) {
         const dim3 grid = xcd_grid(n3 * no);
         hipLaunchKernelGGL((k_ring_z_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
         CK_CHECK(hipGetLastError());
-        hipLaunchKernelGGL((k_ring_w0_t<8, 32, false>), grid, dim3(32 * 32), 0, st, s, t1, scratch, WR);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_32I(k_ring_w0_t, grid, dim3(32 * 32), s, t1, scratch, WR);
         hipLaunchKernelGGL((k_ring_q_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
-        LAUNCH(k_ring_w0, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        if (s.ovvv_c)
+            LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        else
+            LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
         LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
     }
     if (no <= 8 && nv <= 16) {
-        LAUNCH_T(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot,
-                           w.Fvt, X);
+        LAUNCH_TI(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else if (no <= 8 && nv <= 32) {
-        hipLaunchKernelGGL((k_xinit_t<8, 32, false>), xcd_grid(n3 * nv), dim3(8 * 32), 0, st, s, t1, t2, scratch,
-                           w.Fot, w.Fvt, X);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_32I(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }
@@ -1501,7 +1537,7 @@ void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
     if (no <= 8 && nv <= 16) {
-        LAUNCH_T(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
+        LAUNCH_TI(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
     } else if (r1_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(RB_NT), 0, st, s, t2, P1, P1 + np);
         CK_CHECK(hipGetLastError());
