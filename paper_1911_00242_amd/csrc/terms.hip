@@ -865,8 +865,7 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
 // per j instead) and produces the outputs of every j (or i), so every <oo||vv>, <ov||vv>
 // and <ov||vo> element is read once instead of n_occ times.
 template <int OM, int VM, bool EX = false>
-__global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd *Z) {
-    __shared__ cd T1J[OM * VM];
+__global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *__restrict__ t1, cd *__restrict__ Z) {
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv;
     const int64_t nblk = (int64_t)N * N * N * no;
@@ -876,8 +875,7 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd
     const int64_t blk = L / no;
     const int ke = (int)(blk % N), kb = (int)((blk / N) % N), km = (int)(blk / ((int64_t)N * N));
     const int kj = kcv(s.kc, N, km, kb, ke);
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1J[x] = t1[(int64_t)kj * no * nv + x];
-    __syncthreads();
+    const cd *T1J = t1 + (int64_t)kj * no * nv;  // read at wave-uniform addresses (scalar loads)
     const int ne = threadIdx.x;
     if (ne >= no * nv) return;
     const int nn = ne / nv, e = ne % nv;
@@ -899,9 +897,9 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *t1, cd
 }
 
 template <int OM, int VM, bool EX = false, class IT = cd>
-__global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, const cd *Z, cd *WR) {
+__global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__restrict__ t1, const cd *__restrict__ Z,
+                                                      cd *__restrict__ WR) {
     __shared__ cd ZS[OM * OM * VM];  // Z(m, n, j, e) of this m at (n * no + j) * nv + e
-    __shared__ cd T1J[OM * VM];      // t1[kj](j, f)
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t ov = (int64_t)no * nv, blkq = ov * ov;
     const int64_t o3v = (int64_t)no * no * no * nv, ov3 = (int64_t)no * nv * nv * nv;
@@ -915,7 +913,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *t1, c
     const int64_t bb = blk3(N, km, kb, ke);
     const cd *zb = Z + bb * o3v + (int64_t)m * no * no * nv;
     for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) ZS[x] = zb[x];
-    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1J[x] = t1[(int64_t)kj * no * nv + x];
+    const cd *T1J = t1 + (int64_t)kj * no * nv;  // t1[kj](j, f), wave-uniform addresses (scalar loads)
     __syncthreads();
     const int be = threadIdx.x;
     if (be >= nv * nv) return;
