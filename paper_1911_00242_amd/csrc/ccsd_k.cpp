@@ -50,7 +50,8 @@ struct System {
     cd *scr = nullptr, *P1 = nullptr;
     cd *ovvoT = nullptr;  // static ovvo, ovvv, oovv classes with their last two indices swapped
     cd *ovvvT = nullptr, *oovvT = nullptr;
-    ck::cf *ovvv_c = nullptr, *ovvvT_c = nullptr;  // mixed path: complex64 ovvv and ovvvT (no FP64 ovvvT)
+    // mixed path: complex64 copies in place of the three above, and of ovvv and oovv
+    ck::cf *ovvoT_c = nullptr, *ovvv_c = nullptr, *ovvvT_c = nullptr, *oovv_c = nullptr, *oovvT_c = nullptr;
     cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
@@ -113,7 +114,13 @@ struct System {
         s.oovvT = oovvT;
         s.ovvv_c = ovvv_c;
         s.ovvvT_c = ovvvT_c;
+        s.ovvoT_c = ovvoT_c;
+        s.oovvT_c = oovvT_c;
+        s.oovv_c = oovv_c;
         return s;
+    }
+    ck::StaticCopies statics() const {
+        return ck::StaticCopies{ovvoT, ovvvT, oovvT, ovvoT_c, ovvv_c, ovvvT_c, oovv_c, oovvT_c};
     }
     ck::PairTabs pairs() const {
         const int64_t N = d.N;
@@ -425,14 +432,17 @@ void carve(System &S, Carver &c) {
     c.take(S.WR, N3 * o * v * o * v);
     c.take(S.X, N3 * o * v * o * v);
     c.take(S.scr, N3 * o * o * o * v);
-    c.take(S.ovvoT, S.n2());
     if (S.mixed) {
+        c.take(S.ovvoT_c, S.n2());
         c.take(S.ovvv_c, N3 * cls[4]);
         c.take(S.ovvvT_c, N3 * cls[4]);
+        c.take(S.oovv_c, S.n2());
+        c.take(S.oovvT_c, S.n2());
     } else {
+        c.take(S.ovvoT, S.n2());
         c.take(S.ovvvT, N3 * cls[4]);
+        c.take(S.oovvT, S.n2());
     }
-    c.take(S.oovvT, S.n2());
     c.take(S.P1, 2 * N3 * o * v);
     c.take(S.fw.Fov, N * o * v);
     c.take(S.fw.Foo, N * o * o);
@@ -773,8 +783,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                     ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
                                          ctx->stream);
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
-                ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
-                ck::launch_static_swaps(S.dev(), S.ovvvT, S.ovvv_c, S.ovvvT_c, S.oovvT, ctx->stream);
+                ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
                 if (S.mixed) static_split(S, ctx->stream);
                 S.inputs = true;
             }
@@ -811,8 +820,7 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         for (int i = 0; i < 6; ++i)
             CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
-        ck::launch_ovvo_transpose(S.dev(), S.ovvoT, ctx->stream);
-        ck::launch_static_swaps(S.dev(), S.ovvvT, S.ovvv_c, S.ovvvT_c, S.oovvT, ctx->stream);
+        ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
         if (S.mixed) static_split(S, ctx->stream);
         S.e_ok = false;
         CK_CHECK(hipStreamSynchronize(ctx->stream));

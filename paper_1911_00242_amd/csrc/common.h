@@ -70,18 +70,29 @@ struct SysDev {
     const cd *ovvoT;  // ovvo with the last two indices swapped: [km][kb][ke][m][b][j][e]
     const cd *ovvvT;  // ovvv with the last two indices swapped: [km][kb][ke][m][b][f][e]
     const cd *oovvT;  // oovv with the last two indices swapped: [km][kn][ke][m][n][f][e]
-    // Mixed-precision path only (null otherwise): complex64 copies of ovvv and ovvvT for
-    // the side terms that scale them by t1 or t2 (then ovvvT above is not kept).
-    const cf *ovvv_c, *ovvvT_c;
+    // Mixed-precision path only (null otherwise): complex64 copies of the classes the side
+    // kernels read (then ovvoT, ovvvT and oovvT above are not kept).  They enter the
+    // residual scaled by amplitudes, or next to products formed in split bf16, or (oovv)
+    // as the driver term and in the energy, where their rounding errors average out.
+    const cf *ovvv_c, *ovvvT_c, *ovvoT_c, *oovvT_c, *oovv_c;
 };
 
-// The ovvv / ovvvT copy a kernel instantiated for element type IT reads.
+// The copy of a class a kernel instantiated for element type IT reads.
 template <class IT> __device__ inline const IT *ovvv_of(const SysDev &s);
 template <> __device__ inline const cd *ovvv_of<cd>(const SysDev &s) { return s.ovvv; }
 template <> __device__ inline const cf *ovvv_of<cf>(const SysDev &s) { return s.ovvv_c; }
 template <class IT> __device__ inline const IT *ovvvT_of(const SysDev &s);
 template <> __device__ inline const cd *ovvvT_of<cd>(const SysDev &s) { return s.ovvvT; }
 template <> __device__ inline const cf *ovvvT_of<cf>(const SysDev &s) { return s.ovvvT_c; }
+template <class IT> __device__ inline const IT *ovvoT_of(const SysDev &s);
+template <> __device__ inline const cd *ovvoT_of<cd>(const SysDev &s) { return s.ovvoT; }
+template <> __device__ inline const cf *ovvoT_of<cf>(const SysDev &s) { return s.ovvoT_c; }
+template <class IT> __device__ inline const IT *oovvT_of(const SysDev &s);
+template <> __device__ inline const cd *oovvT_of<cd>(const SysDev &s) { return s.oovvT; }
+template <> __device__ inline const cf *oovvT_of<cf>(const SysDev &s) { return s.oovvT_c; }
+template <class IT> __device__ inline const IT *oovv_of(const SysDev &s);
+template <> __device__ inline const cd *oovv_of<cd>(const SysDev &s) { return s.oovv; }
+template <> __device__ inline const cf *oovv_of<cf>(const SysDev &s) { return s.oovv_c; }
 
 // ---------------------------------------------------------------------------------
 // Grouped complex GEMM with gathered operands (all element offsets in complex units):

@@ -302,7 +302,8 @@ void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, u
 }
 
 // ------------------------------------------------------------------ R2 assembly
-// r2 = <ab||ij>* + P(ij)P(ab) X + L, with L the ladders' packed result Lp[K][p'][p]
+// r2 = <ab||ij>* + P(ij)P(ab) X + L (the driver term from the complex64 copy of <ij||ab>),
+// with L the ladders' packed result Lp[K][p'][p]
 // (canonical (ki, i, j) = p', canonical (ka, a, b) = p) expanded by antisymmetry:
 // L(ij, ab) = s_ij s_ab Lp[canonical ij][canonical ab], s = -1 for a pair in the
 // non-canonical order, 0 for a pair of two equal members.
@@ -401,11 +402,11 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
         const cd l1 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, ka, a, kb, b);
         {  // B1 and B2
             const cd x1 = at(Xa, sa, a, b), x2 = at(Xb, sb, a, b), x3 = at(Xc, sc, b, a), x4 = at(Xd, sd, b, a);
-            const cd d1 = cconj(s.oovv[o1 + e]);
+            const cd d1 = cconj(to_cd(s.oovv_c[o1 + e]));
             const cd p1 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
             put(o1 + e, make_double2((d1.x + p1.x) + l1.x, (d1.y + p1.y) + l1.y));
             if (!own_ij) {
-                const cd d2 = cconj(s.oovv[o2 + e]);
+                const cd d2 = cconj(to_cd(s.oovv_c[o2 + e]));
                 const cd p2 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
                 put(o2 + e, make_double2((d2.x + p2.x) - l1.x, (d2.y + p2.y) - l1.y));
             }
@@ -413,11 +414,11 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
         if (!own_ab) {  // B3 and B4: the a slot at kb
             const cd l3 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, kb, a, ka, b);
             const cd x1 = at(Xc, sc, a, b), x2 = at(Xd, sd, a, b), x3 = at(Xa, sa, b, a), x4 = at(Xb, sb, b, a);
-            const cd d3 = cconj(s.oovv[o3 + e]);
+            const cd d3 = cconj(to_cd(s.oovv_c[o3 + e]));
             const cd p3 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
             put(o3 + e, make_double2((d3.x + p3.x) + l3.x, (d3.y + p3.y) + l3.y));
             if (!own_ij) {
-                const cd d4 = cconj(s.oovv[o4 + e]);
+                const cd d4 = cconj(to_cd(s.oovv_c[o4 + e]));
                 const cd p4 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
                 put(o4 + e, make_double2((d4.x + p4.x) - l3.x, (d4.y + p4.y) - l3.y));
             }
@@ -479,7 +480,8 @@ void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, c
 // also writes the split copy of t2 that the next residual's products read and the t2 terms
 // of the energy at the new amplitudes (they need the new t1, hence the order).  The energy
 // is 1/4 <ij||ab> t_ij^ab + 1/2 <ij||ab> t_i^a t_j^b (k_a = k_i) summed over every stored
-// element, plus sum f_ia t_i^a, exactly as the stand-alone energy pass.
+// element, plus sum f_ia t_i^a, exactly as the stand-alone energy pass (both with the
+// complex64 copy of <ij||ab>).
 
 __device__ inline void blk_sum2(double &x, double &y, double (*sh)[256]) {
     const int t = threadIdx.x;
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int
                 cd w = cscale(acc, 0.25);
                 if (ka == ki)
                     w = cadd(w, cscale(cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + jj) * nv + b]), 0.5));
-                const cd p = cmul(s.oovv[e], w);
+                const cd p = cmul(to_cd(s.oovv_c[e]), w);
                 er += p.x;
                 ei += p.y;
             }

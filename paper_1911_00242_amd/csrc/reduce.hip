@@ -72,6 +72,8 @@ void launch_norm2(const Dims &d, const cd *r1, const cd *r2, double *partials, d
 }
 
 // E = sum f_ia t_i^a + 1/4 sum <ij||ab> t_ij^ab + 1/2 sum_{ki,kj} <i ki, j kj||a ki, b kj> t_i^a t_j^b
+// (<ij||ab> from the complex64 copy on the mixed path, as the energy terms of the
+// extrapolation pass)
 __global__ void k_energy(SysDev s, const cd *t1, const cd *t2, double *partials) {
     __shared__ double sh[2][256];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
@@ -93,7 +95,7 @@ __global__ void k_energy(SysDev s, const cd *t1, const cd *t2, double *partials)
                 cd tt = cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + j) * nv + b]);
                 amp = cadd(amp, cscale(tt, 0.5));
             }
-            p = cmul(s.oovv[e], amp);
+            p = cmul(s.oovv_c ? to_cd(s.oovv_c[e]) : s.oovv[e], amp);
         }
         v[0] += p.x;
         v[1] += p.y;

@@ -23,11 +23,14 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
                       hipStream_t st);
 // r2 = <ab||ij> + P(ij)P(ab) X
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st);
-// the static ovvo class with its last two indices swapped (once per set of inputs)
-void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st);
-// ovvv and oovv with their last two indices swapped (once per set of inputs): ovvvT (FP64
-// path) or, when ovvv_c is non-null (mixed path), complex64 copies of ovvv and ovvvT; oovvT
-void launch_static_swaps(const SysDev &s, cd *ovvvT, cf *ovvv_c, cf *ovvvT_c, cd *oovvT, hipStream_t st);
+// Relaid-out copies of the static classes, made once per set of inputs: ovvoT, ovvvT and
+// oovvT (the last two indices swapped) on the FP64 path; on the mixed path (ovvv_c
+// non-null) complex64 ovvoT, ovvv, ovvvT, oovv and oovvT instead.
+struct StaticCopies {
+    cd *ovvoT, *ovvvT, *oovvT;
+    cf *ovvoT_c, *ovvv_c, *ovvvT_c, *oovv_c, *oovvT_c;
+};
+void launch_static_copies(const SysDev &s, const StaticCopies &c, hipStream_t st);
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
 // the two halves of launch_r1: the t2 x integral partial sums (which need no intermediate),
 // then R1 from t1, t2, F and those partials

@@ -217,8 +217,9 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
 // used from LDS.  Fvv: a thread owns a 2 x 2 (a, e) tile and a quarter of the m range;
 // Foo: a thread owns a 2 x 2 (m, i) tile and one sixteenth of the (e, f) range; each LDS
 // read feeds two multiply-adds.  Partial sums are combined through LDS at the end.
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
+    const IT *oovv = oovv_of<IT>(s);
     static_assert(OM % 8 == 0 && VM % 16 == 0, "tiling");
     // taut(x, n, e, f) and <x n||e f> at x * RX + e * VP + f: rows padded to VP = VM + 1 and
     // row blocks to RX = VM * VP + 1, so that the lanes of one 8-lane group read distinct
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int kb = kcv(s.kc, N, p, q, r);
     const int64_t base = blk * s.d.t2blk();
-    cd pt[PER], pg[PER];
+    cd pt[PER];
+    IT pg[PER];  // kept in the stored type until written to LDS, so the load is not waited for early
 #define FB_LOAD(n)                                                                              \
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
         const int x = tid + 256 * u;                                                            \
@@ -240,9 +242,10 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
         if (row < no && e < nv && f < nv) {                                                     \
             const int64_t gi = base + (((int64_t)row * no + (n)) * nv + e) * nv + f;            \
             pt[u] = tau_el(t1, t2, gi, p, q, r, kb, row, (n), e, f, no, nv, 0.5);                \
-            pg[u] = s.oovv[gi];                                                                 \
+            pg[u] = oovv[gi];                                                                   \
         } else {                                                                                \
-            pt[u] = pg[u] = make_double2(0.0, 0.0);                                             \
+            pt[u] = make_double2(0.0, 0.0);                                                     \
+            pg[u] = IT{};                                                                       \
         }                                                                                       \
     }
 #define FB_STORE()                                                                              \
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
         const int x = tid + 256 * u;                                                            \
         const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
         TS[row * RX + e * VP + f] = pt[u];                                                      \
-        GS[row * RX + e * VP + f] = pg[u];                                                      \
+        GS[row * RX + e * VP + f] = to_cd(pg[u]);                                               \
     }
     // Fvv roles: outputs (a0 + 8 da, e0 + 8 de), m quarter; the eight lanes of a group share
     // a0 (one broadcast row) and take eight consecutive e0
@@ -767,12 +770,13 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd
 // ovvoT[km][kb][ke](m,b,j,e) = <m km, b kb || e ke, j kj>: the static ovvo class with its
 // last two indices swapped, made once per set of inputs so that every ring seed below
 // reads contiguous runs.
-__global__ void k_ovvo_transpose(SysDev s, cd *ovvoT) {
+template <class OT>
+__global__ void k_ovvo_transpose(SysDev s, OT *ovvoT) {
     const int no = s.d.no, nv = s.d.nv;
     GRID_STRIDE(idx, s.d.t2()) {
         int e = (int)(idx % nv), j = (int)((idx / nv) % no);
         int64_t mb = idx / ((int64_t)no * nv);  // (block, m, b)
-        ovvoT[idx] = s.ovvo[(mb * nv + e) * no + j];
+        from_cd(s.ovvo[(mb * nv + e) * no + j], ovvoT[idx]);
     }
 }
 
@@ -794,6 +798,7 @@ __global__ void k_to_c64(int64_t n, const cd *src, cf *dst) {
 }
 
 // Z[km][kb][ke](m,n,j,e) = <m km, n kb || e ke, j kj> + sum_f t_j^f <m km, n kb || e ke, f kj>
+template <class IT>
 __global__ void k_ring_z(SysDev s, const cd *t1, cd *Z) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv;
@@ -806,9 +811,9 @@ __global__ void k_ring_z(SysDev s, const cd *t1, cd *Z) {
         // <mn||ej> = -<mn||je>  (ooov block [km,kb,kj])
         cd acc = s.ooov[blk3(N, km, kb, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv + e];
         acc = make_double2(-acc.x, -acc.y);
-        const cd *g = s.oovvT + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
+        const IT *g = oovvT_of<IT>(s) + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
         #pragma unroll 8
-        for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], g[(int64_t)f * nv]);
+        for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], to_cd(g[(int64_t)f * nv]));
         Z[idx] = acc;
     }
 }
@@ -826,7 +831,7 @@ __global__ void k_ring_w0(SysDev s, const cd *t1, const cd *Z, cd *WR) {
         int km = (int)(blk % N), kj = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
         int kb = kcv(s.kc, N, kj, 0, q), ke = kcv(s.kc, N, km, 0, q);
         int64_t bb = blk3(N, km, kb, ke);
-        cd acc = s.ovvoT[bb * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv + e];
+        cd acc = to_cd(ovvoT_of<IT>(s)[bb * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv + e]);
         const IT *g = ovvvT_of<IT>(s) + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
         #pragma unroll 8
         for (int f = 0; f < nv; ++f) cfma(acc, t1[((int64_t)kj * no + j) * nv + f], to_cd(g[(int64_t)f * nv]));
@@ -839,6 +844,7 @@ __global__ void k_ring_w0(SysDev s, const cd *t1, const cd *Z, cd *WR) {
 }
 
 // Q[ka][kb][ki](m,i,j,b) = sum_e t_i^e <m ka, b kb || e ki, j kj> + 1/2 conj(<i ki, j kj || m ka, b kb>)
+template <class IT>
 __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv;
@@ -848,10 +854,10 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
         int64_t blk = idx / o3v;
         int ki = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
         int kj = kcv(s.kc, N, ka, kb, ki);
-        const cd *g = s.ovvoT + blk * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv;
+        const IT *g = ovvoT_of<IT>(s) + blk * s.d.t2blk() + (((int64_t)m * nv + b) * no + j) * nv;
         cd acc = make_double2(0.0, 0.0);
         #pragma unroll 8
-        for (int e = 0; e < nv; ++e) cfma(acc, t1[((int64_t)ki * no + i) * nv + e], g[e]);
+        for (int e = 0; e < nv; ++e) cfma(acc, t1[((int64_t)ki * no + i) * nv + e], to_cd(g[e]));
         cd h = s.ooov[blk3(N, ki, kj, ka) * o3v + (((int64_t)i * no + j) * no + m) * nv + b];
         acc.x += 0.5 * h.x;
         acc.y -= 0.5 * h.y;
@@ -864,7 +870,7 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
 // contracts (over f or e) in registers (for n_vir > 16 the W0 seed keeps one accumulator
 // per j instead) and produces the outputs of every j (or i), so every <oo||vv>, <ov||vv>
 // and <ov||vo> element is read once instead of n_occ times.
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *__restrict__ t1, cd *__restrict__ Z) {
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv;
@@ -879,10 +885,10 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *__rest
     const int ne = threadIdx.x;
     if (ne >= no * nv) return;
     const int nn = ne / nv, e = ne % nv;
-    const cd *g = s.oovvT + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
+    const IT *g = oovvT_of<IT>(s) + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
     cd gr[VM];
 #pragma unroll
-    for (int f = 0; f < VM; ++f) gr[f] = f < nv ? g[(int64_t)f * nv] : make_double2(0.0, 0.0);
+    for (int f = 0; f < VM; ++f) gr[f] = f < nv ? to_cd(g[(int64_t)f * nv]) : make_double2(0.0, 0.0);
     const cd *h = s.ooov + blk3(N, km, kb, kj) * o3v + ((int64_t)m * no + nn) * no * nv + e;
     cd *z = Z + blk * o3v + ((int64_t)m * no + nn) * no * nv + e;
     for (int j = 0; j < no; ++j) {
@@ -919,7 +925,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
     if (be >= nv * nv) return;
     const int b = be / nv, e = be % nv;
     const IT *g = ovvvT_of<IT>(s) + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
-    const cd *w0 = s.ovvoT + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
+    const IT *w0 = ovvoT_of<IT>(s) + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
     cd *wr = WR + blk * blkq + (int64_t)b * ov + (int64_t)m * nv + e;
     if constexpr (VM <= 16) {
         // the row <m b||f e> over f in registers, one j at a time
@@ -929,7 +935,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
 #pragma unroll
         for (int n = 0; n < OM; ++n) tb[n] = n < no ? t1[((int64_t)kb * no + n) * nv + b] : make_double2(0.0, 0.0);
         for (int j = 0; j < no; ++j) {
-            cd acc = w0[(int64_t)j * nv];
+            cd acc = to_cd(w0[(int64_t)j * nv]);
 #pragma unroll
             for (int f = 0; f < VM; ++f)
                 if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
@@ -943,7 +949,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
     // wider rows: one accumulator per j, each <m b||f e> loaded once and used for every j
     cd acc[OM];
 #pragma unroll
-    for (int j = 0; j < OM; ++j) acc[j] = j < no ? w0[(int64_t)j * nv] : make_double2(0.0, 0.0);
+    for (int j = 0; j < OM; ++j) acc[j] = j < no ? to_cd(w0[(int64_t)j * nv]) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int f = 0; f < VM; ++f) {
         if (f >= nv) break;
@@ -965,7 +971,7 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
         if (j < no) wr[(int64_t)j * nv * ov] = acc[j];
 }
 
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd *Q) {
     // The <m b||e j> slab of this m goes through LDS EP values of e at a time (so that
     // many workgroups fit on a CU), at e * (no * nv + 1) + j * nv + b: a lane (j, b) reads
@@ -984,22 +990,22 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     const int64_t blk = L / no;
     const int ki = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
     const int kj = kcv(s.kc, N, ka, kb, ki);
-    const cd *gb = s.ovvoT + blk * s.d.t2blk() + (int64_t)m * nv * no * nv;  // (b, j, e)
+    const IT *gb = ovvoT_of<IT>(s) + blk * s.d.t2blk() + (int64_t)m * nv * no * nv;  // (b, j, e)
     const int nph = no * nv * EP;  // staged elements per phase
-    cd st[EP];
+    IT st[EP];  // in the stored type until written to LDS, so the load is not waited for early
     auto load_phase = [&](int e0) {
 #pragma unroll
         for (int u = 0; u < EP; ++u) {
             const int x = threadIdx.x + u * NT;  // (bj, el) with el fastest
             const int bj = x / EP, e = e0 + x % EP;
-            st[u] = x < nph && e < nv ? gb[(int64_t)bj * nv + e] : make_double2(0.0, 0.0);
+            st[u] = x < nph && e < nv ? gb[(int64_t)bj * nv + e] : IT{};
         }
     };
     auto store_phase = [&]() {
 #pragma unroll
         for (int u = 0; u < EP; ++u) {
             const int x = threadIdx.x + u * NT, bj = x / EP, el = x % EP;
-            if (x < nph) GS[el * rp + (bj % no) * nv + bj / no] = st[u];
+            if (x < nph) GS[el * rp + (bj % no) * nv + bj / no] = to_cd(st[u]);
         }
     };
     load_phase(0);
@@ -1383,8 +1389,7 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     hipLaunchKernelGGL(k_fov, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
     CK_CHECK(hipGetLastError());
     if (no <= 8 && nv <= 16) {
-        LAUNCH_T(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo,
-                           w.Pvv);
+        LAUNCH_TI(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo, w.Pvv);
     } else if (f_blocks_fit(s.d)) {
         hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
@@ -1475,19 +1480,19 @@ void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
     CK_CHECK(hipGetLastError());
 }
 
-void launch_ovvo_transpose(const SysDev &s, cd *ovvoT, hipStream_t st) {
-    LAUNCH(k_ovvo_transpose, s.d.t2(), s, ovvoT);
-}
-
-void launch_static_swaps(const SysDev &s, cd *ovvvT, cf *ovvv_c, cf *ovvvT_c, cd *oovvT, hipStream_t st) {
+void launch_static_copies(const SysDev &s, const StaticCopies &c, hipStream_t st) {
     const int64_t N3 = (int64_t)s.d.N * s.d.N * s.d.N, o = s.d.no, v = s.d.nv;
-    if (ovvv_c) {
-        LAUNCH(k_to_c64, N3 * o * v * v * v, N3 * o * v * v * v, s.ovvv, ovvv_c);
-        LAUNCH(k_swap_last2<cf>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, ovvvT_c);
+    if (c.ovvv_c) {
+        LAUNCH(k_ovvo_transpose<cf>, s.d.t2(), s, c.ovvoT_c);
+        LAUNCH(k_to_c64, N3 * o * v * v * v, N3 * o * v * v * v, s.ovvv, c.ovvv_c);
+        LAUNCH(k_swap_last2<cf>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, c.ovvvT_c);
+        LAUNCH(k_to_c64, s.d.t2(), s.d.t2(), s.oovv, c.oovv_c);
+        LAUNCH(k_swap_last2<cf>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, c.oovvT_c);
     } else {
-        LAUNCH(k_swap_last2<cd>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, ovvvT);
+        LAUNCH(k_ovvo_transpose<cd>, s.d.t2(), s, c.ovvoT);
+        LAUNCH(k_swap_last2<cd>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, c.ovvvT);
+        LAUNCH(k_swap_last2<cd>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, c.oovvT);
     }
-    LAUNCH(k_swap_last2<cd>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, oovvT);
 }
 
 void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
@@ -1496,23 +1501,24 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
     const int64_t n3 = N * N * N;
     if (no <= 8 && nv <= 16) {
         const dim3 grid = xcd_grid(n3 * no);
-        LAUNCH_T(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
+        LAUNCH_TI(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
         LAUNCH_TI(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
-        LAUNCH_T(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
+        LAUNCH_TI(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
     } else if (no <= 8 && nv <= 32) {
         const dim3 grid = xcd_grid(n3 * no);
-        hipLaunchKernelGGL((k_ring_z_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_32I(k_ring_z_t, grid, dim3(8 * 32), s, t1, scratch);
         LAUNCH_32I(k_ring_w0_t, grid, dim3(32 * 32), s, t1, scratch, WR);
-        hipLaunchKernelGGL((k_ring_q_t<8, 32, false>), grid, dim3(8 * 32), 0, st, s, t1, scratch);
-        CK_CHECK(hipGetLastError());
+        LAUNCH_32I(k_ring_q_t, grid, dim3(8 * 32), s, t1, scratch);
     } else {
-        LAUNCH(k_ring_z, n3 * no * no * no * nv, s, t1, scratch);
-        if (s.ovvv_c)
+        if (s.ovvv_c) {
+            LAUNCH(k_ring_z<cf>, n3 * no * no * no * nv, s, t1, scratch);
             LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-        else
+            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
+        } else {
+            LAUNCH(k_ring_z<cd>, n3 * no * no * no * nv, s, t1, scratch);
             LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-        LAUNCH(k_ring_q, n3 * no * no * no * nv, s, t1, scratch);
+            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
+        }
     }
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
