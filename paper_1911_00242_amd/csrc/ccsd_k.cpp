@@ -52,6 +52,7 @@ struct System {
     cd *ovvvT = nullptr, *oovvT = nullptr;
     // mixed path: complex64 copies in place of the three above, and of ovvv and oovv
     ck::cf *ovvoT_c = nullptr, *ovvv_c = nullptr, *ovvvT_c = nullptr, *oovv_c = nullptr, *oovvT_c = nullptr;
+    ck::cf *r2c = nullptr;  // mixed path: R2 in complex64 (res then holds R1 only)
     cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
     double *eo = nullptr, *ev = nullptr, *red = nullptr, *redout = nullptr;
@@ -95,7 +96,7 @@ struct System {
     cd *t1() const { return amp; }
     cd *t2() const { return amp + n1(); }
     cd *r1() const { return res; }
-    cd *r2() const { return res + n1(); }
+    cd *r2() const { return mixed ? nullptr : res + n1(); }  // mixed path: r2c
     ck::SysDev dev() const {
         ck::SysDev s;
         s.d = d;
@@ -408,7 +409,8 @@ void carve(System &S, Carver &c) {
     c.take(S.fock, N * n * n);
     for (int i = 0; i < 6; ++i) c.take(S.eri[i], N3 * cls[i]);
     c.take(S.amp, S.n1() + S.n2());
-    c.take(S.res, S.n1() + S.n2());
+    c.take(S.res, S.mixed ? S.n1() : S.n1() + S.n2());
+    if (S.mixed) c.take(S.r2c, S.n2());
     if (!S.mixed) {
         c.take(S.tau, S.n2());
         c.take(S.tauT, S.n2());
@@ -608,7 +610,7 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>, written split
         run_gemm(c, S, 4);  // X += t2 W_mbej
         run_gemm(c, S, 1);  // both ladders on canonical pairs, into Lp
-        ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2(), S.npart, st);
+        ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2c, S.npart, st);
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     }
     stage_end(c, all);
@@ -764,7 +766,8 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
                                     ctx->stream));
             CK_CHECK(hipMemsetAsync(S.amp, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             amplitudes_changed(S);
-            CK_CHECK(hipMemsetAsync(S.res, 0, (S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            CK_CHECK(hipMemsetAsync(S.res, 0, (S.mixed ? S.n1() : S.n1() + S.n2()) * sizeof(cd), ctx->stream));
+            if (S.mixed) CK_CHECK(hipMemsetAsync(S.r2c, 0, S.n2() * sizeof(ck::cf), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.zeros, 0, 16 * sizeof(cd), ctx->stream));
             if (S.mixed) {
                 CK_CHECK(hipMemcpyAsync(S.dptab, S.ptab.data(), S.ptab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
@@ -843,8 +846,18 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
         launch_norm(ctx, S);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
         if (r1) CK_CHECK(hipMemcpyAsync(r1, S.r1(), S.n1() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
-        if (r2) CK_CHECK(hipMemcpyAsync(r2, S.r2(), S.n2() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        std::vector<ck::cf> r2h;
+        if (r2 && S.mixed) {
+            r2h.resize(S.n2());
+            CK_CHECK(hipMemcpyAsync(r2h.data(), S.r2c, S.n2() * sizeof(ck::cf), hipMemcpyDeviceToHost, ctx->stream));
+        } else if (r2) {
+            CK_CHECK(hipMemcpyAsync(r2, S.r2(), S.n2() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
+        }
         CK_CHECK(hipStreamSynchronize(ctx->stream));
+        for (size_t i = 0; i < r2h.size(); ++i) {  // widened to the caller's complex128
+            r2[2 * i] = r2h[i].x;
+            r2[2 * i + 1] = r2h[i].y;
+        }
         collect_timing(ctx);
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
@@ -888,7 +901,10 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 ck::SysDev sd = S->dev();
                 int m = S->desc.diis_space;
                 if (m == 0) {
-                    ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, ctx->stream);
+                    if (S->mixed)
+                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2c, nullptr, nullptr, ctx->stream);
+                    else
+                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, ctx->stream);
                     amplitudes_changed(*S);
                     continue;
                 }
@@ -896,12 +912,12 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 int held = std::min(S->diis_n + 1, m);
                 if (S->mixed) {
                     std::vector<const ck::cf *> ys(S->derr32.begin(), S->derr32.begin() + held);
-                    ck::launch_update_diis(sd, S->amp, S->res, S->derr32[slot], S->dvec[slot], ys.data(), held, slot,
-                                           S->red, S->redout, ctx->stream);
+                    ck::launch_update_diis(sd, S->amp, S->res, S->r2c, S->derr32[slot], S->dvec[slot], ys.data(),
+                                           held, slot, S->red, S->redout, ctx->stream);
                 } else {
                     std::vector<const cd *> ys(S->derr.begin(), S->derr.begin() + held);
-                    ck::launch_update_diis(sd, S->amp, S->res, S->derr[slot], S->dvec[slot], ys.data(), held, slot,
-                                           S->red, S->redout, ctx->stream);
+                    ck::launch_update_diis(sd, S->amp, S->res, S->r2(), S->derr[slot], S->dvec[slot], ys.data(),
+                                           held, slot, S->red, S->redout, ctx->stream);
                 }
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));

@@ -38,10 +38,11 @@ int lincomb_t2_blocks(const Dims &d);
 void launch_lincomb_pack(const SysDev &s, const cd *const *src, const double *c, int m, cd *t, uint16_t *sp,
                          double *epart, hipStream_t st);
 void launch_energy_pack(const Dims &d, const double *epart, double *out, hipStream_t st);
-// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry;
-// npart (assemble_pack_blocks doubles) receives per-workgroup sums of |r2|^2
+// r2 = <ab||ij>* + P(ij)P(ab) X + the ladders' packed result Lp expanded by antisymmetry,
+// stored in complex64; npart (assemble_pack_blocks doubles) receives per-workgroup sums of
+// |r2|^2 over the stored values
 int64_t assemble_pack_blocks(const Dims &d, const PairTabs &pt);
-void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2, double *npart,
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cf *r2, double *npart,
                              hipStream_t st);
 // out[0] = sum |r1|^2 + sum |r2|^2 from the assembly's partial sums (fixed order)
 void launch_norm_pack(const Dims &d, const PairTabs &pt, const double *npart, const cd *r1, double *out,

@@ -343,7 +343,7 @@ __device__ inline double asm_block_sum(double v, double *sh) {
 
 // npart[blockIdx.x] receives the sum of |r2|^2 over the elements this workgroup writes (0
 // for a workgroup without an orbit), so that the residual norm needs no second pass over R2.
-__global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt, const cd *X, const cd *Lp, cd *r2,
+__global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt, const cd *X, const cd *Lp, cf *r2,
                                                           double *npart) {
     extern __shared__ cd XS[];  // four slabs, rows padded to nv + 1 (LDS form only)
     __shared__ double NS[256];
@@ -393,9 +393,10 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
     const int64_t o3 = blk3(N, ki, kj, kb) * bs + ((int64_t)i * no + j) * vv;
     const int64_t o4 = blk3(N, kj, ki, kb) * bs + ((int64_t)j * no + i) * vv;
     double nsq = 0.0;
-    auto put = [&](int64_t o, cd v) {
-        r2[o] = v;
-        nsq = fma(v.x, v.x, fma(v.y, v.y, nsq));
+    auto put = [&](int64_t o, cd v) {  // stored in complex64; the norm is taken from the stored value
+        from_cd(v, r2[o]);
+        const cd w = to_cd(r2[o]);
+        nsq = fma(w.x, w.x, fma(w.y, w.y, nsq));
     };
     for (int e = threadIdx.x; e < vv; e += blockDim.x) {
         const int a = e / nv, b = e % nv;
@@ -464,7 +465,7 @@ void launch_norm_pack(const Dims &d, const PairTabs &pt, const double *npart, co
     CK_CHECK(hipGetLastError());
 }
 
-void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cd *r2, double *npart,
+void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, const cd *Lp, cf *r2, double *npart,
                              hipStream_t st) {
     const int64_t nv = s.d.nv;
     const int64_t nb = assemble_pack_blocks(s.d, pt);

@@ -115,7 +115,8 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
 }
 
 
-__global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2) {
+template <class R2>
+__global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const R2 *r2, cd *err1, cd *err2) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n1 = s.d.t1(), n2 = s.d.t2();
     GRID_STRIDE(idx, n1 + n2) {
@@ -134,7 +135,8 @@ __global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const cd *r2, c
             int kb = s.kc[((int64_t)ki * N + kj) * N + ka];
             double D = s.eo[(int64_t)ki * no + i] + s.eo[(int64_t)kj * no + j] - s.ev[(int64_t)ka * nv + a] -
                        s.ev[(int64_t)kb * nv + b];
-            cd e = make_double2(r2[x].x / D, r2[x].y / D);
+            const cd rv = to_cd(r2[x]);
+            cd e = make_double2(rv.x / D, rv.y / D);
             t2[x] = cadd(t2[x], e);
             if (err2) err2[x] = e;
         }
@@ -143,14 +145,20 @@ __global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const cd *r2, c
 
 void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_update, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2);
+    hipLaunchKernelGGL(k_update<cd>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2);
+    CK_CHECK(hipGetLastError());
+}
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_update<cf>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2);
     CK_CHECK(hipGetLastError());
 }
 
 // The DIIS step of one iteration in one pass: e = D^-1 R, hist = t + e (the new amplitudes,
 // written only to their history slot: the extrapolation, or a copy when there is none,
 // writes t afterwards), err = e stored as E (complex128, or complex64 on the mixed path,
-// whose residual is itself accurate to about 1e-7 relative), and the partial sums of
+// whose residual is itself accurate to about 1e-7 relative and is stored as E too), and the
+// partial sums of
 // Re <e, y_j> for the m held error vectors, all taken from the stored values (y[self] is
 // err itself, whose product is taken from e, rounded to E, before it is stored).
 // A fixed grid of UPD_BLOCKS workgroups and a fixed summation order, so the dots are
@@ -163,8 +171,8 @@ struct ErrPack {
 };
 
 template <class E>
-__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r, E *err, cd *hist,
-                                                     ErrPack<E> y, int m, int self, double *partials) {
+__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r1, const E *r2, E *err,
+                                                     cd *hist, ErrPack<E> y, int m, int self, double *partials) {
     __shared__ double sh[16][256];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, cons
             const int kb = s.kc[kb3];  // kc is indexed by the block triple (ki, kj, ka)
             D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
         }
-        const cd rv = r[idx];
+        const cd rv = idx < n1 ? r1[idx] : to_cd(r2[idx - n1]);
         const cd e = make_double2(rv.x / D, rv.y / D);
         hist[idx] = cadd(t[idx], e);
         E es;
@@ -206,11 +214,11 @@ __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, cons
 }
 
 template <class E>
-void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r, E *err, cd *hist, const E *const *y, int m,
-                          int self, double *partials, double *out, hipStream_t st) {
+void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r1, const E *r2, E *err, cd *hist,
+                          const E *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
     ErrPack<E> pk{};
     for (int j = 0; j < m; ++j) pk.p[j] = y[j];
-    hipLaunchKernelGGL(k_update_diis<E>, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r, err, hist, pk, m, self,
+    hipLaunchKernelGGL(k_update_diis<E>, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk, m, self,
                        partials);
     CK_CHECK(hipGetLastError());
     for (int j = 0; j < m; ++j) {
@@ -220,13 +228,13 @@ void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r, E *err, cd 
     }
 }
 
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
-                        int self, double *partials, double *out, hipStream_t st) {
-    launch_update_diis_t<cd>(s, t, r, err, hist, y, m, self, partials, out, st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *err, cd *hist,
+                        const cd *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
+    launch_update_diis_t<cd>(s, t, r1, r2, err, hist, y, m, self, partials, out, st);
 }
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cf *err, cd *hist, const cf *const *y, int m,
-                        int self, double *partials, double *out, hipStream_t st) {
-    launch_update_diis_t<cf>(s, t, r, err, hist, y, m, self, partials, out, st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *err, cd *hist,
+                        const cf *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
+    launch_update_diis_t<cf>(s, t, r1, r2, err, hist, y, m, self, partials, out, st);
 }
 
 struct PtrPack {

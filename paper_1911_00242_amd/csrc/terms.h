@@ -45,17 +45,19 @@ constexpr int UPD_BLOCKS = 4096;  // grid of the DIIS update pass (its partials:
 void launch_norm2(const Dims &d, const cd *r1, const cd *r2, double *partials, double *out, hipStream_t st);
 // out[0..1] = complex correlation energy; partials must hold 2*RED_BLOCKS doubles
 void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials, double *out, hipStream_t st);
-// t += r / D, and (optionally) err = r / D
+// t += r / D, and (optionally) err = r / D; r2 complex128, or complex64 (mixed path)
 void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
                    hipStream_t st);
-// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D, hist = t + e
-// (t itself is not written), err = e (complex128 or complex64 storage), and
-// out[j] = Re <e, y_j> for j < m over the stored values (y[self] is err); partials:
-// m*UPD_BLOCKS
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cd *err, cd *hist, const cd *const *y, int m,
-                        int self, double *partials, double *out, hipStream_t st);
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r, cf *err, cd *hist, const cf *const *y, int m,
-                        int self, double *partials, double *out, hipStream_t st);
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2,
+                   hipStream_t st);
+// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D (r = r1 | r2),
+// hist = t + e (t itself is not written), err = e, and out[j] = Re <e, y_j> for j < m over
+// the stored values (y[self] is err); r2 and err complex128, or both complex64 (mixed
+// path); partials: m*UPD_BLOCKS
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *err, cd *hist,
+                        const cd *const *y, int m, int self, double *partials, double *out, hipStream_t st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *err, cd *hist,
+                        const cf *const *y, int m, int self, double *partials, double *out, hipStream_t st);
 // dst = sum_j c[j] * src_j over n complex elements (m <= 16)
 void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st);
 
