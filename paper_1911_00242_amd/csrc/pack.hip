@@ -525,11 +525,13 @@ __global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, int
     }
 }
 
+// EX: n_occ = 8, n_vir = 16 as constants (the index decode of the energy terms becomes shifts)
+template <bool EX>
 __global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int m, cd *t, uint16_t *sp, double *ep2) {
     __shared__ __attribute__((aligned(16))) uint16_t S[4][2048];
     __shared__ double sh[2][256];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
+    const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
+    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, n2 = (int64_t)N * N * N * bs;
     const int64_t nch = (n2 + 7) / 8;
     const int tid = threadIdx.x;
     const cd *t1 = t;  // the new t1, written by k_lincomb_t1
@@ -547,10 +549,10 @@ __global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int
                     acc.y = fma(L.c[j], x.y, acc.y);
                 }
                 t[n1 + e] = acc;
-                const int64_t blk = e / bs;
-                const int x = (int)(e - blk * bs);
+                const int blk = (int)(e / bs);  // momentum block (ki, kj, ka) < N^3
+                const int x = (int)(e - (int64_t)blk * bs);
                 const int b = x % nv, a = (x / nv) % nv, jj = (x / (nv * nv)) % no, i = x / (nv * nv * no);
-                const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+                const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
                 cd w = cscale(acc, 0.25);
                 if (ka == ki)
                     w = cadd(w, cscale(cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + jj) * nv + b]), 0.5));
@@ -610,8 +612,11 @@ void launch_lincomb_pack(const SysDev &s, const cd *const *src, const double *c,
     }
     hipLaunchKernelGGL(k_lincomb_t1, dim3(1), dim3(256), 0, st, s, L, m, t, epart);
     CK_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_lincomb_t2, dim3((unsigned)lincomb_t2_blocks(s.d)), dim3(256), 0, st, s, L, m, t, sp,
-                       epart + 2);
+    const dim3 g((unsigned)lincomb_t2_blocks(s.d));
+    if (s.d.no == 8 && s.d.nv == 16)
+        hipLaunchKernelGGL(k_lincomb_t2<true>, g, dim3(256), 0, st, s, L, m, t, sp, epart + 2);
+    else
+        hipLaunchKernelGGL(k_lincomb_t2<false>, g, dim3(256), 0, st, s, L, m, t, sp, epart + 2);
     CK_CHECK(hipGetLastError());
 }
 

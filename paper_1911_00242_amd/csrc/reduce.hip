@@ -170,12 +170,13 @@ struct ErrPack {
     const E *p[16];
 };
 
-template <class E>
+// EX: n_occ = 8, n_vir = 16 as constants (the index decode becomes shifts).
+template <class E, bool EX>
 __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r1, const E *r2, E *err,
                                                      cd *hist, ErrPack<E> y, int m, int self, double *partials) {
     __shared__ double sh[16][256];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t n1 = s.d.t1(), n2 = s.d.t2(), bs = s.d.t2blk();
+    const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
+    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, n2 = (int64_t)N * N * N * bs;
     double v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = 0.0;
@@ -195,7 +196,8 @@ __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, cons
             D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
         }
         const cd rv = idx < n1 ? r1[idx] : to_cd(r2[idx - n1]);
-        const cd e = make_double2(rv.x / D, rv.y / D);
+        const double iD = 1.0 / D;
+        const cd e = make_double2(rv.x * iD, rv.y * iD);
         hist[idx] = cadd(t[idx], e);
         E es;
         from_cd(e, es);
@@ -218,8 +220,12 @@ void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r1, const E *r
                           const E *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
     ErrPack<E> pk{};
     for (int j = 0; j < m; ++j) pk.p[j] = y[j];
-    hipLaunchKernelGGL(k_update_diis<E>, dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk, m, self,
-                       partials);
+    if (s.d.no == 8 && s.d.nv == 16)
+        hipLaunchKernelGGL((k_update_diis<E, true>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk, m,
+                           self, partials);
+    else
+        hipLaunchKernelGGL((k_update_diis<E, false>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk,
+                           m, self, partials);
     CK_CHECK(hipGetLastError());
     for (int j = 0; j < m; ++j) {
         hipLaunchKernelGGL(k_final_sum<1>, dim3(1), dim3(256), 0, st, partials + (int64_t)j * UPD_BLOCKS,
