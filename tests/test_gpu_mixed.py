@@ -55,11 +55,13 @@ def test_mixed_residual_close_to_oracle(grid, no, nv):
     assert e2 > 0  # the bf16 path really ran
 
 
-def test_mixed_converged_energy_matches_fp64():
+@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 4, 8), ((2, 1, 1), 8, 16)])
+def test_mixed_converged_energy_matches_fp64(grid, no, nv):
     """Converge both paths on a small system (1/N_k-scaled integrals); the mixed fixed
-    point differs from the FP64 one by the product error only."""
-    grid, no, nv = (3, 1, 1), 4, 8
-    f, eris = synth.system(505, grid, no, nv, scale=0.05 / 3)
+    point differs from the FP64 one by the product error only.  8 x 16 is the workload's
+    block shape, whose DIIS update and extrapolation take their constant-shape forms."""
+    N = grid[0] * grid[1] * grid[2]
+    f, eris = synth.system(505, grid, no, nv, scale=0.05 / N)
     ref = O.solve(f, eris, grid, max_iter=60, tol=1e-11, diis_space=6)
     assert ref["converged"]
     out = {}
@@ -76,12 +78,13 @@ def test_mixed_converged_energy_matches_fp64():
     assert de <= 1e-6 * abs(ref["energy"])
 
 
-def test_mixed_extrapolation_caches_match_fresh_passes():
+@pytest.mark.parametrize("grid,no,nv", [((2, 2, 1), 3, 5), ((2, 1, 1), 8, 16)])
+def test_mixed_extrapolation_caches_match_fresh_passes(grid, no, nv):
     """The mixed DIIS extrapolation also writes the split copy of t2 and the energy partial
     sums; the residual and energy taken from them equal the ones from fresh passes over the
     same amplitudes (residual bitwise, energy to rounding)."""
-    grid, no, nv = (2, 2, 1), 3, 5
-    f, eris = synth.system(606, grid, no, nv, scale=0.05 / 4)
+    N = grid[0] * grid[1] * grid[2]
+    f, eris = synth.system(606, grid, no, nv, scale=0.05 / N)
     with ck.Context([dict(grid=grid, no=no, nv=nv, precision=ck.PREC_MIXED, diis_space=4)]) as c:
         c.set_inputs(0, f, eris)
         c.iterate(5, 0.0)  # several extrapolations

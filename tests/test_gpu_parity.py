@@ -133,9 +133,11 @@ def test_jacobi_converged_energy_cfg0():
     assert np.abs(t2 - ref["t2"]).max() <= 1e-10
 
 
-def test_diis_converged_energy():
-    grid, no, nv = (3, 1, 1), 2, 4
-    f, eris = synth.system(77, grid, no, nv, scale=0.1)
+@pytest.mark.parametrize("grid,no,nv,scale", [((3, 1, 1), 2, 4, 0.1), ((2, 1, 1), 8, 16, 0.025)])
+def test_diis_converged_energy(grid, no, nv, scale):
+    """DIIS(6) to ||R|| < 1e-11 against the oracle's DIIS; 8 x 16 takes the constant-shape
+    DIIS update."""
+    f, eris = synth.system(77, grid, no, nv, scale=scale)
     ref = O.solve(f, eris, grid, max_iter=40, tol=1e-11, diis_space=6)
     assert ref["converged"]
     with _ctx([dict(grid=grid, no=no, nv=nv, diis_space=6)]) as c:
