@@ -54,8 +54,11 @@ extern "C" {
 
 #define CCSD_K_PREC_FP64 0  /* complex128 storage, FP64 MFMA contractions            */
 #define CCSD_K_PREC_MIXED 1 /* complex64 operands of the big contractions, split-BF16
-                               MFMA products accumulated in FP32; FP64 master amplitudes,
-                               denominators, norm, energy and DIIS                     */
+                               MFMA products accumulated in FP32; the side terms read
+                               complex64 copies of the integral classes, R2 and the DIIS
+                               error vectors are stored in complex64; FP64 master
+                               amplitudes and DIIS amplitude history, denominators, F
+                               intermediates, norm and energy sums                     */
 
 typedef struct ccsd_k_ctx ccsd_k_ctx;
 
@@ -90,7 +93,8 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
 /* One evaluation of (R1, R2) (eqs. ori_EqSingle, ori_EqDouble) for system sys.
  * t1/t2: host amplitudes to evaluate at (they become the system's current amplitudes);
  * NULL = the current device amplitudes.  r1/r2: host buffers for the result, or NULL to
- * keep it on the device only.  t2 must be antisymmetric, t_{ij}^{ab} = -t_{ji}^{ab} =
+ * keep it on the device only (complex128; on the mixed path r2 is held in complex64 and
+ * widened on the copy).  t2 must be antisymmetric, t_{ij}^{ab} = -t_{ji}^{ab} =
  * -t_{ij}^{ba} (with the momenta exchanged alike), as every CCSD amplitude is: several
  * terms of the T2 equation are combined under one P(ij)P(ab) using that symmetry, so for
  * other input the result differs from the equation by terms that vanish on antisymmetric
