@@ -41,8 +41,7 @@ __global__ __launch_bounds__(256) void k_split(int64_t n, const cd *src, uint16_
             const int64_t e = e0 + t + 256 * j;
             const cd x = e < n ? src[e] : make_double2(0.0, 0.0);
             uint16_t h0, h1, h2, h3;
-            split2(x.x, h0, h1);
-            split2(x.y, h2, h3);
+            split2c(x, h0, h1, h2, h3);
             S[0][t + 256 * j] = h0;
             S[1][t + 256 * j] = h1;
             S[2][t + 256 * j] = h2;
@@ -378,8 +377,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
                     const int m = mb + 8 * (r >> 2) + (r & 3);
                     const int64_t e = (op.cs_row ? op.cs_row[(int64_t)g * M + m] : crow[r]) + cscol[j];
                     uint16_t h0, h1, h2, h3;
-                    split2(v.x, h0, h1);
-                    split2(v.y, h2, h3);
+                    split2c(v, h0, h1, h2, h3);
                     op.Cs[split_index(e, 0)] = h0;
                     op.Cs[split_index(e, 1)] = h1;
                     op.Cs[split_index(e, 2)] = h2;

@@ -24,14 +24,27 @@ __host__ __device__ inline void split2(double x, uint16_t &hi, uint16_t &lo) {
     hi = bf16_rne((float)x);
     lo = bf16_rne((float)(x - (double)bf16_to_f(hi)));
 }
+// Both parts of a complex value at once with the packed hardware conversion
+// (v_cvt_pk_bf16_f32, round to nearest even): the same bits as split2 on each part.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ inline void split2c(cd x, uint16_t &rh, uint16_t &rl, uint16_t &ih, uint16_t &il) {
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{(float)x.x, (float)x.y}, bf16x2_t));
+    const double hr = (double)__builtin_bit_cast(float, hi << 16), hm = (double)__builtin_bit_cast(float, hi & 0xffff0000u);
+    const uint32_t lo =
+        __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{(float)(x.x - hr), (float)(x.y - hm)}, bf16x2_t));
+    rh = (uint16_t)hi;
+    ih = (uint16_t)(hi >> 16);
+    rl = (uint16_t)lo;
+    il = (uint16_t)(lo >> 16);
+}
 
 // eight consecutive elements e0 .. e0+7 (e0 a multiple of 8) as one 64-byte chunk
 __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
     uint16_t h[4][8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        split2(x[j].x, h[0][j], h[1][j]);
-        split2(x[j].y, h[2][j], h[3][j]);
+        split2c(x[j], h[0][j], h[1][j], h[2][j], h[3][j]);
     }
     uint4 *o = (uint4 *)(dst + split_index(e0, 0));
 #pragma unroll

@@ -51,8 +51,7 @@ __global__ __launch_bounds__(256) void k_tau_pack(Dims d, const int32_t *kc, Pai
             }
         }
         uint16_t h0, h1, h2, h3;
-        split2(v.x, h0, h1);
-        split2(v.y, h2, h3);
+        split2c(v, h0, h1, h2, h3);
         const int ch = threadIdx.x >> 3, q = threadIdx.x & 7;
         S[ch * 32 + q] = h0;
         S[ch * 32 + 8 + q] = h1;
@@ -210,8 +209,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
                     }
                 const int64_t o = ((int64_t)K * pt.PV + pab) * ld + pef;
                 uint16_t h0, h1, h2, h3;
-                split2(acc.x, h0, h1);
-                split2(acc.y, h2, h3);
+                split2c(acc, h0, h1, h2, h3);
                 out[split_index(o, 0)] = h0;
                 out[split_index(o, 1)] = h1;
                 out[split_index(o, 2)] = h2;
@@ -561,8 +559,7 @@ __global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int
                 ei += p.y;
             }
             uint16_t h0, h1, h2, h3;
-            split2(acc.x, h0, h1);
-            split2(acc.y, h2, h3);
+            split2c(acc, h0, h1, h2, h3);
             S[0][tid + 256 * q] = h0;
             S[1][tid + 256 * q] = h1;
             S[2][tid + 256 * q] = h2;
