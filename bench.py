@@ -159,8 +159,9 @@ def cpu_baseline(no, nv, N_target):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each k-pair group is independent; sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (its grouped "
+              "products are independent per momentum group, which is how they would be dealt to GPUs)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
