@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--tol-mixed", type=float, default=1e-7,
                     help="the split-BF16 residual has a rounding floor near 1e-8..1e-7 at N_k=27")
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the N_k=27 workload: the batched form, this many independent seeded "
+                         "systems (shapes drawn from seed 40000), converged on both paths")
     return ap.parse_args()
 
 
@@ -156,6 +159,113 @@ def cpu_baseline(no, nv, N_target):
             "sample_seconds": dt * reps}
 
 
+def run_batch(a):
+    """The batched form: a.batch independent systems (N_k from {1, 2, 4, 8}, n_occ from
+    {4, 6, 8, 12}, n_vir from {8, 16, 24, 32}, drawn with tag 3 from seed 40000; system s has
+    seed 40000 + s and integrals scaled by 0.05 / N_k), iterated with DIIS to convergence.
+    The systems go into as few contexts as fit the memory budget, one context iterating all
+    of its systems together on one stream.  Timed on the mixed path: the time per batched
+    iteration over the first a.steps iterations (every system active), and the whole run to
+    convergence (systems converged per second); the FP64 path converges the same systems
+    for the per-system energy reference, and the oracle the smallest few."""
+    import numpy as np
+    import torch
+
+    import paper_1911_00242_amd as ck
+    import synth
+    from oracle import ccsd_k as O
+
+    shapes = synth.batch_shapes(40000, a.batch)
+
+    def desc(d, prec):
+        return dict(grid=d["grid"], no=d["no"], nv=d["nv"], precision=prec, diis_space=a.diis, synthetic=1,
+                    seed=d["seed"], eri_scale=0.05 / int(np.prod(d["grid"])))
+
+    def groups(prec, budget=230e9):
+        sizes = []
+        for d in shapes:
+            c = ck.ccsd_k_init([desc(d, prec)])
+            sizes.append(ck.ccsd_k_workspace_bytes(c) + (1 << 16))
+            ck.ccsd_k_free(c)
+        out, cur, tot = [], [], 0
+        for i, nb in enumerate(sizes):
+            if cur and tot + nb > budget:
+                out.append(cur)
+                cur, tot = [], 0
+            cur.append(i)
+            tot += nb
+        return out + ([cur] if cur else [])
+
+    def converge(prec, tol, timed_steps):
+        energy, conv, rnorm, iter_ms, total = {}, {}, {}, [], 0.0
+        for gi, grp in enumerate(groups(prec)):
+            print(f"[bench] batch {('fp64', 'mixed')[prec]}: group {gi} ({len(grp)} systems)", file=sys.stderr,
+                  flush=True)
+            with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
+                if timed_steps:  # per batched iteration, every system active (one warm-up iteration first)
+                    c.iterate(1, 0.0)
+                ms = []
+                for s in range(timed_steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    c.iterate(1, 0.0)
+                    torch.cuda.synchronize()
+                    ms.append(1000.0 * (time.perf_counter() - t0))
+                iter_ms.append(ms)
+            torch.cuda.empty_cache()
+            with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c.iterate(a.max_iter, tol)
+                torch.cuda.synchronize()
+                total += time.perf_counter() - t0
+                for k, i in enumerate(grp):
+                    energy[i] = c.energy(k)
+                    rnorm[i] = c.residual_norm(k)
+                    conv[i] = rnorm[i] < tol
+            torch.cuda.empty_cache()
+        # a batched iteration of the whole batch: the groups' iterations at the same index
+        per_iter = [sum(g[s] for g in iter_ms) for s in range(timed_steps)] if timed_steps else []
+        return energy, conv, rnorm, per_iter, total
+
+    e_mx, c_mx, n_mx, it_mx, t_mx = converge(1, a.tol_mixed, a.steps)
+    e_64, c_64, _, _, t_64 = converge(0, a.tol, 0)
+    both = [i for i in range(len(shapes)) if c_mx[i] and c_64[i]]
+    de = [abs(e_mx[i] - e_64[i]) for i in both]
+    # the oracle on the smallest systems (pp-ladder work N^4 o^2 v^4)
+    work = sorted(range(len(shapes)), key=lambda i: int(np.prod(shapes[i]["grid"])) ** 4 * shapes[i]["no"] ** 2
+                  * shapes[i]["nv"] ** 4)
+    oracle = []
+    for i in [j for j in work if c_mx[j] and c_64[j]][:3]:
+        d = shapes[i]
+        N = int(np.prod(d["grid"]))
+        print(f"[bench] batch: oracle on system {i} {d['grid']} o={d['no']} v={d['nv']}", file=sys.stderr,
+              flush=True)
+        f, eris = synth.system(d["seed"], d["grid"], d["no"], d["nv"], scale=0.05 / N)
+        ref = O.solve(f, eris, d["grid"], max_iter=a.max_iter, tol=a.tol, diis_space=a.diis)
+        oracle.append({"system": i, "grid": list(d["grid"]), "n_occ": d["no"], "n_vir": d["nv"],
+                       "converged": bool(ref["converged"]), "abs_dE_fp64": abs(e_64[i] - ref["energy"]),
+                       "abs_dE_mixed": abs(e_mx[i] - ref["energy"])})
+    n_conv = sum(1 for i in range(len(shapes)) if c_mx[i])
+    line = {
+        "metric": "systems converged/s (batched form)", "value": n_conv / t_mx, "unit": "systems/s",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "bf16x3/f32acc+f64",
+        "config": {"workload": f"{len(shapes)} independent seeded k-point CCSD systems, N_k from {{1,2,4,8}}, "
+                               f"n_occ from {{4,6,8,12}}, n_vir from {{8,16,24,32}}, DIIS({a.diis})",
+                   "seed": 40000},
+        "systems": len(shapes), "converged_mixed": n_conv, "converged_fp64": sum(c_64.values()),
+        "seconds_to_converge": {"mixed": t_mx, "fp64": t_64},
+        "iteration_ms": {"p50": float(np.percentile(it_mx, 50)), "p99": float(np.percentile(it_mx, 99)),
+                         "samples": len(it_mx)} if it_mx else None,
+        "mixed_vs_fp64_abs_dE": {"max": max(de) if de else None, "median": float(np.median(de)) if de else None,
+                                 "systems": len(de)},
+        "oracle_subset": oracle,
+        "unconverged_mixed": [{"system": i, "grid": list(shapes[i]["grid"]), "n_occ": shapes[i]["no"],
+                               "n_vir": shapes[i]["nv"], "rnorm": n_mx[i]} for i in range(len(shapes)) if not c_mx[i]],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -163,6 +273,9 @@ def main():
               "products are independent per momentum group, which is how they would be dealt to GPUs)",
               file=sys.stderr)
         sys.exit(2)
+    if a.batch:
+        run_batch(a)
+        return
     import torch
 
     import paper_1911_00242_amd as ck
