@@ -201,18 +201,18 @@ def run_batch(a):
         for gi, grp in enumerate(groups(prec)):
             print(f"[bench] batch {('fp64', 'mixed')[prec]}: group {gi} ({len(grp)} systems)", file=sys.stderr,
                   flush=True)
-            with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
-                if timed_steps:  # per batched iteration, every system active (one warm-up iteration first)
+            if timed_steps:  # per batched iteration, every system active (one warm-up iteration first)
+                with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
                     c.iterate(1, 0.0)
-                ms = []
-                for s in range(timed_steps):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    c.iterate(1, 0.0)
-                    torch.cuda.synchronize()
-                    ms.append(1000.0 * (time.perf_counter() - t0))
-                iter_ms.append(ms)
-            torch.cuda.empty_cache()
+                    ms = []
+                    for s in range(timed_steps):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        c.iterate(1, 0.0)
+                        torch.cuda.synchronize()
+                        ms.append(1000.0 * (time.perf_counter() - t0))
+                    iter_ms.append(ms)
+                torch.cuda.empty_cache()
             with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
