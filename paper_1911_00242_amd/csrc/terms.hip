@@ -1375,14 +1375,16 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
         }                                                                                 \
         CK_CHECK(hipGetLastError());                                                      \
     } while (0)
-#define LAUNCH_32I(K, grid, block, ...)                                                   \
+// a wider tile (OMV x VMV, sizes as run-time values), with the element type of the copies
+#define LAUNCH_WI(OMV, VMV, K, grid, block, ...)                                             \
     do {                                                                                  \
         if (s.ovvv_c)                                                                     \
-            hipLaunchKernelGGL((K<8, 32, false, cf>), grid, block, 0, st, __VA_ARGS__);     \
+            hipLaunchKernelGGL((K<OMV, VMV, false, cf>), grid, block, 0, st, __VA_ARGS__);  \
         else                                                                              \
-            hipLaunchKernelGGL((K<8, 32, false, cd>), grid, block, 0, st, __VA_ARGS__);     \
+            hipLaunchKernelGGL((K<OMV, VMV, false, cd>), grid, block, 0, st, __VA_ARGS__);  \
         CK_CHECK(hipGetLastError());                                                      \
     } while (0)
+#define LAUNCH_32I(K, grid, block, ...) LAUNCH_WI(8, 32, K, grid, block, __VA_ARGS__)
 
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
@@ -1509,6 +1511,24 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         LAUNCH_32I(k_ring_z_t, grid, dim3(8 * 32), s, t1, scratch);
         LAUNCH_32I(k_ring_w0_t, grid, dim3(32 * 32), s, t1, scratch, WR);
         LAUNCH_32I(k_ring_q_t, grid, dim3(8 * 32), s, t1, scratch);
+    } else if (no <= 16 && nv <= 16) {
+        const dim3 grid = xcd_grid(n3 * no);
+        LAUNCH_WI(16, 16, k_ring_z_t, grid, dim3(16 * 16), s, t1, scratch);
+        LAUNCH_WI(16, 16, k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
+        if (s.ovvv_c)  // (the 16-row Q seed would keep its accumulators in scratch memory)
+            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
+        else
+            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
+    } else if (no <= 16 && nv <= 32) {  // the W0 seed's Z slab (o^2 v) would not fit LDS
+        const dim3 grid = xcd_grid(n3 * no);
+        LAUNCH_WI(16, 32, k_ring_z_t, grid, dim3(16 * 32), s, t1, scratch);
+        if (s.ovvv_c) {
+            LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
+            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
+        } else {
+            LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
+            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
+        }
     } else {
         if (s.ovvv_c) {
             LAUNCH(k_ring_z<cf>, n3 * no * no * no * nv, s, t1, scratch);
@@ -1524,6 +1544,10 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         LAUNCH_TI(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else if (no <= 8 && nv <= 32) {
         LAUNCH_32I(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
+    } else if (no <= 16 && nv <= 16) {
+        LAUNCH_WI(16, 16, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
+    } else if (no <= 16 && nv <= 32) {
+        LAUNCH_WI(16, 32, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }

@@ -65,6 +65,8 @@ RES_CASES = [
     ((1, 1, 1), 2, 34, False),
     # n_vir between 16 and 32: chunked staging of the blocked F and R1 sums, 32-wide ring tiles
     ((2, 1, 1), 5, 23, True),
+    # n_occ between 8 and 16 with n_vir between 16 and 32: 16-row ring and X seed tiles
+    ((1, 1, 1), 12, 20, False),
 ]
 
 
