@@ -445,14 +445,15 @@ void carve(System &S, Carver &c) {
         c.take(S.ovvvT, N3 * cls[4]);
         c.take(S.oovvT, S.n2());
     }
-    c.take(S.P1, 2 * N3 * o * v);
+    const int64_t fs = ck::fr_splits(S.d);  // slices of the F and R1 block-sum partials
+    c.take(S.P1, 2 * fs * N3 * o * v);
     c.take(S.fw.Fov, N * o * v);
     c.take(S.fw.Foo, N * o * o);
     c.take(S.fw.Fvv, N * v * v);
     c.take(S.fw.Fot, N * o * o);
     c.take(S.fw.Fvt, N * v * v);
-    c.take(S.fw.Poo, N3 * o * o);
-    c.take(S.fw.Pvv, N3 * v * v);
+    c.take(S.fw.Poo, fs * N3 * o * o);
+    c.take(S.fw.Pvv, fs * N3 * v * v);
     c.take(S.zeros, 16);
     c.take(S.eo, N * o);
     c.take(S.ev, N * v);

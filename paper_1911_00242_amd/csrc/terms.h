@@ -5,10 +5,21 @@
 
 namespace ck {
 
+// Workgroups per momentum block of the generic (1024-thread) F and R1 block-sum kernels
+// (n_occ, n_vir <= 32 outside the 8 x 16 tile): the loop over n is split into this many
+// ranges, each writing its own partial sums, so that grids with few momentum blocks still
+// fill the chip (about 256 workgroups, at most one range per n). 1 for every other form.
+// The partial arrays hold this many N^3-block slices.
+__host__ __device__ inline int fr_splits(const Dims &d) {
+    if ((d.no <= 8 && d.nv <= 16) || d.no > 32 || d.nv > 32) return 1;
+    const int n3 = d.N * d.N * d.N, want = (256 + n3 - 1) / n3;
+    return want < d.no ? want : d.no;
+}
+
 struct FWork {
     cd *Fov, *Foo, *Fvv;  // [N][o][v], [N][o][o], [N][v][v]
     cd *Fot, *Fvt;        // [N][o][o], [N][v][v]
-    cd *Poo, *Pvv;        // [N][N][N][o][o], [N][N][N][v][v] partial sums
+    cd *Poo, *Pvv;        // [splits][N][N][N][o][o], [splits][N][N][N][v][v] partial sums
 };
 
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);

@@ -120,7 +120,9 @@ __global__ void k_fvv_partial(SysDev s, const cd *t1, const cd *t2, cd *Pvv) {
 //   Pvv[r][p][q](a,e) = -1/2 sum_{m,n,f} taut(m,n,a,f) <mn||ef>    (k = r, km = p, kn = q)
 // When a whole n-slab (o v (v+1) elements) does not fit FB_SLAB, the two sums take
 // separate passes: Poo over slabs of every row x and a range of e, Pvv over slabs of a
-// range of rows m and every e.
+// range of rows m and every e.  With fr_splits > 1 each pass's list of slabs is cut into
+// that many contiguous ranges, one workgroup each (grid splits x N^3), and split sp writes
+// its partial sums to slice sp of Poo and Pvv.
 constexpr int FB_SLAB = 2176;  // staged complex elements per operand
 inline bool f_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
@@ -130,7 +132,9 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     __shared__ cd red[FB_NT];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
-    const int64_t blk = blockIdx.x;
+    const int64_t n3 = (int64_t)N * N * N;
+    const int64_t blk = blockIdx.x % n3;
+    const int sp = (int)(blockIdx.x / n3), ns = fr_splits(s.d);
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int kb = kcv(s.kc, N, p, q, r);
     const int64_t base = blk * s.d.t2blk();
@@ -157,50 +161,53 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
         b1 = pt < np ? (int)((int64_t)(pt + 1) * cnt / np) : 0;
     };
     const bool one = (int64_t)no * nv * rs <= FB_SLAB;  // both sums from one slab per n
-    const int ec = one ? nv : FB_SLAB / (no * rs);
+    const int ec = one ? nv : FB_SLAB / (no * rs), nes = (nv + ec - 1) / ec;
     cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0);
-    for (int n = 0; n < no; ++n)
-        for (int e0 = 0; e0 < nv; e0 += ec) {
-            const int ne = min(ec, nv - e0);
-            stage(n, 0, no, e0, ne);
+    // this split's range of the slabs (n, e0), n-major
+    const int a0 = sp * no * nes / ns, a1 = (sp + 1) * no * nes / ns;
+    for (int it = a0; it < a1; ++it) {
+        const int n = it / nes, e0 = (it % nes) * ec;
+        const int ne = min(ec, nv - e0);
+        stage(n, 0, no, e0, ne);
+        __syncthreads();
+        int b0, b1;
+        slice(part, parts, ne * nv, b0, b1);
+        for (int ef = b0; ef < b1; ++ef) {
+            const int e = ef / nv, f = ef % nv;
+            cfma(aoo, Ts[(ui * ne + e) * rs + f], Gs[(um * ne + e) * rs + f]);
+        }
+        if (one) {
+            slice(vpart, vparts, no * nv, b0, b1);
+            for (int mf = b0; mf < b1; ++mf) {
+                const int m = mf / nv, f = mf % nv;
+                cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!one) {
+        const int mc = FB_SLAB / (nv * rs), nms = (no + mc - 1) / mc;
+        const int c0 = sp * no * nms / ns, c1 = (sp + 1) * no * nms / ns;
+        for (int it = c0; it < c1; ++it) {
+            const int n = it / nms, m0 = (it % nms) * mc;
+            const int nm = min(mc, no - m0);
+            stage(n, m0, nm, 0, nv);
             __syncthreads();
             int b0, b1;
-            slice(part, parts, ne * nv, b0, b1);
-            for (int ef = b0; ef < b1; ++ef) {
-                const int e = ef / nv, f = ef % nv;
-                cfma(aoo, Ts[(ui * ne + e) * rs + f], Gs[(um * ne + e) * rs + f]);
-            }
-            if (one) {
-                slice(vpart, vparts, no * nv, b0, b1);
-                for (int mf = b0; mf < b1; ++mf) {
-                    const int m = mf / nv, f = mf % nv;
-                    cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
-                }
+            slice(vpart, vparts, nm * nv, b0, b1);
+            for (int mf = b0; mf < b1; ++mf) {
+                const int m = mf / nv, f = mf % nv;
+                cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
             }
             __syncthreads();
         }
-    if (!one) {
-        const int mc = FB_SLAB / (nv * rs);
-        for (int n = 0; n < no; ++n)
-            for (int m0 = 0; m0 < no; m0 += mc) {
-                const int nm = min(mc, no - m0);
-                stage(n, m0, nm, 0, nv);
-                __syncthreads();
-                int b0, b1;
-                slice(vpart, vparts, nm * nv, b0, b1);
-                for (int mf = b0; mf < b1; ++mf) {
-                    const int m = mf / nv, f = mf % nv;
-                    cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
-                }
-                __syncthreads();
-            }
     }
     red[tid] = aoo;
     __syncthreads();
     if (tid < oo) {
         cd sum = make_double2(0.0, 0.0);
         for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * oo + tid]);
-        Poo[blk * oo + (int64_t)um * no + ui] = cscale(sum, 0.5);
+        Poo[(sp * n3 + blk) * oo + (int64_t)um * no + ui] = cscale(sum, 0.5);
     }
     __syncthreads();
     red[tid] = avv;
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     if (tid < vv) {
         cd sum = make_double2(0.0, 0.0);
         for (int pp = 0; pp < vparts; ++pp) sum = cadd(sum, red[pp * vv + tid]);
-        Pvv[(((int64_t)r * N + p) * N + q) * vv + tid] = cscale(sum, -0.5);
+        Pvv[(sp * n3 + ((int64_t)r * N + p) * N + q) * vv + tid] = cscale(sum, -0.5);
     }
 }
 
@@ -337,7 +344,9 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
 //   P1[r][p][q](i,a) += -1/2 sum_{m,n,f} t2(m,n,a,f) <m p, n q || i r, f>   (k = r)
 // written to two partial arrays that k_r1_wave adds.  When the slabs of one n do not fit,
 // the two sums take separate passes: the first over slabs of a range of e (every i, a),
-// the second over slabs of a range of m (every a, i).
+// the second over slabs of a range of m (every a, i).  With fr_splits > 1 each pass's list
+// of slabs is cut into that many contiguous ranges, one workgroup each (grid splits x N^3),
+// and split sp writes slice sp of each partial array.
 constexpr int RB_T = 2176, RB_G = 4352, RB_H = 1152;
 inline bool r1_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
@@ -347,7 +356,9 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     __shared__ cd red[RB_NT];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
-    const int64_t blk = blockIdx.x;
+    const int64_t n3 = (int64_t)N * N * N;
+    const int64_t blk = blockIdx.x % n3;
+    const int sp = (int)(blockIdx.x / n3), ns = fr_splits(s.d);
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int64_t tb = blk * s.d.t2blk();
     const int64_t ov3 = (int64_t)no * nv * vv, o3v = (int64_t)no * no * no * nv;
@@ -378,53 +389,56 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
         }
     };
     const bool one = (int64_t)no * nv * rs <= RB_T && (int64_t)nv * (vv + 1) <= RB_G && (int64_t)no * no * rs <= RB_H;
-    const int ec = one ? nv : min(RB_T / (no * rs), (RB_G / nv - 1) / nv);
+    const int ec = one ? nv : min(RB_T / (no * rs), (RB_G / nv - 1) / nv), nes = (nv + ec - 1) / ec;
     cd accA = make_double2(0.0, 0.0), accB = make_double2(0.0, 0.0);
-    for (int n = 0; n < no; ++n)
-        for (int e0 = 0; e0 < nv; e0 += ec) {
-            const int ne = min(ec, nv - e0), per = ne * nv, gs = per + 1;
-            stage_t(n, 0, no, e0, ne);
-            // <n q, a p || e r, f> for e0 .. e0+ne-1: (a, (e - e0) * nv + f), rows padded to gs
+    // this split's range of the slabs (n, e0), n-major
+    const int a0 = sp * no * nes / ns, a1 = (sp + 1) * no * nes / ns;
+    for (int it = a0; it < a1; ++it) {
+        const int n = it / nes, e0 = (it % nes) * ec;
+        const int ne = min(ec, nv - e0), per = ne * nv, gs = per + 1;
+        stage_t(n, 0, no, e0, ne);
+        // <n q, a p || e r, f> for e0 .. e0+ne-1: (a, (e - e0) * nv + f), rows padded to gs
 #pragma unroll 4
-            for (int x = tid; x < nv * per; x += RB_NT)
-                Gs[(x / per) * gs + x % per] = s.ovvv[gb + (int64_t)n * nv * vv + (int64_t)(x / per) * vv + e0 * nv + x % per];
-            if (one) stage_h(n, 0, no);
+        for (int x = tid; x < nv * per; x += RB_NT)
+            Gs[(x / per) * gs + x % per] = s.ovvv[gb + (int64_t)n * nv * vv + (int64_t)(x / per) * vv + e0 * nv + x % per];
+        if (one) stage_h(n, 0, no);
+        __syncthreads();
+        int b0, b1;
+        slice(per, b0, b1);
+        for (int ef = b0; ef < b1; ++ef) cfma(accA, Ts[(ii * ne + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
+        if (one) {
+            slice(no * nv, b0, b1);
+            for (int mf = b0; mf < b1; ++mf) {
+                const int m = mf / nv, f = mf % nv;
+                cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!one) {
+        const int mc = min(min(no, RB_T / (nv * rs)), RB_H / (no * rs)), nms = (no + mc - 1) / mc;
+        const int c0 = sp * no * nms / ns, c1 = (sp + 1) * no * nms / ns;
+        for (int it = c0; it < c1; ++it) {
+            const int n = it / nms, m0 = (it % nms) * mc;
+            const int nm = min(mc, no - m0);
+            stage_t(n, m0, nm, 0, nv);
+            stage_h(n, m0, nm);
             __syncthreads();
             int b0, b1;
-            slice(per, b0, b1);
-            for (int ef = b0; ef < b1; ++ef) cfma(accA, Ts[(ii * ne + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
-            if (one) {
-                slice(no * nv, b0, b1);
-                for (int mf = b0; mf < b1; ++mf) {
-                    const int m = mf / nv, f = mf % nv;
-                    cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
-                }
+            slice(nm * nv, b0, b1);
+            for (int mf = b0; mf < b1; ++mf) {
+                const int m = mf / nv, f = mf % nv;
+                cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
             }
             __syncthreads();
         }
-    if (!one) {
-        const int mc = min(min(no, RB_T / (nv * rs)), RB_H / (no * rs));
-        for (int n = 0; n < no; ++n)
-            for (int m0 = 0; m0 < no; m0 += mc) {
-                const int nm = min(mc, no - m0);
-                stage_t(n, m0, nm, 0, nv);
-                stage_h(n, m0, nm);
-                __syncthreads();
-                int b0, b1;
-                slice(nm * nv, b0, b1);
-                for (int mf = b0; mf < b1; ++mf) {
-                    const int m = mf / nv, f = mf % nv;
-                    cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
-                }
-                __syncthreads();
-            }
     }
     red[tid] = accA;
     __syncthreads();
     if (tid < nout) {
         cd sum = make_double2(0.0, 0.0);
         for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
-        P1a[blk * nout + tid] = cscale(sum, -0.5);
+        P1a[(sp * n3 + blk) * nout + tid] = cscale(sum, -0.5);
     }
     __syncthreads();
     red[tid] = accB;
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     if (tid < nout) {
         cd sum = make_double2(0.0, 0.0);
         for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
-        P1b[(((int64_t)r * N + p) * N + q) * nout + tid] = cscale(sum, -0.5);
+        P1b[(sp * n3 + ((int64_t)r * N + p) * N + q) * nout + tid] = cscale(sum, -0.5);
     }
 }
 
@@ -572,7 +586,8 @@ __global__ __launch_bounds__(64) void k_fov(SysDev s, const cd *t1, cd *Fov) {
 __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd *Fov, const cd *Poo,
                                                 const cd *Pvv, cd *Foo, cd *Fvv) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
-    const int64_t noo = (int64_t)N * no * no;
+    const int64_t noo = (int64_t)N * no * no, n3 = (int64_t)N * N * N;
+    const int ns = fr_splits(s.d);  // slices of the partial sums
     const int64_t idx = blockIdx.x;
     const int lane = threadIdx.x;
     const int ov = no * nv;
@@ -585,7 +600,8 @@ __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd
             const cd *g = s.ooov + blk3(N, k, kn, k) * ((int64_t)no * no * no * nv);
             cfma(acc, t1[((int64_t)kn * no + nn) * nv + e], g[(((int64_t)m * no + nn) * no + i) * nv + e]);
         }
-        for (int u = lane; u < N * N; u += 64) acc = cadd(acc, Poo[(((int64_t)k * N * N + u) * no + m) * no + i]);
+        for (int u = lane; u < ns * N * N; u += 64)  // split sp = u / N^2, then the momenta of the block
+            acc = cadd(acc, Poo[(((int64_t)(u / (N * N)) * n3 + (int64_t)k * N * N + u % (N * N)) * no + m) * no + i]);
         acc = wave_sum(acc);
         if (lane == 0) {
             const cd *fk = s.fock + (int64_t)k * n * n;
@@ -604,7 +620,8 @@ __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd
             cfma(acc, t1[((int64_t)km * no + m) * nv + f], g[(((int64_t)m * nv + a) * nv + e) * nv + f]);
         }
         acc = make_double2(-acc.x, -acc.y);
-        for (int u = lane; u < N * N; u += 64) acc = cadd(acc, Pvv[(((int64_t)k * N * N + u) * nv + a) * nv + e]);
+        for (int u = lane; u < ns * N * N; u += 64)
+            acc = cadd(acc, Pvv[(((int64_t)(u / (N * N)) * n3 + (int64_t)k * N * N + u % (N * N)) * nv + a) * nv + e]);
         acc = wave_sum(acc);
         if (lane == 0) {
             const cd *fk = s.fock + (int64_t)k * n * n;
@@ -1393,7 +1410,8 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo, w.Pvv);
     } else if (f_blocks_fit(s.d)) {
-        hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N)), dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
+        hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N * fr_splits(s.d))), dim3(FB_NT), 0, st, s, t1, t2,
+                           w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_foo_partial, N * N * N * no * no, s, t1, t2, w.Poo);
@@ -1559,15 +1577,20 @@ void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st) {
     CK_CHECK(hipGetLastError());
 }
 
-static bool r1_two_parts(const Dims &d) { return (d.no <= 8 && d.nv <= 16) || r1_blocks_fit(d); }
+// partial arrays of N^3 o v elements that the R1 block sums leave for k_r1_wave
+static int r1_parts(const Dims &d) {
+    if (d.no <= 8 && d.nv <= 16) return 2;
+    return r1_blocks_fit(d) ? 2 * fr_splits(d) : 1;
+}
 
 void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
-    const int64_t np = N * N * N * no * nv;  // P1 holds two partial arrays of np elements
+    const int64_t np = N * N * N * no * nv;  // P1 holds r1_parts partial arrays of np elements
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
     } else if (r1_blocks_fit(s.d)) {
-        hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N)), dim3(RB_NT), 0, st, s, t2, P1, P1 + np);
+        const int ns = fr_splits(s.d);
+        hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N * ns)), dim3(RB_NT), 0, st, s, t2, P1, P1 + ns * np);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_r1_partial, N * N * N * no * nv, s, t2, P1);
@@ -1578,7 +1601,7 @@ void launch_r1_final(const SysDev &s, const cd *t1, const cd *t2, const FWork &w
                      hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1,
-                       r1_two_parts(s.d) ? 2 : 1, r1);
+                       r1_parts(s.d), r1);
     CK_CHECK(hipGetLastError());
 }
 
