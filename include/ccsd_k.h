@@ -106,7 +106,11 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
  * stored elements of (R1, R2) and, if the norm is >= tol, applies t <- t + D^-1 R (then
  * DIIS when diis_space > 0).  Stops when every system has ||R|| < tol or after max_iter
  * residual evaluations.  *iters: evaluations done (max over systems); *max_rnorm: largest
- * last norm.  Returns CCSD_K_NOT_CONVERGED if some system did not converge. */
+ * last norm.  Returns CCSD_K_NOT_CONVERGED if some system did not converge.  With more than one
+ * system active, the systems run side by side on four internal streams (default priority,
+ * created on the first such call, destroyed by ccsd_k_free), ordered after the work already
+ * on the context's stream and joined back into it before each host synchronization; each
+ * system's results do not depend on this. */
 int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm);
 
 /* Last residual 2-norm of system sys (after ccsd_k_residual or ccsd_k_iterate). */
@@ -137,7 +141,9 @@ int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, in
 
 /* Per-stage device timing with HIP events on the context's stream (0 = off).  Stages:
  * 0 particle-particle ladder, 1 hole-hole ladder, 2 W_mnij build, 3 ring W build,
- * 4 ring product, 5 the whole residual evaluation (all of the above and every other term). */
+ * 4 ring product, 5 the whole residual evaluation (all of the above and every other term).
+ * When ccsd_k_iterate runs several systems side by side the events sit on their streams
+ * and each interval also counts the time of work from other systems that overlaps it. */
 int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable);
 int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches);
 

@@ -151,6 +151,11 @@ struct ccsd_k_ctx {
     std::vector<EventPair> pending, pool;
     double stage_ms[ST_COUNT] = {};
     int64_t stage_n[ST_COUNT] = {};
+    // streams (default priority, created on first use) on which the systems of a batch run
+    // side by side, with the events that order them after and before work on `stream`
+    std::vector<hipStream_t> lanes;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
 };
 
 namespace {
@@ -570,8 +575,54 @@ void collect_timing(ccsd_k_ctx *c) {
     c->pending.clear();
 }
 
-void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st = nullptr) {
-    if (!st) st = c->stream;
+// ---------------------------------------------------------------- systems side by side
+constexpr int NLANES = 4;
+
+// The streams for a set of systems: the context's own stream for one system; for several,
+// the lanes, each system to the lane with the least work so far (largest first, work
+// taken as N^4 (o v)^2 (o + v)^2 plus a fixed per-system part for its ~40 launches), after
+// a fork event on the context's stream.  join_lanes orders the context's stream after them.
+std::vector<hipStream_t> fork_lanes(ccsd_k_ctx *c, const std::vector<System *> &sys) {
+    std::vector<hipStream_t> out(sys.size(), c->stream);
+    if (sys.size() < 2) return out;
+    if (c->lanes.empty()) {
+        CK_CHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+        for (int l = 0; l < NLANES; ++l) {
+            hipStream_t st;
+            hipEvent_t ev;
+            CK_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            c->lanes.push_back(st);
+            CK_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            c->joins.push_back(ev);
+        }
+    }
+    CK_CHECK(hipEventRecord(c->fork, c->stream));
+    for (hipStream_t st : c->lanes) CK_CHECK(hipStreamWaitEvent(st, c->fork, 0));
+    std::vector<double> work(sys.size());
+    std::vector<size_t> order(sys.size());
+    for (size_t k = 0; k < sys.size(); ++k) {
+        const double N = sys[k]->d.N, o = sys[k]->d.no, v = sys[k]->d.nv;
+        work[k] = N * N * N * N * (o * v) * (o * v) * (o + v) * (o + v) + 2e8;
+        order[k] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+    double load[NLANES] = {};
+    for (size_t k : order) {
+        const int l = (int)(std::min_element(load, load + NLANES) - load);
+        load[l] += work[k];
+        out[k] = c->lanes[l];
+    }
+    return out;
+}
+void join_lanes(ccsd_k_ctx *c, const std::vector<hipStream_t> &used) {
+    if (used.size() < 2) return;
+    for (int l = 0; l < NLANES; ++l) {
+        CK_CHECK(hipEventRecord(c->joins[l], c->lanes[l]));
+        CK_CHECK(hipStreamWaitEvent(c->stream, c->joins[l], 0));
+    }
+}
+
+void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st) {
     EventPair ep{};
     stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage, st);
     if (S.mixed) ck::gemm_split(S.sg[i], st);
@@ -579,24 +630,23 @@ void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st = nullptr) {
     stage_end(c, ep, st);
 }
 
-// One evaluation of (R1, R2) at the current amplitudes, left in S.res.
-void residual_device(ccsd_k_ctx *c, System &S) {
-    hipStream_t st = c->stream;
+// One evaluation of (R1, R2) at the current amplitudes, left in S.res, on stream st.
+void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
     ck::SysDev s = S.dev();
     EventPair all{};
-    stage_begin(c, all, ST_RES);
+    stage_begin(c, all, ST_RES, st);
     if (!S.mixed) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
         ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, false, st);
-        run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>
+        run_gemm(c, S, 0, st);  // W_mnij += 1/2 tau <mn||ef>
         ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
         ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
-        run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>
-        run_gemm(c, S, 4);  // X += t2 W_mbej
+        run_gemm(c, S, 3, st);  // W_mbej += 1/2 t2 <mn||ef>
+        run_gemm(c, S, 4, st);  // X += t2 W_mbej
         ck::launch_assemble_r2(s, S.X, S.r2(), st);
-        run_gemm(c, S, 1);  // particle-particle ladder
-        run_gemm(c, S, 2);  // hole-hole ladder
+        run_gemm(c, S, 1, st);  // particle-particle ladder
+        run_gemm(c, S, 2, st);  // hole-hole ladder
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
         const int64_t R = S.PV + S.PO;
@@ -605,25 +655,25 @@ void residual_device(ccsd_k_ctx *c, System &S) {
         ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
         ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
-        run_gemm(c, S, 0);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
+        run_gemm(c, S, 0, st);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
         ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, st);
         ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
-        run_gemm(c, S, 3);  // W_mbej += 1/2 t2 <mn||ef>, written split
-        run_gemm(c, S, 4);  // X += t2 W_mbej
-        run_gemm(c, S, 1);  // both ladders on canonical pairs, into Lp
+        run_gemm(c, S, 3, st);  // W_mbej += 1/2 t2 <mn||ef>, written split
+        run_gemm(c, S, 4, st);  // X += t2 W_mbej
+        run_gemm(c, S, 1, st);  // both ladders on canonical pairs, into Lp
         ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2c, S.npart, st);
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     }
-    stage_end(c, all);
+    stage_end(c, all, st);
 }
 
 // every write of the amplitudes other than the mixed DIIS extrapolation
 void amplitudes_changed(System &S) { S.sp_ok = S.e_ok = false; }
 
 // ||R||^2 into S.redout[0] after residual_device (the mixed assembly left partial sums)
-void launch_norm(ccsd_k_ctx *c, System &S) {
-    if (S.mixed) ck::launch_norm_pack(S.d, S.pairs(), S.npart, S.r1(), S.redout, c->stream);
-    else ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, c->stream);
+void launch_norm(System &S, hipStream_t st) {
+    if (S.mixed) ck::launch_norm_pack(S.d, S.pairs(), S.npart, S.r1(), S.redout, st);
+    else ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, st);
 }
 
 // split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
@@ -843,8 +893,8 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
         if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t1 || t2) amplitudes_changed(S);
-        residual_device(ctx, S);
-        launch_norm(ctx, S);
+        residual_device(ctx, S, ctx->stream);
+        launch_norm(S, ctx->stream);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
         if (r1) CK_CHECK(hipMemcpyAsync(r1, S.r1(), S.n1() * sizeof(cd), hipMemcpyDeviceToHost, ctx->stream));
         std::vector<ck::cf> r2h;
@@ -882,9 +932,13 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
             for (auto &S : ctx->sys)
                 if (!S.converged) active.push_back(&S);
             if (active.empty()) break;
-            for (System *S : active) {
-                residual_device(ctx, *S);
-                launch_norm(ctx, *S);
+            {
+                const std::vector<hipStream_t> ls = fork_lanes(ctx, active);
+                for (size_t k = 0; k < active.size(); ++k) {
+                    residual_device(ctx, *active[k], ls[k]);
+                    launch_norm(*active[k], ls[k]);
+                }
+                join_lanes(ctx, ls);
             }
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             done = it + 1;
@@ -898,14 +952,17 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 else upd.push_back(S);
             }
             if (numeric_error) break;
-            for (System *S : upd) {
+            const std::vector<hipStream_t> ls = fork_lanes(ctx, upd);
+            for (size_t k = 0; k < upd.size(); ++k) {
+                System *S = upd[k];
+                hipStream_t st = ls[k];
                 ck::SysDev sd = S->dev();
                 int m = S->desc.diis_space;
                 if (m == 0) {
                     if (S->mixed)
-                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2c, nullptr, nullptr, ctx->stream);
+                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2c, nullptr, nullptr, st);
                     else
-                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, ctx->stream);
+                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, st);
                     amplitudes_changed(*S);
                     continue;
                 }
@@ -914,15 +971,18 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 if (S->mixed) {
                     std::vector<const ck::cf *> ys(S->derr32.begin(), S->derr32.begin() + held);
                     ck::launch_update_diis(sd, S->amp, S->res, S->r2c, S->derr32[slot], S->dvec[slot], ys.data(),
-                                           held, slot, S->red, S->redout, ctx->stream);
+                                           held, slot, S->red, S->redout, st);
                 } else {
                     std::vector<const cd *> ys(S->derr.begin(), S->derr.begin() + held);
                     ck::launch_update_diis(sd, S->amp, S->res, S->r2(), S->derr[slot], S->dvec[slot], ys.data(),
-                                           held, slot, S->red, S->redout, ctx->stream);
+                                           held, slot, S->red, S->redout, st);
                 }
             }
+            join_lanes(ctx, ls);
             CK_CHECK(hipStreamSynchronize(ctx->stream));
-            for (System *S : upd) {
+            const std::vector<hipStream_t> lc = fork_lanes(ctx, upd);
+            for (size_t k = 0; k < upd.size(); ++k) {
+                System *S = upd[k];
                 int m = S->desc.diis_space;
                 if (m == 0) continue;
                 int slot = S->diis_head;
@@ -947,13 +1007,14 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
                 }
                 if (S->mixed) {
                     ck::launch_lincomb_pack(S->dev(), src.data(), coef.data(), (int)src.size(), S->amp, S->sp_t2,
-                                            S->epart, ctx->stream);
+                                            S->epart, lc[k]);
                     S->sp_ok = S->e_ok = true;
                 } else {
                     ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), (int)src.size(), S->amp,
-                                       ctx->stream);
+                                       lc[k]);
                 }
             }
+            join_lanes(ctx, lc);
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             collect_timing(ctx);
         }
@@ -1185,6 +1246,12 @@ void ccsd_k_free(ccsd_k_ctx *ctx) {
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
         }
+        for (hipStream_t st : ctx->lanes) (void)hipStreamSynchronize(st);
+    }
+    if (!ctx->failed) {
+        for (hipStream_t st : ctx->lanes) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : ctx->joins) (void)hipEventDestroy(ev);
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     }
     delete ctx;
 }

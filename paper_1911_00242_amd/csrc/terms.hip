@@ -1111,8 +1111,8 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 // The same X seed in one blocked pass for n_occ <= OM, n_vir <= VM: a workgroup per
 // (q, ki, kj, a) in XCD-contiguous order, a thread per (j, b) holding the no values of X at
 // (i, a, j, b) for every i.  Every <ov||vv> and t2 element is read once (t2 of this a goes
-// through LDS, with each (i, n) run of b contiguous, half of the i at a time so that more
-// workgroups fit on a CU; its loads are issued before the integral terms and land in LDS
+// through LDS, with each (i, n) run of b contiguous, a half of the i at a time (a quarter
+// for 16-row tiles) so that more workgroups fit on a CU; its loads are issued before the integral terms and land in LDS
 // after them); the Q slab of (ka, kb, ki) is shared by the nv workgroups of one (q, ki, kj),
 // which run next to each other on one XCD, so it comes from L2 after the first.  t1 is read
 // at wave-uniform addresses (scalar loads).  The coefficients -1, -1/2, 1/2, -1/2 of the four
@@ -1121,7 +1121,8 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
                                                     const cd *Fot, const cd *Fvt, cd *X) {
-    constexpr int IH = (OM + 1) / 2;  // i values per LDS phase
+    constexpr int NPH = OM > 8 ? 4 : 2;          // LDS phases over i
+    constexpr int IH = (OM + NPH - 1) / NPH;  // i values per phase
     constexpr int NT = OM * VM;       // threads
     __shared__ cd T2S[IH * OM * (VM + 1)];  // t2[ki,kj,ka](i0 + il, n, a, b) at (il * no + n) * (nv + 1) + b
     __shared__ cd FV[VM * VM];        // 1/2 Fvt[kb](b, f) at f * nv + b
@@ -1190,7 +1191,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
     }
     store_half();
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < NPH; ++p) {
         const int i0 = p * IH;
         if (i0 >= no) break;
         if (p > 0) {
