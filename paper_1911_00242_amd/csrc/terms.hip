@@ -128,8 +128,9 @@ inline bool f_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
 constexpr int FB_NT = 1024;
 __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
+    static_assert(FB_NT <= FB_SLAB, "the reduction reuses the t slab");
     __shared__ cd Ts[FB_SLAB], Gs[FB_SLAB];
-    __shared__ cd red[FB_NT];
+    cd *red = Ts;  // after the last slab (two workgroups fit on a CU)
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
     const int64_t n3 = (int64_t)N * N * N;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
             __syncthreads();
         }
     }
+    __syncthreads();  // every read of the last slab is done
     red[tid] = aoo;
     __syncthreads();
     if (tid < oo) {
