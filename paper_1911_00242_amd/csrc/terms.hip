@@ -1110,6 +1110,42 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
     }
 }
 
+// The t1 x Q term of the X seed for the 16-row tiles, written to X before k_xinit_t adds
+// the others: X[q,ki,kj](i, a, j, b) = -sum_m t_m^a(ka) Q[ka,kb,ki](m, i, j, b).  A workgroup
+// per (X block, i, range of 256 (j, b)); the thread of (j, b) keeps Q(m, i, j, b) for every m
+// in registers and forms every a, so each Q element is read once (inside k_xinit_t each of
+// the n_vir workgroups of a block would read the whole o^3 v slab again); t1 at
+// wave-uniform addresses.
+template <int OM>
+__global__ __launch_bounds__(256) void k_xinit_q(SysDev s, const cd *__restrict__ t1, const cd *__restrict__ Q,
+                                                 cd *__restrict__ X) {
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t ov = (int64_t)no * nv, o3v = ov * no * no;
+    const int nch = (int)((ov + 255) / 256);
+    const int64_t nblk = (int64_t)N * N * N * no * nch;
+    const int64_t L = xcd_block(nblk);
+    if (L >= nblk) return;
+    const int ch = (int)(L % nch), i = (int)((L / nch) % no);
+    const int64_t blk = L / ((int64_t)nch * no);  // (q, ki, kj) as in k_xinit_t
+    const int kj = (int)(blk % N), ki = (int)((blk / N) % N), q = (int)(blk / ((int64_t)N * N));
+    const int ka = kcv(s.kc, N, ki, q, 0), kb = kcv(s.kc, N, kj, 0, q);
+    const int jb = ch * 256 + threadIdx.x;
+    if (jb >= ov) return;
+    const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + (int64_t)i * ov + jb;
+    cd qm[OM];
+#pragma unroll
+    for (int m = 0; m < OM; ++m) qm[m] = m < no ? qb[(int64_t)m * no * ov] : make_double2(0.0, 0.0);
+    const cd *ta = t1 + (int64_t)ka * no * nv;
+    cd *xb = X + blk * ov * ov + (int64_t)i * nv * ov + jb;
+    for (int a = 0; a < nv; ++a) {
+        cd acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < OM; ++m)
+            if (m < no) cfma(acc, ta[m * nv + a], qm[m]);
+        xb[(int64_t)a * ov] = make_double2(-acc.x, -acc.y);
+    }
+}
+
 // The same X seed in one blocked pass for n_occ <= OM, n_vir <= VM: a workgroup per
 // (q, ki, kj, a) in XCD-contiguous order, a thread per (j, b) holding the no values of X at
 // (i, a, j, b) for every i.  Every <ov||vv> and t2 element is read once (t2 of this a goes
@@ -1119,10 +1155,12 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
 // which run next to each other on one XCD, so it comes from L2 after the first.  t1 is read
 // at wave-uniform addresses (scalar loads).  The coefficients -1, -1/2, 1/2, -1/2 of the four
 // terms are folded into one factor of each product (exact scalings), so one accumulator per
-// i takes all of them.
+// i takes all of them.  With 16-row tiles the t1 x Q term is already in X (k_xinit_q) and
+// the accumulators start from it.
 template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, const cd *t2, const cd *Q,
                                                     const cd *Fot, const cd *Fvt, cd *X) {
+    constexpr bool QX = OM > 8;                  // the t1 x Q term is in X already
     constexpr int NPH = OM > 8 ? 4 : 2;          // LDS phases over i
     constexpr int IH = (OM + NPH - 1) / NPH;  // i values per phase
     constexpr int NT = OM * VM;       // threads
@@ -1166,6 +1204,14 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
     cd acc[OM];
 #pragma unroll
     for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
+    if constexpr (QX) {
+        if (act) {
+            const cd *x0 = X + blk * ov * ov + (int64_t)a * ov + jb;
+#pragma unroll
+            for (int i = 0; i < OM; ++i)
+                if (i < no) acc[i] = x0[(int64_t)i * nv * ov];
+        }
+    }
     if (act) {
         // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
         const IT *gb = ovvv_of<IT>(s) + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
@@ -1183,7 +1229,7 @@ __global__ __launch_bounds__(OM * VM) void k_xinit_t(SysDev s, const cd *t1, con
         const cd *qb = Q + blk3(N, ka, kb, ki) * o3v + jb;
 #pragma unroll
         for (int m = 0; m < OM; ++m) {
-            if (m >= no) break;
+            if (QX || m >= no) break;
             const cd tv = t1[((int64_t)ka * no + m) * nv + a];
             const cd tm = make_double2(-tv.x, -tv.y);
 #pragma unroll
@@ -1565,10 +1611,14 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
         LAUNCH_TI(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else if (no <= 8 && nv <= 32) {
         LAUNCH_32I(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
-    } else if (no <= 16 && nv <= 16) {
-        LAUNCH_WI(16, 16, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else if (no <= 16 && nv <= 32) {
-        LAUNCH_WI(16, 32, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
+        hipLaunchKernelGGL(k_xinit_q<16>, xcd_grid(n3 * no * ((no * nv + 255) / 256)), dim3(256), 0, st, s, t1,
+                           scratch, X);
+        CK_CHECK(hipGetLastError());
+        if (nv <= 16)
+            LAUNCH_WI(16, 16, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
+        else
+            LAUNCH_WI(16, 32, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }
