@@ -127,6 +127,7 @@ constexpr int FB_SLAB = 2176;  // staged complex elements per operand
 inline bool f_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
 constexpr int FB_NT = 1024;
+template <class IT>  // element type of the <oo||vv> copy read (complex64 on the mixed path)
 __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
     static_assert(FB_NT <= FB_SLAB, "the reduction reuses the t slab");
     __shared__ cd Ts[FB_SLAB], Gs[FB_SLAB];
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
             const int row = x / per, e = (x % per) / nv, f = x % nv;
             const int64_t gi = base + (((int64_t)(x0 + row) * no + n) * nv + e0 + e) * nv + f;
             Ts[(row * ne + e) * rs + f] = tau_el(t1, t2, gi, p, q, r, kb, x0 + row, n, e0 + e, f, no, nv, 0.5);
-            Gs[(row * ne + e) * rs + f] = s.oovv[gi];
+            Gs[(row * ne + e) * rs + f] = to_cd(oovv_of<IT>(s)[gi]);
         }
     };
     auto slice = [](int pt, int np, int cnt, int &b0, int &b1) {
@@ -353,6 +354,7 @@ constexpr int RB_T = 2176, RB_G = 4352, RB_H = 1152;
 inline bool r1_blocks_fit(const Dims &d) { return d.no <= 32 && d.nv <= 32; }
 
 constexpr int RB_NT = 1024;
+template <class IT>  // element type of the <ov||vv> copy read (complex64 on the mixed path)
 __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd *P1a, cd *P1b) {
     __shared__ cd Ts[RB_T], Gs[RB_G], Hs[RB_H];
     __shared__ cd red[RB_NT];
@@ -402,7 +404,8 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
         // <n q, a p || e r, f> for e0 .. e0+ne-1: (a, (e - e0) * nv + f), rows padded to gs
 #pragma unroll 4
         for (int x = tid; x < nv * per; x += RB_NT)
-            Gs[(x / per) * gs + x % per] = s.ovvv[gb + (int64_t)n * nv * vv + (int64_t)(x / per) * vv + e0 * nv + x % per];
+            Gs[(x / per) * gs + x % per] =
+                to_cd(ovvv_of<IT>(s)[gb + (int64_t)n * nv * vv + (int64_t)(x / per) * vv + e0 * nv + x % per]);
         if (one) stage_h(n, 0, no);
         __syncthreads();
         int b0, b1;
@@ -1459,8 +1462,11 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo, w.Pvv);
     } else if (f_blocks_fit(s.d)) {
-        hipLaunchKernelGGL(k_f_blocks, dim3((unsigned)(N * N * N * fr_splits(s.d))), dim3(FB_NT), 0, st, s, t1, t2,
-                           w.Poo, w.Pvv);
+        const dim3 grid((unsigned)(N * N * N * fr_splits(s.d)));
+        if (s.oovv_c)
+            hipLaunchKernelGGL(k_f_blocks<cf>, grid, dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
+        else
+            hipLaunchKernelGGL(k_f_blocks<cd>, grid, dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_foo_partial, N * N * N * no * no, s, t1, t2, w.Poo);
@@ -1643,7 +1649,11 @@ void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
         LAUNCH_TI(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
     } else if (r1_blocks_fit(s.d)) {
         const int ns = fr_splits(s.d);
-        hipLaunchKernelGGL(k_r1_blocks, dim3((unsigned)(N * N * N * ns)), dim3(RB_NT), 0, st, s, t2, P1, P1 + ns * np);
+        const dim3 grid((unsigned)(N * N * N * ns));
+        if (s.ovvv_c)
+            hipLaunchKernelGGL(k_r1_blocks<cf>, grid, dim3(RB_NT), 0, st, s, t2, P1, P1 + ns * np);
+        else
+            hipLaunchKernelGGL(k_r1_blocks<cd>, grid, dim3(RB_NT), 0, st, s, t2, P1, P1 + ns * np);
         CK_CHECK(hipGetLastError());
     } else {
         LAUNCH(k_r1_partial, N * N * N * no * nv, s, t2, P1);
