@@ -585,16 +585,26 @@ constexpr int NLANES = 4;
 std::vector<hipStream_t> fork_lanes(ccsd_k_ctx *c, const std::vector<System *> &sys) {
     std::vector<hipStream_t> out(sys.size(), c->stream);
     if (sys.size() < 2) return out;
-    if (c->lanes.empty()) {
-        CK_CHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-        for (int l = 0; l < NLANES; ++l) {
-            hipStream_t st;
-            hipEvent_t ev;
-            CK_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            c->lanes.push_back(st);
-            CK_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            c->joins.push_back(ev);
+    if (c->lanes.empty()) {  // all or nothing: a failed creation leaves no partial set
+        hipEvent_t fork = nullptr;
+        std::vector<hipStream_t> lanes(NLANES, nullptr);
+        std::vector<hipEvent_t> joins(NLANES, nullptr);
+        hipError_t err = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int l = 0; err == hipSuccess && l < NLANES; ++l) {
+            err = hipStreamCreateWithFlags(&lanes[l], hipStreamNonBlocking);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&joins[l], hipEventDisableTiming);
         }
+        if (err != hipSuccess) {
+            for (hipStream_t st : lanes)
+                if (st) (void)hipStreamDestroy(st);
+            for (hipEvent_t ev : joins)
+                if (ev) (void)hipEventDestroy(ev);
+            if (fork) (void)hipEventDestroy(fork);
+            throw ck::HipError(err, "creating the streams of systems side by side", __FILE__, __LINE__);
+        }
+        c->fork = fork;
+        c->lanes = lanes;
+        c->joins = joins;
     }
     CK_CHECK(hipEventRecord(c->fork, c->stream));
     for (hipStream_t st : c->lanes) CK_CHECK(hipStreamWaitEvent(st, c->fork, 0));
