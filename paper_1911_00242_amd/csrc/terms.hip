@@ -131,7 +131,7 @@ template <class IT>  // element type of the <oo||vv> copy read (complex64 on the
 __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv) {
     static_assert(FB_NT <= FB_SLAB, "the reduction reuses the t slab");
     __shared__ cd Ts[FB_SLAB], Gs[FB_SLAB];
-    cd *red = Ts;  // after the last slab (two workgroups fit on a CU)
+    cd *red = Ts;  // after the last slab
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, rs = nv + 1;
     const int tid = threadIdx.x;
     const int64_t n3 = (int64_t)N * N * N;
@@ -143,9 +143,13 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     const int oo = no * no, parts = FB_NT / oo;
     const int u = tid % oo, part = tid / oo;  // Foo output (m,i) = u, slice = part
     const int um = u / no, ui = u % no;
-    const int vparts = FB_NT / vv;  // threads per Fvv output (v^2 <= FB_NT)
-    const int vo = tid % vv, vpart = tid / vv;
+    // Fvv: a thread per output pair (a, e), (a + ha, e), which share every <mn||ef> read
+    const int ha = (nv + 1) / 2, hv = ha * nv;
+    const int vparts = FB_NT / hv;  // threads per output pair (ha n_vir <= FB_NT)
+    const int vo = tid % hv, vpart = tid / hv;
     const int va = vo / nv, ve = vo % nv;
+    const bool two = va + ha < nv;      // the second output exists (odd n_vir)
+    const int va2 = two ? va + ha : va;  // (a duplicate read otherwise, discarded)
     // slab of rows x0 .. x0+nx-1 and e0 .. e0+ne-1 of n: element (x, e, f) at
     // ((x - x0) * ne + e - e0) * rs + f
     auto stage = [&](int n, int x0, int nx, int e0, int ne) {
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
     };
     const bool one = (int64_t)no * nv * rs <= FB_SLAB;  // both sums from one slab per n
     const int ec = one ? nv : FB_SLAB / (no * rs), nes = (nv + ec - 1) / ec;
-    cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0);
+    cd aoo = make_double2(0.0, 0.0), avv = make_double2(0.0, 0.0), avv2 = make_double2(0.0, 0.0);
     // this split's range of the slabs (n, e0), n-major
     const int a0 = sp * no * nes / ns, a1 = (sp + 1) * no * nes / ns;
     for (int it = a0; it < a1; ++it) {
@@ -182,7 +186,9 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
             slice(vpart, vparts, no * nv, b0, b1);
             for (int mf = b0; mf < b1; ++mf) {
                 const int m = mf / nv, f = mf % nv;
-                cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
+                const cd g = Gs[(m * nv + ve) * rs + f];
+                cfma(avv, Ts[(m * nv + va) * rs + f], g);
+                cfma(avv2, Ts[(m * nv + va2) * rs + f], g);
             }
         }
         __syncthreads();
@@ -199,7 +205,9 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
             slice(vpart, vparts, nm * nv, b0, b1);
             for (int mf = b0; mf < b1; ++mf) {
                 const int m = mf / nv, f = mf % nv;
-                cfma(avv, Ts[(m * nv + va) * rs + f], Gs[(m * nv + ve) * rs + f]);
+                const cd g = Gs[(m * nv + ve) * rs + f];
+                cfma(avv, Ts[(m * nv + va) * rs + f], g);
+                cfma(avv2, Ts[(m * nv + va2) * rs + f], g);
             }
             __syncthreads();
         }
@@ -213,12 +221,21 @@ __global__ __launch_bounds__(FB_NT) void k_f_blocks(SysDev s, const cd *t1, cons
         Poo[(sp * n3 + blk) * oo + (int64_t)um * no + ui] = cscale(sum, 0.5);
     }
     __syncthreads();
+    cd *pv = Pvv + (sp * n3 + ((int64_t)r * N + p) * N + q) * vv;
     red[tid] = avv;
     __syncthreads();
-    if (tid < vv) {
+    if (tid < hv) {
         cd sum = make_double2(0.0, 0.0);
-        for (int pp = 0; pp < vparts; ++pp) sum = cadd(sum, red[pp * vv + tid]);
-        Pvv[(sp * n3 + ((int64_t)r * N + p) * N + q) * vv + tid] = cscale(sum, -0.5);
+        for (int pp = 0; pp < vparts; ++pp) sum = cadd(sum, red[pp * hv + tid]);
+        pv[va * nv + ve] = cscale(sum, -0.5);
+    }
+    __syncthreads();
+    red[tid] = avv2;
+    __syncthreads();
+    if (tid < hv && two) {
+        cd sum = make_double2(0.0, 0.0);
+        for (int pp = 0; pp < vparts; ++pp) sum = cadd(sum, red[pp * hv + tid]);
+        pv[(va + ha) * nv + ve] = cscale(sum, -0.5);
     }
 }
 
