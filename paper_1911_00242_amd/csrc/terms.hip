@@ -386,9 +386,14 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     const int64_t gb = blk3(N, q, p, r) * ov3;  // ovvv block [q,p,r]: (n, a, e, f)
     const int64_t hb = blk * o3v;               // ooov block [p,q,r]: (m, n, i, f)
     const int nout = no * nv;                   // outputs (i, a)
-    const int parts = RB_NT / nout;             // threads per output
-    const int part = tid / nout, oi = tid % nout;
+    // a thread per output pair (i, a), (i + ho, a): the pair shares its <n q, a p||e r, f>
+    // reads in the first sum and its t2 reads in the second
+    const int ho = (no + 1) / 2, hout = ho * nv;
+    const int parts = RB_NT / hout;             // threads per output pair
+    const int part = tid / hout, oi = tid % hout;
     const int ii = oi / nv, aa = oi % nv;
+    const bool two = ii + ho < no;              // the second output exists (odd n_occ)
+    const int ii2 = two ? ii + ho : ii;         // (a duplicate read otherwise, discarded)
     auto slice = [&](int cnt, int &b0, int &b1) {
         b0 = part < parts ? (int)((int64_t)part * cnt / parts) : 0;
         b1 = part < parts ? (int)((int64_t)(part + 1) * cnt / parts) : 0;
@@ -412,6 +417,7 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     const bool one = (int64_t)no * nv * rs <= RB_T && (int64_t)nv * (vv + 1) <= RB_G && (int64_t)no * no * rs <= RB_H;
     const int ec = one ? nv : min(RB_T / (no * rs), (RB_G / nv - 1) / nv), nes = (nv + ec - 1) / ec;
     cd accA = make_double2(0.0, 0.0), accB = make_double2(0.0, 0.0);
+    cd accA2 = make_double2(0.0, 0.0), accB2 = make_double2(0.0, 0.0);
     // this split's range of the slabs (n, e0), n-major
     const int a0 = sp * no * nes / ns, a1 = (sp + 1) * no * nes / ns;
     for (int it = a0; it < a1; ++it) {
@@ -427,12 +433,18 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
         __syncthreads();
         int b0, b1;
         slice(per, b0, b1);
-        for (int ef = b0; ef < b1; ++ef) cfma(accA, Ts[(ii * ne + ef / nv) * rs + ef % nv], Gs[aa * gs + ef]);
+        for (int ef = b0; ef < b1; ++ef) {
+            const cd g = Gs[aa * gs + ef];
+            cfma(accA, Ts[(ii * ne + ef / nv) * rs + ef % nv], g);
+            cfma(accA2, Ts[(ii2 * ne + ef / nv) * rs + ef % nv], g);
+        }
         if (one) {
             slice(no * nv, b0, b1);
             for (int mf = b0; mf < b1; ++mf) {
                 const int m = mf / nv, f = mf % nv;
-                cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+                const cd t = Ts[(m * nv + aa) * rs + f];
+                cfma(accB, t, Hs[(m * no + ii) * rs + f]);
+                cfma(accB2, t, Hs[(m * no + ii2) * rs + f]);
             }
         }
         __syncthreads();
@@ -450,25 +462,25 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
             slice(nm * nv, b0, b1);
             for (int mf = b0; mf < b1; ++mf) {
                 const int m = mf / nv, f = mf % nv;
-                cfma(accB, Ts[(m * nv + aa) * rs + f], Hs[(m * no + ii) * rs + f]);
+                const cd t = Ts[(m * nv + aa) * rs + f];
+                cfma(accB, t, Hs[(m * no + ii) * rs + f]);
+                cfma(accB2, t, Hs[(m * no + ii2) * rs + f]);
             }
             __syncthreads();
         }
     }
-    red[tid] = accA;
-    __syncthreads();
-    if (tid < nout) {
-        cd sum = make_double2(0.0, 0.0);
-        for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
-        P1a[(sp * n3 + blk) * nout + tid] = cscale(sum, -0.5);
-    }
-    __syncthreads();
-    red[tid] = accB;
-    __syncthreads();
-    if (tid < nout) {
-        cd sum = make_double2(0.0, 0.0);
-        for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * nout + tid]);
-        P1b[(sp * n3 + ((int64_t)r * N + p) * N + q) * nout + tid] = cscale(sum, -0.5);
+    cd *pa = P1a + (sp * n3 + blk) * nout, *pb = P1b + (sp * n3 + ((int64_t)r * N + p) * N + q) * nout;
+    const cd accs[4] = {accA, accA2, accB, accB2};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {  // (first sum, i), (first, i + ho), (second, i), (second, i + ho)
+        if (w > 0) __syncthreads();
+        red[tid] = accs[w];
+        __syncthreads();
+        if (tid < hout && (w % 2 == 0 || two)) {
+            cd sum = make_double2(0.0, 0.0);
+            for (int pp = 0; pp < parts; ++pp) sum = cadd(sum, red[pp * hout + tid]);
+            (w < 2 ? pa : pb)[(ii + (w % 2) * ho) * nv + aa] = cscale(sum, -0.5);
+        }
     }
 }
 
