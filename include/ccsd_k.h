@@ -47,7 +47,8 @@ extern "C" {
 #define CCSD_K_OK 0
 #define CCSD_K_NOT_CONVERGED 1 /* iterate: max_iter reached before ||R|| < tol      */
 #define CCSD_K_EINVAL (-1)     /* bad argument, size, pointer or index                */
-#define CCSD_K_ENOMEM (-2)     /* workspace smaller than ccsd_k_workspace_bytes       */
+#define CCSD_K_ENOMEM (-2)     /* workspace smaller than ccsd_k_workspace_bytes, or a
+                                  host allocation failed                            */
 #define CCSD_K_EDEVICE (-3)    /* a HIP runtime call failed                            */
 #define CCSD_K_ESTATE (-4)     /* call out of order (e.g. before bind) or after EDEVICE */
 #define CCSD_K_ENUMERIC (-5)   /* non-finite residual norm or energy                   */
@@ -74,8 +75,8 @@ typedef struct {
     double eri_scale;   /* scale of the raw complex Gaussians of the synthetic recipe   */
 } ccsd_k_system;
 
-/* Plan n_sys independent systems (1..4096).  hip_stream: a hipStream_t, or NULL for the
- * default stream.  Validates sizes; allocates host memory only.  On failure *out is NULL
+/* Plan n_sys independent systems (1..4096), each with N_k <= 512.  hip_stream: a
+ * hipStream_t, or NULL for the default stream.  Validates sizes; allocates host memory only.  On failure *out is NULL
  * and ccsd_k_last_error(NULL) holds the reason. */
 int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out);
 
@@ -87,12 +88,15 @@ int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes);
  * where requested, and sets every amplitude to zero.  ENOMEM if bytes is too small. */
 int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes);
 
-/* Copy one system's Fock matrix and integral classes from host memory (layouts above). */
+/* Copy one system's Fock matrix and integral classes from host memory (layouts above).
+ * EINVAL when an orbital energy (real part of a Fock diagonal element) is not finite or
+ * when a T1 or T2 denominator of the update (Sec. 4.4) is zero.  Resets the system's DIIS
+ * history. */
 int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]);
 
 /* One evaluation of (R1, R2) (eqs. ori_EqSingle, ori_EqDouble) for system sys.
  * t1/t2: host amplitudes to evaluate at (they become the system's current amplitudes);
- * NULL = the current device amplitudes.  r1/r2: host buffers for the result, or NULL to
+ * NULL = the current device amplitudes; passing either resets the system's DIIS history.  r1/r2: host buffers for the result, or NULL to
  * keep it on the device only (complex128; on the mixed path r2 is held in complex64 and
  * widened on the copy).  t2 must be antisymmetric, t_{ij}^{ab} = -t_{ji}^{ab} =
  * -t_{ij}^{ba} (with the momenta exchanged alike), as every CCSD amplitude is: several

@@ -135,6 +135,19 @@ def f_intermediates(f, eris: Eris, t1, t2, kc, no):
 # --------------------------------------------------------------------------------------
 # W intermediates (Sec. 2, the three definitions ending with eq. Def_Woovv)
 # --------------------------------------------------------------------------------------
+def w_mnij_block(eris: Eris, t1, tau, kc, km, kn, ki):
+    """One block W_{m km n kn i ki j kj} (k_j by conservation):
+    <mn||ij> + P(ij) t_j^c <mn||ic> + 1/4 tau_ij^ef <mn||ef>."""
+    N = t1.shape[0]
+    kj = kc[km, kn, ki]
+    w = eris.block("oooo", km, kn, ki).copy()
+    w += _con("jc,mnic->mnij", t1[kj], eris.block("ooov", km, kn, ki))
+    w -= _con("ic,mnjc->mnij", t1[ki], eris.block("ooov", km, kn, kj))
+    for ke in range(N):
+        w += 0.25 * _con("ijef,mnef->mnij", tau[ki, kj, ke], eris.block("oovv", km, kn, ke))
+    return w
+
+
 def w_mnij(eris: Eris, t1, tau, kc):
     """W_{m km n kn i ki j kj}: <mn||ij> + P(ij) t_j^c <mn||ic> + 1/4 tau_ij^ef <mn||ef>."""
     N = t1.shape[0]
@@ -143,13 +156,7 @@ def w_mnij(eris: Eris, t1, tau, kc):
     for km in range(N):
         for kn in range(N):
             for ki in range(N):
-                kj = kc[km, kn, ki]
-                w = eris.block("oooo", km, kn, ki).copy()
-                w += _con("jc,mnic->mnij", t1[kj], eris.block("ooov", km, kn, ki))
-                w -= _con("ic,mnjc->mnij", t1[ki], eris.block("ooov", km, kn, kj))
-                for ke in range(N):
-                    w += 0.25 * _con("ijef,mnef->mnij", tau[ki, kj, ke], eris.block("oovv", km, kn, ke))
-                W[km, kn, ki] = w
+                W[km, kn, ki] = w_mnij_block(eris, t1, tau, kc, km, kn, ki)
     return W
 
 
@@ -166,39 +173,81 @@ def w_abef_block(eris: Eris, t1, tau, kc, ka, kb, ke):
     return w
 
 
-def w_mbej(eris: Eris, t1, t2, kc):
-    """Ring intermediate, printed as W_{j kj n kn}^{b kb f kf}; stored here as
-    Wr[km][kb][ke](m,b,e,j) = W_{j n}^{b f} with n -> m, f -> e (k_j fixed by conservation):
+def w_mbej_block(eris: Eris, t1, t2, kc, km, kb, ke):
+    """One block Wr[km][kb][ke](m,b,e,j) of the ring intermediate (k_j by conservation),
+    printed as W_{j kj n kn}^{b kb f kf} with n -> m, f -> e:
       <mb||ej> + t_j^f <mb||ef> - t_n^b <mn||ej> - 1/2 t_{jn}^{fb} <mn||ef> - t_j^f t_n^b <mn||ef>
     with n of the third term at k_b."""
+    N = t1.shape[0]
+    kj = kc[km, kb, ke]
+    w = eris.block("ovvo", km, kb, ke).copy()
+    w += _con("jf,mbef->mbej", t1[kj], eris.block("ovvv", km, kb, ke))
+    w -= _con("nb,mnej->mbej", t1[kb], eris.block("oovo", km, kb, ke))
+    w -= _con("jf,nb,mnef->mbej", t1[kj], t1[kb], eris.block("oovv", km, kb, ke))
+    for kn in range(N):
+        kf = kc[kj, kn, kb]
+        w -= 0.5 * _con("jnfb,mnef->mbej", t2[kj, kn, kf], eris.block("oovv", km, kn, ke))
+    return w
+
+
+def w_mbej(eris: Eris, t1, t2, kc):
+    """Ring intermediate for every block: Wr[km][kb][ke](m,b,e,j) (see w_mbej_block)."""
     N, no, nv = t1.shape
     W = np.zeros((N, N, N, no, nv, nv, no), dtype=np.complex128)
     for km in range(N):
         for kb in range(N):
             for ke in range(N):
-                kj = kc[km, kb, ke]
-                w = eris.block("ovvo", km, kb, ke).copy()
-                w += _con("jf,mbef->mbej", t1[kj], eris.block("ovvv", km, kb, ke))
-                w -= _con("nb,mnej->mbej", t1[kb], eris.block("oovo", km, kb, ke))
-                w -= _con("jf,nb,mnef->mbej", t1[kj], t1[kb], eris.block("oovv", km, kb, ke))
-                for kn in range(N):
-                    kf = kc[kj, kn, kb]
-                    w -= 0.5 * _con("jnfb,mnef->mbej", t2[kj, kn, kf], eris.block("oovv", km, kn, ke))
-                W[km, kb, ke] = w
+                W[km, kb, ke] = w_mbej_block(eris, t1, t2, kc, km, kb, ke)
     return W
 
 
-# --------------------------------------------------------------------------------------
-# Residuals (eqs. ori_EqSingle and ori_EqDouble); R = 0 at the solution
-# --------------------------------------------------------------------------------------
-def residual(f, classes: dict, t1, t2, kc):
-    """Return (R1, R2): the right-hand sides of the T1 and T2 equations of Sec. 2."""
-    N, no, nv = t1.shape
-    eris = Eris(classes, kc)
-    Foo, Fvv, Fov = f_intermediates(f, eris, t1, t2, kc, no)
-    tau = make_tau(t1, t2, kc, 0.5)
+def ring_x_block(eris: Eris, t1, t2, kc, wr, ki, kj, ka):
+    """Ring quantity X_{i ki j kj}^{a ka b kb} before P(ab)P(ij):
+    sum_n t_{i n}^{a f} W_{j n}^{b f} - t_i^c t_r^a <r b||c j>; wr(kn, kb, kf) returns a
+    block of the ring intermediate."""
+    N = t1.shape[0]
+    kb = kc[ki, kj, ka]
+    x = -_con("ic,ra,rbcj->ijab", t1[ki], t1[ka], eris.block("ovvo", ka, kb, ki))
+    for kn in range(N):
+        kf = kc[ki, kn, ka]
+        # t_{i ki n kn}^{a ka f kf} W_{j kj n kn}^{b kb f kf}
+        x = x + _con("inaf,nbfj->ijab", t2[ki, kn, ka], wr(kn, kb, kf))
+    return x
 
-    # ---------------- T1 equation ----------------
+
+def r2_block_nonladder(eris: Eris, t1, t2, tau, Fvt, Fot, kc, wmn, x, ki, kj, ka):
+    """Every term of the T2 equation for block (ki, kj, ka) except the particle-particle
+    ladder: the driver, the F terms, 1/2 tau W_mnij, P(ab)P(ij) of the ring quantity and the
+    two single-amplitude integral terms.  wmn(km, kn, ki) and x(ki, kj, ka) return blocks of
+    W_mnij and of the ring quantity."""
+    N = t1.shape[0]
+    kb = kc[ki, kj, ka]
+    r = np.conj(eris.block("oovv", ki, kj, ka))  # <ab||ij> = conj(<ij||ab>)
+    # P(ab) t_ij^{af} Fvt(b,f), f at kb
+    r = r + _con("ijaf,bf->ijab", t2[ki, kj, ka], Fvt[kb])
+    r = r - _con("ijbf,af->ijab", t2[ki, kj, kb], Fvt[ka])
+    # -P(ij) t_in^{ab} Fot(n,j), n at kj
+    r = r - _con("inab,nj->ijab", t2[ki, kj, ka], Fot[kj])
+    r = r + _con("jnab,ni->ijab", t2[kj, ki, ka], Fot[ki])
+    # 1/2 tau_mn^ab W_mnij
+    for km in range(N):
+        kn = kc[ki, kj, km]
+        r = r + 0.5 * _con("mnab,mnij->ijab", tau[km, kn, ka], wmn(km, kn, ki))
+    # P(ab)P(ij) ring
+    r = r + x(ki, kj, ka) - x(kj, ki, ka).transpose(1, 0, 2, 3)
+    r = r - x(ki, kj, kb).transpose(0, 1, 3, 2) + x(kj, ki, kb).transpose(1, 0, 3, 2)
+    # P(ij) <a ka b kb || c ki j kj> t_{i ki}^{c ki}
+    r = r + _con("abcj,ic->ijab", eris.block("vvvo", ka, kb, ki), t1[ki])
+    r = r - _con("abci,jc->ijab", eris.block("vvvo", ka, kb, kj), t1[kj])
+    # -P(ab) t_{r ka}^{a ka} <r ka b kb || i ki j kj>
+    r = r - _con("ra,rbij->ijab", t1[ka], eris.block("ovoo", ka, kb, ki))
+    r = r + _con("rb,raij->ijab", t1[kb], eris.block("ovoo", kb, ka, ki))
+    return r
+
+
+def t1_residual(f, eris: Eris, t1, t2, Foo, Fvv, Fov):
+    """R1: the right-hand side of the T1 equation (eq. ori_EqSingle)."""
+    N, no, nv = t1.shape
     R1 = np.zeros_like(t1)
     for k in range(N):
         r = np.conj(f[k, :no, no:])  # f_ai = conj(f_ia)
@@ -214,11 +263,32 @@ def residual(f, classes: dict, t1, t2, kc):
                 # +1/2 t_{i k, n kn}^{e km, f kf} <a k, n kn || e km, f kf>
                 r = r + 0.5 * _con("inef,anef->ia", t2[k, kn, km], eris.block("vovv", k, kn, km))
         R1[k] = r
+    return R1
 
-    # ---------------- T2 equation ----------------
-    # Fvt(b,f) = F^{bf} - 1/2 t_r^b F_r^f ;  Fot(n,j) = F_nj + 1/2 t_j^c F_n^c   (both at one k)
+
+def _f_tilde(t1, Foo, Fvv, Fov):
+    """Fvt(b,f) = F^{bf} - 1/2 t_r^b F_r^f and Fot(n,j) = F_nj + 1/2 t_j^c F_n^c (one k)."""
+    N = t1.shape[0]
     Fvt = np.stack([Fvv[k] - 0.5 * _con("rb,rf->bf", t1[k], Fov[k]) for k in range(N)])
     Fot = np.stack([Foo[k] + 0.5 * _con("jc,nc->nj", t1[k], Fov[k]) for k in range(N)])
+    return Fvt, Fot
+
+
+# --------------------------------------------------------------------------------------
+# Residuals (eqs. ori_EqSingle and ori_EqDouble); R = 0 at the solution
+# --------------------------------------------------------------------------------------
+def residual(f, classes: dict, t1, t2, kc):
+    """Return (R1, R2): the right-hand sides of the T1 and T2 equations of Sec. 2."""
+    N, no, nv = t1.shape
+    eris = Eris(classes, kc)
+    Foo, Fvv, Fov = f_intermediates(f, eris, t1, t2, kc, no)
+    tau = make_tau(t1, t2, kc, 0.5)
+
+    # ---------------- T1 equation ----------------
+    R1 = t1_residual(f, eris, t1, t2, Foo, Fvv, Fov)
+
+    # ---------------- T2 equation ----------------
+    Fvt, Fot = _f_tilde(t1, Foo, Fvv, Fov)
     Wmn = w_mnij(eris, t1, tau, kc)
     Wr = w_mbej(eris, t1, t2, kc)
 
@@ -227,40 +297,15 @@ def residual(f, classes: dict, t1, t2, kc):
     for ki in range(N):
         for kj in range(N):
             for ka in range(N):
-                kb = kc[ki, kj, ka]
-                x = -_con("ic,ra,rbcj->ijab", t1[ki], t1[ka], eris.block("ovvo", ka, kb, ki))
-                for kn in range(N):
-                    kf = kc[ki, kn, ka]
-                    # t_{i ki n kn}^{a ka f kf} W_{j kj n kn}^{b kb f kf}
-                    x = x + _con("inaf,nbfj->ijab", t2[ki, kn, ka], Wr[kn, kb, kf])
-                X[ki, kj, ka] = x
+                X[ki, kj, ka] = ring_x_block(eris, t1, t2, kc, lambda a, b, c: Wr[a, b, c], ki, kj, ka)
 
     R2 = np.zeros_like(t2)
     for ki in range(N):
         for kj in range(N):
             for ka in range(N):
-                kb = kc[ki, kj, ka]
-                r = np.conj(eris.block("oovv", ki, kj, ka))  # <ab||ij> = conj(<ij||ab>)
-                # P(ab) t_ij^{af} Fvt(b,f), f at kb
-                r = r + _con("ijaf,bf->ijab", t2[ki, kj, ka], Fvt[kb])
-                r = r - _con("ijbf,af->ijab", t2[ki, kj, kb], Fvt[ka])
-                # -P(ij) t_in^{ab} Fot(n,j), n at kj
-                r = r - _con("inab,nj->ijab", t2[ki, kj, ka], Fot[kj])
-                r = r + _con("jnab,ni->ijab", t2[kj, ki, ka], Fot[ki])
-                # 1/2 tau_mn^ab W_mnij
-                for km in range(N):
-                    kn = kc[ki, kj, km]
-                    r = r + 0.5 * _con("mnab,mnij->ijab", tau[km, kn, ka], Wmn[km, kn, ki])
-                # P(ab)P(ij) ring
-                r = r + X[ki, kj, ka] - X[kj, ki, ka].transpose(1, 0, 2, 3)
-                r = r - X[ki, kj, kb].transpose(0, 1, 3, 2) + X[kj, ki, kb].transpose(1, 0, 3, 2)
-                # P(ij) <a ka b kb || c ki j kj> t_{i ki}^{c ki}
-                r = r + _con("abcj,ic->ijab", eris.block("vvvo", ka, kb, ki), t1[ki])
-                r = r - _con("abci,jc->ijab", eris.block("vvvo", ka, kb, kj), t1[kj])
-                # -P(ab) t_{r ka}^{a ka} <r ka b kb || i ki j kj>
-                r = r - _con("ra,rbij->ijab", t1[ka], eris.block("ovoo", ka, kb, ki))
-                r = r + _con("rb,raij->ijab", t1[kb], eris.block("ovoo", kb, ka, ki))
-                R2[ki, kj, ka] = r
+                R2[ki, kj, ka] = r2_block_nonladder(eris, t1, t2, tau, Fvt, Fot, kc,
+                                                    lambda a, b, c: Wmn[a, b, c],
+                                                    lambda a, b, c: X[a, b, c], ki, kj, ka)
 
     # particle-particle ladder 1/2 W_abef tau_ij^ef: one W^{ab ef} block at a time
     for ka in range(N):
@@ -271,6 +316,70 @@ def residual(f, classes: dict, t1, t2, kc):
                     kj = kc[ka, kb, ki]
                     R2[ki, kj, ka] += 0.5 * _con("abef,ijef->ijab", W, tau[ki, kj, ke])
     return R1, R2
+
+
+class LazyClasses:
+    """Integral classes served block by block: ``provider(cls, kp, kq, kr)`` returns the
+    block [p][q][r][s] of a stored class; every block is kept once produced.  Lets the
+    block-restricted residual run where whole classes do not fit in host memory."""
+
+    def __init__(self, provider, stored=CLASSES):
+        self.provider = provider
+        self.stored = tuple(stored)
+        self.cache = {}
+
+    def __contains__(self, cls):
+        return cls in self.stored
+
+    def __getitem__(self, cls):
+        outer = self
+
+        class _View:
+            def __getitem__(self, key):
+                k = (cls,) + tuple(int(x) for x in key)
+                if k not in outer.cache:
+                    outer.cache[k] = outer.provider(cls, *k[1:])
+                return outer.cache[k]
+
+        return _View()
+
+
+def residual_blocks(f, classes, t1, t2, kc, blocks):
+    """R1 in full and R2 on the listed momentum blocks (ki, kj, ka) only, term by term as in
+    ``residual`` (same intermediates, same order of the sums), computing each intermediate
+    block only where a listed block needs it.  ``classes``: a dict of whole classes or a
+    ``LazyClasses``."""
+    N, no, nv = t1.shape
+    eris = Eris(classes, kc)
+    Foo, Fvv, Fov = f_intermediates(f, eris, t1, t2, kc, no)
+    tau = make_tau(t1, t2, kc, 0.5)
+    R1 = t1_residual(f, eris, t1, t2, Foo, Fvv, Fov)
+    Fvt, Fot = _f_tilde(t1, Foo, Fvv, Fov)
+    memo = {}
+
+    def cached(tag, fn, *key):
+        if (tag,) + key not in memo:
+            memo[(tag,) + key] = fn(*key)
+        return memo[(tag,) + key]
+
+    def wmn(km, kn, ki):
+        return cached("wmn", lambda a, b, c: w_mnij_block(eris, t1, tau, kc, a, b, c), km, kn, ki)
+
+    def wr(km, kb, ke):
+        return cached("wr", lambda a, b, c: w_mbej_block(eris, t1, t2, kc, a, b, c), km, kb, ke)
+
+    def x(ki, kj, ka):
+        return cached("x", lambda a, b, c: ring_x_block(eris, t1, t2, kc, wr, a, b, c), ki, kj, ka)
+
+    out = {}
+    for (ki, kj, ka) in blocks:
+        kb = kc[ki, kj, ka]
+        r = r2_block_nonladder(eris, t1, t2, tau, Fvt, Fot, kc, wmn, x, ki, kj, ka)
+        for ke in range(N):
+            W = cached("wabef", lambda a, b, c: w_abef_block(eris, t1, tau, kc, a, b, c), ka, kb, ke)
+            r += 0.5 * _con("abef,ijef->ijab", W, tau[ki, kj, ke])
+        out[(ki, kj, ka)] = r
+    return R1, out
 
 
 # --------------------------------------------------------------------------------------

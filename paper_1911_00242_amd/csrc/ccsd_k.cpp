@@ -10,6 +10,9 @@
 #include "../../include/ccsd_k.h"
 
 #include <algorithm>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -23,6 +26,10 @@
 namespace {
 
 thread_local std::string g_init_error;
+
+// Largest mesh a context plans: the host momentum table holds N_k^3 entries and the
+// contraction tables O(N_k^2 n^2) (N_k = 512: 0.5 GB for the table alone).
+constexpr int64_t CK_MAX_NK = 512;
 
 using ck::cd;
 
@@ -466,14 +473,24 @@ void carve(System &S, Carver &c) {
     c.take(S.redout, 32);
     c.take(S.dkc, N3);
     c.take(S.dtab, (int64_t)S.tables.size());
-    int m = S.desc.diis_space;
-    S.dvec.assign(m, nullptr);
-    S.derr.assign(S.mixed ? 0 : m, nullptr);
-    S.derr32.assign(S.mixed ? m : 0, nullptr);
+    // the DIIS history pointers are written only when assigning: a size query (assign
+    // false) on a bound context must leave them intact
+    const int m = S.desc.diis_space;
+    if (c.assign) {
+        S.dvec.assign(m, nullptr);
+        S.derr.assign(S.mixed ? 0 : m, nullptr);
+        S.derr32.assign(S.mixed ? m : 0, nullptr);
+    }
     for (int i = 0; i < m; ++i) {
-        c.take(S.dvec[i], S.n1() + S.n2());
-        if (S.mixed) c.take(S.derr32[i], S.n1() + S.n2());
-        else c.take(S.derr[i], S.n1() + S.n2());
+        cd *vec = nullptr, *err = nullptr;
+        ck::cf *err32 = nullptr;
+        c.take(vec, S.n1() + S.n2());
+        if (S.mixed) c.take(err32, S.n1() + S.n2());
+        else c.take(err, S.n1() + S.n2());
+        if (!c.assign) continue;
+        S.dvec[i] = vec;
+        if (S.mixed) S.derr32[i] = err32;
+        else S.derr[i] = err;
     }
 }
 
@@ -680,6 +697,14 @@ void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
 // every write of the amplitudes other than the mixed DIIS extrapolation
 void amplitudes_changed(System &S) { S.sp_ok = S.e_ok = false; }
 
+// a new trajectory (new inputs or amplitudes from the caller): empty DIIS history
+void reset_iteration(System &S) {
+    S.diis_n = 0;
+    S.diis_head = 0;
+    S.converged = false;
+    std::fill(S.B.begin(), S.B.end(), 0.0);
+}
+
 // ||R||^2 into S.redout[0] after residual_device (the mixed assembly left partial sums)
 void launch_norm(System &S, hipStream_t st) {
     if (S.mixed) ck::launch_norm_pack(S.d, S.pairs(), S.npart, S.r1(), S.redout, st);
@@ -751,14 +776,17 @@ bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &c) {
 
 }  // namespace
 
-// ====================================================================== C ABI
-extern "C" {
+// ====================================================================== ABI bodies
+namespace {
 
-int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out) {
+int impl_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out) {
     if (out) *out = nullptr;
     if (!sys || !out) return fail(nullptr, CCSD_K_EINVAL, "null argument");
     if (n_sys < 1 || n_sys > 4096) return fail(nullptr, CCSD_K_EINVAL, "n_sys must be in 1..4096");
-    auto *c = new ccsd_k_ctx();
+    // owned here until the plan is complete: a failure below (an invalid system, or a host
+    // allocation of the tables) frees it
+    std::unique_ptr<ccsd_k_ctx> holder(new ccsd_k_ctx());
+    ccsd_k_ctx *c = holder.get();
     c->stream = (hipStream_t)hip_stream;
     c->sys.resize(n_sys);
     for (int s = 0; s < n_sys; ++s) {
@@ -766,25 +794,20 @@ int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_
         System &S = c->sys[s];
         S.desc = d;
         std::string id = "system " + std::to_string(s) + ": ";
-        if (d.grid[0] < 1 || d.grid[1] < 1 || d.grid[2] < 1 || (int64_t)d.grid[0] * d.grid[1] * d.grid[2] > 4096) {
-            delete c;
-            return fail(nullptr, CCSD_K_EINVAL, id + "grid entries must be >= 1 with N_k <= 4096");
+        if (d.grid[0] < 1 || d.grid[1] < 1 || d.grid[2] < 1 || (int64_t)d.grid[0] * d.grid[1] * d.grid[2] > CK_MAX_NK) {
+            return fail(nullptr, CCSD_K_EINVAL, id + "grid entries must be >= 1 with N_k <= " + std::to_string(CK_MAX_NK));
         }
         if (d.n_occ < 1 || d.n_vir < 1 || d.n_occ > 256 || d.n_vir > 256) {
-            delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "n_occ and n_vir must be in 1..256");
         }
         if (d.precision != CCSD_K_PREC_FP64 && d.precision != CCSD_K_PREC_MIXED) {
-            delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "unsupported precision");
         }
         S.mixed = d.precision == CCSD_K_PREC_MIXED;
         if (d.diis_space != 0 && (d.diis_space < 2 || d.diis_space > 16)) {
-            delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "diis_space must be 0 or 2..16");
         }
         if (d.synthetic && !(d.eri_scale > 0.0 && std::isfinite(d.eri_scale))) {
-            delete c;
             return fail(nullptr, CCSD_K_EINVAL, id + "eri_scale must be positive");
         }
         S.mesh = ck::Mesh{d.grid[0], d.grid[1], d.grid[2], d.grid[0] * d.grid[1] * d.grid[2]};
@@ -797,11 +820,11 @@ int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_
         build_tables(S);
         S.B.assign((size_t)d.diis_space * d.diis_space, 0.0);
     }
-    *out = c;
+    *out = holder.release();
     return CCSD_K_OK;
 }
 
-int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
+int impl_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
     if (!ctx || !bytes) return CCSD_K_EINVAL;
     Carver cv{0, 0, false};
     for (auto &S : const_cast<ccsd_k_ctx *>(ctx)->sys) carve(S, cv);
@@ -809,7 +832,7 @@ int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
     return CCSD_K_OK;
 }
 
-int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
+int impl_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
     int rc = check_ctx(ctx, false);
     if (rc) return rc;
     if (ctx->bound) return fail(ctx, CCSD_K_ESTATE, "workspace already bound");
@@ -862,7 +885,7 @@ int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
     return CCSD_K_OK;
 }
 
-int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]) {
+int impl_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]) {
     int rc = check_sys(ctx, sys, false);
     if (rc) return rc;
     if (!fock || !eri) return fail(ctx, CCSD_K_EINVAL, "null input");
@@ -871,14 +894,44 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
     System &S = ctx->sys[sys];
     const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, n = o + v, N3 = N * N * N;
     const int64_t cls[6] = {o * o * o * o, o * o * o * v, o * o * v * v, o * v * v * o, o * v * v * v, v * v * v * v};
-    // denominators need f_ii != f_aa for every pair (Sec. 4.4 divides by D)
-    for (int64_t k = 0; k < N; ++k)
-        for (int64_t i = 0; i < o; ++i)
-            for (int64_t a = 0; a < v; ++a) {
-                double fi = fock[2 * ((k * n + i) * n + i)], fa = fock[2 * ((k * n + o + a) * n + o + a)];
-                if (!(std::isfinite(fi) && std::isfinite(fa)) || fi == fa)
-                    return fail(ctx, CCSD_K_EINVAL, "orbital energies give a zero or non-finite denominator");
-            }
+    // The update of Sec. 4.4 divides by D_i^a = f_ii - f_aa (same k) and by
+    // D_ij^ab = f_ii + f_jj - f_aa - f_bb over every momentum-conserving block: all of them
+    // must be finite and nonzero.  When every occupied energy lies below every virtual one
+    // (the usual case) all denominators are negative; otherwise each is checked.
+    std::vector<double> eo(N * o), ev(N * v);
+    double omax = -INFINITY, vmin = INFINITY;
+    for (int64_t k = 0; k < N; ++k) {
+        for (int64_t i = 0; i < o; ++i) eo[k * o + i] = fock[2 * ((k * n + i) * n + i)];
+        for (int64_t a = 0; a < v; ++a) ev[k * v + a] = fock[2 * ((k * n + o + a) * n + o + a)];
+    }
+    for (double e : eo) {
+        if (!std::isfinite(e)) return fail(ctx, CCSD_K_EINVAL, "non-finite orbital energy");
+        omax = std::max(omax, e);
+    }
+    for (double e : ev) {
+        if (!std::isfinite(e)) return fail(ctx, CCSD_K_EINVAL, "non-finite orbital energy");
+        vmin = std::min(vmin, e);
+    }
+    if (!(omax < vmin)) {
+        for (int64_t k = 0; k < N; ++k)
+            for (int64_t i = 0; i < o; ++i)
+                for (int64_t a = 0; a < v; ++a)
+                    if (eo[k * o + i] - ev[k * v + a] == 0.0)
+                        return fail(ctx, CCSD_K_EINVAL, "orbital energies give a zero T1 denominator");
+        for (int64_t ki = 0; ki < N; ++ki)
+            for (int64_t kj = 0; kj < N; ++kj)
+                for (int64_t ka = 0; ka < N; ++ka) {
+                    const int64_t kb = S.kc[(ki * N + kj) * N + ka];
+                    for (int64_t i = 0; i < o; ++i)
+                        for (int64_t j = 0; j < o; ++j)
+                            for (int64_t a = 0; a < v; ++a)
+                                for (int64_t b = 0; b < v; ++b) {
+                                    const double D = eo[ki * o + i] + eo[kj * o + j] - ev[ka * v + a] - ev[kb * v + b];
+                                    if (D == 0.0 || !std::isfinite(D))
+                                        return fail(ctx, CCSD_K_EINVAL, "orbital energies give a zero T2 denominator");
+                                }
+                }
+    }
     try {
         CK_CHECK(hipMemcpyAsync(S.fock, fock, N * n * n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         for (int i = 0; i < 6; ++i)
@@ -892,17 +945,21 @@ int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const do
         return fail(ctx, CCSD_K_EDEVICE, e.what);
     }
     S.inputs = true;
+    reset_iteration(S);  // a DIIS history of another Hamiltonian would mislead the next iterate
     return CCSD_K_OK;
 }
 
-int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1, double *r2) {
+int impl_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1, double *r2) {
     int rc = check_sys(ctx, sys);
     if (rc) return rc;
     System &S = ctx->sys[sys];
     try {
         if (t1) CK_CHECK(hipMemcpyAsync(S.t1(), t1, S.n1() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         if (t2) CK_CHECK(hipMemcpyAsync(S.t2(), t2, S.n2() * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
-        if (t1 || t2) amplitudes_changed(S);
+        if (t1 || t2) {
+            amplitudes_changed(S);
+            reset_iteration(S);  // the caller's amplitudes start a new trajectory
+        }
         residual_device(ctx, S, ctx->stream);
         launch_norm(S, ctx->stream);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
@@ -927,7 +984,7 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
     return CCSD_K_OK;
 }
 
-int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm) {
+int impl_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (max_iter < 0 || !(tol >= 0.0)) return fail(ctx, CCSD_K_EINVAL, "bad max_iter or tol");
@@ -1043,7 +1100,7 @@ int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters
     return all ? CCSD_K_OK : CCSD_K_NOT_CONVERGED;
 }
 
-int ccsd_k_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm) {
+int impl_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm) {
     int rc = check_sys(ctx, sys, false);
     if (rc) return rc;
     if (!rnorm) return CCSD_K_EINVAL;
@@ -1051,7 +1108,7 @@ int ccsd_k_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm) {
     return CCSD_K_OK;
 }
 
-int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
+int impl_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
     int rc = check_sys(ctx, sys);
     if (rc) return rc;
     System &S = ctx->sys[sys];
@@ -1070,7 +1127,7 @@ int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
     return CCSD_K_OK;
 }
 
-int ccsd_k_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2) {
+int impl_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2) {
     int rc = check_sys(ctx, sys, false);
     if (rc) return rc;
     System &S = ctx->sys[sys];
@@ -1084,7 +1141,7 @@ int ccsd_k_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2) 
     return CCSD_K_OK;
 }
 
-int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2) {
+int impl_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2) {
     int rc = check_sys(ctx, sys, false);
     if (rc) return rc;
     System &S = ctx->sys[sys];
@@ -1096,13 +1153,11 @@ int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const 
     } catch (const ck::HipError &e) {
         return fail(ctx, CCSD_K_EDEVICE, e.what);
     }
-    S.diis_n = 0;
-    S.diis_head = 0;
-    S.converged = false;
+    reset_iteration(S);
     return CCSD_K_OK;
 }
 
-int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops) {
+int impl_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops) {
     if (!ctx || sys < 0 || sys >= (int32_t)ctx->sys.size()) return CCSD_K_EINVAL;
     const ck::Dims &d = ctx->sys[sys].d;
     double N = d.N, o = d.no, v = d.nv;
@@ -1121,7 +1176,7 @@ int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double 
     return CCSD_K_OK;
 }
 
-int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
+int impl_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
                          int64_t *K) {
     if (!ctx || sys < 0 || sys >= (int32_t)ctx->sys.size() || product < 0 || product > 4) return CCSD_K_EINVAL;
     const System &S = ctx->sys[sys];
@@ -1143,7 +1198,7 @@ int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, in
     return CCSD_K_OK;
 }
 
-int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
+int impl_timing(ccsd_k_ctx *ctx, int32_t enable) {
     if (!ctx) return CCSD_K_EINVAL;
     try {
         collect_timing(ctx);
@@ -1158,7 +1213,7 @@ int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
     return CCSD_K_OK;
 }
 
-int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches) {
+int impl_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches) {
     if (!ctx || stage < 0 || stage >= ST_COUNT) return CCSD_K_EINVAL;
     try {
         collect_timing(ctx);
@@ -1170,7 +1225,7 @@ int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t 
     return CCSD_K_OK;
 }
 
-int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
+int impl_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
                        int32_t reference) {
     if (G < 1 || M < 1 || N < 1 || K < 0 || !A || !B || !C) return fail(nullptr, CCSD_K_EINVAL, "bad gemm arguments");
     std::vector<int64_t> tab;
@@ -1247,6 +1302,91 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
     return rc;
 }
 
+
+// Every ABI entry runs inside this guard: no C++ exception crosses the C ABI.  Device
+// errors surface as ck::HipError (EDEVICE), host allocation failures as std::bad_alloc.
+template <class F>
+int guarded(ccsd_k_ctx *c, F &&f) {
+    try {
+        return f();
+    } catch (const ck::HipError &e) {
+        return fail(c, CCSD_K_EDEVICE, e.what);
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCSD_K_ENOMEM, "host memory allocation failed");
+    } catch (const std::exception &e) {
+        return fail(c, CCSD_K_EINVAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(c, CCSD_K_EINVAL, "unknown internal error");
+    }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int ccsd_k_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_ctx **out) {
+    return guarded(nullptr, [&] { return impl_init(sys, n_sys, hip_stream, out); });
+}
+
+int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
+    return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_workspace_bytes(ctx, bytes); });
+}
+
+int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
+    return guarded(ctx, [&] { return impl_bind_workspace(ctx, device_ptr, bytes); });
+}
+
+int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]) {
+    return guarded(ctx, [&] { return impl_set_inputs(ctx, sys, fock, eri); });
+}
+
+int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2, double *r1, double *r2) {
+    return guarded(ctx, [&] { return impl_residual(ctx, sys, t1, t2, r1, r2); });
+}
+
+int ccsd_k_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm) {
+    return guarded(ctx, [&] { return impl_iterate(ctx, max_iter, tol, iters, max_rnorm); });
+}
+
+int ccsd_k_residual_norm(ccsd_k_ctx *ctx, int32_t sys, double *rnorm) {
+    return guarded(ctx, [&] { return impl_residual_norm(ctx, sys, rnorm); });
+}
+
+int ccsd_k_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
+    return guarded(ctx, [&] { return impl_energy(ctx, sys, e_re, e_im); });
+}
+
+int ccsd_k_get_amplitudes(ccsd_k_ctx *ctx, int32_t sys, double *t1, double *t2) {
+    return guarded(ctx, [&] { return impl_get_amplitudes(ctx, sys, t1, t2); });
+}
+
+int ccsd_k_set_amplitudes(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *t2) {
+    return guarded(ctx, [&] { return impl_set_amplitudes(ctx, sys, t1, t2); });
+}
+
+int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *other_flops) {
+    return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_flops(ctx, sys, gemm_flops, other_flops); });
+}
+
+int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
+                         int64_t *K) {
+    return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_product_shape(ctx, sys, product, G, M, N, K); });
+}
+
+int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
+    return guarded(ctx, [&] { return impl_timing(ctx, enable); });
+}
+
+int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches) {
+    return guarded(ctx, [&] { return impl_timing_get(ctx, stage, total_ms, launches); });
+}
+
+int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
+                       int32_t reference) {
+    return guarded(nullptr, [&] { return impl_debug_zgemm(G, M, N, K, A, B, C, reference); });
+}
+
 void ccsd_k_free(ccsd_k_ctx *ctx) {
     if (!ctx) return;
     if (!ctx->failed) {
@@ -1258,10 +1398,16 @@ void ccsd_k_free(ccsd_k_ctx *ctx) {
         }
         for (hipStream_t st : ctx->lanes) (void)hipStreamSynchronize(st);
     }
-    if (!ctx->failed) {
-        for (hipStream_t st : ctx->lanes) (void)hipStreamDestroy(st);
-        for (hipEvent_t ev : ctx->joins) (void)hipEventDestroy(ev);
-        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    // after a device error the handles are still released (best effort, errors ignored)
+    for (hipStream_t st : ctx->lanes) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : ctx->joins) (void)hipEventDestroy(ev);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->failed) {
+        for (auto &p : ctx->pending) ctx->pool.push_back(p);
+        for (auto &p : ctx->pool) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
     }
     delete ctx;
 }

@@ -47,11 +47,13 @@ def test_mixed_residual_close_to_oracle(grid, no, nv):
     with ck.Context([dict(grid=grid, no=no, nv=nv, precision=ck.PREC_MIXED)]) as c:
         c.set_inputs(0, f, eris)
         g1, g2 = c.residual(0, t1, t2)
-    # relative to the largest residual element; every product term is O(|R|) here
+    # relative to the largest residual element; every product term is O(|R|) here.  A split
+    # product is exact to about 3 * 2^-17 of |x||y| per term and the terms largely cancel
+    # in sign, so the residual error sits near 1e-7 of max|R| (observed 5e-8 to 3e-7)
     e2 = np.abs(g2 - R2).max() / np.abs(R2).max()
     e1 = np.abs(g1 - R1).max() / np.abs(R1).max()
     print(f"  max rel err R2 {e2:.2e} R1 {e1:.2e}")
-    assert e2 <= 2e-4 and e1 <= 1e-12 * 0 + 2e-4
+    assert e2 <= 1e-5 and e1 <= 1e-5
     assert e2 > 0  # the bf16 path really ran
 
 
@@ -75,7 +77,8 @@ def test_mixed_converged_energy_matches_fp64(grid, no, nv):
     de = abs(out[ck.PREC_MIXED][1] - ref["energy"])
     dt2 = np.abs(out[ck.PREC_MIXED][2] - ref["t2"]).max()
     print(f"mixed: |dE| = {de:.3e} Eh, max|dT2| = {dt2:.3e}, E = {ref['energy']}")
-    assert de <= 1e-6 * abs(ref["energy"])
+    assert de <= 1e-8  # the bar on converged mixed-precision energies, absolute
+    assert dt2 <= 1e-6
 
 
 @pytest.mark.parametrize("grid,no,nv", [((2, 2, 1), 3, 5), ((2, 1, 1), 8, 16)])

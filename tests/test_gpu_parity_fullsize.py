@@ -24,6 +24,7 @@ pytestmark = pytest.mark.gpu
 GRID, NO, NV, SEED = (3, 3, 3), 8, 16, 303
 N = 27
 SCALE = 0.05 / N
+TSEED, TSCALE = 4242, 0.01  # seeded test amplitudes (t1 != 0)
 # sampled momentum blocks (ki, kj, ka): corners, the middle, ki = ka and ki = kj cases
 BLOCKS = [(0, 0, 0), (1, 2, 3), (26, 25, 24), (5, 9, 5), (13, 13, 13), (7, 20, 11), (4, 4, 17)]
 
@@ -58,6 +59,15 @@ def runs():
         out["e"] = c.energy(0)
         out["r1"], out["r2"] = c.residual(0)
         _log("FP64 path: one update, energy and residual done")
+        # seeded amplitudes with t1 != 0 (the synthetic f_ov is zero, so the iteration keeps
+        # t1 = 0 and the T1 terms would multiply zeros)
+        ta1, ta2 = synth.test_amplitudes(TSEED, GRID, NO, NV, scale=TSCALE)
+        g1, g2 = c.residual(0, ta1, ta2)
+        out["r1_t"], out["r2_t"] = g1, {b: g2[b].copy() for b in BLOCKS}
+        out["r2_t_asym"] = _asym(g2)
+        del g2
+        out["e_t"] = c.energy(0)
+        _log("FP64 path: residual and energy at seeded amplitudes with t1 != 0 done")
     torch.cuda.empty_cache()
     _log("mixed path: workspace and device-generated inputs")
     with ck.Context([_desc(ck.PREC_MIXED)], device="cuda:0") as c:
@@ -65,8 +75,49 @@ def runs():
         out["e_mixed"] = c.energy(0)
         out["r1_mixed"], out["r2_mixed"] = c.residual(0)
         _log("mixed path: energy and residual at the same amplitudes done")
+        g1, g2 = c.residual(0, ta1, ta2)
+        out["r1_t_mixed"], out["r2_t_mixed"] = g1, {b: g2[b].copy() for b in BLOCKS}
+        del g2
+        out["e_t_mixed"] = c.energy(0)
+        _log("mixed path: residual and energy at the seeded amplitudes done")
     torch.cuda.empty_cache()
+    out["ta1"], out["ta2"] = ta1, ta2
     return out
+
+
+def _asym(r2):
+    """Largest violation of R(ij,ab) = -R(ji,ab) = -R(ij,ba) over the sampled blocks,
+    relative to max|R2| there."""
+    kc = O.kconserv(GRID)
+    worst, scale = 0.0, max(np.abs(r2[b]).max() for b in BLOCKS)
+    for (ki, kj, ka) in BLOCKS:
+        kb = kc[ki, kj, ka]
+        x = r2[ki, kj, ka]
+        worst = max(worst, np.abs(x + r2[kj, ki, ka].transpose(1, 0, 2, 3)).max(),
+                    np.abs(x + r2[ki, kj, kb].transpose(0, 1, 3, 2)).max())
+    return worst / scale
+
+
+@pytest.fixture(scope="module")
+def oracle_t(runs):
+    """The block-restricted oracle at the seeded amplitudes: R1 in full, R2 on the sampled
+    blocks, and the energy; <oo||vv> as a whole class, every other class block by block."""
+    _log("host: generating the <oo||vv> class (5.2 GB) and the Fock matrix")
+    oovv = synth.eri_class(SEED, GRID, NO, NV, "oovv", scale=SCALE)
+    f = synth.fock(SEED, GRID, NO, NV)
+    kc = O.kconserv(GRID)
+
+    def provider(cls, kp, kq, kr):
+        if cls == "oovv":
+            return oovv[kp, kq, kr]
+        return synth.eri_block(SEED, GRID, NO, NV, cls, kp, kq, kr, scale=SCALE)
+
+    lazy = O.LazyClasses(provider)
+    _log("oracle: R1 and the sampled R2 blocks at the seeded amplitudes")
+    R1, R2b = O.residual_blocks(f, lazy, runs["ta1"], runs["ta2"], kc, BLOCKS)
+    _log("oracle: energy at the seeded amplitudes")
+    e = O.energy(f, {"oovv": oovv}, runs["ta1"], runs["ta2"], kc)
+    return dict(R1=R1, R2=R2b, e=e)
 
 
 def _oovv(ki, kj, ka):
@@ -122,7 +173,34 @@ def test_residual_antisymmetric(runs):
 
 def test_mixed_within_error_model_of_fp64(runs):
     """Same amplitudes on both paths: the mixed residual within the bar of its parity tests
-    against the oracle (2e-4 of max|R|), the energy within 1e-8 Eh."""
-    assert _rel(runs["r2_mixed"], runs["r2"]) <= 2e-4
-    assert _rel(runs["r1_mixed"], runs["r1"]) <= 2e-4
+    against the oracle (1e-5 of max|R|), the energy within 1e-8 Eh."""
+    assert _rel(runs["r2_mixed"], runs["r2"]) <= 1e-5
+    assert _rel(runs["r1_mixed"], runs["r1"]) <= 1e-5
     assert abs(runs["e_mixed"] - runs["e"]) <= 1e-8
+
+
+def test_fp64_residual_at_t1_matches_oracle(runs, oracle_t):
+    """Element by element at the full size with t1 != 0: R1 in full and the sampled R2
+    blocks against the block-restricted oracle (every T1 path of the residual: the T1
+    dressing of <ab||ef>, the t1 parts of the W seeds, tau's t1 t1 products, the F terms)."""
+    ref = np.stack([oracle_t["R2"][b] for b in BLOCKS])
+    got = np.stack([runs["r2_t"][b] for b in BLOCKS])
+    assert _rel(got, ref) <= 1e-12
+    assert _rel(runs["r1_t"], oracle_t["R1"]) <= 1e-12
+    assert runs["r2_t_asym"] <= 1e-12
+
+
+def test_energy_at_t1_matches_oracle(runs, oracle_t):
+    """The energy with its t1 t1 term at the seeded amplitudes."""
+    assert abs(runs["e_t"] - oracle_t["e"]) <= 1e-12 * abs(oracle_t["e"])
+
+
+def test_mixed_residual_at_t1_matches_oracle(runs, oracle_t):
+    """The mixed path at the seeded amplitudes, element by element within 1e-5 of max|R|
+    (its t1-polynomial terms pass through the packed tau, the packed dressing and the
+    packed assembly), the energy within 1e-8 Eh."""
+    ref = np.stack([oracle_t["R2"][b] for b in BLOCKS])
+    got = np.stack([runs["r2_t_mixed"][b] for b in BLOCKS])
+    assert _rel(got, ref) <= 1e-5
+    assert _rel(runs["r1_t_mixed"], oracle_t["R1"]) <= 1e-5
+    assert abs(runs["e_t_mixed"] - oracle_t["e"]) <= 1e-8

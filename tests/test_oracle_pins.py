@@ -312,3 +312,63 @@ def test_energy_invariant_under_orbital_rotation(grid, no, nv):
     assert a["converged"] and b["converged"]
     assert abs(fr[0] - f[0]).max() > 1e-3  # the rotation really changed the Fock matrix
     assert abs(a["energy"] - b["energy"]) <= 1e-10 * max(1.0, abs(a["energy"]))
+
+
+# ------------------------------------------------------------------ norm and DIIS pins
+def test_residual_norm_closed_form():
+    """The convergence norm (the 2-norm over every stored element of R1 and R2) on a case
+    with a known answer: |3+4i| = 5 in R1 and 12 in R2 give sqrt(25 + 144) = 13.  Dropping
+    either part, or taking real parts instead of moduli, gives 12, 5 or sqrt(153)."""
+    R1 = np.zeros((2, 1, 2), np.complex128)
+    R2 = np.zeros((2, 2, 2, 1, 1, 2, 2), np.complex128)
+    R1[1, 0, 1] = 3 + 4j
+    R2[0, 1, 1, 0, 0, 1, 0] = -12j
+    assert O.residual_norm(R1, R2) == 13.0
+    assert O.residual_norm(np.zeros_like(R1), np.zeros_like(R2)) == 0.0
+
+
+def test_diis_hand_solved_two_vector_extrapolation():
+    """Pulay DIIS with two held vectors minimizes |c1 e1 + c2 e2| under c1 + c2 = 1, whose
+    solution is c1 = (<e2,e2> - <e1,e2>) / (<e1,e1> - 2<e1,e2> + <e2,e2>) with the real
+    part of the Hermitian overlap.  e1 = (1, i), e2 = (-1, 2 + 2i): <e1,e1> = 2, <e2,e2> = 9,
+    Re<e1,e2> = -1 + 2 = 1, so c1 = 8/9, c2 = 1/9.  A mis-signed overlap (-1) would give
+    c1 = 10/13; an unconjugated product (Re(i (2+2i)) = -2, so -3) gives c1 = 12/17."""
+    d = O.Diis(6)
+    v1 = np.array([1.0 + 0j, 0.0, 5.0])
+    v2 = np.array([0.0 + 0j, 3.0, -1.0])
+    e1 = np.array([1.0 + 0j, 1j])
+    e2 = np.array([-1.0 + 0j, 2 + 2j])
+    out1 = d.update(v1, e1)
+    assert np.array_equal(out1, v1)  # one held vector: no extrapolation
+    out2 = d.update(v2, e2)
+    c1, c2 = 8 / 9, 1 / 9
+    assert np.allclose(out2, c1 * v1 + c2 * v2, rtol=0, atol=1e-15)
+
+
+def test_diis_fifo_drops_the_oldest_vector():
+    """With a depth of 2 the third update extrapolates from the second and third vectors
+    only: orthogonal errors of norms 2 and 1 give c = (1/5, 4/5)."""
+    d = O.Diis(2)
+    vs = [np.array([1.0 + 0j, 2.0]), np.array([3.0 + 0j, -1.0]), np.array([-2.0 + 0j, 4.0])]
+    es = [np.array([1.0 + 0j, 0.0]), np.array([2.0 + 0j, 0.0]), np.array([0.0 + 0j, 1.0])]
+    for v, e in zip(vs[:2], es[:2]):
+        d.update(v, e)
+    out = d.update(vs[2], es[2])
+    assert np.allclose(out, 0.2 * vs[1] + 0.8 * vs[2], rtol=0, atol=1e-15)
+
+
+def test_block_restricted_residual_equals_full():
+    """The block-restricted oracle (R2 on chosen momentum blocks, integrals served block by
+    block) equals the full oracle, which the brute force pins, on a 3x3x1 mesh (k != -k
+    along two axes) at amplitudes with t1 != 0."""
+    grid, no, nv = (3, 3, 1), 2, 3
+    kc = O.kconserv(grid)
+    f, eris = synth.system(808, grid, no, nv, scale=0.1)
+    t1, t2 = synth.test_amplitudes(809, grid, no, nv, scale=0.2)
+    R1, R2 = O.residual(f, eris, t1, t2, kc)
+    lazy = O.LazyClasses(lambda cls, kp, kq, kr: synth.eri_block(808, grid, no, nv, cls, kp, kq, kr, scale=0.1))
+    blocks = [(0, 0, 0), (1, 2, 3), (8, 7, 5), (4, 4, 4), (2, 6, 2)]
+    B1, B2 = O.residual_blocks(f, lazy, t1, t2, kc, blocks)
+    assert np.abs(B1 - R1).max() <= 1e-15 * np.abs(R1).max()
+    for b in blocks:
+        assert np.abs(B2[b] - R2[b]).max() <= 1e-15 * np.abs(R2).max(), b
