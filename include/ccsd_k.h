@@ -158,6 +158,23 @@ int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t 
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
                        double *C, int32_t reference);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the product of ccsd_k_debug_zgemm,
+ * C[g] = A[g] . B[g]^T, on caller-owned DEVICE arrays (complex128, dense row-major:
+ * A [G][M][K], B [G][N][K], C [G][M][N]), enqueued on hip_stream (NULL: the default
+ * stream) without allocating, copying through the host or synchronizing.  variant: 0 the
+ * tiled FP64 MFMA kernel, 2 the split-BF16 MFMA kernel (the kernels of the residual's
+ * grouped products; same results as ccsd_k_debug_zgemm with reference = 0 or 2).  The
+ * offset tables, a zero block and the split operands live in a fixed per-device array of
+ * 64 MiB that the library holds from the first call on a device until the process ends;
+ * a product needing more (8 bytes per table entry, G (2M + 2N + K) entries, plus 8 bytes
+ * per operand element for variant 2) is rejected with EINVAL.  Calls on one GPU share that
+ * array: calls that overlap in time (other streams or threads) race and must be ordered by
+ * the caller.  Errors: EINVAL (bad or too large sizes, null pointers; reason in
+ * ccsd_k_last_error(NULL)), EDEVICE (a launch failed). */
+int ccsd_k_zgemm_noalloc(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
+                         double *C, int32_t variant, void *hip_stream);
+
 /* Release host state; the caller frees the workspace afterwards. NULL is ignored. */
 void ccsd_k_free(ccsd_k_ctx *ctx);
 

@@ -69,13 +69,14 @@ _lib_timing = _sig("ccsd_k_timing", ctypes.c_int, [_p, _i32])
 _lib_timing_get = _sig("ccsd_k_timing_get", ctypes.c_int, [_p, _i32, _dp, ctypes.POINTER(_i64)])
 _lib_free = _sig("ccsd_k_free", None, [_p])
 _lib_dbg_gemm = _sig("ccsd_k_debug_zgemm", ctypes.c_int, [_i32, _i32, _i32, _i32, _dp, _dp, _dp, _i32])
+_lib_noalloc_gemm = _sig("ccsd_k_zgemm_noalloc", ctypes.c_int, [_i32, _i32, _i32, _i32, _p, _p, _p, _i32, _p])
 _lib_err = _sig("ccsd_k_last_error", ctypes.c_char_p, [_p])
 
 SYMBOLS = ("ccsd_k_init", "ccsd_k_workspace_bytes", "ccsd_k_bind_workspace", "ccsd_k_set_inputs",
            "ccsd_k_residual", "ccsd_k_iterate", "ccsd_k_residual_norm", "ccsd_k_energy",
            "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_product_shape",
            "ccsd_k_timing",
-           "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_free", "ccsd_k_last_error")
+           "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_zgemm_noalloc", "ccsd_k_free", "ccsd_k_last_error")
 
 
 class CcsdKError(RuntimeError):
@@ -199,6 +200,12 @@ def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference=False) -> np.ndar
     C = np.empty((G, M, N), np.complex128)
     _check(_lib_dbg_gemm(G, M, N, K, _ptr(A), _ptr(B), _ptr(C), int(reference)), None)
     return C
+
+
+def ccsd_k_zgemm_noalloc(G, M, N, K, a_ptr: int, b_ptr: int, c_ptr: int, variant: int = 0, stream=None):
+    """C[g] = A[g] @ B[g].T on device arrays given by address (complex128, dense row-major),
+    enqueued on ``stream`` (a hipStream_t address or None) without any allocation."""
+    return _check(_lib_noalloc_gemm(G, M, N, K, a_ptr, b_ptr, c_ptr, variant, stream), None)
 
 
 def ccsd_k_free(ctx):

@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "mixed.h"
+#include "noalloc.h"
 #include "pack.h"
 #include "terms.h"
 
@@ -1380,6 +1381,16 @@ int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
 
 int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t *launches) {
     return guarded(ctx, [&] { return impl_timing_get(ctx, stage, total_ms, launches); });
+}
+
+int ccsd_k_zgemm_noalloc(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
+                         int32_t variant, void *hip_stream) {
+    return guarded(nullptr, [&] {
+        std::string err;
+        const int rc = ck::noalloc_zgemm(G, M, N, K, A, B, C, variant, (hipStream_t)hip_stream, err);
+        if (rc == 0) return CCSD_K_OK;
+        return fail(nullptr, rc == -1 ? CCSD_K_EINVAL : CCSD_K_EDEVICE, err);
+    });
 }
 
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B, double *C,
