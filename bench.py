@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--nv", type=int, default=16)
     ap.add_argument("--seed", type=int, default=303)
     ap.add_argument("--diis", type=int, default=6)
+    ap.add_argument("--grouping", choices=["standard", "rearranged"], default="standard",
+                    help="hole-hole grouping of the FP64 path: Sec. 2 (standard) or Sec. 3.3.4 (rearranged)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--converge", type=int, default=1, help="after timing, iterate to convergence and "
                     "compare the paths' energies and amplitudes (0 = skip)")
@@ -77,16 +79,18 @@ def parse():
     ap.add_argument("--tol-mixed", type=float, default=1e-7,
                     help="the split-BF16 residual has a rounding floor near 1e-8..1e-7 at N_k=27")
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--batch-summary", type=int, default=1,
+                    help="also run the 96-system batched form on the mixed path and report it under 'batch'")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the N_k=27 workload: the batched form, this many independent seeded "
                          "systems (shapes drawn from seed 40000), converged on both paths")
     return ap.parse_args()
 
 
-def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter):
+def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter, grouping=0):
     N = grid[0] * grid[1] * grid[2]
     desc = dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=diis, synthetic=1, seed=seed,
-                eri_scale=0.05 / N)
+                eri_scale=0.05 / N, grouping=grouping if prec == 0 else 0)
     print(f"[bench] {('fp64', 'mixed')[prec]}: binding workspace", file=sys.stderr, flush=True)
     ctx = ck.Context([desc], device="cuda:0")
     gemm_flops, other_flops = ctx.flops(0)
@@ -96,8 +100,8 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
     for w in range(warmup):
         ctx.iterate(1, 0.0)
         print(f"[bench] warmup {w + 1}/{warmup} done", file=sys.stderr, flush=True)
+    # timed region: each iteration replayed from the captured graph (stage timing off)
     torch.cuda.synchronize()
-    ctx.timing(True)
     t0 = time.perf_counter()
     energy = None
     for s in range(steps):
@@ -105,15 +109,21 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
         energy = ctx.energy(0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    print(f"[bench] {steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    # per-product launch times: HIP events on the library's stream around every product
+    # launch over as many further iterations (enqueued directly: events are not captured)
+    ctx.timing(True)
+    for s in range(steps):
+        ctx.iterate(1, 0.0)
     stages = {name: ctx.timing_get(name) for name in ck.STAGES}
     ctx.timing(False)
-    print(f"[bench] {steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] {steps} timed-stage steps done", file=sys.stderr, flush=True)
     exec_flops = sum(8.0 * G * M * Nn * K for (G, M, Nn, K) in shapes.values())
     out = dict(seconds=dt, gemm_flops=gemm_flops, exec_flops=exec_flops, shapes=shapes, other_flops=other_flops,
                stages=stages,
                energy=energy, workspace_bytes=ctx.nbytes, rnorm=ctx.residual_norm(0))
     if converge:
-        done = warmup + steps
+        done = warmup + 2 * steps  # warm-up, timed and stage-timing iterations
         rc, it, rn = ctx.iterate(max(0, max_iter - done), tol)
         out.update(conv_rc=rc, conv_iters=done + it, conv_rnorm=rn, conv_energy=ctx.energy(0),
                    t2=ctx.get_amplitudes(0)[1])
@@ -125,11 +135,21 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(no, nv, N_target):
     """The FP64 oracle on a bounded sample (about 10-25 s of CPU work): residuals on a
     2x2x2 mesh with the same per-k block shapes, repeated until 10 s have passed (at most
     four), the time per residual scaled to the target mesh by the N_k^4 algorithmic flop
-    ratio."""
+    ratio; and one residual on a 2x1x1 mesh with a single BLAS thread, scaled the same way."""
     import numpy as np
 
     import synth
@@ -146,90 +166,130 @@ def cpu_baseline(no, nv, N_target):
         reps += 1
     dt = (time.perf_counter() - t0) / reps
     threads = 1
+    single = None
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
 
         threads = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+        g1 = (2, 1, 1)
+        f1, e1 = synth.system(303, g1, no, nv, scale=0.05 / 2)
+        a1, a2 = synth.test_amplitudes(1, g1, no, nv, scale=0.01)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            O.residual(f1, e1, a1, a2, O.kconserv(g1))
+            d1 = time.perf_counter() - t0
+        r1 = (N_target / 2.0) ** 4
+        single = {"value": 1.0 / (d1 * r1), "unit": "evals/s", "threads": 1,
+                  "sample": f"one oracle residual on a 2x1x1 mesh ({d1:.2f} s), scaled by {r1:.0f}"}
     except Exception:
         pass
     ratio = (N_target / 8.0) ** 4
     return {"value": 1.0 / (dt * ratio), "unit": "evals/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{reps} oracle residual(s) on a 2x2x2 mesh with n_occ={no}, n_vir={nv} per k "
                       f"({dt:.2f} s each), scaled by the N_k^4 flop ratio {ratio:.0f} to N_k={N_target}",
-            "sample_seconds": dt * reps}
+            "sample_seconds": dt * reps, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "cpu_model": _cpu_model(), "one_thread": single}
+
+
+def _batch_shapes(a):
+    import synth
+
+    return synth.batch_shapes(40000, a.batch or 96)
+
+
+def _batch_converge(a, shapes, prec, tol, timed_steps):
+    """Converge a batch of independent systems on one path.  The systems go into as few
+    contexts as fit the memory budget, one context iterating all of its systems together
+    (side by side on its lanes, each iteration one captured graph).  Returns per-system
+    energies, convergence flags and norms, the time of each of the first timed_steps batched
+    iterations (every system active, after one warm-up iteration) and the time to converge."""
+    import numpy as np
+    import torch
+
+    import paper_1911_00242_amd as ck
+
+    def desc(d):
+        return dict(grid=d["grid"], no=d["no"], nv=d["nv"], precision=prec, diis_space=a.diis, synthetic=1,
+                    seed=d["seed"], eri_scale=0.05 / int(np.prod(d["grid"])))
+
+    sizes = []
+    for d in shapes:
+        c = ck.ccsd_k_init([desc(d)])
+        sizes.append(ck.ccsd_k_workspace_bytes(c) + (1 << 16))
+        ck.ccsd_k_free(c)
+    groups, cur, tot = [], [], 0
+    for i, nb in enumerate(sizes):
+        if cur and tot + nb > 230e9:
+            groups.append(cur)
+            cur, tot = [], 0
+        cur.append(i)
+        tot += nb
+    groups += [cur] if cur else []
+    energy, conv, rnorm, iter_ms, total = {}, {}, {}, [], 0.0
+    for gi, grp in enumerate(groups):
+        print(f"[bench] batch {('fp64', 'mixed')[prec]}: group {gi} ({len(grp)} systems)", file=sys.stderr,
+              flush=True)
+        if timed_steps:
+            with ck.Context([desc(shapes[i]) for i in grp], device="cuda:0") as c:
+                c.iterate(1, 0.0)
+                ms = []
+                for s in range(timed_steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    c.iterate(1, 0.0)
+                    torch.cuda.synchronize()
+                    ms.append(1000.0 * (time.perf_counter() - t0))
+                iter_ms.append(ms)
+            torch.cuda.empty_cache()
+        with ck.Context([desc(shapes[i]) for i in grp], device="cuda:0") as c:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.iterate(a.max_iter, tol)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            for k, i in enumerate(grp):
+                energy[i] = c.energy(k)
+                rnorm[i] = c.residual_norm(k)
+                conv[i] = rnorm[i] < tol
+        torch.cuda.empty_cache()
+    # a batched iteration of the whole batch: the groups' iterations at the same index
+    per_iter = [sum(g[s] for g in iter_ms) for s in range(timed_steps)] if timed_steps else []
+    return energy, conv, rnorm, per_iter, total
+
+
+def batch_summary(a):
+    """The batched form on the mixed path (the default bench line's "batch" key): systems
+    converged per second and the time per batched iteration."""
+    import numpy as np
+
+    shapes = _batch_shapes(a)
+    e, c, n, it, t = _batch_converge(a, shapes, 1, a.tol_mixed, 5)
+    n_conv = sum(1 for i in range(len(shapes)) if c[i])
+    return {"systems": len(shapes), "converged_mixed": n_conv, "systems_converged_per_s": n_conv / t,
+            "seconds_to_converge": t, "tol": a.tol_mixed,
+            "iteration_ms": {"p50": float(np.percentile(it, 50)), "p99": float(np.percentile(it, 99)),
+                             "samples": len(it)} if it else None,
+            "workload": f"{len(shapes)} seeded systems, N_k from {{1,2,4,8}}, n_occ from {{4,6,8,12}}, "
+                        f"n_vir from {{8,16,24,32}} (seed 40000), integrals x 0.05/N_k, DIIS({a.diis})"}
 
 
 def run_batch(a):
     """The batched form: a.batch independent systems (N_k from {1, 2, 4, 8}, n_occ from
     {4, 6, 8, 12}, n_vir from {8, 16, 24, 32}, drawn with tag 3 from seed 40000; system s has
     seed 40000 + s and integrals scaled by 0.05 / N_k), iterated with DIIS to convergence.
-    The systems go into as few contexts as fit the memory budget, one context iterating all
-    of its systems together on one stream.  Timed on the mixed path: the time per batched
-    iteration over the first a.steps iterations (every system active), and the whole run to
-    convergence (systems converged per second); the FP64 path converges the same systems
-    for the per-system energy reference, and the oracle the smallest few."""
+    Timed on the mixed path: the time per batched iteration over the first a.steps
+    iterations (every system active), and the whole run to convergence (systems converged
+    per second); the FP64 path converges the same systems for the per-system energy
+    reference, and the oracle the smallest few."""
     import numpy as np
-    import torch
 
-    import paper_1911_00242_amd as ck
     import synth
     from oracle import ccsd_k as O
 
-    shapes = synth.batch_shapes(40000, a.batch)
-
-    def desc(d, prec):
-        return dict(grid=d["grid"], no=d["no"], nv=d["nv"], precision=prec, diis_space=a.diis, synthetic=1,
-                    seed=d["seed"], eri_scale=0.05 / int(np.prod(d["grid"])))
-
-    def groups(prec, budget=230e9):
-        sizes = []
-        for d in shapes:
-            c = ck.ccsd_k_init([desc(d, prec)])
-            sizes.append(ck.ccsd_k_workspace_bytes(c) + (1 << 16))
-            ck.ccsd_k_free(c)
-        out, cur, tot = [], [], 0
-        for i, nb in enumerate(sizes):
-            if cur and tot + nb > budget:
-                out.append(cur)
-                cur, tot = [], 0
-            cur.append(i)
-            tot += nb
-        return out + ([cur] if cur else [])
-
-    def converge(prec, tol, timed_steps):
-        energy, conv, rnorm, iter_ms, total = {}, {}, {}, [], 0.0
-        for gi, grp in enumerate(groups(prec)):
-            print(f"[bench] batch {('fp64', 'mixed')[prec]}: group {gi} ({len(grp)} systems)", file=sys.stderr,
-                  flush=True)
-            if timed_steps:  # per batched iteration, every system active (one warm-up iteration first)
-                with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
-                    c.iterate(1, 0.0)
-                    ms = []
-                    for s in range(timed_steps):
-                        torch.cuda.synchronize()
-                        t0 = time.perf_counter()
-                        c.iterate(1, 0.0)
-                        torch.cuda.synchronize()
-                        ms.append(1000.0 * (time.perf_counter() - t0))
-                    iter_ms.append(ms)
-                torch.cuda.empty_cache()
-            with ck.Context([desc(shapes[i], prec) for i in grp], device="cuda:0") as c:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                c.iterate(a.max_iter, tol)
-                torch.cuda.synchronize()
-                total += time.perf_counter() - t0
-                for k, i in enumerate(grp):
-                    energy[i] = c.energy(k)
-                    rnorm[i] = c.residual_norm(k)
-                    conv[i] = rnorm[i] < tol
-            torch.cuda.empty_cache()
-        # a batched iteration of the whole batch: the groups' iterations at the same index
-        per_iter = [sum(g[s] for g in iter_ms) for s in range(timed_steps)] if timed_steps else []
-        return energy, conv, rnorm, per_iter, total
-
-    e_mx, c_mx, n_mx, it_mx, t_mx = converge(1, a.tol_mixed, a.steps)
-    e_64, c_64, _, _, t_64 = converge(0, a.tol, 0)
+    shapes = _batch_shapes(a)
+    e_mx, c_mx, n_mx, it_mx, t_mx = _batch_converge(a, shapes, 1, a.tol_mixed, a.steps)
+    e_64, c_64, _, _, t_64 = _batch_converge(a, shapes, 0, a.tol, 0)
     both = [i for i in range(len(shapes)) if c_mx[i] and c_64[i]]
     de = [abs(e_mx[i] - e_64[i]) for i in both]
     # the oracle on the smallest systems (pp-ladder work N^4 o^2 v^4)
@@ -286,7 +346,7 @@ def main():
     res = {}
     for p in paths:
         res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup, a.converge,
-                          a.tol if p == 0 else a.tol_mixed, a.max_iter)
+                          a.tol if p == 0 else a.tol_mixed, a.max_iter, 1 if a.grouping == "rearranged" else 0)
     head = 1 if 1 in res else 0
     r = res[head]
     ms = 1000.0 * r["seconds"] / a.steps
@@ -344,6 +404,8 @@ def main():
             line["mixed_vs_fp64"] = {"abs_dE": abs(res[1]["conv_energy"] - res[0]["conv_energy"]),
                                      "max_abs_dT2": float(np.abs(res[1]["t2"] - res[0]["t2"]).max()),
                                      "reference": "FP64 GPU path converged to ||R|| < tol"}
+    if a.batch_summary and (grid, a.no, a.nv) == ((3, 3, 3), 8, 16):
+        line["batch"] = batch_summary(a)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(a.no, a.nv, N)

@@ -61,6 +61,15 @@ extern "C" {
                                amplitudes and DIIS amplitude history, denominators, F
                                intermediates, norm and energy sums                     */
 
+/* Grouping of the hole-hole terms of the T2 equation.  STANDARD: Sec. 2 (eq. ori_EqDouble)
+ * with W_mnij built once from tau and applied once, 1/2 tau_mn^ab W_mnij.  REARRANGED (FP64
+ * path): the grouping of Sec. 3.3.4 (eqs. A_3rd, def_X, and the t2 Y-tilde_{mnij} term of
+ * eq. A_4th with def_Y_oo): X-tilde = t2 <mn||ef>, then 1/4 t2 X-tilde and t2 Y-tilde as
+ * two separate products, tau's single-amplitude part of the hole-hole ladder as a small
+ * contraction; one more N_k^4 n_occ^4 n_vir^2 product than STANDARD, same result. */
+#define CCSD_K_GROUPING_STANDARD 0
+#define CCSD_K_GROUPING_REARRANGED 1
+
 typedef struct ccsd_k_ctx ccsd_k_ctx;
 
 typedef struct {
@@ -73,6 +82,7 @@ typedef struct {
                            (seed, eri_scale) by the seeded recipe; 0: ccsd_k_set_inputs  */
     uint64_t seed;
     double eri_scale;   /* scale of the raw complex Gaussians of the synthetic recipe   */
+    int32_t grouping;   /* CCSD_K_GROUPING_STANDARD or (FP64 path) _REARRANGED            */
 } ccsd_k_system;
 
 /* Plan n_sys independent systems (1..4096), each with N_k <= 512.  hip_stream: a
@@ -143,6 +153,63 @@ int ccsd_k_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double 
 int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int64_t *G, int64_t *M, int64_t *N,
                          int64_t *K);
 
+/* Arithmetic forms of a grouped product of a mixed-precision system.  The operands of a
+ * product are stored in 8 bytes per complex element, either split (four bf16 values, the
+ * high and low halves of the real and imaginary parts) or as complex64; products accumulate
+ * in FP32 and add their result to FP64 (or complex64 / split) outputs.
+ *   SPLIT2_PRESPLIT  split storage, each real product hi*hi + hi*lo + lo*hi on bf16 MFMA
+ *                    (about 2^-16 relative per product; the default);
+ *   SPLIT2           the same arithmetic on complex64 storage, split in registers;
+ *   SPLIT3           complex64 storage split into three bf16 terms, six bf16 MFMA products
+ *                    per real product (every term down to 2^-16 of |x||y| kept, about FP32
+ *                    accuracy);
+ *   FP32             complex64 storage, FP32 MFMA.
+ * The ladder family (products 0 and 2) and the ring family (products 3 and 4) each keep
+ * one storage: complex64 as soon as one product of the family takes a complex64 form, and a
+ * SPLIT2_PRESPLIT product of such a family runs as SPLIT2.  (The precision pattern of the
+ * paper's contractions, Sec. 4.3.4, is not fixed by the paper; these forms are ours.) */
+#define CCSD_K_FORM_SPLIT2_PRESPLIT 0
+#define CCSD_K_FORM_SPLIT2 1
+#define CCSD_K_FORM_SPLIT3 2
+#define CCSD_K_FORM_FP32 3
+
+/* Set / read the arithmetic form of product (numbering of ccsd_k_timing_get: 0 the
+ * particle-particle ladder, which carries the hole-hole ladder too on this path, 2 W_mnij,
+ * 3 W_mbej, 4 ring) of mixed-precision system sys.  EINVAL for an FP64 system, product 1 or
+ * an unknown form.  A change of a family's storage converts its static operands again. */
+int ccsd_k_set_product_form(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t form);
+int ccsd_k_get_product_form(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *form);
+
+/* Autotuner: choose the form of every product of mixed-precision system sys.  For each
+ * product it measures every form's average launch time on the system's own operands and
+ * tables (the workspace must be bound; the overwritten intermediates are recomputed by the
+ * next residual) and every form's error, max|C_form - C_fp64| / max|C_fp64| on seeded
+ * operands of the product's K (and up to 256 rows and columns) against the FP64 MFMA kernel.
+ * Per family it keeps the faster of the two storages whose products all stay within budget
+ * (each product of a complex64 family taking its fastest admissible form); if none does,
+ * the most accurate forms.  cache_path (NULL: none): a text file of measurements keyed by
+ * device and product shape, read before measuring and appended to after.  forms[5]
+ * (optional) receives the chosen form per product (-1 for product 1); report (optional,
+ * 5 x 4 x 2 doubles) the measured (ms, error) per product and form. */
+int ccsd_k_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache_path, int32_t *forms,
+                    double *report);
+
+/* Graph replay in ccsd_k_iterate (on by default): one iteration of every active system
+ * (residual, norm, and the update gated on that norm on the device: plain substitution, or
+ * the DIIS update, the DIIS step solved on the device and the extrapolation) is captured
+ * once as a HIP graph and replayed, with one copy of the systems' norms to the host per
+ * iteration; it is captured again when the active set, a product form or the tolerance
+ * changes.  Results are bitwise those of the same work enqueued directly (enable = 0,
+ * while stage timing is on, or on a context created with the null stream, which cannot be
+ * captured). */
+int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable);
+
+/* Precision escalation in ccsd_k_iterate (on by default): a mixed-precision system whose
+ * residual norm has not halved for four iterations while above the tolerance has reached
+ * the rounding floor of its two-term split products; those products are then switched to
+ * CCSD_K_FORM_SPLIT3 (once per system).  enable = 0 keeps the forms fixed. */
+int ccsd_k_set_escalation(ccsd_k_ctx *ctx, int32_t enable);
+
 /* Per-stage device timing with HIP events on the context's stream (0 = off).  Stages:
  * 0 particle-particle ladder, 1 hole-hole ladder, 2 W_mnij build, 3 ring W build,
  * 4 ring product, 5 the whole residual evaluation (all of the above and every other term).
@@ -153,7 +220,9 @@ int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t 
 
 /* Diagnostic: dense grouped complex product C[g] = A[g] . B[g]^T on the device with the
  * tiled FP64 MFMA kernel (reference = 0), the one-thread-per-element FP64 kernel
- * (reference = 1), or the split-BF16 MFMA kernel of the mixed path (reference = 2).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
+ * (reference = 1), the split-BF16 MFMA kernel of the mixed path on pre-split operands
+ * (reference = 2), or the complex64-operand kernel in one of its arithmetic forms:
+ * two-term split-BF16 (3), three-term split-BF16 (4) or FP32 MFMA (5).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
  * Allocates and frees its own device buffers; synchronizes the default stream. */
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
                        double *C, int32_t reference);

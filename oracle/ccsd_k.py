@@ -245,11 +245,12 @@ def r2_block_nonladder(eris: Eris, t1, t2, tau, Fvt, Fot, kc, wmn, x, ki, kj, ka
     return r
 
 
-def t1_residual(f, eris: Eris, t1, t2, Foo, Fvv, Fov):
-    """R1: the right-hand side of the T1 equation (eq. ori_EqSingle)."""
+def t1_residual(f, eris: Eris, t1, t2, Foo, Fvv, Fov, ks=None):
+    """R1: the right-hand side of the T1 equation (eq. ori_EqSingle), at the momenta ``ks``
+    (default all; the other blocks are left zero)."""
     N, no, nv = t1.shape
     R1 = np.zeros_like(t1)
-    for k in range(N):
+    for k in (range(N) if ks is None else ks):
         r = np.conj(f[k, :no, no:])  # f_ai = conj(f_ia)
         r = r + _con("ic,ac->ia", t1[k], Fvv[k])
         r = r - _con("ra,ri->ia", t1[k], Foo[k])
@@ -344,16 +345,21 @@ class LazyClasses:
         return _View()
 
 
-def residual_blocks(f, classes, t1, t2, kc, blocks):
-    """R1 in full and R2 on the listed momentum blocks (ki, kj, ka) only, term by term as in
-    ``residual`` (same intermediates, same order of the sums), computing each intermediate
-    block only where a listed block needs it.  ``classes``: a dict of whole classes or a
-    ``LazyClasses``."""
+def residual_blocks(f, classes, t1, t2, kc, blocks, r1_ks=None, callback=None):
+    """R1 (at the momenta ``r1_ks``, default all) and R2 on the listed momentum blocks
+    (ki, kj, ka) only, term by term as in ``residual`` (same intermediates, same order of the
+    sums), computing each intermediate block only where a listed block needs it.
+    ``classes``: a dict of whole classes or a ``LazyClasses``.  ``callback(step)``, if given,
+    is called after each stage (progress reporting of long runs)."""
     N, no, nv = t1.shape
     eris = Eris(classes, kc)
     Foo, Fvv, Fov = f_intermediates(f, eris, t1, t2, kc, no)
+    if callback:
+        callback("F intermediates")
     tau = make_tau(t1, t2, kc, 0.5)
-    R1 = t1_residual(f, eris, t1, t2, Foo, Fvv, Fov)
+    R1 = t1_residual(f, eris, t1, t2, Foo, Fvv, Fov, ks=r1_ks)
+    if callback:
+        callback("R1")
     Fvt, Fot = _f_tilde(t1, Foo, Fvv, Fov)
     memo = {}
 
@@ -379,6 +385,8 @@ def residual_blocks(f, classes, t1, t2, kc, blocks):
             W = cached("wabef", lambda a, b, c: w_abef_block(eris, t1, tau, kc, a, b, c), ka, kb, ke)
             r += 0.5 * _con("abef,ijef->ijab", W, tau[ki, kj, ke])
         out[(ki, kj, ka)] = r
+        if callback:
+            callback(f"R2 block {(ki, kj, ka)}")
     return R1, out
 
 

@@ -31,6 +31,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 PREC_FP64, PREC_MIXED = 0, 1
+GROUPING_STANDARD, GROUPING_REARRANGED = 0, 1
+FORM_SPLIT2_PRESPLIT, FORM_SPLIT2, FORM_SPLIT3, FORM_FP32 = 0, 1, 2, 3
+FORMS = ("split2_presplit", "split2", "split3", "fp32")
 CLASSES = ("oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv")
 STAGES = ("pp_ladder", "hh_ladder", "w_mnij", "w_mbej", "ring", "residual")
 
@@ -38,7 +41,8 @@ STAGES = ("pp_ladder", "hh_ladder", "w_mnij", "w_mbej", "ring", "residual")
 class ccsd_k_system(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32 * 3), ("n_occ", ctypes.c_int32), ("n_vir", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("diis_space", ctypes.c_int32),
-                ("synthetic", ctypes.c_int32), ("seed", ctypes.c_uint64), ("eri_scale", ctypes.c_double)]
+                ("synthetic", ctypes.c_int32), ("seed", ctypes.c_uint64), ("eri_scale", ctypes.c_double),
+                ("grouping", ctypes.c_int32)]
 
 
 _p = ctypes.c_void_p
@@ -65,6 +69,11 @@ _lib_get_amp = _sig("ccsd_k_get_amplitudes", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_set_amp = _sig("ccsd_k_set_amplitudes", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_flops = _sig("ccsd_k_flops", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_shape = _sig("ccsd_k_product_shape", ctypes.c_int, [_p, _i32, _i32] + [ctypes.POINTER(_i64)] * 4)
+_lib_set_form = _sig("ccsd_k_set_product_form", ctypes.c_int, [_p, _i32, _i32, _i32])
+_lib_get_form = _sig("ccsd_k_get_product_form", ctypes.c_int, [_p, _i32, _i32, ctypes.POINTER(_i32)])
+_lib_autotune = _sig("ccsd_k_autotune", ctypes.c_int, [_p, _i32, _f64, ctypes.c_char_p, ctypes.POINTER(_i32), _dp])
+_lib_escalation = _sig("ccsd_k_set_escalation", ctypes.c_int, [_p, _i32])
+_lib_graphs = _sig("ccsd_k_set_graphs", ctypes.c_int, [_p, _i32])
 _lib_timing = _sig("ccsd_k_timing", ctypes.c_int, [_p, _i32])
 _lib_timing_get = _sig("ccsd_k_timing_get", ctypes.c_int, [_p, _i32, _dp, ctypes.POINTER(_i64)])
 _lib_free = _sig("ccsd_k_free", None, [_p])
@@ -75,6 +84,7 @@ _lib_err = _sig("ccsd_k_last_error", ctypes.c_char_p, [_p])
 SYMBOLS = ("ccsd_k_init", "ccsd_k_workspace_bytes", "ccsd_k_bind_workspace", "ccsd_k_set_inputs",
            "ccsd_k_residual", "ccsd_k_iterate", "ccsd_k_residual_norm", "ccsd_k_energy",
            "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_product_shape",
+           "ccsd_k_set_product_form", "ccsd_k_get_product_form", "ccsd_k_autotune", "ccsd_k_set_escalation", "ccsd_k_set_graphs",
            "ccsd_k_timing",
            "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_zgemm_noalloc", "ccsd_k_free", "ccsd_k_last_error")
 
@@ -116,6 +126,7 @@ def ccsd_k_init(systems, stream=None):
         arr[i].synthetic = int(s.get("synthetic", 0))
         arr[i].seed = int(s.get("seed", 0))
         arr[i].eri_scale = float(s.get("eri_scale", 0.05))
+        arr[i].grouping = int(s.get("grouping", GROUPING_STANDARD))
     out = _p()
     _check(_lib_init(arr, len(systems), stream, ctypes.byref(out)), None)
     return out
@@ -180,6 +191,33 @@ def ccsd_k_product_shape(ctx, sys, product):
     return tuple(int(x.value) for x in out)
 
 
+def ccsd_k_set_product_form(ctx, sys, product, form):
+    return _check(_lib_set_form(ctx, sys, product, form), ctx)
+
+
+def ccsd_k_get_product_form(ctx, sys, product) -> int:
+    f = _i32()
+    _check(_lib_get_form(ctx, sys, product, ctypes.byref(f)), ctx)
+    return int(f.value)
+
+
+def ccsd_k_autotune(ctx, sys, budget, cache_path=None):
+    """Returns (forms per product, report[product][form] = (ms, error))."""
+    forms = (_i32 * 5)()
+    rep = np.zeros((5, 4, 2))
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_lib_autotune(ctx, sys, float(budget), path, forms, rep.ctypes.data_as(_dp)), ctx)
+    return [int(x) for x in forms], rep
+
+
+def ccsd_k_set_escalation(ctx, enable: bool):
+    return _check(_lib_escalation(ctx, 1 if enable else 0), ctx)
+
+
+def ccsd_k_set_graphs(ctx, enable: bool):
+    return _check(_lib_graphs(ctx, 1 if enable else 0), ctx)
+
+
 def ccsd_k_timing(ctx, enable: bool):
     return _check(_lib_timing(ctx, 1 if enable else 0), ctx)
 
@@ -192,7 +230,8 @@ def ccsd_k_timing_get(ctx, stage: int):
 
 def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference=False) -> np.ndarray:
     """C[g] = A[g] @ B[g].T on the device (A [G,M,K], B [G,N,K] complex128).
-    reference: False/0 tiled FP64 MFMA, True/1 per-element FP64, 2 split-BF16 MFMA."""
+    reference: False/0 tiled FP64 MFMA, True/1 per-element FP64, 2 split-BF16 MFMA on pre-split
+    operands; on complex64 operands 3 two-term split-BF16, 4 three-term split-BF16, 5 FP32 MFMA."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     B = np.ascontiguousarray(B, dtype=np.complex128)
     G, M, K = A.shape
@@ -278,6 +317,21 @@ class Context:
     def product_shape(self, product, sys=0):
         """(G, M, N, K) of a grouped product as executed; product is a stage name or number."""
         return ccsd_k_product_shape(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product)
+
+    def set_product_form(self, product, form, sys=0):
+        ccsd_k_set_product_form(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product, form)
+
+    def product_form(self, product, sys=0):
+        return ccsd_k_get_product_form(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product)
+
+    def autotune(self, budget, cache_path=None, sys=0):
+        return ccsd_k_autotune(self.ctx, sys, budget, cache_path)
+
+    def set_escalation(self, enable=True):
+        ccsd_k_set_escalation(self.ctx, enable)
+
+    def set_graphs(self, enable=True):
+        ccsd_k_set_graphs(self.ctx, enable)
 
     def timing(self, enable=True):
         ccsd_k_timing(self.ctx, enable)

@@ -23,6 +23,7 @@
 #include "noalloc.h"
 #include "pack.h"
 #include "terms.h"
+#include "tune.h"
 
 namespace {
 
@@ -56,6 +57,12 @@ struct System {
     cd *amp = nullptr, *res = nullptr;  // [t1 | t2], [r1 | r2]
     cd *tau = nullptr, *tauT = nullptr, *Vt = nullptr, *WT = nullptr, *WR = nullptr, *X = nullptr;
     cd *scr = nullptr, *P1 = nullptr;
+    // rearranged hole-hole grouping (grouping 1, FP64 path): the per-block transpose of t2
+    // (B operand of the two hole-hole products) and X-tilde = t2 <mn||ef> (WT layout); the
+    // W_mnij buffer WT then holds Y-tilde.  gr: X-tilde, 1/4 X-tilde t2, Y-tilde t2
+    cd *t2T = nullptr, *XT = nullptr;
+    Gemm gr[3];
+    bool rearranged() const { return desc.grouping == CCSD_K_GROUPING_REARRANGED; }
     cd *ovvoT = nullptr;  // static ovvo, ovvv, oovv classes with their last two indices swapped
     cd *ovvvT = nullptr, *oovvT = nullptr;
     // mixed path: complex64 copies in place of the three above, and of ovvv and oovv
@@ -93,11 +100,30 @@ struct System {
     double *epart = nullptr;
     bool sp_ok = false, e_ok = false;
     ck::SplitOps sg[5];
+    // arithmetic form of each mixed product slot of sg (ck::Arith; slot 2 unused).  The
+    // ladder family (slots 0, 1) and the ring family (3, 4) each keep their operands in one
+    // storage: split storage while every product of the family is PRESPLIT2, complex64
+    // otherwise (a PRESPLIT2 product of a complex64 family then runs as SPLIT2)
+    int arith[5] = {ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2,
+                    ck::ARITH_PRESPLIT2};
+    bool c64_lad() const { return ck::arith_c64(arith[0]) || ck::arith_c64(arith[1]); }
+    bool c64_ring() const { return ck::arith_c64(arith[3]) || ck::arith_c64(arith[4]); }
+    bool c64_of(int slot) const { return slot < 3 ? c64_lad() : c64_ring(); }
+    // k extent of one FP32-accumulated chunk of every mixed product (0: the whole k range;
+    // a multiple of 16 otherwise), see run_split_product
+    int kchunk = 0;
+    // device DIIS state (ck::DiisDev): FIFO head and count, overlaps, new overlaps, coefficients
+    int32_t *dstate = nullptr;
+    double *dB = nullptr, *dbnew = nullptr, *dcoef = nullptr;
+    ck::DiisDev diis() const { return ck::DiisDev{dstate, dB, dbnew, dcoef, desc.diis_space}; }
+    bool diis_reset = true;  // the device DIIS state must be cleared before the next update
     // host state
-    int diis_n = 0, diis_head = 0;
-    std::vector<double> B;  // diis_space x diis_space error overlaps
     double rnorm = -1.0;
     bool converged = false, inputs = false;
+    // stagnation watch of the mixed path (see watch_stagnation): norm at the last halving
+    // and iterations since
+    double rn_ref = INFINITY;
+    int stall = 0;
 
     int64_t n1() const { return d.t1(); }
     int64_t n2() const { return d.t2(); }
@@ -164,6 +190,13 @@ struct ccsd_k_ctx {
     std::vector<hipStream_t> lanes;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
+    bool escalate = true;  // raise stagnating mixed systems to three-term split products
+    // iterations replayed from one captured graph (off while stage timing is on); the graph
+    // is captured again whenever what it depends on changes (iteration_signature)
+    bool graphs = true;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gsig;
+    double *dnorms = nullptr;  // device: ||R||^2 of every system after an iteration
 };
 
 namespace {
@@ -440,10 +473,14 @@ void carve(System &S, Carver &c) {
         c.take(S.pk_oovv, 4 * N * PO * PV);
         c.take(S.Lp, N * PO * PV);
         c.take(S.npart, ck::assemble_pack_blocks(S.d, S.pairs()));
-        c.take(S.epart, 2 + 2 * (int64_t)ck::lincomb_t2_blocks(S.d));
+        c.take(S.epart, 2 + 2 * ck::lincomb_pack_blocks(S.d, S.pairs()));
         c.take(S.dptab, (int64_t)S.ptab.size());
     }
     c.take(S.WT, N3 * cls[0]);
+    if (S.rearranged()) {
+        c.take(S.t2T, S.n2());
+        c.take(S.XT, N3 * cls[0]);
+    }
     c.take(S.WR, N3 * o * v * o * v);
     c.take(S.X, N3 * o * v * o * v);
     c.take(S.scr, N3 * o * o * o * v);
@@ -474,6 +511,11 @@ void carve(System &S, Carver &c) {
     c.take(S.redout, 32);
     c.take(S.dkc, N3);
     c.take(S.dtab, (int64_t)S.tables.size());
+    const int md = std::max(S.desc.diis_space, 1);
+    c.take(S.dstate, 4);
+    c.take(S.dB, md * md);
+    c.take(S.dbnew, md);
+    c.take(S.dcoef, md);
     // the DIIS history pointers are written only when assigning: a size query (assign
     // false) on a bound context must leave them intact
     const int m = S.desc.diis_space;
@@ -482,12 +524,14 @@ void carve(System &S, Carver &c) {
         S.derr.assign(S.mixed ? 0 : m, nullptr);
         S.derr32.assign(S.mixed ? m : 0, nullptr);
     }
+    // mixed path: packed history (t1 in full, t2 on the antisymmetry-orbit representatives)
+    const int64_t hl = S.mixed ? ck::packed_len(S.d, S.pairs()) : S.n1() + S.n2();
     for (int i = 0; i < m; ++i) {
         cd *vec = nullptr, *err = nullptr;
         ck::cf *err32 = nullptr;
-        c.take(vec, S.n1() + S.n2());
-        if (S.mixed) c.take(err32, S.n1() + S.n2());
-        else c.take(err, S.n1() + S.n2());
+        c.take(vec, hl);
+        if (S.mixed) c.take(err32, hl);
+        else c.take(err, hl);
         if (!c.assign) continue;
         S.dvec[i] = vec;
         if (S.mixed) S.derr32[i] = err32;
@@ -533,6 +577,23 @@ void bind_ops(System &S) {
         g.op.c_row = T + g.tab[4];
         g.op.c_col = T + g.tab[5];
         g.op.zeros = S.zeros;
+    }
+    if (S.rearranged()) {
+        // X-tilde = t2 . <mn||ef>^T (the W_mnij product on t2, alpha 1, into XT); the two
+        // hole-hole products on the transposed t2: r2 += 1/4 X-tilde t2T and r2 += Y t2T
+        S.gr[0] = S.g[0];
+        S.gr[0].op.A = S.t2();
+        S.gr[0].op.C = S.XT;
+        S.gr[0].op.alpha = 1.0;
+        S.gr[0].op.beta = 0.0;
+        S.gr[1] = S.g[2];
+        S.gr[1].op.A = S.XT;
+        S.gr[1].op.B = S.t2T;
+        S.gr[1].op.alpha = 0.25;
+        S.gr[2] = S.g[2];
+        S.gr[2].op.A = S.WT;
+        S.gr[2].op.B = S.t2T;
+        S.gr[2].op.alpha = 1.0;
     }
     if (!S.mixed) return;
     // the ladder family on packed pairs (gp: W_mnij, then both ladders as one product; slot
@@ -650,10 +711,74 @@ void join_lanes(ccsd_k_ctx *c, const std::vector<hipStream_t> &used) {
     }
 }
 
+void apply_form(ccsd_k_ctx *c, System &S, int slot, int a);
+
+// Precision escalation of the mixed path.  The products carry rounding errors that change
+// from one iteration to the next (the two-term split ~2^-16 relative per product, FP32
+// accumulation ~2^-24 sqrt(steps) of the running sum), so the residual of a mixed system
+// has a floor that grows with the coupling strength; a system whose residual norm has not
+// halved for four iterations while still above the tolerance is at that floor.  Every
+// product it runs in a two-term form is then raised to the three-term split, and every
+// product accumulates in FP32 over chunks of 256 k only, adding the chunks in FP64.
+// Applied once per system.
+void watch_stagnation(ccsd_k_ctx *c, System &S) {
+    if (!S.mixed) return;
+    if (S.rnorm < 0.5 * S.rn_ref) {
+        S.rn_ref = S.rnorm;
+        S.stall = 0;
+        return;
+    }
+    if (++S.stall < 4) return;
+    S.stall = 0;
+    S.rn_ref = S.rnorm;
+    if (S.kchunk) return;  // escalated already
+    for (int slot : {0, 1, 3, 4})
+        if (S.arith[slot] == ck::ARITH_PRESPLIT2 || S.arith[slot] == ck::ARITH_SPLIT2)
+            apply_form(c, S, slot, ck::ARITH_SPLIT3);
+    S.kchunk = 256;
+}
+
+// product slot i of the mixed path in its arithmetic form, on its family's storage.  With
+// S.kchunk > 0 the k range is cut into chunks of that many k, each a launch that adds its
+// part to the FP64 output (the first with the product's beta, the rest with 1; only the
+// last writes the split or complex64 copy): FP32 accumulation then spans one chunk.
+void run_split_product(System &S, int i, hipStream_t st) {
+    const bool c64 = S.c64_of(i);
+    const int a = !c64 ? (int)ck::ARITH_PRESPLIT2
+                       : (S.arith[i] == ck::ARITH_PRESPLIT2 ? (int)ck::ARITH_SPLIT2 : S.arith[i]);
+    auto launch = [&](const ck::SplitOps &o) {
+        if (c64) ck::gemm_c64(o, a, st);
+        else ck::gemm_split(o, st);
+    };
+    const ck::SplitOps &op = S.sg[i];
+    const int kc = S.kchunk;
+    if (kc <= 0 || op.K <= kc) {
+        launch(op);
+        return;
+    }
+    for (int k0 = 0; k0 < op.K; k0 += kc) {
+        ck::SplitOps o = op;
+        o.kld = op.K;
+        o.a_k = op.a_k + k0;
+        o.b_k = op.b_k + k0;
+        o.K = std::min(kc, op.K - k0);
+        o.beta = k0 == 0 ? op.beta : 1.0;
+        if (k0 + kc < op.K) o.Cs = nullptr;
+        launch(o);
+    }
+}
+
+void run_op(ccsd_k_ctx *c, const Gemm &g, int stage, hipStream_t st) {
+    EventPair ep{};
+    stage_begin(c, ep, stage, st);
+    ck::gemm_f64(g.op, st);
+    stage_end(c, ep, st);
+}
+
 void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st) {
     EventPair ep{};
     stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage, st);
-    if (S.mixed) ck::gemm_split(S.sg[i], st);
+    if (S.mixed) run_split_product(S, i, st);
     else ck::gemm_f64(S.g[i].op, st);
     stage_end(c, ep, st);
 }
@@ -663,7 +788,27 @@ void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
     ck::SysDev s = S.dev();
     EventPair all{};
     stage_begin(c, all, ST_RES, st);
-    if (!S.mixed) {
+    if (!S.mixed && S.rearranged()) {
+        // the hole-hole part in the grouping of Sec. 3.3.4: X-tilde = t2 <mn||ef>,
+        // 1/4 t2 X-tilde and t2 Y-tilde_{mnij} as separate products, tau's single-amplitude
+        // part of the hole-hole ladder by a small kernel; everything else as below
+        ck::launch_tau(s, S.t1(), S.t2(), S.tau, nullptr, st);
+        ck::launch_block_transpose(S.d, S.t2(), S.t2T, st);
+        ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
+        ck::launch_wmnij_init(s, S.t1(), S.WT, false, st);
+        ck::launch_ytilde(s, S.t1(), S.WT, st);
+        run_op(c, S.gr[0], ST_WMN, st);  // X-tilde
+        ck::launch_vvvv_dress(s, S.t1(), S.Vt, st);
+        ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
+        run_gemm(c, S, 3, st);
+        run_gemm(c, S, 4, st);
+        ck::launch_assemble_r2(s, S.X, S.r2(), st);
+        run_gemm(c, S, 1, st);  // particle-particle ladder
+        run_op(c, S.gr[1], ST_HH, st);  // A-tilde: 1/4 t2 X-tilde
+        run_op(c, S.gr[2], ST_HH, st);  // t2 Y-tilde_{mnij}
+        ck::launch_hh_t1_rest(s, S.t1(), S.WT, S.XT, S.r2(), st);
+        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
+    } else if (!S.mixed) {
         ck::launch_tau(s, S.t1(), S.t2(), S.tau, S.tauT, st);
         ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, false, st);
@@ -678,13 +823,14 @@ void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
         const int64_t R = S.PV + S.PO;
-        if (!S.sp_ok) ck::launch_split(S.n2(), S.t2(), S.sp_t2, st);
+        if (!S.sp_ok) ck::launch_operand(S.n2(), S.t2(), S.sp_t2, S.c64_ring(), st);
         S.sp_ok = true;
-        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R, st);
+        ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R,
+                            S.c64_lad(), st);
         ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
         run_gemm(c, S, 0, st);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
-        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, st);
+        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, S.c64_lad(), st);
         ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
         run_gemm(c, S, 3, st);  // W_mbej += 1/2 t2 <mn||ef>, written split
         run_gemm(c, S, 4, st);  // X += t2 W_mbej
@@ -700,11 +846,13 @@ void amplitudes_changed(System &S) { S.sp_ok = S.e_ok = false; }
 
 // a new trajectory (new inputs or amplitudes from the caller): empty DIIS history
 void reset_iteration(System &S) {
-    S.diis_n = 0;
-    S.diis_head = 0;
+    S.diis_reset = true;
     S.converged = false;
-    std::fill(S.B.begin(), S.B.end(), 0.0);
+    S.rn_ref = INFINITY;
+    S.stall = 0;
 }
+
+__global__ void k_copy_scalar(const double *src, double *dst) { *dst = *src; }
 
 // ||R||^2 into S.redout[0] after residual_device (the mixed assembly left partial sums)
 void launch_norm(System &S, hipStream_t st) {
@@ -714,8 +862,8 @@ void launch_norm(System &S, hipStream_t st) {
 
 // split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
 void static_split(System &S, hipStream_t st) {
-    ck::launch_split(S.n2(), S.eri[2], S.sp_oovv, st);
-    ck::launch_oovv_pack(S.d, S.dkc, S.pairs(), S.eri[2], S.pk_oovv, st);
+    ck::launch_operand(S.n2(), S.eri[2], S.sp_oovv, S.c64_ring(), st);
+    ck::launch_oovv_pack(S.d, S.dkc, S.pairs(), S.eri[2], S.pk_oovv, S.c64_lad(), st);
 }
 
 double read_scalar(ccsd_k_ctx *c, const double *dptr) {
@@ -741,39 +889,6 @@ int check_sys(ccsd_k_ctx *c, int32_t sys, bool need_inputs = true) {
     return CCSD_K_OK;
 }
 
-// Pulay DIIS step on [t1|t2] after the Jacobi update (error = R/D).  Solves the bordered
-// system of error overlaps on the host in FP64 (Gaussian elimination with pivoting).
-bool diis_solve(const std::vector<double> &B, int m, std::vector<double> &c) {
-    int n = m + 1;
-    std::vector<double> A((size_t)n * n, 0.0), r(n, 0.0);
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) A[i * n + j] = B[i * m + j];
-    for (int i = 0; i < m; ++i) A[i * n + m] = A[m * n + i] = 1.0;
-    r[m] = 1.0;
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int i = col + 1; i < n; ++i)
-            if (std::fabs(A[i * n + col]) > std::fabs(A[piv * n + col])) piv = i;
-        if (A[piv * n + col] == 0.0) return false;
-        if (piv != col) {
-            for (int j = 0; j < n; ++j) std::swap(A[col * n + j], A[piv * n + j]);
-            std::swap(r[col], r[piv]);
-        }
-        for (int i = col + 1; i < n; ++i) {
-            double f = A[i * n + col] / A[col * n + col];
-            for (int j = col; j < n; ++j) A[i * n + j] -= f * A[col * n + j];
-            r[i] -= f * r[col];
-        }
-    }
-    std::vector<double> x(n, 0.0);
-    for (int i = n - 1; i >= 0; --i) {
-        double s = r[i];
-        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
-        x[i] = s / A[i * n + i];
-    }
-    c.assign(x.begin(), x.begin() + m);
-    return true;
-}
 
 }  // namespace
 
@@ -805,6 +920,10 @@ int impl_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_
             return fail(nullptr, CCSD_K_EINVAL, id + "unsupported precision");
         }
         S.mixed = d.precision == CCSD_K_PREC_MIXED;
+        if (d.grouping != CCSD_K_GROUPING_STANDARD && d.grouping != CCSD_K_GROUPING_REARRANGED)
+            return fail(nullptr, CCSD_K_EINVAL, id + "unknown grouping");
+        if (d.grouping == CCSD_K_GROUPING_REARRANGED && S.mixed)
+            return fail(nullptr, CCSD_K_EINVAL, id + "the rearranged hole-hole grouping runs on the FP64 path only");
         if (d.diis_space != 0 && (d.diis_space < 2 || d.diis_space > 16)) {
             return fail(nullptr, CCSD_K_EINVAL, id + "diis_space must be 0 or 2..16");
         }
@@ -819,7 +938,6 @@ int impl_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_
             for (int b = 0; b < N; ++b)
                 for (int k = 0; k < N; ++k) S.kc[((int64_t)a * N + b) * N + k] = kcons(S.mesh, a, b, k);
         build_tables(S);
-        S.B.assign((size_t)d.diis_space * d.diis_space, 0.0);
     }
     *out = holder.release();
     return CCSD_K_OK;
@@ -829,6 +947,8 @@ int impl_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes) {
     if (!ctx || !bytes) return CCSD_K_EINVAL;
     Carver cv{0, 0, false};
     for (auto &S : const_cast<ccsd_k_ctx *>(ctx)->sys) carve(S, cv);
+    double *norms = nullptr;
+    cv.take(norms, (int64_t)ctx->sys.size());
     *bytes = cv.off + 256;
     return CCSD_K_OK;
 }
@@ -845,6 +965,7 @@ int impl_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
     try {
         Carver cv{(uintptr_t)device_ptr, 0, true};
         for (auto &S : ctx->sys) carve(S, cv);
+        cv.take(ctx->dnorms, (int64_t)ctx->sys.size());
         for (auto &S : ctx->sys) {
             CK_CHECK(hipMemcpyAsync(S.dkc, S.kc.data(), S.kc.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
             CK_CHECK(hipMemcpyAsync(S.dtab, S.tables.data(), S.tables.size() * sizeof(int64_t), hipMemcpyHostToDevice,
@@ -985,6 +1106,62 @@ int impl_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *
     return CCSD_K_OK;
 }
 
+// One iteration of the systems in `active`: residual, norm (also copied to the context's
+// norm array), and the update gated on that norm (plain substitution, or the DIIS update,
+// its step and the extrapolation), enqueued on the context's stream and its lanes with no
+// host decision in between, so that it can be captured once and replayed as a graph.
+void enqueue_iteration(ccsd_k_ctx *c, const std::vector<System *> &active, double tol) {
+    const std::vector<hipStream_t> ls = fork_lanes(c, active);
+    for (size_t k = 0; k < active.size(); ++k) {
+        System &S = *active[k];
+        const hipStream_t st = ls[k];
+        residual_device(c, S, st);
+        launch_norm(S, st);
+        hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, st, S.redout, c->dnorms + (&S - c->sys.data()));
+        CK_CHECK(hipGetLastError());
+        const ck::Gate gate{S.redout, tol};
+        const ck::SysDev sd = S.dev();
+        if (S.desc.diis_space == 0) {
+            if (S.mixed) ck::launch_update(sd, S.t1(), S.t2(), S.r1(), S.r2c, nullptr, nullptr, gate, st);
+            else ck::launch_update(sd, S.t1(), S.t2(), S.r1(), S.r2(), nullptr, nullptr, gate, st);
+            continue;
+        }
+        std::vector<const cd *> src(S.dvec.begin(), S.dvec.end());
+        if (S.mixed) {
+            ck::launch_update_diis_pack(sd, S.pairs(), S.amp, S.res, S.r2c, S.derr32.data(), S.dvec.data(), S.diis(),
+                                        gate, S.red, st);
+            ck::launch_lincomb_packed(sd, S.pairs(), src.data(), S.diis(), gate, S.amp, S.sp_t2, S.c64_ring(), S.epart,
+                                      st);
+        } else {
+            ck::launch_update_diis(sd, S.amp, S.res, S.r2(), S.derr.data(), S.dvec.data(), S.diis(), gate, S.red, st);
+            ck::launch_lincomb(S.n1() + S.n2(), src.data(), S.diis(), gate, S.amp, st);
+        }
+    }
+    join_lanes(c, ls);
+}
+
+// What a captured iteration depends on beyond the buffers: the active set, each system's
+// arithmetic forms, k chunk and whether its residual re-splits t2, and the tolerance.
+std::vector<int64_t> iteration_signature(ccsd_k_ctx *c, double tol) {
+    std::vector<int64_t> sig;
+    int64_t tb;
+    std::memcpy(&tb, &tol, sizeof tb);
+    sig.push_back(tb);
+    for (const System &S : c->sys) {
+        sig.push_back(S.converged ? -1 : 1);
+        for (int a : S.arith) sig.push_back(a);
+        sig.push_back(S.kchunk);
+        sig.push_back(S.sp_ok ? 1 : 0);
+    }
+    return sig;
+}
+
+void drop_graph(ccsd_k_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->gsig.clear();
+}
+
 int impl_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, double *max_rnorm) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
@@ -993,6 +1170,7 @@ int impl_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, 
         if (!ctx->sys[s].inputs) return fail(ctx, CCSD_K_ESTATE, "inputs of system " + std::to_string(s) + " not set");
     int done = 0;
     bool numeric_error = false;
+    std::vector<double> hn(ctx->sys.size(), 0.0);
     try {
         for (auto &S : ctx->sys) S.converged = false;
         for (int it = 0; it < max_iter; ++it) {
@@ -1000,93 +1178,62 @@ int impl_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, 
             for (auto &S : ctx->sys)
                 if (!S.converged) active.push_back(&S);
             if (active.empty()) break;
-            {
-                const std::vector<hipStream_t> ls = fork_lanes(ctx, active);
-                for (size_t k = 0; k < active.size(); ++k) {
-                    residual_device(ctx, *active[k], ls[k]);
-                    launch_norm(*active[k], ls[k]);
+            for (System *S : active)
+                if (S->diis_reset) {  // outside any captured work
+                    CK_CHECK(hipMemsetAsync(S->dstate, 0, 4 * sizeof(int32_t), ctx->stream));
+                    S->diis_reset = false;
                 }
-                join_lanes(ctx, ls);
+            if (ctx->graphs && !ctx->timing && ctx->stream) {  // (the null stream cannot be captured)
+                const std::vector<int64_t> sig = iteration_signature(ctx, tol);
+                if (!ctx->gexec || sig != ctx->gsig) {
+                    drop_graph(ctx);
+                    if (active.size() > 1) {  // the lanes exist before the capture starts
+                        const std::vector<hipStream_t> ls0 = fork_lanes(ctx, active);
+                        join_lanes(ctx, ls0);
+                    }
+                    CK_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+                    try {
+                        enqueue_iteration(ctx, active, tol);
+                    } catch (...) {
+                        hipGraph_t g = nullptr;
+                        (void)hipStreamEndCapture(ctx->stream, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    hipGraph_t g = nullptr;
+                    CK_CHECK(hipStreamEndCapture(ctx->stream, &g));
+                    const hipError_t ie = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    CK_CHECK(ie);
+                    ctx->gsig = sig;
+                }
+                CK_CHECK(hipGraphLaunch(ctx->gexec, ctx->stream));
+            } else {
+                enqueue_iteration(ctx, active, tol);
             }
+            CK_CHECK(hipMemcpyAsync(hn.data(), ctx->dnorms, hn.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                    ctx->stream));
             CK_CHECK(hipStreamSynchronize(ctx->stream));
             done = it + 1;
-            std::vector<System *> upd;
             for (System *S : active) {
-                double h = 0.0;
-                CK_CHECK(hipMemcpy(&h, S->redout, sizeof(double), hipMemcpyDeviceToHost));
-                S->rnorm = std::sqrt(h);
+                S->rnorm = std::sqrt(hn[S - ctx->sys.data()]);
                 if (!std::isfinite(S->rnorm)) numeric_error = true;
-                if (S->rnorm < tol) S->converged = true;
-                else upd.push_back(S);
-            }
-            if (numeric_error) break;
-            const std::vector<hipStream_t> ls = fork_lanes(ctx, upd);
-            for (size_t k = 0; k < upd.size(); ++k) {
-                System *S = upd[k];
-                hipStream_t st = ls[k];
-                ck::SysDev sd = S->dev();
-                int m = S->desc.diis_space;
-                if (m == 0) {
-                    if (S->mixed)
-                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2c, nullptr, nullptr, st);
-                    else
-                        ck::launch_update(sd, S->t1(), S->t2(), S->r1(), S->r2(), nullptr, nullptr, st);
-                    amplitudes_changed(*S);
+                if (S->rnorm < tol) {  // the gate closed on the device too: no update
+                    S->converged = true;
+                    if (S->mixed) S->sp_ok = true;
                     continue;
                 }
-                int slot = S->diis_head;
-                int held = std::min(S->diis_n + 1, m);
-                if (S->mixed) {
-                    std::vector<const ck::cf *> ys(S->derr32.begin(), S->derr32.begin() + held);
-                    ck::launch_update_diis(sd, S->amp, S->res, S->r2c, S->derr32[slot], S->dvec[slot], ys.data(),
-                                           held, slot, S->red, S->redout, st);
-                } else {
-                    std::vector<const cd *> ys(S->derr.begin(), S->derr.begin() + held);
-                    ck::launch_update_diis(sd, S->amp, S->res, S->r2(), S->derr[slot], S->dvec[slot], ys.data(),
-                                           held, slot, S->red, S->redout, st);
-                }
+                // the update ran: the extrapolation of the mixed path left the operand copy
+                // of t2 and the energy partial sums of the new amplitudes
+                if (S->mixed && S->desc.diis_space > 0) S->sp_ok = S->e_ok = true;
+                else amplitudes_changed(*S);
+                if (ctx->escalate) watch_stagnation(ctx, *S);
             }
-            join_lanes(ctx, ls);
-            CK_CHECK(hipStreamSynchronize(ctx->stream));
-            const std::vector<hipStream_t> lc = fork_lanes(ctx, upd);
-            for (size_t k = 0; k < upd.size(); ++k) {
-                System *S = upd[k];
-                int m = S->desc.diis_space;
-                if (m == 0) continue;
-                int slot = S->diis_head;
-                int held = std::min(S->diis_n + 1, m);
-                double dots[16];
-                CK_CHECK(hipMemcpy(dots, S->redout, held * sizeof(double), hipMemcpyDeviceToHost));
-                for (int j = 0; j < held; ++j) S->B[slot * m + j] = S->B[j * m + slot] = dots[j];
-                S->diis_n = held;
-                S->diis_head = (slot + 1) % m;
-                // the new amplitudes are in dvec[slot]: extrapolate into amp, or copy them
-                // (a combination with the single coefficient 1, exact) when there is no
-                // extrapolation; the held slots in FIFO order do not matter for the solution
-                std::vector<double> Bs((size_t)held * held), coef;
-                for (int i = 0; i < held; ++i)
-                    for (int j = 0; j < held; ++j) Bs[i * held + j] = S->B[i * m + j];
-                std::vector<const cd *> src;
-                if (held >= 2 && diis_solve(Bs, held, coef)) {
-                    for (int j = 0; j < held; ++j) src.push_back(S->dvec[j]);
-                } else {
-                    src.push_back(S->dvec[slot]);
-                    coef.assign(1, 1.0);
-                }
-                if (S->mixed) {
-                    ck::launch_lincomb_pack(S->dev(), src.data(), coef.data(), (int)src.size(), S->amp, S->sp_t2,
-                                            S->epart, lc[k]);
-                    S->sp_ok = S->e_ok = true;
-                } else {
-                    ck::launch_lincomb(S->n1() + S->n2(), src.data(), coef.data(), (int)src.size(), S->amp,
-                                       lc[k]);
-                }
-            }
-            join_lanes(ctx, lc);
-            CK_CHECK(hipStreamSynchronize(ctx->stream));
+            if (numeric_error) break;
             collect_timing(ctx);
         }
     } catch (const ck::HipError &e) {
+        drop_graph(ctx);
         return fail(ctx, CCSD_K_EDEVICE, e.what);
     }
     double worst = 0.0;
@@ -1115,7 +1262,7 @@ int impl_energy(ccsd_k_ctx *ctx, int32_t sys, double *e_re, double *e_im) {
     System &S = ctx->sys[sys];
     double e[2] = {0.0, 0.0};
     try {
-        if (S.e_ok) ck::launch_energy_pack(S.d, S.epart, S.redout, ctx->stream);
+        if (S.e_ok) ck::launch_energy_packed(S.d, S.pairs(), S.epart, S.redout, ctx->stream);
         else ck::launch_energy(S.dev(), S.t1(), S.t2(), S.red, S.redout, ctx->stream);
         CK_CHECK(hipMemcpyAsync(e, S.redout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
         CK_CHECK(hipStreamSynchronize(ctx->stream));
@@ -1166,6 +1313,8 @@ int impl_flops(const ccsd_k_ctx *ctx, int32_t sys, double *gemm_flops, double *o
     double macs = N4 * o * o * v * v * v * v      // particle-particle ladder
                   + 2.0 * N4 * o * o * o * o * v * v  // W_mnij build + hole-hole ladder
                   + 2.0 * N4 * o * o * o * v * v * v;  // ring W build + ring product
+    // the rearranged hole-hole grouping applies t2 X-tilde and t2 Y-tilde separately
+    if (ctx->sys[sys].rearranged()) macs += N4 * o * o * o * o * v * v;
     if (gemm_flops) *gemm_flops = 8.0 * macs;
     double N3 = N * N * N;
     double small = N3 * (o * v * v * v * v * 2.0     // T1 dressing of <ab||ef>
@@ -1196,6 +1345,174 @@ int impl_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int6
     if (M) *M = o.M;
     if (N) *N = o.N;
     if (K) *K = o.K;
+    return CCSD_K_OK;
+}
+
+// product numbering of the timing stages (0 pp-ladder, 1 hh-ladder, 2 W_mnij, 3 ring W,
+// 4 ring) -> mixed product slot of S.sg
+constexpr int kSlotOfProduct[5] = {1, 2, 0, 3, 4};
+
+// Give product slot i the arithmetic form a; when its family's storage changes, the static
+// operands of the family are converted again and the split copy of t2 is marked stale.
+void apply_form(ccsd_k_ctx *c, System &S, int slot, int a) {
+    const bool lad = S.c64_lad(), ring = S.c64_ring();
+    S.arith[slot] = a;
+    if (lad != S.c64_lad() || ring != S.c64_ring()) {
+        S.sp_ok = false;
+        if (S.inputs) static_split(S, c->stream);
+    }
+}
+
+int check_mixed_product(ccsd_k_ctx *ctx, int32_t sys, int32_t product) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    if (!ctx->sys[sys].mixed) return fail(ctx, CCSD_K_EINVAL, "arithmetic forms apply to mixed-precision systems");
+    if (product < 0 || product > 4 || product == 1)
+        return fail(ctx, CCSD_K_EINVAL, "product must be 0, 2, 3 or 4 (the hole-hole ladder runs inside product 0)");
+    return CCSD_K_OK;
+}
+
+int impl_set_product_form(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t form) {
+    int rc = check_mixed_product(ctx, sys, product);
+    if (rc) return rc;
+    if (form < 0 || form >= ck::ARITH_COUNT) return fail(ctx, CCSD_K_EINVAL, "form must be in 0..3");
+    System &S = ctx->sys[sys];
+    try {
+        apply_form(ctx, S, kSlotOfProduct[product], form);
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    return CCSD_K_OK;
+}
+
+int impl_get_product_form(const ccsd_k_ctx *cctx, int32_t sys, int32_t product, int32_t *form) {
+    ccsd_k_ctx *ctx = const_cast<ccsd_k_ctx *>(cctx);
+    int rc = check_mixed_product(ctx, sys, product);
+    if (rc) return rc;
+    if (!form) return fail(ctx, CCSD_K_EINVAL, "null form");
+    *form = ctx->sys[sys].arith[kSlotOfProduct[product]];
+    return CCSD_K_OK;
+}
+
+// Average launch time (ms) of product slot i in arithmetic form a on the system's own
+// operands and tables.  Timing does not depend on the values; the outputs it overwrites
+// (W_mnij / W_mbej operands, Lp, X) are all recomputed by the next residual before use.
+double time_form(ccsd_k_ctx *c, System &S, int slot, int a, int reps) {
+    hipEvent_t e0, e1;
+    CK_CHECK(hipEventCreate(&e0));
+    CK_CHECK(hipEventCreate(&e1));
+    float ms = 0.f;
+    try {
+        auto launch = [&] {
+            if (ck::arith_c64(a)) ck::gemm_c64(S.sg[slot], a, c->stream);
+            else ck::gemm_split(S.sg[slot], c->stream);
+        };
+        launch();  // warm-up
+        CK_CHECK(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) launch();
+        CK_CHECK(hipEventRecord(e1, c->stream));
+        CK_CHECK(hipEventSynchronize(e1));
+        CK_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms / reps;
+}
+
+// Choose the arithmetic form of every mixed product of system sys: the fastest choice whose
+// measured product error is within budget.  A family (ladder: slots 0, 1; ring: 3, 4) runs
+// either all on split storage (every product PRESPLIT2) or all on complex64 storage (each
+// product any of SPLIT2, SPLIT3, FP32); the faster admissible option wins.  With no
+// admissible option the family takes, per product, the most accurate form.
+int impl_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache_path, int32_t *forms,
+                  double *report) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    System &S = ctx->sys[sys];
+    if (!S.mixed) return fail(ctx, CCSD_K_EINVAL, "arithmetic forms apply to mixed-precision systems");
+    if (!(budget > 0.0)) return fail(ctx, CCSD_K_EINVAL, "budget must be positive");
+    static const int slots[4] = {0, 1, 3, 4};  // W_mnij, ladders, W_mbej, ring
+    ck::TuneRecord rec[5];
+    try {
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+        const std::string dev = ck::device_key();
+        for (int slot : slots) {
+            const ck::SplitOps &o = S.sg[slot];
+            const std::string key = ck::tune_key(dev, o.G, o.M, o.N, o.K, o.fast);
+            if (ck::cache_lookup(cache_path, key, rec[slot])) continue;
+            ck::TuneRecord r;
+            for (int a = 0; a < ck::ARITH_COUNT; ++a) r.ms[a] = time_form(ctx, S, slot, a, 3);
+            const std::vector<double> e =
+                ck::form_errors(std::min(o.M, 256), std::min(o.N, 256), o.K, 1911 + slot, ctx->stream);
+            for (int a = 0; a < ck::ARITH_COUNT; ++a) r.err[a] = e[a];
+            rec[slot] = r;
+            ck::cache_store(cache_path, key, r);
+        }
+        int choice[5];
+        for (int fam = 0; fam < 2; ++fam) {
+            const int s0 = slots[2 * fam], s1 = slots[2 * fam + 1];
+            double t_split = -1.0, t_c64 = 0.0;
+            bool c64_ok = true;
+            if (rec[s0].err[0] <= budget && rec[s1].err[0] <= budget) t_split = rec[s0].ms[0] + rec[s1].ms[0];
+            int best[2];
+            for (int u = 0; u < 2; ++u) {
+                const ck::TuneRecord &r = rec[u ? s1 : s0];
+                int b = -1;
+                for (int a = 1; a < ck::ARITH_COUNT; ++a)
+                    if (r.err[a] <= budget && (b < 0 || r.ms[a] < r.ms[b])) b = a;
+                if (b < 0) {  // nothing within budget: the most accurate form
+                    c64_ok = false;
+                    b = 1;
+                    for (int a = 2; a < ck::ARITH_COUNT; ++a)
+                        if (r.err[a] < r.err[b]) b = a;
+                }
+                best[u] = b;
+                t_c64 += r.ms[b];
+            }
+            if (t_split >= 0.0 && (!c64_ok || t_split <= t_c64)) {
+                choice[s0] = choice[s1] = ck::ARITH_PRESPLIT2;
+            } else {
+                choice[s0] = best[0];
+                choice[s1] = best[1];
+            }
+        }
+        // the timing runs left stale operands: recompute them from the amplitudes
+        amplitudes_changed(S);
+        for (int slot : slots) S.arith[slot] = choice[slot];
+        if (S.inputs) static_split(S, ctx->stream);
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+        if (forms)
+            for (int p = 0; p < 5; ++p) forms[p] = p == 1 ? -1 : S.arith[kSlotOfProduct[p]];
+        if (report)
+            for (int p = 0; p < 5; ++p)
+                for (int a = 0; a < ck::ARITH_COUNT; ++a) {
+                    const bool none = p == 1;
+                    report[(p * ck::ARITH_COUNT + a) * 2] = none ? 0.0 : rec[kSlotOfProduct[p]].ms[a];
+                    report[(p * ck::ARITH_COUNT + a) * 2 + 1] = none ? 0.0 : rec[kSlotOfProduct[p]].err[a];
+                }
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    return CCSD_K_OK;
+}
+
+int impl_set_graphs(ccsd_k_ctx *ctx, int32_t enable) {
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    ctx->graphs = enable != 0;
+    if (!ctx->graphs) drop_graph(ctx);
+    return CCSD_K_OK;
+}
+
+int impl_set_escalation(ccsd_k_ctx *ctx, int32_t enable) {
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    ctx->escalate = enable != 0;
     return CCSD_K_OK;
 }
 
@@ -1287,6 +1604,27 @@ int impl_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A
             CK_CHECK(hipDeviceSynchronize());
             (void)hipFree(sA);
             (void)hipFree(sB);
+        } else if (reference >= 3 && reference <= 5) {
+            // complex64 operands, product in the arithmetic form reference - 2 (split-BF16 with
+            // two or three terms, or FP32 MFMA)
+            auto padded = [](int64_t n) { return (n + 63) / 64 * 64; };
+            int64_t pa = padded((int64_t)na), pb = padded((int64_t)nb);
+            ck::cf *cA = nullptr, *cB = nullptr;
+            CK_CHECK(hipMalloc(&cA, pa * sizeof(ck::cf)));
+            CK_CHECK(hipMalloc(&cB, pb * sizeof(ck::cf)));
+            ck::launch_to_c64((int64_t)na, dA, cA, nullptr);
+            ck::launch_to_c64((int64_t)nb, dB, cB, nullptr);
+            ck::SplitOps so{};
+            so.A = reinterpret_cast<const uint16_t *>(cA); so.B = reinterpret_cast<const uint16_t *>(cB); so.C = dC;
+            so.zeros = reinterpret_cast<const uint16_t *>(dZ);
+            so.a_row = op.a_row; so.a_k = op.a_k; so.b_col = op.b_col; so.b_k = op.b_k;
+            so.c_row = op.c_row; so.c_col = op.c_col;
+            so.G = G; so.M = M; so.N = N; so.K = K; so.alpha = 1.0; so.beta = 0.0;
+            so.fast = (K % 8 == 0) ? 1 : 0;
+            ck::gemm_c64(so, reference - 2, nullptr);
+            CK_CHECK(hipDeviceSynchronize());
+            (void)hipFree(cA);
+            (void)hipFree(cB);
         } else {
             ck::gemm_f64(op, nullptr);
         }
@@ -1375,6 +1713,27 @@ int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, in
     return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_product_shape(ctx, sys, product, G, M, N, K); });
 }
 
+int ccsd_k_set_product_form(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t form) {
+    return guarded(ctx, [&] { return impl_set_product_form(ctx, sys, product, form); });
+}
+
+int ccsd_k_get_product_form(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *form) {
+    return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_get_product_form(ctx, sys, product, form); });
+}
+
+int ccsd_k_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache_path, int32_t *forms,
+                    double *report) {
+    return guarded(ctx, [&] { return impl_autotune(ctx, sys, budget, cache_path, forms, report); });
+}
+
+int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable) {
+    return guarded(ctx, [&] { return impl_set_graphs(ctx, enable); });
+}
+
+int ccsd_k_set_escalation(ccsd_k_ctx *ctx, int32_t enable) {
+    return guarded(ctx, [&] { return impl_set_escalation(ctx, enable); });
+}
+
 int ccsd_k_timing(ccsd_k_ctx *ctx, int32_t enable) {
     return guarded(ctx, [&] { return impl_timing(ctx, enable); });
 }
@@ -1400,6 +1759,7 @@ int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double 
 
 void ccsd_k_free(ccsd_k_ctx *ctx) {
     if (!ctx) return;
+    drop_graph(ctx);
     if (!ctx->failed) {
         (void)hipStreamSynchronize(ctx->stream);
         for (auto &p : ctx->pending) ctx->pool.push_back(p);

@@ -66,15 +66,15 @@ void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st) {
 // ------------------------------------------------------------------ the GEMM
 // Eight consecutive k of one row of one plane, element by element (zeros out of range).
 __device__ inline u32x4 gather8(const uint16_t *base, const int64_t *ktab, const uint16_t *zeros, int g, int K,
-                                int kb, bool rok, int64_t row, int p) {
+                                int64_t kld, int kb, bool rok, int64_t row, int p) {
     uint32_t v[4];
 #pragma unroll
     for (int j = 0; j < 8; j += 2) {
         const int k = kb + j;
         const uint16_t *x0 =
-            (rok && k < K) ? base + split_index(row + ktab[(int64_t)g * K + min(k, K - 1)], p) : zeros;
+            (rok && k < K) ? base + split_index(row + ktab[(int64_t)g * kld + min(k, K - 1)], p) : zeros;
         const uint16_t *x1 =
-            (rok && k + 1 < K) ? base + split_index(row + ktab[(int64_t)g * K + min(k + 1, K - 1)], p) : zeros;
+            (rok && k + 1 < K) ? base + split_index(row + ktab[(int64_t)g * kld + min(k + 1, K - 1)], p) : zeros;
         v[j / 2] = (uint32_t)*x0 | (uint32_t)*x1 << 16;
     }
     return u32x4{v[0], v[1], v[2], v[3]};
@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 
     const int tid = threadIdx.x;
     const int M = op.M, N = op.N, K = op.K;
+    const int64_t kld = op.kld ? op.kld : K;
     const GemmTile tile = gemm_tile((M + BM - 1) / BM, (N + BN - 1) / BN, op.G, 8);
     if (!tile.valid) return;
     const int g = tile.g;
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
     }
     bf16x8 FA[2][2][4], FB[2][2][4];  // [set][fragment row i / column j][plane]: current, next stage
     bf16x8 NA[2][2];                   // -A_im of the current set, per fragment row
-    u32x4 sa[2][4], sb[2][4];   // staging sets: this thread's pieces of A and B of one stage
+    u32x4 sa[3][4], sb[3][4];   // staging sets: this thread's pieces of A and B of one stage
     int64_t ak_cur = 0, bk_cur = 0, ak_nxt = 0, bk_nxt = 0;
     // FAST implies K % 8 == 0 and K >= 8: clamp to the last whole 8-run so a 16-byte load
     // never leaves the operand; otherwise clamp to the last k
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 #define CK_KOFS(k0, ak, bk)                                          \
     {                                                                \
         const int kb_ = min((k0) + lc * 8, kclamp);                  \
-        ak = op.a_k[(int64_t)g * K + kb_];                           \
-        bk = op.b_k[(int64_t)g * K + kb_];                           \
+        ak = op.a_k[(int64_t)g * kld + kb_];                         \
+        bk = op.b_k[(int64_t)g * kld + kb_];                         \
     }
     // row lr + 8i of A or B, stage k0, into staging set S.  Separate names for the A and
     // B sets (no pointer select between them) keep the staging arrays in registers.
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
             const uint16_t *src_ = ok_ ? abase##i + ak_cur * 4 : op.zeros;                              \
             sa[S][i] = *(const u32x4 *)src_;                                                           \
         } else {                                                                                       \
-            sa[S][i] = gather8(op.A, op.a_k, op.zeros, g, K, kb_, aok##i, arow##i, lp);                \
+            sa[S][i] = gather8(op.A, op.a_k, op.zeros, g, K, kld, kb_, aok##i, arow##i, lp);                \
         }                                                                                              \
     }
 #define CK_LOADB(k0, S, i)                                                                              \
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
             const uint16_t *src_ = ok_ ? bbase##i + bk_cur * 4 : op.zeros;                              \
             sb[S][i] = *(const u32x4 *)src_;                                                           \
         } else {                                                                                       \
-            sb[S][i] = gather8(op.B, op.b_k, op.zeros, g, K, kb_, bok##i, bcol##i, lp);                \
+            sb[S][i] = gather8(op.B, op.b_k, op.zeros, g, K, kld, kb_, bok##i, bcol##i, lp);                \
         }                                                                                              \
     }
 #define CK_STOREA(buf, S, i) *(u32x4 *)(&As[buf][sto + (i) * 8 * RS]) = sa[S][i]
@@ -230,33 +231,33 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
 
     // one pipelined stage KT held in LDS buffer BUF (literal 0 or 1), its fragments in
     // register set BUF; staging set BUF receives stage KT+2, set BUF^1 holds stage KT+1
-#define CK_STAGE(KT, BUF)                                                                                             \
+#define CK_STAGE(KT, BUF, LS, SS)                                                                                             \
     {                                                                                                                 \
         CK_NEG(FA[BUF][0], NA[0]);                                                                                    \
         CK_NEG(FA[BUF][1], NA[1]);                                                                                    \
-        CK_MF(0, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_KOFS(((KT) + 3) * BK, ak_nxt, bk_nxt); CK_SLOT;       \
-        CK_MF(0, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADA(((KT) + 2) * BK, BUF, 0); CK_SLOT;              \
-        CK_MF(0, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADA(((KT) + 2) * BK, BUF, 1); CK_SLOT;              \
-        CK_MF(0, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADA(((KT) + 2) * BK, BUF, 2); CK_SLOT;              \
-        CK_MF(1, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADA(((KT) + 2) * BK, BUF, 3); CK_SLOT;              \
-        CK_MF(1, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADB(((KT) + 2) * BK, BUF, 0); CK_SLOT;              \
-        CK_MF(1, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADB(((KT) + 2) * BK, BUF, 1); CK_SLOT;              \
-        CK_MF(1, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADB(((KT) + 2) * BK, BUF, 2); CK_SLOT;              \
-        CK_MF(2, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADB(((KT) + 2) * BK, BUF, 3); CK_SLOT;              \
+        CK_MF(0, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_KOFS(((KT) + 4) * BK, ak_nxt, bk_nxt); CK_SLOT;       \
+        CK_MF(0, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADA(((KT) + 3) * BK, LS, 0); CK_SLOT;              \
+        CK_MF(0, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADA(((KT) + 3) * BK, LS, 1); CK_SLOT;              \
+        CK_MF(0, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADA(((KT) + 3) * BK, LS, 2); CK_SLOT;              \
+        CK_MF(1, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADA(((KT) + 3) * BK, LS, 3); CK_SLOT;              \
+        CK_MF(1, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_LOADB(((KT) + 3) * BK, LS, 0); CK_SLOT;              \
+        CK_MF(1, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_LOADB(((KT) + 3) * BK, LS, 1); CK_SLOT;              \
+        CK_MF(1, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_LOADB(((KT) + 3) * BK, LS, 2); CK_SLOT;              \
+        CK_MF(2, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_LOADB(((KT) + 3) * BK, LS, 3); CK_SLOT;              \
         CK_MF(2, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                 \
         CK_MF(2, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                 \
         CK_MF(2, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                 \
         CK_MF(3, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_SLOT;                                                 \
         CK_MF(3, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_SLOT;                                                 \
         CK_MF(3, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_SLOT;                                                 \
-        CK_MF(3, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;             \
-        CK_MF(4, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;             \
-        CK_MF(4, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;             \
-        CK_MF(4, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREA((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;             \
-        CK_MF(4, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 0); CK_SLOT;             \
-        CK_MF(5, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 1); CK_SLOT;             \
-        CK_MF(5, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 2); CK_SLOT;             \
-        CK_MF(5, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREB((BUF) ^ 1, (BUF) ^ 1, 3); CK_SLOT;             \
+        CK_MF(3, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREA((BUF) ^ 1, SS, 0); CK_SLOT;             \
+        CK_MF(4, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREA((BUF) ^ 1, SS, 1); CK_SLOT;             \
+        CK_MF(4, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREA((BUF) ^ 1, SS, 2); CK_SLOT;             \
+        CK_MF(4, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREA((BUF) ^ 1, SS, 3); CK_SLOT;             \
+        CK_MF(4, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_STOREB((BUF) ^ 1, SS, 0); CK_SLOT;             \
+        CK_MF(5, c00r, c00i, FA[BUF][0], NA[0], FB[BUF][0]); CK_STOREB((BUF) ^ 1, SS, 1); CK_SLOT;             \
+        CK_MF(5, c01r, c01i, FA[BUF][0], NA[0], FB[BUF][1]); CK_STOREB((BUF) ^ 1, SS, 2); CK_SLOT;             \
+        CK_MF(5, c10r, c10i, FA[BUF][1], NA[1], FB[BUF][0]); CK_STOREB((BUF) ^ 1, SS, 3); CK_SLOT;             \
         CK_MF(5, c11r, c11i, FA[BUF][1], NA[1], FB[BUF][1]); CK_SLOT;                                                 \
         __syncthreads();                                                                                              \
         CK_SLOT;                                                                                                      \
@@ -301,6 +302,9 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         CK_LOADA(BK, 1, 0); CK_LOADA(BK, 1, 1); CK_LOADA(BK, 1, 2); CK_LOADA(BK, 1, 3);
         CK_LOADB(BK, 1, 0); CK_LOADB(BK, 1, 1); CK_LOADB(BK, 1, 2); CK_LOADB(BK, 1, 3);
         CK_KOFS(2 * BK, ak_cur, bk_cur);
+        CK_LOADA(2 * BK, 2, 0); CK_LOADA(2 * BK, 2, 1); CK_LOADA(2 * BK, 2, 2); CK_LOADA(2 * BK, 2, 3);
+        CK_LOADB(2 * BK, 2, 0); CK_LOADB(2 * BK, 2, 1); CK_LOADB(2 * BK, 2, 2); CK_LOADB(2 * BK, 2, 3);
+        CK_KOFS(3 * BK, ak_cur, bk_cur);
         __syncthreads();
         // (constant indices only: a loop index here would let the compiler move the
         // register arrays to LDS)
@@ -308,14 +312,24 @@ __global__ __launch_bounds__(256) void k_gemm_split(SplitOps op) {
         CK_RDA(FA[0][1][0], 0, fa1, 0); CK_RDA(FA[0][1][1], 0, fa1, 1); CK_RDA(FA[0][1][2], 0, fa1, 2); CK_RDA(FA[0][1][3], 0, fa1, 3);
         CK_RDB(FB[0][0][0], 0, fb0, 0); CK_RDB(FB[0][0][1], 0, fb0, 1); CK_RDB(FB[0][0][2], 0, fb0, 2); CK_RDB(FB[0][0][3], 0, fb0, 3);
         CK_RDB(FB[0][1][0], 0, fb1, 0); CK_RDB(FB[0][1][1], 0, fb1, 1); CK_RDB(FB[0][1][2], 0, fb1, 2); CK_RDB(FB[0][1][3], 0, fb1, 3);
-        // unrolled by two so that every register set has a fixed role in each half; one
-        // exit, so the accumulators keep their registers across the halves
+        // unrolled by six (two LDS buffers and fragment sets, three staging sets) so that
+        // every register set has a fixed role in each stage; one exit, so the accumulators
+        // keep their registers across the stages.  Stage t: LDS buffer t % 2, loads into
+        // staging set t % 3, LDS writes from set (t + 1) % 3.
         int kt = 0;
-        for (; kt + 1 < nk; kt += 2) {
-            CK_STAGE(kt, 0);
-            CK_STAGE(kt + 1, 1);
+        for (; kt + 5 < nk; kt += 6) {
+            CK_STAGE(kt, 0, 0, 1);
+            CK_STAGE(kt + 1, 1, 1, 2);
+            CK_STAGE(kt + 2, 0, 2, 0);
+            CK_STAGE(kt + 3, 1, 0, 1);
+            CK_STAGE(kt + 4, 0, 1, 2);
+            CK_STAGE(kt + 5, 1, 2, 0);
         }
-        if (kt < nk) CK_STAGE(kt, 0);
+        if (kt < nk) CK_STAGE(kt, 0, 0, 1);
+        if (kt + 1 < nk) CK_STAGE(kt + 1, 1, 1, 2);
+        if (kt + 2 < nk) CK_STAGE(kt + 2, 0, 2, 0);
+        if (kt + 3 < nk) CK_STAGE(kt + 3, 1, 0, 1);
+        if (kt + 4 < nk) CK_STAGE(kt + 4, 0, 1, 2);
     }
 #undef CK_SLOT
 #undef CK_MF

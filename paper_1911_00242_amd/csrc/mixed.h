@@ -53,6 +53,31 @@ __device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8]) {
                           h[p][4] | (uint32_t)h[p][5] << 16, h[p][6] | (uint32_t)h[p][7] << 16);
 }
 
+// One element, or eight consecutive ones, in the storage of an operand family: split
+// storage (c64 false) or complex64 storage (c64 true: element e at float2 index e).
+__device__ inline void put_elem(uint16_t *dst, int64_t e, cd v, bool c64) {
+    if (c64) {
+        reinterpret_cast<cf *>(dst)[e] = make_float2((float)v.x, (float)v.y);
+        return;
+    }
+    uint16_t h0, h1, h2, h3;
+    split2c(v, h0, h1, h2, h3);
+    dst[split_index(e, 0)] = h0;
+    dst[split_index(e, 1)] = h1;
+    dst[split_index(e, 2)] = h2;
+    dst[split_index(e, 3)] = h3;
+}
+__device__ inline void put_chunk(uint16_t *dst, int64_t e0, const cd (&x)[8], bool c64) {
+    if (!c64) {
+        put_chunk(dst, e0, x);
+        return;
+    }
+    float4 *o = reinterpret_cast<float4 *>(reinterpret_cast<cf *>(dst) + e0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        o[q] = make_float4((float)x[2 * q].x, (float)x[2 * q].y, (float)x[2 * q + 1].x, (float)x[2 * q + 1].y);
+}
+
 // Grouped complex GEMM on split-BF16 operands; same offset tables as GemmOps (element
 // offsets into the unsplit operand, mapped through split_index).  C is complex128.
 // fast = 1 when every aligned group of 8 k indices is contiguous and starts at a multiple
@@ -70,10 +95,29 @@ struct SplitOps {
     int G, M, N, K;
     double alpha, beta;
     int fast;
+    // entries per group of the k tables (a_k[g * kld + k]); 0: K.  A product over a range of
+    // k is then a_k, b_k offset to the range's first k with K its length.
+    int64_t kld = 0;
 };
 
 void gemm_split(const SplitOps &op, hipStream_t s);
+
+// Arithmetic forms of a mixed-precision product.  PRESPLIT2 runs on split storage (the
+// layout above); the other three on complex64 storage (interleaved float2, element e at
+// float2 index e; an operand of n elements takes round_up(n, 8) of them, the same bytes
+// as its split storage), splitting in registers.
+enum Arith { ARITH_PRESPLIT2 = 0, ARITH_SPLIT2 = 1, ARITH_SPLIT3 = 2, ARITH_FP32 = 3, ARITH_COUNT = 4 };
+inline bool arith_c64(int a) { return a != ARITH_PRESPLIT2; }
+// the product on complex64 operands (A, B, Cs of op read / written as complex64)
+void gemm_c64(const SplitOps &op, int arith, hipStream_t s);
+// complex64 storage of n complex128 elements (round to nearest; padding zeroed)
+void launch_to_c64(int64_t n, const cd *src, cf *dst, hipStream_t st);
 // split storage of n complex128 elements (pad of the last chunk zeroed)
 void launch_split(int64_t n, const cd *src, uint16_t *dst, hipStream_t st);
+// an operand in the storage of its family
+inline void launch_operand(int64_t n, const cd *src, uint16_t *dst, bool c64, hipStream_t st) {
+    if (c64) launch_to_c64(n, src, reinterpret_cast<cf *>(dst), st);
+    else launch_split(n, src, dst, st);
+}
 
 }  // namespace ck

@@ -10,7 +10,8 @@
 // columns.  The ladder products therefore run on packed operands, canonical pairs of every
 // group in a fixed order padded with zeros to a multiple of 16, and take an eighth of the
 // work of the full products; their result stays packed (Lp) until the R2 assembly expands
-// it.  Every packed operand is written here in split storage.
+// it.  Every packed operand is written here in the storage of the ladder family: split
+// storage, or complex64 when the family's products run on complex64 operands.
 #include <algorithm>
 
 #include "common.h"
@@ -27,7 +28,7 @@ namespace ck {
 // words.  EX: n_occ = 8, n_vir = 16 as constants.
 template <bool EX>
 __global__ __launch_bounds__(256) void k_tau_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *t1,
-                                                  const cd *t2, uint16_t *out, int64_t ld) {
+                                                  const cd *t2, uint16_t *out, int64_t ld, bool c64) {
     __shared__ __align__(16) uint16_t S[256 * 4];  // chunk-local split layout: chunk * 32 + plane * 8 + q
     const int N = d.N, no = EX ? 8 : d.no, nv = EX ? 16 : d.nv;
     const int64_t t2blk = (int64_t)no * no * nv * nv;
@@ -49,6 +50,13 @@ __global__ __launch_bounds__(256) void k_tau_pack(Dims d, const int32_t *kc, Pai
                 const int64_t idx = blk3(N, ki, kj, ke) * t2blk + (((int64_t)i * no + j) * nv + e) * nv + f;
                 v = tau_el(t1, t2, idx, ki, kj, ke, kf, i, j, e, f, no, nv, 1.0);
             }
+        }
+        if (c64) {  // complex64 storage: consecutive threads write consecutive elements of a row
+            if (x < total) {
+                const int64_t row = x / pt.PV;
+                reinterpret_cast<cf *>(out)[row * ld + (x - row * pt.PV)] = make_float2((float)v.x, (float)v.y);
+            }
+            continue;  // uniform over the grid: no barrier is skipped by part of a workgroup
         }
         uint16_t h0, h1, h2, h3;
         split2c(v, h0, h1, h2, h3);
@@ -118,9 +126,25 @@ __global__ __launch_bounds__(256) void k_tau_transpose(int PO, int PV, const uin
     }
 }
 
+// The same transpose in complex64 storage: 8-byte elements through a 64 x 64 LDS tile.
+__global__ __launch_bounds__(256) void k_tau_transpose_c64(int PO, int PV, const uint2 *src, int64_t lds, uint2 *dst,
+                                                           int64_t ldd) {
+    __shared__ uint2 T[TT][TT + 1];  // [p' - m0][p - n0]
+    const int K = blockIdx.z, m0 = blockIdx.y * TT, n0 = blockIdx.x * TT;
+    for (int u = threadIdx.x; u < TT * TT; u += blockDim.x) {
+        const int r = u / TT, c = u % TT, row = m0 + r, col = n0 + c;
+        if (row < PO && col < PV) T[r][c] = src[((int64_t)K * PO + row) * lds + col];
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < TT * TT; u += blockDim.x) {
+        const int r = u / TT, c = u % TT, row = n0 + r, col = m0 + c;
+        if (row < PV && col < PO) dst[((int64_t)K * PV + row) * ldd + col] = T[c][r];
+    }
+}
+
 // oovv_pk[K][p'][p] = <m km, n kn || e ke, f kf> for canonical (km, m, n) = p' and canonical
 // (ke, e, f) = p of group K: the B operand of the W_mnij product (static).
-__global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oovv, uint16_t *out) {
+__global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oovv, uint16_t *out, bool c64) {
     const int N = d.N, no = d.no, nv = d.nv;
     const int nch = pt.PV / 8;
     const int64_t total = (int64_t)N * pt.PO * nch;
@@ -142,7 +166,7 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
             const int kn = kcv(kc, N, K, 0, km);
             v[q] = oovv[blk3(N, km, kn, ke) * d.t2blk() + (((int64_t)mm * no + nn) * nv + e) * nv + f];
         }
-        put_chunk(out, row * pt.PV + (int64_t)c * 8, v);
+        put_chunk(out, row * pt.PV + (int64_t)c * 8, v, c64);
     }
 }
 
@@ -156,7 +180,7 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // when o v^2 <= 2048).  For n_occ <= OM and o v <= 2048.
 template <int OM>
 __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
-                                                         int64_t ld) {
+                                                         int64_t ld, bool c64) {
     __shared__ cd G1[2048];
     __shared__ cd TA[OM * 64];
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
@@ -207,13 +231,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
                         cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
                         acc = csub(acc, cmul(TA[m * na + a], g2[m]));
                     }
-                const int64_t o = ((int64_t)K * pt.PV + pab) * ld + pef;
-                uint16_t h0, h1, h2, h3;
-                split2c(acc, h0, h1, h2, h3);
-                out[split_index(o, 0)] = h0;
-                out[split_index(o, 1)] = h1;
-                out[split_index(o, 2)] = h2;
-                out[split_index(o, 3)] = h3;
+                put_elem(out, ((int64_t)K * pt.PV + pab) * ld + pef, acc, c64);
             }
         }
     }
@@ -221,7 +239,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
 
 // Plain form for other sizes: a thread per 8 consecutive p of one p', every term from
 // global memory.
-__global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uint16_t *out, int64_t ld) {
+__global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uint16_t *out, int64_t ld, bool c64) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
     const int nch = pt.PV / 8;
@@ -249,7 +267,7 @@ __global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uin
             }
             v[q] = acc;
         }
-        put_chunk(out, row * ld + (int64_t)c * 8, v);
+        put_chunk(out, row * ld + (int64_t)c * 8, v, c64);
     }
 }
 
@@ -262,40 +280,44 @@ static dim3 pack_grid(int64_t threads) {
 bool dress_pack_ok(const Dims &d) { return d.no <= 32 && (int64_t)d.no * d.nv <= 2048; }
 
 void launch_tau_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *t1, const cd *t2,
-                     uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, hipStream_t st) {
+                     uint16_t *tau_pk, int64_t ld_tau, uint16_t *tauT_pk, int64_t ld_tauT, bool c64, hipStream_t st) {
     const int64_t N = d.N;
     const dim3 g = pack_grid(N * pt.PO * pt.PV);
     if (d.no == 8 && d.nv == 16)
-        hipLaunchKernelGGL(k_tau_pack<true>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau);
+        hipLaunchKernelGGL(k_tau_pack<true>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau, c64);
     else
-        hipLaunchKernelGGL(k_tau_pack<false>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau);
+        hipLaunchKernelGGL(k_tau_pack<false>, g, dim3(256), 0, st, d, kc, pt, t1, t2, tau_pk, ld_tau, c64);
     CK_CHECK(hipGetLastError());
     const dim3 gt((unsigned)((pt.PV + TT - 1) / TT), (unsigned)((pt.PO + TT - 1) / TT), (unsigned)N);
-    hipLaunchKernelGGL(k_tau_transpose, gt, dim3(256), 0, st, pt.PO, pt.PV, tau_pk, ld_tau, tauT_pk, ld_tauT);
+    if (c64)
+        hipLaunchKernelGGL(k_tau_transpose_c64, gt, dim3(256), 0, st, pt.PO, pt.PV, (const uint2 *)tau_pk, ld_tau,
+                           (uint2 *)tauT_pk, ld_tauT);
+    else
+        hipLaunchKernelGGL(k_tau_transpose, gt, dim3(256), 0, st, pt.PO, pt.PV, tau_pk, ld_tau, tauT_pk, ld_tauT);
     CK_CHECK(hipGetLastError());
 }
 
-void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out,
+void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, const cd *oovv, uint16_t *out, bool c64,
                       hipStream_t st) {
     const int64_t N = d.N;
-    hipLaunchKernelGGL(k_oovv_pack, pack_grid(N * pt.PO * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, oovv, out);
+    hipLaunchKernelGGL(k_oovv_pack, pack_grid(N * pt.PO * (pt.PV / 8)), dim3(256), 0, st, d, kc, pt, oovv, out, c64);
     CK_CHECK(hipGetLastError());
 }
 
-void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld,
+void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, uint16_t *out, int64_t ld, bool c64,
                             hipStream_t st) {
     const int64_t N = s.d.N, nv = s.d.nv;
     const int64_t n = (int64_t)pt.ndblk * nv;
     const dim3 grid((unsigned)((n + 7) / 8 * 8));
     if (!dress_pack_ok(s.d))
         hipLaunchKernelGGL(k_vvvv_dress_pack_plain, pack_grid(N * pt.PV * (pt.PV / 8)), dim3(256), 0, st, s, pt, t1,
-                           out, ld);
+                           out, ld, c64);
     else if (s.d.no <= 8)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else if (s.d.no <= 16)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else
-        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out, ld);
+        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     CK_CHECK(hipGetLastError());
 }
 
@@ -476,7 +498,8 @@ void launch_assemble_r2_pack(const SysDev &s, const PairTabs &pt, const cd *X, c
 // ------------------------------------------------------------------ DIIS extrapolation
 // t <- sum_j c_j src_j for the mixed path, split in two passes over the (t1 | t2) vector:
 // the t1 part (with the f_ia t_i^a term of the correlation energy), then the t2 part, which
-// also writes the split copy of t2 that the next residual's products read and the t2 terms
+// (k_lincomb_t2_pack, from the packed history below) also writes the operand copy of t2 that
+// the next residual's products read and the t2 terms
 // of the energy at the new amplitudes (they need the new t1, hence the order).  The energy
 // is 1/4 <ij||ab> t_ij^ab + 1/2 <ij||ab> t_i^a t_j^b (k_a = k_i) summed over every stored
 // element, plus sum f_ia t_i^a, exactly as the stand-alone energy pass (both with the
@@ -498,7 +521,35 @@ __device__ inline void blk_sum2(double &x, double &y, double (*sh)[256]) {
     y = sh[1][0];
 }
 
-__global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, int m, cd *t, double *ep1) {
+constexpr int LINPACK_VMAX = 48;  // largest n_vir whose v x (v + 1) slab the extrapolation keeps in LDS
+
+struct ErrPackF {
+    cf *p[16];
+};
+struct HistPackD {
+    cd *p[16];
+};
+constexpr int UPD_PACK_BLOCKS = 4096;
+
+// sixteen running sums over the workgroup (fixed order); valid in v after the call
+__device__ inline void blk_sum16(double (&v)[16], double (*sh)[256]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sh[j][t] = v[j];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) sh[j][t] += sh[j][t + w];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = sh[j][0];
+}
+
+__global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, DiisDev dd, Gate gate, cd *t, double *ep1) {
+    if (!gate.open()) return;
+    const int m = dd.state[1];
     __shared__ double sh[2][256];
     const int no = s.d.no, nv = s.d.nv, n = no + nv;
     const int64_t n1 = s.d.t1();
@@ -507,8 +558,9 @@ __global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, int
         cd acc = make_double2(0.0, 0.0);
         for (int j = 0; j < m; ++j) {
             const cd x = L.src[j][idx];
-            acc.x = fma(L.c[j], x.x, acc.x);
-            acc.y = fma(L.c[j], x.y, acc.y);
+            const double c = dd.coef[j];
+            acc.x = fma(c, x.x, acc.x);
+            acc.y = fma(c, x.y, acc.y);
         }
         t[idx] = acc;
         const int a = (int)(idx % nv), i = (int)((idx / nv) % no), k = (int)(idx / ((int64_t)no * nv));
@@ -520,63 +572,6 @@ __global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, int
     if (threadIdx.x == 0) {
         ep1[0] = er;
         ep1[1] = ei;
-    }
-}
-
-// EX: n_occ = 8, n_vir = 16 as constants (the index decode of the energy terms becomes shifts)
-template <bool EX>
-__global__ __launch_bounds__(256) void k_lincomb_t2(SysDev s, LincombArgs L, int m, cd *t, uint16_t *sp, double *ep2) {
-    __shared__ __attribute__((aligned(16))) uint16_t S[4][2048];
-    __shared__ double sh[2][256];
-    const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
-    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, n2 = (int64_t)N * N * N * bs;
-    const int64_t nch = (n2 + 7) / 8;
-    const int tid = threadIdx.x;
-    const cd *t1 = t;  // the new t1, written by k_lincomb_t1
-    double er = 0.0, ei = 0.0;
-    for (int64_t c0 = (int64_t)blockIdx.x * 256; c0 < nch; c0 += (int64_t)gridDim.x * 256) {
-        const int64_t e0 = c0 * 8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t e = e0 + tid + 256 * q;
-            cd acc = make_double2(0.0, 0.0);
-            if (e < n2) {
-                for (int j = 0; j < m; ++j) {
-                    const cd x = L.src[j][n1 + e];
-                    acc.x = fma(L.c[j], x.x, acc.x);
-                    acc.y = fma(L.c[j], x.y, acc.y);
-                }
-                t[n1 + e] = acc;
-                const int blk = (int)(e / bs);  // momentum block (ki, kj, ka) < N^3
-                const int x = (int)(e - (int64_t)blk * bs);
-                const int b = x % nv, a = (x / nv) % nv, jj = (x / (nv * nv)) % no, i = x / (nv * nv * no);
-                const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
-                cd w = cscale(acc, 0.25);
-                if (ka == ki)
-                    w = cadd(w, cscale(cmul(t1[((int64_t)ki * no + i) * nv + a], t1[((int64_t)kj * no + jj) * nv + b]), 0.5));
-                const cd p = cmul(to_cd(s.oovv_c[e]), w);
-                er += p.x;
-                ei += p.y;
-            }
-            uint16_t h0, h1, h2, h3;
-            split2c(acc, h0, h1, h2, h3);
-            S[0][tid + 256 * q] = h0;
-            S[1][tid + 256 * q] = h1;
-            S[2][tid + 256 * q] = h2;
-            S[3][tid + 256 * q] = h3;
-        }
-        __syncthreads();
-        if (c0 + tid < nch) {
-            uint4 *o = (uint4 *)(sp + (c0 + tid) * 32);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) o[p] = *(const uint4 *)&S[p][8 * tid];
-        }
-        __syncthreads();
-    }
-    blk_sum2(er, ei, sh);
-    if (tid == 0) {
-        ep2[blockIdx.x] = er;
-        ep2[gridDim.x + blockIdx.x] = ei;
     }
 }
 
@@ -595,31 +590,188 @@ __global__ __launch_bounds__(256) void k_energy_final(const double *ep1, const d
     }
 }
 
-int lincomb_t2_blocks(const Dims &d) {
-    const int64_t nch = (d.t2() + 7) / 8;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((nch + 255) / 256, LINCOMB_T2_BLOCKS));
+// ------------------------------------------------------------------ packed DIIS history
+// The DIIS vectors of the mixed path hold t1 in full and t2 only on the representative block
+// of each antisymmetry orbit (pt.ablk: ki <= kj, ka <= kb; the whole o^2 v^2 block):
+// packed element (r, x) is t2[ablk[r]][x].  Every orbit member is +- a representative
+// element (t_ij^ab = -t_ji^ab = -t_ij^ba with the momenta), so an overlap over the full
+// vector is the packed overlap with weight w(r) = (ki < kj ? 2 : 1) (ka < kb ? 2 : 1) on
+// block r: the coefficients are the full ones, from about a quarter of the bytes.
+__device__ inline double pack_weight(int N, int blk, const int32_t *kc) {
+    const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
+    const int kb = kc[blk];
+    return (ki < kj ? 2.0 : 1.0) * (ka < kb ? 2.0 : 1.0);
 }
 
-void launch_lincomb_pack(const SysDev &s, const cd *const *src, const double *c, int m, cd *t, uint16_t *sp,
-                         double *epart, hipStream_t st) {
-    LincombArgs L{};
-    for (int j = 0; j < m; ++j) {
-        L.src[j] = src[j];
-        L.c[j] = c[j];
+template <bool EX>
+__global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt, const cd *t, const cd *r1, const cf *r2,
+                                                          ErrPackF y, HistPackD hp, DiisDev dd, Gate gate,
+                                                          double *partials) {
+    if (!gate.open()) return;
+    const int self = dd.state[0], m = min(dd.state[1] + 1, dd.m);
+    cf *err = y.p[self];
+    cd *hist = hp.p[self];
+    __shared__ double sh[16][256];
+    const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
+    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, np = n1 + (int64_t)pt.nablk * bs;
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < np; idx += (int64_t)gridDim.x * blockDim.x) {
+        double D, w = 1.0;
+        int64_t full;  // position in the full (t1 | t2) vector
+        if (idx < n1) {
+            const int x = (int)idx;
+            const int a = x % nv, i = (x / nv) % no, k = x / (no * nv);
+            D = s.eo[k * no + i] - s.ev[k * nv + a];
+            full = idx;
+        } else {
+            const int64_t r = (idx - n1) / bs;
+            const int x = (int)(idx - n1 - r * bs);
+            const int blk = pt.ablk[r];
+            const int b = x % nv, a = (x / nv) % nv, j = (x / (nv * nv)) % no, i = x / (nv * nv * no);
+            const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
+            const int kb = s.kc[blk];
+            D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
+            w = pack_weight(N, blk, s.kc);
+            full = n1 + (int64_t)blk * bs + x;
+        }
+        const cd rv = idx < n1 ? r1[idx] : to_cd(r2[full - n1]);
+        const double iD = 1.0 / D;
+        const cd e = make_double2(rv.x * iD, rv.y * iD);
+        hist[idx] = cadd(t[full], e);
+        cf es;
+        from_cd(e, es);
+        const cd ed = to_cd(es);
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < m) {
+                const cd b = j == self ? ed : to_cd(y.p[j][idx]);
+                v[j] = fma(w, fma(ed.x, b.x, ed.y * b.y), v[j]);
+            }
+        err[idx] = es;
     }
-    hipLaunchKernelGGL(k_lincomb_t1, dim3(1), dim3(256), 0, st, s, L, m, t, epart);
-    CK_CHECK(hipGetLastError());
-    const dim3 g((unsigned)lincomb_t2_blocks(s.d));
+    blk_sum16(v, sh);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < m; ++j) partials[(int64_t)j * UPD_PACK_BLOCKS + blockIdx.x] = v[j];
+}
+
+// t2 part of the extrapolation from packed history: a workgroup per (representative block,
+// i, j) (i <= j when ki == kj) forms the v x v slab sum_j c_j hist_j in LDS and writes the
+// orbit's members, t(ki,kj,ka; i,j) = L, t(kj,ki,ka; j,i) = -L, t(ki,kj,kb; i,j) = -L^T,
+// t(kj,ki,kb; j,i) = L^T (members that coincide with another are written once), each also
+// into the operand storage of the ring family (sp) and into the energy partial sums
+// (1/4 <ij||ab> t_ij^ab + 1/2 <ij||ab> t_i^a t_j^b, k_a = k_i, per written element).
+__global__ __launch_bounds__(256) void k_lincomb_t2_pack(SysDev s, PairTabs pt, LincombArgs L, DiisDev dd, Gate gate,
+                                                         cd *t, uint16_t *sp, bool c64, double *ep2) {
+    if (!gate.open()) return;
+    const int m = dd.state[1];
+    extern __shared__ cd SL[];  // v x (v + 1) (LDS form, n_vir <= LINPACK_VMAX)
+    __shared__ double sh[2][256];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv, vp = nv + 1;
+    const bool lds = nv <= LINPACK_VMAX;
+    const int64_t n1 = s.d.t1(), bs = s.d.t2blk();
+    const int64_t nblk = (int64_t)pt.nablk * no * no;
+    const int64_t L0 = blockIdx.x;
+    const int j = (int)(L0 % no), i = (int)((L0 / no) % no);
+    const int64_t r = L0 / ((int64_t)no * no);
+    double er = 0.0, ei = 0.0;
+    const int blk = r < pt.nablk ? pt.ablk[r] : 0;
+    const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
+    const bool live = L0 < nblk && !(ki == kj && i > j);
+    if (live) {
+        const int kb = kcv(s.kc, N, ki, kj, ka);
+        const int64_t src = n1 + r * bs + ((int64_t)i * no + j) * vv;
+        auto comb = [&](int e) {
+            cd acc = make_double2(0.0, 0.0);
+            for (int q = 0; q < m; ++q) {
+                const cd x = L.src[q][src + e];
+                const double c = dd.coef[q];
+                acc.x = fma(c, x.x, acc.x);
+                acc.y = fma(c, x.y, acc.y);
+            }
+            return acc;
+        };
+        if (lds) {
+            for (int e = threadIdx.x; e < vv; e += blockDim.x) SL[(e / nv) * vp + e % nv] = comb(e);
+            __syncthreads();
+        }
+        const cd *t1 = t;  // the new t1 (written by k_lincomb_t1 before this pass)
+        // one member: block (k1, k2, k3) with the pair (x at k1, y at k2) and a-slot momentum k3
+        auto put = [&](int k1, int k2, int k3, int x, int y, int a, int b, cd v) {
+            const int64_t o = blk3(N, k1, k2, k3) * bs + ((int64_t)x * no + y) * vv + (int64_t)a * nv + b;
+            t[n1 + o] = v;
+            put_elem(sp, o, v, c64);
+            cd wv = cscale(v, 0.25);
+            if (k3 == k1)
+                wv = cadd(wv, cscale(cmul(t1[((int64_t)k1 * no + x) * nv + a], t1[((int64_t)k2 * no + y) * nv + b]), 0.5));
+            const cd p = cmul(to_cd(s.oovv_c[o]), wv);
+            er += p.x;
+            ei += p.y;
+        };
+        const bool own_ij = ki == kj, own_ab = ka == kb;
+        for (int e = threadIdx.x; e < vv; e += blockDim.x) {
+            const int a = e / nv, b = e % nv;
+            const cd l = lds ? SL[a * vp + b] : comb(e), lt = lds ? SL[b * vp + a] : comb(b * nv + a);
+            put(ki, kj, ka, i, j, a, b, l);
+            if (!own_ij || i != j) {
+                if (!own_ij) put(kj, ki, ka, j, i, a, b, make_double2(-l.x, -l.y));
+                else put(ki, ki, ka, j, i, a, b, make_double2(-l.x, -l.y));  // the (j, i) slab of the same block
+            }
+            if (!own_ab) {
+                put(ki, kj, kb, i, j, a, b, make_double2(-lt.x, -lt.y));
+                if (!own_ij) put(kj, ki, kb, j, i, a, b, lt);
+                else if (i != j) put(ki, ki, kb, j, i, a, b, lt);
+            }
+        }
+    }
+    blk_sum2(er, ei, sh);
+    if (threadIdx.x == 0) {
+        ep2[blockIdx.x] = er;
+        ep2[gridDim.x + blockIdx.x] = ei;
+    }
+}
+
+int64_t packed_len(const Dims &d, const PairTabs &pt) { return d.t1() + (int64_t)pt.nablk * d.t2blk(); }
+
+void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cf *r2,
+                             cf *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
+                             hipStream_t st) {
+    ErrPackF pk{};
+    HistPackD hp{};
+    for (int j = 0; j < dd.m; ++j) {
+        pk.p[j] = err[j];
+        hp.p[j] = hist[j];
+    }
     if (s.d.no == 8 && s.d.nv == 16)
-        hipLaunchKernelGGL(k_lincomb_t2<true>, g, dim3(256), 0, st, s, L, m, t, sp, epart + 2);
+        hipLaunchKernelGGL((k_update_diis_pack<true>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1, r2, pk,
+                           hp, dd, gate, partials);
     else
-        hipLaunchKernelGGL(k_lincomb_t2<false>, g, dim3(256), 0, st, s, L, m, t, sp, epart + 2);
+        hipLaunchKernelGGL((k_update_diis_pack<false>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1, r2, pk,
+                           hp, dd, gate, partials);
+    CK_CHECK(hipGetLastError());
+    launch_diis_solve(dd, gate, partials, UPD_PACK_BLOCKS, st);
+}
+
+int64_t lincomb_pack_blocks(const Dims &d, const PairTabs &pt) { return std::max<int64_t>(1, (int64_t)pt.nablk * d.no * d.no); }
+
+void launch_lincomb_packed(const SysDev &s, const PairTabs &pt, const cd *const *src, const DiisDev &dd, Gate gate,
+                           cd *t, uint16_t *sp, bool c64, double *epart, hipStream_t st) {
+    LincombArgs L{};
+    for (int j = 0; j < dd.m; ++j) L.src[j] = src[j];
+    hipLaunchKernelGGL(k_lincomb_t1, dim3(1), dim3(256), 0, st, s, L, dd, gate, t, epart);
+    CK_CHECK(hipGetLastError());
+    const int64_t nb = lincomb_pack_blocks(s.d, pt);
+    const size_t lds = s.d.nv <= LINPACK_VMAX ? (size_t)s.d.nv * (s.d.nv + 1) * sizeof(cd) : 0;
+    hipLaunchKernelGGL(k_lincomb_t2_pack, dim3((unsigned)nb), dim3(256), lds, st, s, pt, L, dd, gate, t, sp, c64,
+                       epart + 2);
     CK_CHECK(hipGetLastError());
 }
 
-void launch_energy_pack(const Dims &d, const double *epart, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, epart, epart + 2, lincomb_t2_blocks(d), out);
+void launch_energy_packed(const Dims &d, const PairTabs &pt, const double *epart, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, epart, epart + 2, (int)lincomb_pack_blocks(d, pt), out);
     CK_CHECK(hipGetLastError());
 }
+
 
 }  // namespace ck

@@ -116,7 +116,8 @@ void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials
 
 
 template <class R2>
-__global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const R2 *r2, cd *err1, cd *err2) {
+__global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const R2 *r2, cd *err1, cd *err2, Gate gate) {
+    if (!gate.open()) return;
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n1 = s.d.t1(), n2 = s.d.t2();
     GRID_STRIDE(idx, n1 + n2) {
@@ -143,14 +144,16 @@ __global__ void k_update(SysDev s, cd *t1, cd *t2, const cd *r1, const R2 *r2, c
     }
 }
 
-void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2, Gate gate,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_update<cd>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2);
+    hipLaunchKernelGGL(k_update<cd>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2,
+                       gate);
     CK_CHECK(hipGetLastError());
 }
-void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2,
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2, Gate gate,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_update<cf>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2);
+    hipLaunchKernelGGL(k_update<cf>, grid_for(s.d.t1() + s.d.t2()), dim3(256), 0, st, s, t1, t2, r1, r2, err1, err2,
+                       gate);
     CK_CHECK(hipGetLastError());
 }
 
@@ -167,13 +170,22 @@ void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, 
 // momentum block and a 32-bit offset inside it.
 template <class E>
 struct ErrPack {
-    const E *p[16];
+    E *p[16];
+};
+struct HistPack {
+    cd *p[16];
 };
 
-// EX: n_occ = 8, n_vir = 16 as constants (the index decode becomes shifts).
+// EX: n_occ = 8, n_vir = 16 as constants (the index decode becomes shifts).  The slot and
+// the number of held vectors come from the device DIIS state; nothing happens when the
+// gate is closed (the system converged at this residual).
 template <class E, bool EX>
-__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r1, const E *r2, E *err,
-                                                     cd *hist, ErrPack<E> y, int m, int self, double *partials) {
+__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r1, const E *r2, ErrPack<E> y,
+                                                     HistPack hp, DiisDev dd, Gate gate, double *partials) {
+    if (!gate.open()) return;
+    const int self = dd.state[0], m = min(dd.state[1] + 1, dd.m);
+    E *err = y.p[self];
+    cd *hist = hp.p[self];
     __shared__ double sh[16][256];
     const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
     const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, n2 = (int64_t)N * N * N * bs;
@@ -216,60 +228,138 @@ __global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, cons
 }
 
 template <class E>
-void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r1, const E *r2, E *err, cd *hist,
-                          const E *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
+void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r1, const E *r2, E *const *err, cd *const *hist,
+                          const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
     ErrPack<E> pk{};
-    for (int j = 0; j < m; ++j) pk.p[j] = y[j];
-    if (s.d.no == 8 && s.d.nv == 16)
-        hipLaunchKernelGGL((k_update_diis<E, true>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk, m,
-                           self, partials);
-    else
-        hipLaunchKernelGGL((k_update_diis<E, false>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, err, hist, pk,
-                           m, self, partials);
-    CK_CHECK(hipGetLastError());
-    for (int j = 0; j < m; ++j) {
-        hipLaunchKernelGGL(k_final_sum<1>, dim3(1), dim3(256), 0, st, partials + (int64_t)j * UPD_BLOCKS,
-                           UPD_BLOCKS, out + j);
-        CK_CHECK(hipGetLastError());
+    HistPack hp{};
+    for (int j = 0; j < dd.m; ++j) {
+        pk.p[j] = err[j];
+        hp.p[j] = hist[j];
     }
+    if (s.d.no == 8 && s.d.nv == 16)
+        hipLaunchKernelGGL((k_update_diis<E, true>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, pk, hp, dd, gate,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_update_diis<E, false>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, pk, hp, dd,
+                           gate, partials);
+    CK_CHECK(hipGetLastError());
+    launch_diis_solve(dd, gate, partials, UPD_BLOCKS, st);
 }
 
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *err, cd *hist,
-                        const cd *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
-    launch_update_diis_t<cd>(s, t, r1, r2, err, hist, y, m, self, partials, out, st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *const *err, cd *const *hist,
+                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
+    launch_update_diis_t<cd>(s, t, r1, r2, err, hist, dd, gate, partials, st);
 }
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *err, cd *hist,
-                        const cf *const *y, int m, int self, double *partials, double *out, hipStream_t st) {
-    launch_update_diis_t<cf>(s, t, r1, r2, err, hist, y, m, self, partials, out, st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *const *err, cd *const *hist,
+                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
+    launch_update_diis_t<cf>(s, t, r1, r2, err, hist, dd, gate, partials, st);
+}
+
+// The DIIS step on the device, one workgroup: the overlaps of the new error vector with the
+// held ones (sums of the update pass's partials, fixed order) become row and column `slot`
+// of B; with two or more vectors held the bordered system
+//   [ B 1 ; 1^T 0 ] [ c ; lambda ] = [ 0 ; 1 ]
+// is solved by Gaussian elimination with partial pivoting (FP64), otherwise (or when it is
+// singular) c is the unit vector of the new slot, i.e. the new amplitudes unchanged.  Then
+// the FIFO advances.  Only B's held slots take part, so the FIFO order does not matter.
+__global__ __launch_bounds__(256) void k_diis_solve(DiisDev dd, Gate gate, const double *partials, int nparts) {
+    if (!gate.open()) return;
+    __shared__ double sh[256];
+    __shared__ double A[17 * 17], rhs[17];
+    const int m = dd.m, slot = dd.state[0], held = min(dd.state[1] + 1, m);
+    for (int j = 0; j < held; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += 256) v += partials[(int64_t)j * nparts + b];
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            dd.bnew[j] = sh[0];
+            dd.B[slot * m + j] = dd.B[j * m + slot] = sh[0];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < m; ++j) dd.coef[j] = 0.0;
+    bool ok = held >= 2;
+    if (ok) {
+        const int n = held + 1;
+        for (int i = 0; i < n * n; ++i) A[i] = 0.0;
+        for (int i = 0; i < held; ++i)
+            for (int j = 0; j < held; ++j) A[i * n + j] = dd.B[i * m + j];
+        for (int i = 0; i < held; ++i) A[i * n + held] = A[held * n + i] = 1.0;
+        for (int i = 0; i < n; ++i) rhs[i] = 0.0;
+        rhs[held] = 1.0;
+        for (int col = 0; col < n && ok; ++col) {
+            int piv = col;
+            for (int i = col + 1; i < n; ++i)
+                if (fabs(A[i * n + col]) > fabs(A[piv * n + col])) piv = i;
+            if (A[piv * n + col] == 0.0) {
+                ok = false;
+                break;
+            }
+            if (piv != col) {
+                for (int j = 0; j < n; ++j) {
+                    const double x = A[col * n + j];
+                    A[col * n + j] = A[piv * n + j];
+                    A[piv * n + j] = x;
+                }
+                const double x = rhs[col];
+                rhs[col] = rhs[piv];
+                rhs[piv] = x;
+            }
+            for (int i = col + 1; i < n; ++i) {
+                const double f = A[i * n + col] / A[col * n + col];
+                for (int j = col; j < n; ++j) A[i * n + j] -= f * A[col * n + j];
+                rhs[i] -= f * rhs[col];
+            }
+        }
+        if (ok) {
+            for (int i = n - 1; i >= 0; --i) {
+                double v = rhs[i];
+                for (int j = i + 1; j < n; ++j) v -= A[i * n + j] * rhs[j];
+                rhs[i] = v / A[i * n + i];
+            }
+            for (int j = 0; j < held; ++j) dd.coef[j] = rhs[j];
+        }
+    }
+    if (!ok) dd.coef[slot] = 1.0;
+    dd.state[0] = (slot + 1) % m;
+    dd.state[1] = held;
+}
+
+void launch_diis_solve(const DiisDev &dd, Gate gate, const double *partials, int nparts, hipStream_t st) {
+    hipLaunchKernelGGL(k_diis_solve, dim3(1), dim3(256), 0, st, dd, gate, partials, nparts);
+    CK_CHECK(hipGetLastError());
 }
 
 struct PtrPack {
     const cd *p[16];
 };
-struct CoefPack {
-    double c[16];
-};
 
-__global__ void k_lincomb(int64_t n, PtrPack src, CoefPack c, int m, cd *dst) {
+// dst = sum_j coef[j] src_j over the vectors held (device state, after the DIIS step)
+__global__ void k_lincomb(int64_t n, PtrPack src, DiisDev dd, Gate gate, cd *dst) {
+    if (!gate.open()) return;
+    const int m = dd.state[1];
     GRID_STRIDE(i, n) {
         cd acc = make_double2(0.0, 0.0);
         for (int j = 0; j < m; ++j) {
-            cd s = src.p[j][i];
-            acc.x = fma(c.c[j], s.x, acc.x);
-            acc.y = fma(c.c[j], s.y, acc.y);
+            const cd s = src.p[j][i];
+            const double c = dd.coef[j];
+            acc.x = fma(c, s.x, acc.x);
+            acc.y = fma(c, s.y, acc.y);
         }
         dst[i] = acc;
     }
 }
 
-void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st) {
+void launch_lincomb(int64_t n, const cd *const *src, const DiisDev &dd, Gate gate, cd *dst, hipStream_t st) {
     PtrPack pk{};
-    CoefPack cp{};
-    for (int j = 0; j < m; ++j) {
-        pk.p[j] = src[j];
-        cp.c[j] = c[j];
-    }
-    hipLaunchKernelGGL(k_lincomb, grid_for(n), dim3(256), 0, st, n, pk, cp, m, dst);
+    for (int j = 0; j < dd.m; ++j) pk.p[j] = src[j];
+    hipLaunchKernelGGL(k_lincomb, grid_for(n), dim3(256), 0, st, n, pk, dd, gate, dst);
     CK_CHECK(hipGetLastError());
 }
 

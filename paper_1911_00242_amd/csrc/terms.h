@@ -28,6 +28,12 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
 // (all that the packed W_mnij product reads); the plain fallback ignores it
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st);
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st);
+// per momentum block (o^2 x v^2) -> (v^2 x o^2)
+void launch_block_transpose(const Dims &d, const cd *src, cd *dst, hipStream_t st);
+// rearranged hole-hole grouping (FP64 path): Y-tilde_{mnij} in place on the W_mnij seed, and
+// the single-amplitude rest of the hole-hole ladder added to r2
+void launch_ytilde(const SysDev &s, const cd *t1, cd *WT, hipStream_t st);
+void launch_hh_t1_rest(const SysDev &s, const cd *t1, const cd *Y, const cd *X, cd *r2, hipStream_t st);
 // ring seeds: W_mbej without its t2 part (WR) and X = every non-ladder, non-driver term
 // arranged for one P(ij)P(ab); needs the F combinations of w
 void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
@@ -56,21 +62,44 @@ constexpr int UPD_BLOCKS = 4096;  // grid of the DIIS update pass (its partials:
 void launch_norm2(const Dims &d, const cd *r1, const cd *r2, double *partials, double *out, hipStream_t st);
 // out[0..1] = complex correlation energy; partials must hold 2*RED_BLOCKS doubles
 void launch_energy(const SysDev &s, const cd *t1, const cd *t2, double *partials, double *out, hipStream_t st);
+// The iteration's gate: the update kernels of a system run only while its residual norm
+// of this iteration (norm2 = ||R||^2 on the device) is at or above tol, so that one
+// enqueued (or graph-replayed) iteration leaves a converged system's amplitudes alone.  The
+// host takes the same decision, sqrt(norm2) < tol, from the same value.
+struct Gate {
+    const double *norm2;
+    double tol;
+    __device__ bool open() const { return sqrt(*norm2) >= tol; }
+};
+
+// Device-resident DIIS state of one system: state[0] the slot the next update writes (FIFO
+// head), state[1] the vectors held before it; B the m x m error overlaps (row / column of a
+// slot rewritten when the slot is), bnew the overlaps of the newest error vector, coef the
+// extrapolation coefficients of the held slots.
+struct DiisDev {
+    int32_t *state;
+    double *B, *bnew, *coef;
+    int m;
+};
+
 // t += r / D, and (optionally) err = r / D; r2 complex128, or complex64 (mixed path)
-void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2,
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, cd *err1, cd *err2, Gate gate,
                    hipStream_t st);
-void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2,
+void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2, Gate gate,
                    hipStream_t st);
-// DIIS form of the update over the contiguous (t1, t2) vector: e = r / D (r = r1 | r2),
-// hist = t + e (t itself is not written), err = e, and out[j] = Re <e, y_j> for j < m over
-// the stored values (y[self] is err); r2 and err complex128, or both complex64 (mixed
-// path); partials: m*UPD_BLOCKS
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *err, cd *hist,
-                        const cd *const *y, int m, int self, double *partials, double *out, hipStream_t st);
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *err, cd *hist,
-                        const cf *const *y, int m, int self, double *partials, double *out, hipStream_t st);
-// dst = sum_j c[j] * src_j over n complex elements (m <= 16)
-void launch_lincomb(int64_t n, const cd *const *src, const double *c, int m, cd *dst, hipStream_t st);
+// DIIS form of the update over the contiguous (t1, t2) vector (FP64 path): e = r / D
+// (r = r1 | r2), hist[slot] = t + e (t itself is not written), err[slot] = e, the overlaps
+// Re <e, err_j> of the held vectors over the stored values, then the DIIS step on the
+// device (launch_diis_solve); partials: 16 * UPD_BLOCKS
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *const *err, cd *const *hist,
+                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st);
+void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *const *err, cd *const *hist,
+                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st);
+// the DIIS step: overlaps from nparts partial sums per held vector, B, the bordered solve,
+// the coefficients and the FIFO advance (one workgroup)
+void launch_diis_solve(const DiisDev &dd, Gate gate, const double *partials, int nparts, hipStream_t st);
+// dst = sum_j coef[j] * src_j over n complex elements, the held vectors of dd
+void launch_lincomb(int64_t n, const cd *const *src, const DiisDev &dd, Gate gate, cd *dst, hipStream_t st);
 
 // device synthetic inputs (same recipe as the host generator) ------------------------
 void launch_synth_fock(const Mesh &m, int no, int nv, uint64_t seed, cd *fock, hipStream_t st);

@@ -711,6 +711,61 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
     }
 }
 
+// ------------------------------------------------------------------ rearranged hole-hole grouping
+// The hole-hole part of the T2 equation in the grouping of Sec. 3.3.4 (eqs. A_3rd, def_X and
+// the t2 Y-tilde_{mnij} term of eq. A_4th, with Y-tilde of eq. def_Y_oo), FP64 path.  On
+// the W_mnij seed (<mn||ij> + P(ij) t_j^c <mn||ic>, same layout), in place:
+//   Y[ki][kj][km](i,j,m,n) = 1/2 seed + 1/2 sum_cd t_i^c t_j^d <mn||cd>   (k_c = k_i, k_d = k_j)
+__global__ void k_ytilde(SysDev s, const cd *t1, cd *WT) {
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o4 = (int64_t)no * no * no * no;
+    GRID_STRIDE(idx, (int64_t)N * N * N * o4) {
+        const int nn = (int)(idx % no), m = (int)((idx / no) % no);
+        const int j = (int)((idx / ((int64_t)no * no)) % no), i = (int)((idx / ((int64_t)no * no * no)) % no);
+        const int64_t blk = idx / o4;
+        const int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+        const int kn = kcv(s.kc, N, ki, kj, km);
+        const cd *g = s.oovv + blk3(N, km, kn, ki) * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv;
+        const cd *ti = t1 + ((int64_t)ki * no + i) * nv, *tj = t1 + ((int64_t)kj * no + j) * nv;
+        cd acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < nv; ++c) {
+            cd inner = make_double2(0.0, 0.0);
+            for (int dd = 0; dd < nv; ++dd) cfma(inner, tj[dd], g[(int64_t)c * nv + dd]);
+            cfma(acc, ti[c], inner);
+        }
+        const cd w = WT[idx];
+        WT[idx] = make_double2(0.5 * (w.x + acc.x), 0.5 * (w.y + acc.y));
+    }
+}
+
+// The part of the hole-hole ladder 1/2 tau_mn^ab W_mnij carried by tau's single-amplitude
+// products, which the t2-only products of the rearranged grouping leave out: with
+// W = 2 Y + 1/2 X-tilde (X-tilde = t2 <mn||ef>) and the antisymmetry of W in (m, n),
+//   r2[ki][kj][ka](i,j,a,b) += sum_mn t_{m ka}^a t_{n kb}^b W[ki][kj][ka](i,j,m,n)
+__global__ void k_hh_t1_rest(SysDev s, const cd *t1, const cd *Y, const cd *X, cd *r2) {
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o4 = (int64_t)no * no * no * no;
+    GRID_STRIDE(idx, s.d.t2()) {
+        const int b = (int)(idx % nv), a = (int)((idx / nv) % nv);
+        const int j = (int)((idx / ((int64_t)nv * nv)) % no), i = (int)((idx / ((int64_t)nv * nv * no)) % no);
+        const int64_t blk = idx / s.d.t2blk();
+        const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+        const int kb = kcv(s.kc, N, ki, kj, ka);
+        const int64_t wb = blk * o4 + ((int64_t)i * no + j) * no * no;
+        cd acc = make_double2(0.0, 0.0);
+        for (int m = 0; m < no; ++m) {
+            cd inner = make_double2(0.0, 0.0);
+            for (int nn = 0; nn < no; ++nn) {
+                const cd y = Y[wb + m * no + nn], x = X[wb + m * no + nn];
+                const cd w = make_double2(2.0 * y.x + 0.5 * x.x, 2.0 * y.y + 0.5 * x.y);
+                cfma(inner, t1[((int64_t)kb * no + nn) * nv + b], w);
+            }
+            cfma(acc, t1[((int64_t)ka * no + m) * nv + a], inner);
+        }
+        r2[idx] = cadd(r2[idx], acc);
+    }
+}
+
 // Blocked form for n_occ <= OM, n_vir <= VM: one workgroup per (ki, kj, km, m) stages
 // <mn||ie> for all (n, i, e) (ki block) and for all (n, j, e) (kj block), <mn||ij> and
 // both t1 blocks in LDS, so every ooov / oooo element is read once with contiguous loads;
@@ -1570,6 +1625,22 @@ void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStr
     } else {
         LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
     }
+}
+
+void launch_block_transpose(const Dims &d, const cd *src, cd *dst, hipStream_t st) {
+    const int R = d.no * d.no, C = d.nv * d.nv;
+    dim3 g((unsigned)((int64_t)((R + 31) / 32) * ((C + 31) / 32) * d.N * d.N * d.N));
+    hipLaunchKernelGGL(k_block_transpose, g, dim3(256), 0, st, d, src, dst);
+    CK_CHECK(hipGetLastError());
+}
+
+void launch_ytilde(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
+    const int64_t N = s.d.N, no = s.d.no;
+    LAUNCH(k_ytilde, N * N * N * no * no * no * no, s, t1, WT);
+}
+
+void launch_hh_t1_rest(const SysDev &s, const cd *t1, const cd *Y, const cd *X, cd *r2, hipStream_t st) {
+    LAUNCH(k_hh_t1_rest, s.d.t2(), s, t1, Y, X, r2);
 }
 
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {

@@ -68,7 +68,7 @@ def main():
         t2_values=[[float(v.real), float(v.imag)] for v in vals],
     )
     with open(out, "w") as fh:
-        json.dump(rec, fh, indent=0)
+        json.dump(rec, fh, separators=(",", ":"))
     print("wrote", out)
 
 

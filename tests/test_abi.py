@@ -28,9 +28,10 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_system_struct_layout_matches_header():
-    assert ctypes.sizeof(ck.ccsd_k_system) == 48
+    assert ctypes.sizeof(ck.ccsd_k_system) == 56
     assert ck.ccsd_k_system.seed.offset == 32
     assert ck.ccsd_k_system.eri_scale.offset == 40
+    assert ck.ccsd_k_system.grouping.offset == 48
 
 
 @pytest.mark.parametrize("bad", [
@@ -39,6 +40,8 @@ def test_system_struct_layout_matches_header():
     dict(grid=(2, 1, 1), no=2, nv=2, precision=7),
     dict(grid=(2, 1, 1), no=2, nv=2, diis_space=1),
     dict(grid=(2, 1, 1), no=2, nv=2, synthetic=1, eri_scale=-1.0),
+    dict(grid=(2, 1, 1), no=2, nv=2, grouping=2),
+    dict(grid=(2, 1, 1), no=2, nv=2, grouping=1, precision=1),
 ])
 def test_init_rejects_bad_descriptions(bad):
     with pytest.raises(ck.CcsdKError) as e:

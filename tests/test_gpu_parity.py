@@ -266,3 +266,104 @@ def test_general_inputs_rotated_orbitals():
             out.append(c.energy(0))
     assert abs(out[1] - ref["energy"]) <= 1e-10
     assert abs(out[0] - out[1]) <= 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_cfg1_converged_matches_oracle_golden():
+    """2x2x2 mesh (N_k=8), n_occ=8, n_vir=24, integrals x 0.05/N_k, DIIS(6) to ||R|| < 1e-12
+    on the FP64 path against the oracle's converged solution of the same system, stored by
+    tests/golden/make_cfg1_converged.py: energy within 1e-11 Eh, t1 and the sampled t2
+    elements within 1e-10.  Inputs are generated on the device by the same seeded recipe
+    (equal to the host generator up to the last bits of its transcendental functions)."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg1_converged.json")
+    g = json.load(open(path))
+    grid, no, nv = tuple(g["grid"]), g["n_occ"], g["n_vir"]
+    desc = dict(grid=grid, no=no, nv=nv, diis_space=g["diis_space"], synthetic=1, seed=g["seed"],
+                eri_scale=g["eri_scale"])
+    print("cfg1 converged: iterating on the GPU", flush=True)
+    with _ctx([desc]) as c:
+        rc, iters, rn = c.iterate(60, g["tol"])
+        e = c.energy(0)
+        t1, t2 = c.get_amplitudes(0)
+    assert rc == ck.OK
+    e_ref = complex(*g["energy"])
+    t1_ref = np.array([complex(*x) for x in g["t1"]]).reshape(t1.shape)
+    vals = np.array([t2[tuple(p)] for p in g["t2_positions"]])
+    vals_ref = np.array([complex(*x) for x in g["t2_values"]])
+    print(f"  evaluations {iters} (oracle {g['iterations'] + 1}), |dE| {abs(e - e_ref):.2e}, "
+          f"max|dt1| {np.abs(t1 - t1_ref).max():.2e}, max|dt2| sampled {np.abs(vals - vals_ref).max():.2e}", flush=True)
+    assert abs(iters - (g["iterations"] + 1)) <= 1
+    assert abs(e - e_ref) <= 1e-11
+    assert np.abs(t1 - t1_ref).max() <= 1e-10
+    assert np.abs(vals - vals_ref).max() <= 1e-10
+    assert abs(np.linalg.norm(t2.ravel()) - g["t2_norm"]) <= 1e-10 * g["t2_norm"]
+
+
+@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 2, 3), ((2, 2, 1), 3, 5), ((3, 3, 1), 2, 4), ((2, 1, 1), 8, 16)])
+def test_rearranged_grouping_matches_rearranged_oracle(grid, no, nv):
+    """The hole-hole part in the grouping of Sec. 3.3.4 (X-tilde, A-tilde, t2 Y-tilde_{mnij}
+    and the single-amplitude rest) on the FP64 path: its residual equals the rearranged
+    equations' oracle (which is pinned equal to the original ones) to 1e-12, and so does
+    the standard grouping's."""
+    from oracle import rearranged as RA
+
+    print(f"rearranged grouping grid={grid} no={no} nv={nv}", flush=True)
+    N = int(np.prod(grid))
+    kc = O.kconserv(grid)
+    f, eris = synth.system(707 + N, grid, no, nv, scale=0.1 / N)
+    t1, t2 = synth.test_amplitudes(71 + N, grid, no, nv, scale=0.1)
+    A1, A2 = RA.residual(f, eris, t1, t2, kc)
+    out = {}
+    for grouping in (ck.GROUPING_STANDARD, ck.GROUPING_REARRANGED):
+        with _ctx([dict(grid=grid, no=no, nv=nv, grouping=grouping)]) as c:
+            c.set_inputs(0, f, eris)
+            out[grouping] = c.residual(0, t1, t2)
+    for grouping, (g1, g2) in out.items():
+        assert _rel(g2, A2) <= 1e-12, grouping
+        assert _rel(g1, A1) <= 1e-12, grouping
+
+
+def test_rearranged_grouping_converges_to_the_same_energy():
+    grid, no, nv = (3, 1, 1), 4, 8
+    f, eris = synth.system(717, grid, no, nv, scale=0.05 / 3)
+    es = []
+    for grouping in (ck.GROUPING_STANDARD, ck.GROUPING_REARRANGED):
+        with _ctx([dict(grid=grid, no=no, nv=nv, diis_space=6, grouping=grouping)]) as c:
+            c.set_inputs(0, f, eris)
+            rc, it, rn = c.iterate(60, 1e-11)
+            assert rc == ck.OK
+            es.append(c.energy(0))
+    assert abs(es[0] - es[1]) <= 1e-12
+
+
+def _run(descs, inputs, graphs, iters, tol):
+    with _ctx(descs) as c:
+        c.set_graphs(graphs)
+        for i, (f, e) in enumerate(inputs):
+            c.set_inputs(i, f, e)
+        rc, it, rn = c.iterate(iters, tol)
+        out = [(c.energy(i), c.get_amplitudes(i), c.residual_norm(i)) for i in range(len(descs))]
+    return rc, it, out
+
+
+@pytest.mark.parametrize("prec,diis", [(0, 6), (1, 6), (1, 0), (0, 0)])
+def test_graph_replay_is_bitwise_equal(prec, diis):
+    """An iteration captured once as a HIP graph and replayed gives bitwise the results of
+    the same work enqueued directly, on a batch whose systems converge at different
+    iterations (the graph is captured again as the active set shrinks) and whose DIIS step
+    runs on the device."""
+    descs = [dict(grid=(2, 1, 1), no=3, nv=5, precision=prec, diis_space=diis),
+             dict(grid=(3, 1, 1), no=2, nv=4, precision=prec, diis_space=diis),
+             dict(grid=(2, 2, 1), no=2, nv=3, precision=prec, diis_space=diis)]
+    inputs = [synth.system(60 + i, d["grid"], d["no"], d["nv"], scale=0.05 / np.prod(d["grid"]))
+              for i, d in enumerate(descs)]
+    tol = 1e-9 if prec == 0 else 1e-7
+    a = _run(descs, inputs, True, 40, tol)
+    b = _run(descs, inputs, False, 40, tol)
+    assert a[0] == b[0] and a[1] == b[1]
+    for (ea, (t1a, t2a), ra), (eb, (t1b, t2b), rb) in zip(a[2], b[2]):
+        assert ea == eb and ra == rb
+        assert np.array_equal(t1a, t1b) and np.array_equal(t2a, t2b)

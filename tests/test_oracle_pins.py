@@ -370,5 +370,7 @@ def test_block_restricted_residual_equals_full():
     blocks = [(0, 0, 0), (1, 2, 3), (8, 7, 5), (4, 4, 4), (2, 6, 2)]
     B1, B2 = O.residual_blocks(f, lazy, t1, t2, kc, blocks)
     assert np.abs(B1 - R1).max() <= 1e-15 * np.abs(R1).max()
+    C1, _ = O.residual_blocks(f, lazy, t1, t2, kc, blocks[:1], r1_ks=[2, 7])
+    assert np.array_equal(C1[[2, 7]], B1[[2, 7]]) and not np.any(C1[[0, 1, 3, 4, 5, 6, 8]])
     for b in blocks:
         assert np.abs(B2[b] - R2[b]).max() <= 1e-15 * np.abs(R2).max(), b
