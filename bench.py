@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--grouping", choices=["standard", "rearranged"], default="standard",
                     help="hole-hole grouping of the FP64 path: Sec. 2 (standard) or Sec. 3.3.4 (rearranged)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=float, default=0.0,
+                    help="mixed path: run the autotuner with this error budget before timing (0 = keep the "
+                         "default forms) and report its choices")
     ap.add_argument("--converge", type=int, default=1, help="after timing, iterate to convergence and "
                     "compare the paths' energies and amplitudes (0 = skip)")
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -87,12 +90,22 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter, grouping=0):
+def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter, grouping=0,
+             autotune=0.0):
     N = grid[0] * grid[1] * grid[2]
     desc = dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=diis, synthetic=1, seed=seed,
                 eri_scale=0.05 / N, grouping=grouping if prec == 0 else 0)
     print(f"[bench] {('fp64', 'mixed')[prec]}: binding workspace", file=sys.stderr, flush=True)
     ctx = ck.Context([desc], device="cuda:0")
+    tuned = None
+    if autotune and prec == 1:
+        ctx.iterate(1, 0.0)  # operands of real amplitudes in the buffers
+        forms, rep = ctx.autotune(autotune)
+        tuned = {"budget": autotune, "forms": {name: (ck.FORMS[f] if f >= 0 else None)
+                                                for name, f in zip(ck.STAGES[:5], forms)},
+                 "measured": {name: {ck.FORMS[a]: {"ms": rep[p, a, 0], "error": rep[p, a, 1]} for a in range(4)}
+                              for p, name in enumerate(ck.STAGES[:5]) if p != 1}}
+        print(f"[bench] autotune budget {autotune}: {tuned['forms']}", file=sys.stderr, flush=True)
     gemm_flops, other_flops = ctx.flops(0)
     # executed shapes of the five grouped products (the mixed path runs the ladder family
     # on canonical antisymmetric pairs, a quarter of the algorithmic work)
@@ -119,7 +132,8 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
     ctx.timing(False)
     print(f"[bench] {steps} timed-stage steps done", file=sys.stderr, flush=True)
     exec_flops = sum(8.0 * G * M * Nn * K for (G, M, Nn, K) in shapes.values())
-    out = dict(seconds=dt, gemm_flops=gemm_flops, exec_flops=exec_flops, shapes=shapes, other_flops=other_flops,
+    forms = {name: ctx.product_form(name) for name in PRODUCT_KERNEL if name != "hh_ladder"} if prec == 1 else {}
+    out = dict(seconds=dt, tuned=tuned, forms=forms, gemm_flops=gemm_flops, exec_flops=exec_flops, shapes=shapes, other_flops=other_flops,
                stages=stages,
                energy=energy, workspace_bytes=ctx.nbytes, rnorm=ctx.residual_norm(0))
     if converge:
@@ -346,7 +360,8 @@ def main():
     res = {}
     for p in paths:
         res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup, a.converge,
-                          a.tol if p == 0 else a.tol_mixed, a.max_iter, 1 if a.grouping == "rearranged" else 0)
+                          a.tol if p == 0 else a.tol_mixed, a.max_iter, 1 if a.grouping == "rearranged" else 0,
+                          a.autotune)
     head = 1 if 1 in res else 0
     r = res[head]
     ms = 1000.0 * r["seconds"] / a.steps
@@ -365,9 +380,15 @@ def main():
         if not n or not G:
             return None
         avg = tot_ms / n
-        achieved = per_cmac * G * M * Nn * K / (avg / 1000.0) / 1e12
+        unit_flops, pk = per_cmac, peak
+        form = r["forms"].get(name, 0)
+        if head == 1 and form == 2:  # three-term split: six bf16 products per real product
+            unit_flops = 48.0
+        elif head == 1 and form == 3:  # FP32 MFMA: four real products per complex MAC
+            unit_flops, pk = 8.0, PEAK["fp32"]
+        achieved = unit_flops * G * M * Nn * K / (avg / 1000.0) / 1e12
         traffic = measured_traffic(f"{name}_{path}") if (grid, a.no, a.nv) == ((3, 3, 3), 8, 16) else None
-        return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        return {"bound": "mfma", "achieved": achieved, "peak": pk, "unit": "TFLOP/s", "frac": achieved / pk,
                 "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
                 "kernel": PRODUCT_KERNEL[name] + (" (both ladders, packed pairs)" if head == 1 and name == "pp_ladder"
                                                    else ""),
@@ -389,6 +410,8 @@ def main():
         "stages_ms_per_step": {k: v[0] / a.steps for k, v in r["stages"].items()},
         "energy": [r["energy"].real, r["energy"].imag],
     }
+    if r.get("tuned"):
+        line["autotune"] = r["tuned"]
     if 0 in res and 1 in res:
         line["fp64_path"] = {"evals_per_s": a.steps / res[0]["seconds"],
                              "tflops": res[0]["exec_flops"] * a.steps / res[0]["seconds"] / 1e12}

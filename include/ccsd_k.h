@@ -206,8 +206,10 @@ int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable);
 
 /* Precision escalation in ccsd_k_iterate (on by default): a mixed-precision system whose
  * residual norm has not halved for four iterations while above the tolerance has reached
- * the rounding floor of its two-term split products; those products are then switched to
- * CCSD_K_FORM_SPLIT3 (once per system).  enable = 0 keeps the forms fixed. */
+ * the rounding floor of its products (two-term split products, FP32 accumulation); its
+ * two-term products are then switched to CCSD_K_FORM_SPLIT3 and every product accumulates
+ * in FP32 over chunks of 256 k only, the chunks added in FP64; a second such stall
+ * shortens the chunks to 64 k.  enable = 0 keeps the forms fixed. */
 int ccsd_k_set_escalation(ccsd_k_ctx *ctx, int32_t enable);
 
 /* Per-stage device timing with HIP events on the context's stream (0 = off).  Stages:

@@ -719,8 +719,8 @@ void apply_form(ccsd_k_ctx *c, System &S, int slot, int a);
 // has a floor that grows with the coupling strength; a system whose residual norm has not
 // halved for four iterations while still above the tolerance is at that floor.  Every
 // product it runs in a two-term form is then raised to the three-term split, and every
-// product accumulates in FP32 over chunks of 256 k only, adding the chunks in FP64.
-// Applied once per system.
+// product accumulates in FP32 over chunks of 256 k only, adding the chunks in FP64; a
+// second stall shortens the chunks to 64 k.
 void watch_stagnation(ccsd_k_ctx *c, System &S) {
     if (!S.mixed) return;
     if (S.rnorm < 0.5 * S.rn_ref) {
@@ -731,11 +731,14 @@ void watch_stagnation(ccsd_k_ctx *c, System &S) {
     if (++S.stall < 4) return;
     S.stall = 0;
     S.rn_ref = S.rnorm;
-    if (S.kchunk) return;  // escalated already
-    for (int slot : {0, 1, 3, 4})
-        if (S.arith[slot] == ck::ARITH_PRESPLIT2 || S.arith[slot] == ck::ARITH_SPLIT2)
-            apply_form(c, S, slot, ck::ARITH_SPLIT3);
-    S.kchunk = 256;
+    if (S.kchunk == 0) {
+        for (int slot : {0, 1, 3, 4})
+            if (S.arith[slot] == ck::ARITH_PRESPLIT2 || S.arith[slot] == ck::ARITH_SPLIT2)
+                apply_form(c, S, slot, ck::ARITH_SPLIT3);
+        S.kchunk = 256;
+    } else if (S.kchunk > 64) {
+        S.kchunk = 64;  // a second stall: chunks of 64 k
+    }
 }
 
 // product slot i of the mixed path in its arithmetic form, on its family's storage.  With
