@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--autotune", type=float, default=0.0,
                     help="mixed path: run the autotuner with this error budget before timing (0 = keep the "
                          "default forms) and report its choices")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="mixed path: side kernels on a second stream beside the grouped products (0 = one stream)")
     ap.add_argument("--converge", type=int, default=1, help="after timing, iterate to convergence and "
                     "compare the paths' energies and amplitudes (0 = skip)")
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -91,12 +93,13 @@ def parse():
 
 
 def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge, tol, max_iter, grouping=0,
-             autotune=0.0):
+             autotune=0.0, overlap=True):
     N = grid[0] * grid[1] * grid[2]
     desc = dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=diis, synthetic=1, seed=seed,
                 eri_scale=0.05 / N, grouping=grouping if prec == 0 else 0)
     print(f"[bench] {('fp64', 'mixed')[prec]}: binding workspace", file=sys.stderr, flush=True)
     ctx = ck.Context([desc], device="cuda:0")
+    ctx.set_overlap(overlap)
     tuned = None
     if autotune and prec == 1:
         ctx.iterate(1, 0.0)  # operands of real amplitudes in the buffers
@@ -361,7 +364,7 @@ def main():
     for p in paths:
         res[p] = run_path(ck, torch, p, grid, a.no, a.nv, a.seed, a.diis, a.steps, a.warmup, a.converge,
                           a.tol if p == 0 else a.tol_mixed, a.max_iter, 1 if a.grouping == "rearranged" else 0,
-                          a.autotune)
+                          a.autotune, bool(a.overlap))
     head = 1 if 1 in res else 0
     r = res[head]
     ms = 1000.0 * r["seconds"] / a.steps

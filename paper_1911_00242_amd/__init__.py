@@ -74,6 +74,7 @@ _lib_get_form = _sig("ccsd_k_get_product_form", ctypes.c_int, [_p, _i32, _i32, c
 _lib_autotune = _sig("ccsd_k_autotune", ctypes.c_int, [_p, _i32, _f64, ctypes.c_char_p, ctypes.POINTER(_i32), _dp])
 _lib_escalation = _sig("ccsd_k_set_escalation", ctypes.c_int, [_p, _i32])
 _lib_graphs = _sig("ccsd_k_set_graphs", ctypes.c_int, [_p, _i32])
+_lib_overlap = _sig("ccsd_k_set_overlap", ctypes.c_int, [_p, _i32])
 _lib_timing = _sig("ccsd_k_timing", ctypes.c_int, [_p, _i32])
 _lib_timing_get = _sig("ccsd_k_timing_get", ctypes.c_int, [_p, _i32, _dp, ctypes.POINTER(_i64)])
 _lib_free = _sig("ccsd_k_free", None, [_p])
@@ -84,7 +85,7 @@ _lib_err = _sig("ccsd_k_last_error", ctypes.c_char_p, [_p])
 SYMBOLS = ("ccsd_k_init", "ccsd_k_workspace_bytes", "ccsd_k_bind_workspace", "ccsd_k_set_inputs",
            "ccsd_k_residual", "ccsd_k_iterate", "ccsd_k_residual_norm", "ccsd_k_energy",
            "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_product_shape",
-           "ccsd_k_set_product_form", "ccsd_k_get_product_form", "ccsd_k_autotune", "ccsd_k_set_escalation", "ccsd_k_set_graphs",
+           "ccsd_k_set_product_form", "ccsd_k_get_product_form", "ccsd_k_autotune", "ccsd_k_set_escalation", "ccsd_k_set_graphs", "ccsd_k_set_overlap",
            "ccsd_k_timing",
            "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_zgemm_noalloc", "ccsd_k_free", "ccsd_k_last_error")
 
@@ -218,6 +219,10 @@ def ccsd_k_set_graphs(ctx, enable: bool):
     return _check(_lib_graphs(ctx, 1 if enable else 0), ctx)
 
 
+def ccsd_k_set_overlap(ctx, enable: bool):
+    return _check(_lib_overlap(ctx, 1 if enable else 0), ctx)
+
+
 def ccsd_k_timing(ctx, enable: bool):
     return _check(_lib_timing(ctx, 1 if enable else 0), ctx)
 
@@ -332,6 +337,9 @@ class Context:
 
     def set_graphs(self, enable=True):
         ccsd_k_set_graphs(self.ctx, enable)
+
+    def set_overlap(self, enable=True):
+        ccsd_k_set_overlap(self.ctx, enable)
 
     def timing(self, enable=True):
         ccsd_k_timing(self.ctx, enable)

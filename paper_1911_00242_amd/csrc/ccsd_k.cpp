@@ -56,7 +56,7 @@ struct System {
     cd *fock = nullptr, *eri[6] = {};
     cd *amp = nullptr, *res = nullptr;  // [t1 | t2], [r1 | r2]
     cd *tau = nullptr, *tauT = nullptr, *Vt = nullptr, *WT = nullptr, *WR = nullptr, *X = nullptr;
-    cd *scr = nullptr, *P1 = nullptr;
+    cd *scr = nullptr, *scrq = nullptr, *P1 = nullptr;
     // rearranged hole-hole grouping (grouping 1, FP64 path): the per-block transpose of t2
     // (B operand of the two hole-hole products) and X-tilde = t2 <mn||ef> (WT layout); the
     // W_mnij buffer WT then holds Y-tilde.  gr: X-tilde, 1/4 X-tilde t2, Y-tilde t2
@@ -197,6 +197,13 @@ struct ccsd_k_ctx {
     hipGraphExec_t gexec = nullptr;
     std::vector<int64_t> gsig;
     double *dnorms = nullptr;  // device: ||R||^2 of every system after an iteration
+    // A one-system mixed residual runs the side kernels that do not feed the next grouped
+    // product (the F sums, the dressed <ab||ef>, the X seed, R1) on a second stream beside
+    // the products (default priority, created before any capture); off while stage timing
+    // is on, so that every product is timed alone.
+    bool overlap = true;
+    hipStream_t side = nullptr;
+    hipEvent_t sev[4] = {};  // fork, dressed <ab||ef> ready, X seed ready, R1 ready
 };
 
 namespace {
@@ -484,6 +491,7 @@ void carve(System &S, Carver &c) {
     c.take(S.WR, N3 * o * v * o * v);
     c.take(S.X, N3 * o * v * o * v);
     c.take(S.scr, N3 * o * o * o * v);
+    if (S.mixed) c.take(S.scrq, N3 * o * o * o * v);  // the X seed's Q beside the W seed's Z
     if (S.mixed) {
         c.take(S.ovvoT_c, S.n2());
         c.take(S.ovvv_c, N3 * cls[4]);
@@ -786,6 +794,34 @@ void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st) {
     stage_end(c, ep, st);
 }
 
+// The second stream of a one-system mixed residual and its events, created once, outside
+// any capture (all or nothing).
+void ensure_side(ccsd_k_ctx *c) {
+    if (c->side || !c->overlap) return;
+    bool any = false;
+    for (const System &S : c->sys) any = any || S.mixed;
+    if (!any) return;
+    hipStream_t st = nullptr;
+    hipEvent_t ev[4] = {};
+    hipError_t err = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    for (int i = 0; err == hipSuccess && i < 4; ++i) err = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (err != hipSuccess) {
+        if (st) (void)hipStreamDestroy(st);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        throw ck::HipError(err, "creating the side stream of the mixed residual", __FILE__, __LINE__);
+    }
+    c->side = st;
+    for (int i = 0; i < 4; ++i) c->sev[i] = ev[i];
+}
+
+// The side stream for a residual of S on st, or null to run everything on st: only for a
+// mixed system on the context's own stream (one active system) with stage timing off.
+hipStream_t side_stream(ccsd_k_ctx *c, const System &S, hipStream_t st) {
+    if (!S.mixed || !c->overlap || !c->side || c->timing || st != c->stream) return nullptr;
+    return c->side;
+}
+
 // One evaluation of (R1, R2) at the current amplitudes, left in S.res, on stream st.
 void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
     ck::SysDev s = S.dev();
@@ -825,21 +861,41 @@ void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
         run_gemm(c, S, 2, st);  // hole-hole ladder
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
+        // Two chains that meet only at the ring and ladder products and at the end: the
+        // products with their seeds (tau, the W_mnij and W_mbej seeds), and the side kernels
+        // (the F sums, the dressed <ab||ef>, the X seed, R1).  With a side stream the second
+        // chain runs beside the first, ordered by events; without one, before it on st.
+        // Every kernel writes buffers the other chain neither reads nor writes (the dressing
+        // and tau write disjoint 64-byte chunks of pk_B), so the results are the same.
         const int64_t R = S.PV + S.PO;
+        const hipStream_t sb = side_stream(c, S, st);
+        const hipStream_t s2 = sb ? sb : st;
+        if (sb) {
+            CK_CHECK(hipEventRecord(c->sev[0], st));
+            CK_CHECK(hipStreamWaitEvent(sb, c->sev[0], 0));
+        }
+        ck::launch_f(s, S.t1(), S.t2(), S.fw, s2);
+        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, S.c64_lad(), s2);
+        if (sb) CK_CHECK(hipEventRecord(c->sev[1], sb));
+        ck::launch_ring_x(s, S.t1(), S.t2(), S.fw, S.scrq, S.X, s2);
+        if (sb) CK_CHECK(hipEventRecord(c->sev[2], sb));
+        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), s2);
+        if (sb) CK_CHECK(hipEventRecord(c->sev[3], sb));
+
         if (!S.sp_ok) ck::launch_operand(S.n2(), S.t2(), S.sp_t2, S.c64_ring(), st);
         S.sp_ok = true;
         ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R,
                             S.c64_lad(), st);
-        ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
         run_gemm(c, S, 0, st);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
-        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, S.c64_lad(), st);
-        ck::launch_ring_init(s, S.t1(), S.t2(), S.fw, S.scr, S.WR, S.X, st);
+        ck::launch_ring_w(s, S.t1(), S.scr, S.WR, st);
         run_gemm(c, S, 3, st);  // W_mbej += 1/2 t2 <mn||ef>, written split
+        if (sb) CK_CHECK(hipStreamWaitEvent(st, c->sev[2], 0));
         run_gemm(c, S, 4, st);  // X += t2 W_mbej
+        if (sb) CK_CHECK(hipStreamWaitEvent(st, c->sev[1], 0));
         run_gemm(c, S, 1, st);  // both ladders on canonical pairs, into Lp
         ck::launch_assemble_r2_pack(s, S.pairs(), S.X, S.Lp, S.r2c, S.npart, st);
-        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
+        if (sb) CK_CHECK(hipStreamWaitEvent(st, c->sev[3], 0));
     }
     stage_end(c, all, st);
 }
@@ -861,6 +917,18 @@ __global__ void k_copy_scalar(const double *src, double *dst) { *dst = *src; }
 void launch_norm(System &S, hipStream_t st) {
     if (S.mixed) ck::launch_norm_pack(S.d, S.pairs(), S.npart, S.r1(), S.redout, st);
     else ck::launch_norm2(S.d, S.r1(), S.r2(), S.red, S.redout, st);
+}
+
+// The padding of the packed W_mnij and dressed <ab||ef> (pk_A, pk_B) is never written by
+// their producers and must read as zero in the family's storage.  A 64-byte chunk holds the
+// same eight elements in split and complex64 storage but at different bytes, so an element
+// written in the other storage (a change of storage, or a timing run of another form)
+// leaves non-zero bytes in the padding elements of its chunk.  Clearing both buffers
+// restores the padding; the next residual rewrites every other element.
+void clear_packed(System &S, hipStream_t st) {
+    const int64_t R = S.PV + S.PO;
+    CK_CHECK(hipMemsetAsync(S.pk_A, 0, 4 * S.d.N * (int64_t)S.PO * R * sizeof(uint16_t), st));
+    CK_CHECK(hipMemsetAsync(S.pk_B, 0, 4 * S.d.N * (int64_t)S.PV * R * sizeof(uint16_t), st));
 }
 
 // split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
@@ -981,11 +1049,7 @@ int impl_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
             if (S.mixed) {
                 CK_CHECK(hipMemcpyAsync(S.dptab, S.ptab.data(), S.ptab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                         ctx->stream));
-                // the padding of the packed W_mnij and dressed <ab||ef> is never written by their
-                // producers and must read as zero
-                const int64_t R = S.PV + S.PO;
-                CK_CHECK(hipMemsetAsync(S.pk_A, 0, 4 * S.d.N * (int64_t)S.PO * R * sizeof(uint16_t), ctx->stream));
-                CK_CHECK(hipMemsetAsync(S.pk_B, 0, 4 * S.d.N * (int64_t)S.PV * R * sizeof(uint16_t), ctx->stream));
+                clear_packed(S, ctx->stream);
             }
             bind_ops(S);
             if (S.desc.synthetic) {
@@ -1085,6 +1149,7 @@ int impl_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double *
             amplitudes_changed(S);
             reset_iteration(S);  // the caller's amplitudes start a new trajectory
         }
+        ensure_side(ctx);
         residual_device(ctx, S, ctx->stream);
         launch_norm(S, ctx->stream);
         S.rnorm = std::sqrt(read_scalar(ctx, S.redout));
@@ -1176,6 +1241,7 @@ int impl_iterate(ccsd_k_ctx *ctx, int32_t max_iter, double tol, int32_t *iters, 
     std::vector<double> hn(ctx->sys.size(), 0.0);
     try {
         for (auto &S : ctx->sys) S.converged = false;
+        ensure_side(ctx);  // before any capture
         for (int it = 0; it < max_iter; ++it) {
             std::vector<System *> active;
             for (auto &S : ctx->sys)
@@ -1360,6 +1426,7 @@ constexpr int kSlotOfProduct[5] = {1, 2, 0, 3, 4};
 void apply_form(ccsd_k_ctx *c, System &S, int slot, int a) {
     const bool lad = S.c64_lad(), ring = S.c64_ring();
     S.arith[slot] = a;
+    if (lad != S.c64_lad()) clear_packed(S, c->stream);
     if (lad != S.c64_lad() || ring != S.c64_ring()) {
         S.sp_ok = false;
         if (S.inputs) static_split(S, c->stream);
@@ -1484,8 +1551,10 @@ int impl_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache
                 choice[s1] = best[1];
             }
         }
-        // the timing runs left stale operands: recompute them from the amplitudes
+        // the timing runs left stale operands, and outputs written in the other storage:
+        // recompute them from the amplitudes, with the packed padding cleared
         amplitudes_changed(S);
+        clear_packed(S, ctx->stream);
         for (int slot : slots) S.arith[slot] = choice[slot];
         if (S.inputs) static_split(S, ctx->stream);
         CK_CHECK(hipStreamSynchronize(ctx->stream));
@@ -1509,6 +1578,14 @@ int impl_set_graphs(ccsd_k_ctx *ctx, int32_t enable) {
     if (rc) return rc;
     ctx->graphs = enable != 0;
     if (!ctx->graphs) drop_graph(ctx);
+    return CCSD_K_OK;
+}
+
+int impl_set_overlap(ccsd_k_ctx *ctx, int32_t enable) {
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    ctx->overlap = enable != 0;
+    drop_graph(ctx);  // a captured iteration holds the other form
     return CCSD_K_OK;
 }
 
@@ -1733,6 +1810,10 @@ int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable) {
     return guarded(ctx, [&] { return impl_set_graphs(ctx, enable); });
 }
 
+int ccsd_k_set_overlap(ccsd_k_ctx *ctx, int32_t enable) {
+    return guarded(ctx, [&] { return impl_set_overlap(ctx, enable); });
+}
+
 int ccsd_k_set_escalation(ccsd_k_ctx *ctx, int32_t enable) {
     return guarded(ctx, [&] { return impl_set_escalation(ctx, enable); });
 }
@@ -1771,9 +1852,13 @@ void ccsd_k_free(ccsd_k_ctx *ctx) {
             (void)hipEventDestroy(p.b);
         }
         for (hipStream_t st : ctx->lanes) (void)hipStreamSynchronize(st);
+        if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     }
     // after a device error the handles are still released (best effort, errors ignored)
     for (hipStream_t st : ctx->lanes) (void)hipStreamDestroy(st);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    for (hipEvent_t ev : ctx->sev)
+        if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : ctx->joins) (void)hipEventDestroy(ev);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->failed) {

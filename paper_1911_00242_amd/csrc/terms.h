@@ -38,6 +38,11 @@ void launch_hh_t1_rest(const SysDev &s, const cd *t1, const cd *Y, const cd *X, 
 // arranged for one P(ij)P(ab); needs the F combinations of w
 void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
                       hipStream_t st);
+// the same in two independent parts, each with its own scratch (N^3 o^3 v elements): the
+// W_mbej seed (WR) and the X seed (needs the F combinations of w)
+void launch_ring_w(const SysDev &s, const cd *t1, cd *scratch, cd *WR, hipStream_t st);
+void launch_ring_x(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *X,
+                   hipStream_t st);
 // r2 = <ab||ij> + P(ij)P(ab) X
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st);
 // Relaid-out copies of the static classes, made once per set of inputs: ovvoT, ovvvT and

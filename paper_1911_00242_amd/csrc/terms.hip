@@ -1670,48 +1670,53 @@ void launch_static_copies(const SysDev &s, const StaticCopies &c, hipStream_t st
     }
 }
 
-void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
-                      hipStream_t st) {
+// The W_mbej seed: Z into scratch, then W0 (reads Z) into WR.
+void launch_ring_w(const SysDev &s, const cd *t1, cd *scratch, cd *WR, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t n3 = N * N * N;
     if (no <= 8 && nv <= 16) {
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_TI(k_ring_z_t, grid, dim3(8 * 16), s, t1, scratch);
         LAUNCH_TI(k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
-        LAUNCH_TI(k_ring_q_t, grid, dim3(8 * 16), s, t1, scratch);
     } else if (no <= 8 && nv <= 32) {
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_32I(k_ring_z_t, grid, dim3(8 * 32), s, t1, scratch);
         LAUNCH_32I(k_ring_w0_t, grid, dim3(32 * 32), s, t1, scratch, WR);
-        LAUNCH_32I(k_ring_q_t, grid, dim3(8 * 32), s, t1, scratch);
     } else if (no <= 16 && nv <= 16) {
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_WI(16, 16, k_ring_z_t, grid, dim3(16 * 16), s, t1, scratch);
         LAUNCH_WI(16, 16, k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
-        if (s.ovvv_c)  // (the 16-row Q seed would keep its accumulators in scratch memory)
-            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
-        else
-            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
     } else if (no <= 16 && nv <= 32) {  // the W0 seed's Z slab (o^2 v) would not fit LDS
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_WI(16, 32, k_ring_z_t, grid, dim3(16 * 32), s, t1, scratch);
-        if (s.ovvv_c) {
+        if (s.ovvv_c)
             LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
-        } else {
+        else
             LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
-        }
     } else {
         if (s.ovvv_c) {
             LAUNCH(k_ring_z<cf>, n3 * no * no * no * nv, s, t1, scratch);
             LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-            LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
         } else {
             LAUNCH(k_ring_z<cd>, n3 * no * no * no * nv, s, t1, scratch);
             LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-            LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
         }
+    }
+}
+
+// The X seed: Q into scratch, then the one-pass seed (reads Q, t2 and the F blocks) into X.
+void launch_ring_x(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *X,
+                   hipStream_t st) {
+    const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t n3 = N * N * N;
+    if (no <= 8 && nv <= 16) {
+        LAUNCH_TI(k_ring_q_t, xcd_grid(n3 * no), dim3(8 * 16), s, t1, scratch);
+    } else if (no <= 8 && nv <= 32) {
+        LAUNCH_32I(k_ring_q_t, xcd_grid(n3 * no), dim3(8 * 32), s, t1, scratch);
+    } else if (s.ovvv_c) {  // (the 16-row Q seed would keep its accumulators in scratch memory)
+        LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
+    } else {
+        LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
     }
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_xinit_t, xcd_grid(n3 * nv), dim3(8 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
@@ -1728,6 +1733,12 @@ void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &
     } else {
         LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }
+}
+
+void launch_ring_init(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *scratch, cd *WR, cd *X,
+                      hipStream_t st) {
+    launch_ring_w(s, t1, scratch, WR, st);
+    launch_ring_x(s, t1, t2, w, scratch, X, st);
 }
 
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st) {

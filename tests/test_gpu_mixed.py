@@ -188,13 +188,18 @@ def test_families_in_different_storages():
         assert e2 <= 1e-5
 
 
-def test_autotune_budgets_and_cache(tmp_path):
+@pytest.mark.parametrize("grid,no,nv", [((2, 1, 1), 8, 16), ((3, 1, 1), 5, 7)])
+def test_autotune_budgets_and_cache(tmp_path, grid, no, nv):
     """A loose budget admits the pre-split two-term form, a tight one only the three-term
     split or FP32; the second call with the same cache measures nothing new; the residual
-    after tuning (whose timing runs overwrite intermediates) still matches the oracle."""
-    grid, no, nv = (2, 1, 1), 8, 16
+    after tuning (whose timing runs overwrite intermediates) still matches the oracle.  On
+    the 3x1x1 mesh with 5 x 7 orbitals the canonical pair counts per momentum group (35
+    occupied, 70 virtual) are not multiples of 8, so the padding of the packed operands
+    shares 64-byte chunks with real elements, which the timing runs of the other storage
+    write."""
     kc = O.kconserv(grid)
-    f, eris = synth.system(616, grid, no, nv, scale=0.05 / 2)
+    N = int(np.prod(grid))
+    f, eris = synth.system(616, grid, no, nv, scale=0.05 / N)
     t1, t2 = synth.test_amplitudes(61, grid, no, nv, scale=0.05)
     R1, R2 = O.residual(f, eris, t1, t2, kc)
     cache = str(tmp_path / "tune.txt")
@@ -223,6 +228,31 @@ def test_autotune_budgets_and_cache(tmp_path):
         c.autotune(1e-2, cache)
         g1, g2 = c.residual(0, t1, t2)
         assert np.abs(g2 - R2).max() / np.abs(R2).max() <= 1e-5
+
+
+@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 5, 7), ((2, 1, 1), 10, 3)])
+def test_storage_changes_keep_packed_padding(grid, no, nv):
+    """Moving the ladder family from split to complex64 storage and back (as escalation and
+    the autotuner do) leaves every residual equal to the oracle's within the mixed bar, on
+    shapes whose packed padding shares 64-byte chunks with real pairs; then an iteration
+    from the same amplitudes is finite."""
+    kc = O.kconserv(grid)
+    N = int(np.prod(grid))
+    f, eris = synth.system(617, grid, no, nv, scale=0.05 / N)
+    t1, t2 = synth.test_amplitudes(62, grid, no, nv, scale=0.05)
+    R1, R2 = O.residual(f, eris, t1, t2, kc)
+    with ck.Context([dict(grid=grid, no=no, nv=nv, precision=ck.PREC_MIXED, diis_space=4)]) as c:
+        c.set_inputs(0, f, eris)
+        for forms in ((0, 0), (2, 2), (0, 0), (3, 1), (0, 0)):  # (pp_ladder, w_mnij)
+            c.set_product_form(0, forms[0])
+            c.set_product_form(2, forms[1])
+            g1, g2 = c.residual(0, t1, t2)
+            e = np.abs(g2 - R2).max() / np.abs(R2).max()
+            print(f"forms {forms}: max rel err R2 {e:.2e}", flush=True)
+            assert np.isfinite(g2).all() and e <= 1e-5
+        c.set_amplitudes(0, t1, t2)
+        rc, it, rn = c.iterate(2, 0.0)
+        assert np.isfinite(rn)
 
 
 @pytest.mark.timeout(600)
