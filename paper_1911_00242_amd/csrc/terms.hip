@@ -1634,12 +1634,117 @@ void launch_block_transpose(const Dims &d, const cd *src, cd *dst, hipStream_t s
     CK_CHECK(hipGetLastError());
 }
 
+// Y-tilde in two steps for n_occ <= OM, n_vir <= VM: a workgroup per (ki, kj, km, m) in
+// XCD-contiguous order stages the <mn||cd> rows of its m (every n, c, d; the block has
+// k_c = k_i and k_d = k_j) and both t1 blocks in LDS, forms
+//   Z(n, i, d) = sum_c t_i^c <mn||cd>
+// in LDS, then Y(i, j, m, n) = 1/2 seed + 1/2 sum_d Z(n, i, d) t_j^d for every (i, j, n).
+// o^3 v^2 + o^4 v complex MACs per block instead of o^4 v^2, and every <oo||vv> element is
+// read once: ((ki, kj, km) -> (km, kn, ki) is one to one).
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_ytilde_t(SysDev s, const cd *t1, cd *WT) {
+    constexpr int VP = VM + 1;
+    __shared__ cd G[OM * VM * VP];   // <m n||c d> at (n * nv + c) * VP + d
+    __shared__ cd Z[OM * OM * VP];   // Z(n, i, d) at (n * no + i) * VP + d
+    __shared__ cd TI[OM * VM], TJ[OM * VM];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o4 = (int64_t)no * no * no * no;
+    const int64_t nwg = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nwg);
+    if (L >= nwg) return;
+    const int m = (int)(L % no);
+    const int64_t blk = L / no;
+    const int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+    const int kn = kcv(s.kc, N, ki, kj, km);
+    const cd *g = s.oovv + blk3(N, km, kn, ki) * s.d.t2blk() + (int64_t)m * no * nv * nv;
+    const int ovv = no * nv * nv;
+    for (int x = threadIdx.x; x < ovv; x += blockDim.x) G[(x / nv) * VP + x % nv] = g[x];
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) {
+        TI[x] = t1[(int64_t)ki * no * nv + x];
+        TJ[x] = t1[(int64_t)kj * no * nv + x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {  // (n, i, d), d fastest
+        const int d = x % nv, i = (x / nv) % no, n = x / (nv * no);
+        cd acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < nv; ++c) cfma(acc, TI[i * nv + c], G[(n * nv + c) * VP + d]);
+        Z[(n * no + i) * VP + d] = acc;
+    }
+    __syncthreads();
+    cd *wb = WT + blk * o4 + (int64_t)m * no;
+    for (int x = threadIdx.x; x < no * no * no; x += blockDim.x) {  // (i, j, n), n fastest
+        const int n = x % no, j = (x / no) % no, i = x / (no * no);
+        cd acc = make_double2(0.0, 0.0);
+        for (int d = 0; d < nv; ++d) cfma(acc, Z[(n * no + i) * VP + d], TJ[j * nv + d]);
+        cd *w = wb + ((int64_t)i * no + j) * no * no + n;
+        const cd v = *w;
+        *w = make_double2(0.5 * (v.x + acc.x), 0.5 * (v.y + acc.y));
+    }
+}
+
+// The single-amplitude rest of the hole-hole ladder in two steps for n_occ <= OM,
+// n_vir <= VM: a workgroup per (ki, kj, ka, i) stages W(j, m, n) = 2 Y + 1/2 X-tilde of its i
+// and both t1 blocks in LDS, forms U(j, m, b) = sum_n W(j, m, n) t_{n kb}^b in LDS, then adds
+// sum_m t_{m ka}^a U(j, m, b) to r2(i, j, a, b) for every (j, a, b), a contiguous o v^2 run.
+template <int OM, int VM>
+__global__ __launch_bounds__(256) void k_hh_t1_rest_t(SysDev s, const cd *t1, const cd *Y, const cd *X, cd *r2) {
+    constexpr int OP = OM + 1, VP = VM + 1;
+    __shared__ cd W[OM * OM * OP];   // W(j, m, n) at (j * no + m) * OP + n
+    __shared__ cd U[OM * OM * VP];   // U(j, m, b) at (j * no + m) * VP + b
+    __shared__ cd TA[OM * VM], TB[OM * VM];
+    const int N = s.d.N, no = s.d.no, nv = s.d.nv;
+    const int64_t o4 = (int64_t)no * no * no * no;
+    const int64_t nwg = (int64_t)N * N * N * no;
+    const int64_t L = xcd_block(nwg);
+    if (L >= nwg) return;
+    const int i = (int)(L % no);
+    const int64_t blk = L / no;
+    const int ka = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
+    const int kb = kcv(s.kc, N, ki, kj, ka);
+    const int o3 = no * no * no;
+    const int64_t wb = blk * o4 + (int64_t)i * o3;
+    for (int x = threadIdx.x; x < o3; x += blockDim.x) {
+        const cd y = Y[wb + x], xt = X[wb + x];
+        W[(x / no) * OP + x % no] = make_double2(2.0 * y.x + 0.5 * xt.x, 2.0 * y.y + 0.5 * xt.y);
+    }
+    for (int x = threadIdx.x; x < no * nv; x += blockDim.x) {
+        TA[x] = t1[(int64_t)ka * no * nv + x];
+        TB[x] = t1[(int64_t)kb * no * nv + x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {  // (j, m, b), b fastest
+        const int b = x % nv, jm = x / nv;
+        cd acc = make_double2(0.0, 0.0);
+        for (int n = 0; n < no; ++n) cfma(acc, W[jm * OP + n], TB[n * nv + b]);
+        U[jm * VP + b] = acc;
+    }
+    __syncthreads();
+    cd *rb = r2 + blk * s.d.t2blk() + (int64_t)i * no * nv * nv;
+    for (int x = threadIdx.x; x < no * nv * nv; x += blockDim.x) {  // (j, a, b), b fastest
+        const int b = x % nv, a = (x / nv) % nv, j = x / (nv * nv);
+        cd acc = make_double2(0.0, 0.0);
+        for (int mm = 0; mm < no; ++mm) cfma(acc, TA[mm * nv + a], U[(j * no + mm) * VP + b]);
+        rb[x] = cadd(rb[x], acc);
+    }
+}
+
 void launch_ytilde(const SysDev &s, const cd *t1, cd *WT, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no;
+    if (no <= 8 && s.d.nv <= 16) {
+        hipLaunchKernelGGL((k_ytilde_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, WT);
+        CK_CHECK(hipGetLastError());
+        return;
+    }
     LAUNCH(k_ytilde, N * N * N * no * no * no * no, s, t1, WT);
 }
 
 void launch_hh_t1_rest(const SysDev &s, const cd *t1, const cd *Y, const cd *X, cd *r2, hipStream_t st) {
+    const int64_t N = s.d.N, no = s.d.no;
+    if (no <= 8 && s.d.nv <= 16) {
+        hipLaunchKernelGGL((k_hh_t1_rest_t<8, 16>), xcd_grid(N * N * N * no), dim3(256), 0, st, s, t1, Y, X, r2);
+        CK_CHECK(hipGetLastError());
+        return;
+    }
     LAUNCH(k_hh_t1_rest, s.d.t2(), s, t1, Y, X, r2);
 }
 

@@ -302,12 +302,14 @@ def test_cfg1_converged_matches_oracle_golden():
     assert abs(np.linalg.norm(t2.ravel()) - g["t2_norm"]) <= 1e-10 * g["t2_norm"]
 
 
-@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 2, 3), ((2, 2, 1), 3, 5), ((3, 3, 1), 2, 4), ((2, 1, 1), 8, 16)])
+@pytest.mark.parametrize("grid,no,nv", [((3, 1, 1), 2, 3), ((2, 2, 1), 3, 5), ((3, 3, 1), 2, 4), ((2, 1, 1), 8, 16),
+                                        ((2, 1, 1), 3, 18), ((1, 1, 1), 10, 3)])
 def test_rearranged_grouping_matches_rearranged_oracle(grid, no, nv):
     """The hole-hole part in the grouping of Sec. 3.3.4 (X-tilde, A-tilde, t2 Y-tilde_{mnij}
     and the single-amplitude rest) on the FP64 path: its residual equals the rearranged
     equations' oracle (which is pinned equal to the original ones) to 1e-12, and so does
-    the standard grouping's."""
+    the standard grouping's.  Shapes up to 8 x 16 take the two-step LDS forms of Y-tilde and
+    of the single-amplitude rest, the last two the one-thread-per-element forms."""
     from oracle import rearranged as RA
 
     print(f"rearranged grouping grid={grid} no={no} nv={nv}", flush=True)
