@@ -342,11 +342,15 @@ void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, u
 // representative (ki == kj and i == j, or ka == kb) are not written twice.
 constexpr int ASMP_VMAX = 31;  // four padded slabs within 64 KB of dynamic LDS
 
+// The packed ladder value of the virtual pair (x at kx, y at ky) in the row Lrow: the stored
+// canonical value, its negative for the exchanged pair, zero on the diagonal.  Branch free
+// (the address is selected, the load always made), so that the loads of an element are in
+// flight together.
 __device__ inline cd asm_lab(const cd *Lrow, const int32_t *vposK, int vv, int nv, int kx, int x, int ky, int y) {
-    if (kx < ky || (kx == ky && x < y)) return Lrow[vposK[(int64_t)kx * vv + x * nv + y]];
-    if (kx == ky && x == y) return make_double2(0.0, 0.0);
-    const cd l = Lrow[vposK[(int64_t)ky * vv + y * nv + x]];
-    return make_double2(-l.x, -l.y);
+    const bool fwd = kx < ky || (kx == ky && x < y), diag = kx == ky && x == y;
+    const int pos = vposK[fwd ? (int64_t)kx * vv + x * nv + y : (int64_t)ky * vv + y * nv + x];
+    const cd l = Lrow[diag ? 0 : pos];
+    return diag ? make_double2(0.0, 0.0) : fwd ? l : make_double2(-l.x, -l.y);
 }
 
 // Sum of |x|^2 over the workgroup (256 threads), in a fixed order; the result is valid in
@@ -414,32 +418,39 @@ __global__ __launch_bounds__(256) void k_assemble_r2_pack(SysDev s, PairTabs pt,
     const int64_t o4 = blk3(N, kj, ki, kb) * bs + ((int64_t)j * no + i) * vv;
     double nsq = 0.0;
     auto put = [&](int64_t o, cd v) {  // stored in complex64; the norm is taken from the stored value
-        from_cd(v, r2[o]);
-        const cd w = to_cd(r2[o]);
+        cf c;
+        from_cd(v, c);
+        r2[o] = c;
+        const cd w = to_cd(c);
         nsq = fma(w.x, w.x, fma(w.y, w.y, nsq));
     };
     for (int e = threadIdx.x; e < vv; e += blockDim.x) {
         const int a = e / nv, b = e % nv;
-        const cd l1 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, ka, a, kb, b);
+        // every global load of the element first and without branches (members that do not
+        // exist re-read the first one's integral, a cache hit), one round trip together
+        const cf g1 = s.oovv_c[o1 + e], g2 = s.oovv_c[(own_ij ? o1 : o2) + e];
+        const cf g3 = s.oovv_c[(own_ab ? o1 : o3) + e], g4 = s.oovv_c[(own_ab || own_ij ? o1 : o4) + e];
+        const cd la = asm_lab(Lrow, vposK, vv, nv, ka, a, kb, b), lb = asm_lab(Lrow, vposK, vv, nv, kb, a, ka, b);
+        const cd l1 = po < 0 ? make_double2(0.0, 0.0) : la;
         {  // B1 and B2
             const cd x1 = at(Xa, sa, a, b), x2 = at(Xb, sb, a, b), x3 = at(Xc, sc, b, a), x4 = at(Xd, sd, b, a);
-            const cd d1 = cconj(to_cd(s.oovv_c[o1 + e]));
+            const cd d1 = cconj(to_cd(g1));
             const cd p1 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
             put(o1 + e, make_double2((d1.x + p1.x) + l1.x, (d1.y + p1.y) + l1.y));
             if (!own_ij) {
-                const cd d2 = cconj(to_cd(s.oovv_c[o2 + e]));
+                const cd d2 = cconj(to_cd(g2));
                 const cd p2 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
                 put(o2 + e, make_double2((d2.x + p2.x) - l1.x, (d2.y + p2.y) - l1.y));
             }
         }
         if (!own_ab) {  // B3 and B4: the a slot at kb
-            const cd l3 = po < 0 ? make_double2(0.0, 0.0) : asm_lab(Lrow, vposK, vv, nv, kb, a, ka, b);
+            const cd l3 = po < 0 ? make_double2(0.0, 0.0) : lb;
             const cd x1 = at(Xc, sc, a, b), x2 = at(Xd, sd, a, b), x3 = at(Xa, sa, b, a), x4 = at(Xb, sb, b, a);
-            const cd d3 = cconj(to_cd(s.oovv_c[o3 + e]));
+            const cd d3 = cconj(to_cd(g3));
             const cd p3 = make_double2((x1.x + x4.x) - (x2.x + x3.x), (x1.y + x4.y) - (x2.y + x3.y));
             put(o3 + e, make_double2((d3.x + p3.x) + l3.x, (d3.y + p3.y) + l3.y));
             if (!own_ij) {
-                const cd d4 = cconj(to_cd(s.oovv_c[o4 + e]));
+                const cd d4 = cconj(to_cd(g4));
                 const cd p4 = make_double2((x2.x + x3.x) - (x1.x + x4.x), (x2.y + x3.y) - (x1.y + x4.y));
                 put(o4 + e, make_double2((d4.x + p4.x) - l3.x, (d4.y + p4.y) - l3.y));
             }
@@ -637,16 +648,39 @@ __global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt,
             full = n1 + (int64_t)blk * bs + x;
         }
         const cd rv = idx < n1 ? r1[idx] : to_cd(r2[full - n1]);
+        const cd tv = t[full];
+        // the stored error vectors of this element, loaded before any is used and without
+        // branches (a load under a branch is waited for inside it), so that they take one
+        // memory round trip for the element instead of one each: the first eight
+        // unconditionally, those beyond the space in use re-reading vector 0 (a cache hit);
+        // larger spaces load the rest one by one
+        float bx[16], by[16];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const cf b = (j < m ? y.p[j] : y.p[0])[idx];
+            bx[j] = b.x;
+            by[j] = b.y;
+        }
+#pragma unroll
+        for (int j = 8; j < 16; ++j) {
+            bx[j] = 0.f;
+            by[j] = 0.f;
+            if (j < m) {
+                const cf b = y.p[j][idx];
+                bx[j] = b.x;
+                by[j] = b.y;
+            }
+        }
         const double iD = 1.0 / D;
         const cd e = make_double2(rv.x * iD, rv.y * iD);
-        hist[idx] = cadd(t[full], e);
+        hist[idx] = cadd(tv, e);
         cf es;
         from_cd(e, es);
         const cd ed = to_cd(es);
 #pragma unroll
         for (int j = 0; j < 16; ++j)
             if (j < m) {
-                const cd b = j == self ? ed : to_cd(y.p[j][idx]);
+                const cd b = j == self ? ed : make_double2((double)bx[j], (double)by[j]);
                 v[j] = fma(w, fma(ed.x, b.x, ed.y * b.y), v[j]);
             }
         err[idx] = es;
@@ -682,9 +716,25 @@ __global__ __launch_bounds__(256) void k_lincomb_t2_pack(SysDev s, PairTabs pt, 
     if (live) {
         const int kb = kcv(s.kc, N, ki, kj, ka);
         const int64_t src = n1 + r * bs + ((int64_t)i * no + j) * vv;
+        // sum_q c_q hist_q at e: the first eight vectors loaded without branches before any is
+        // used (those beyond the space in use re-read vector 0 and take coefficient 0), so they
+        // take one memory round trip; larger spaces add the rest one by one
         auto comb = [&](int e) {
+            double xr[8], xi[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const cd x = (q < m ? L.src[q] : L.src[0])[src + e];
+                xr[q] = x.x;
+                xi[q] = x.y;
+            }
             cd acc = make_double2(0.0, 0.0);
-            for (int q = 0; q < m; ++q) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double c = q < m ? dd.coef[q] : 0.0;
+                acc.x = fma(c, xr[q], acc.x);
+                acc.y = fma(c, xi[q], acc.y);
+            }
+            for (int q = 8; q < m; ++q) {
                 const cd x = L.src[q][src + e];
                 const double c = dd.coef[q];
                 acc.x = fma(c, x.x, acc.x);

@@ -254,33 +254,49 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
     constexpr int VP = VM + 1, RX = VM * VP + 1, SL = OM * RX;
     constexpr int PER = OM * VM * VM / 256;  // slab elements staged per thread
     __shared__ cd TS[SL], GS[SL];
+    __shared__ cd T1P[OM * VM], T1Q[OM * VM];  // t1[p], t1[q] for tau's single-amplitude part
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int tid = threadIdx.x;
     const int64_t blk = blockIdx.x;
     const int r = (int)(blk % N), q = (int)((blk / N) % N), p = (int)(blk / ((int64_t)N * N));
     const int kb = kcv(s.kc, N, p, q, r);
     const int64_t base = blk * s.d.t2blk();
+    for (int x = tid; x < no * nv; x += 256) {
+        T1P[x] = t1[(int64_t)p * no * nv + x];
+        T1Q[x] = t1[(int64_t)q * no * nv + x];
+    }
+    // A slab is loaded as stored (t2 and the integral, with no arithmetic in between, so
+    // that every load of the thread is in flight at once) and turned into tau (t1 from LDS)
+    // when written to LDS.
     cd pt[PER];
-    IT pg[PER];  // kept in the stored type until written to LDS, so the load is not waited for early
+    IT pg[PER];
 #define FB_LOAD(n)                                                                              \
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
         const int x = tid + 256 * u;                                                            \
         const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
-        if (row < no && e < nv && f < nv) {                                                     \
-            const int64_t gi = base + (((int64_t)row * no + (n)) * nv + e) * nv + f;            \
-            pt[u] = tau_el(t1, t2, gi, p, q, r, kb, row, (n), e, f, no, nv, 0.5);                \
-            pg[u] = oovv[gi];                                                                   \
-        } else {                                                                                \
-            pt[u] = make_double2(0.0, 0.0);                                                     \
-            pg[u] = IT{};                                                                       \
-        }                                                                                       \
+        const bool in_ = row < no && e < nv && f < nv;                                          \
+        const int64_t gi = base + (((int64_t)(in_ ? row : 0) * no + (n)) * nv + (in_ ? e : 0)) * nv + (in_ ? f : 0); \
+        pt[u] = t2[gi];                                                                         \
+        pg[u] = oovv[gi];                                                                       \
     }
-#define FB_STORE()                                                                              \
+#define FB_STORE(n)                                                                             \
     _Pragma("unroll") for (int u = 0; u < PER; ++u) {                                           \
         const int x = tid + 256 * u;                                                            \
         const int row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;                           \
-        TS[row * RX + e * VP + f] = pt[u];                                                      \
-        GS[row * RX + e * VP + f] = to_cd(pg[u]);                                               \
+        const bool in_ = row < no && e < nv && f < nv;                                          \
+        cd v = pt[u];                                                                           \
+        if (in_ && r == p) {                                                                    \
+            const cd pp = cmul(T1P[row * nv + e], T1Q[(n) * nv + f]);                           \
+            v.x += 0.5 * pp.x;                                                                  \
+            v.y += 0.5 * pp.y;                                                                  \
+        }                                                                                       \
+        if (in_ && kb == p) {                                                                   \
+            const cd pp = cmul(T1P[row * nv + f], T1Q[(n) * nv + e]);                           \
+            v.x -= 0.5 * pp.x;                                                                  \
+            v.y -= 0.5 * pp.y;                                                                  \
+        }                                                                                       \
+        TS[row * RX + e * VP + f] = in_ ? v : make_double2(0.0, 0.0);                          \
+        GS[row * RX + e * VP + f] = in_ ? to_cd(pg[u]) : make_double2(0.0, 0.0);               \
     }
     // Fvv roles: outputs (a0 + 8 da, e0 + 8 de), m quarter; the eight lanes of a group share
     // a0 (one broadcast row) and take eight consecutive e0
@@ -293,7 +309,8 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
     cd v00 = {0, 0}, v01 = {0, 0}, v10 = {0, 0}, v11 = {0, 0};
     cd o00 = {0, 0}, o01 = {0, 0}, o10 = {0, 0}, o11 = {0, 0};
     FB_LOAD(0)
-    FB_STORE()
+    __syncthreads();  // t1 blocks in LDS
+    FB_STORE(0)
     __syncthreads();
     for (int n = 0; n < no; ++n) {
         if (n + 1 < no) FB_LOAD(n + 1)
@@ -324,7 +341,7 @@ __global__ __launch_bounds__(256) void k_f_blocks_t(SysDev s, const cd *t1, cons
         }
         __syncthreads();
         if (n + 1 < no) {
-            FB_STORE()
+            FB_STORE(n + 1)
         }
         __syncthreads();
     }
@@ -1012,6 +1029,7 @@ template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__restrict__ t1, const cd *__restrict__ Z,
                                                       cd *__restrict__ WR) {
     __shared__ cd ZS[OM * OM * VM];  // Z(m, n, j, e) of this m at (n * no + j) * nv + e
+    __shared__ cd T1S[VM <= 16 && OM <= 8 ? OM * VM : 1];  // t1[kj](j, f) (n_occ <= 8, n_vir <= 16)
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv;
     const int64_t ov = (int64_t)no * nv, blkq = ov * ov;
     const int64_t o3v = (int64_t)no * no * no * nv, ov3 = (int64_t)no * nv * nv * nv;
@@ -1024,15 +1042,77 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
     const int kb = kcv(s.kc, N, kj, 0, q), ke = kcv(s.kc, N, km, 0, q);
     const int64_t bb = blk3(N, km, kb, ke);
     const cd *zb = Z + bb * o3v + (int64_t)m * no * no * nv;
-    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) ZS[x] = zb[x];
-    const cd *T1J = t1 + (int64_t)kj * no * nv;  // t1[kj](j, f), wave-uniform addresses (scalar loads)
-    __syncthreads();
+    const cd *T1J = t1 + (int64_t)kj * no * nv;  // t1[kj](j, f)
     const int be = threadIdx.x;
-    if (be >= nv * nv) return;
-    const int b = be / nv, e = be % nv;
+    const bool act = be < nv * nv;
+    const int b = act ? be / nv : 0, e = act ? be % nv : 0;
     const IT *g = ovvvT_of<IT>(s) + bb * ov3 + ((int64_t)m * nv + b) * nv * nv + e;
     const IT *w0 = ovvoT_of<IT>(s) + bb * s.d.t2blk() + ((int64_t)m * nv + b) * no * nv + e;
     cd *wr = WR + blk * blkq + (int64_t)b * ov + (int64_t)m * nv + e;
+    if constexpr (VM <= 16 && OM <= 8) {
+        // Every global operand of the thread (the row <m b||f e> over f, <m b||e j> over j,
+        // t1 at kb) is loaded before the shared slabs and before any use, so all of them are
+        // in flight together (converted element by element, they would each take a full
+        // memory round trip); then one j at a time, the stored values converted on use.
+        // (component arrays: an array of the HIP vector structs would be kept in memory)
+        constexpr int NT = VM * VM, ZN = (OM * OM * VM + NT - 1) / NT;
+        const int nz = no * no * nv;
+        double zx[ZN], zy[ZN];
+#pragma unroll
+        for (int u = 0; u < ZN; ++u) {  // the Z slab first: its LDS stores wait for it alone
+            const int x = threadIdx.x + u * NT;
+            const cd v = zb[x < nz ? x : 0];
+            zx[u] = v.x;
+            zy[u] = v.y;
+        }
+        const cd t1v = T1J[threadIdx.x < no * nv ? threadIdx.x : 0];
+        using ST = decltype(IT{}.x);
+        ST gx[VM], gy[VM], wx[OM], wy[OM];
+        double tx[OM], ty[OM];
+#pragma unroll
+        for (int f = 0; f < VM; ++f) {
+            const IT v = g[(int64_t)(act && f < nv ? f : 0) * nv];
+            gx[f] = act && f < nv ? v.x : ST(0);
+            gy[f] = act && f < nv ? v.y : ST(0);
+        }
+#pragma unroll
+        for (int j = 0; j < OM; ++j) {
+            const IT v = w0[(int64_t)(act && j < no ? j : 0) * nv];
+            wx[j] = v.x;
+            wy[j] = v.y;
+        }
+#pragma unroll
+        for (int n = 0; n < OM; ++n) {
+            const cd v = t1[((int64_t)kb * no + (n < no ? n : 0)) * nv + b];
+            tx[n] = v.x;
+            ty[n] = v.y;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < ZN; ++u) {
+            const int x = threadIdx.x + u * NT;
+            if (x < nz) ZS[x] = make_double2(zx[u], zy[u]);
+        }
+        if (threadIdx.x < no * nv) T1S[threadIdx.x] = t1v;
+        __syncthreads();
+        if (!act) return;
+#pragma unroll
+        for (int j = 0; j < OM; ++j) {
+            if (j >= no) break;
+            cd acc = make_double2((double)wx[j], (double)wy[j]);
+#pragma unroll
+            for (int f = 0; f < VM; ++f)
+                if (f < nv) cfma(acc, T1S[j * nv + f], make_double2((double)gx[f], (double)gy[f]));
+#pragma unroll
+            for (int n = 0; n < OM; ++n)
+                if (n < no) acc = csub(acc, cmul(make_double2(tx[n], ty[n]), ZS[(n * no + j) * nv + e]));
+            wr[(int64_t)j * nv * ov] = acc;
+        }
+        return;
+    }
+    for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) ZS[x] = zb[x];
+    __syncthreads();
+    if (!act) return;
     if constexpr (VM <= 16) {
         // the row <m b||f e> over f in registers, one j at a time
         cd gr[VM], tb[OM];
