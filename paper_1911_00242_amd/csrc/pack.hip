@@ -221,17 +221,32 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
                 g2[m] = m < no ? to_cd(g2b[(int64_t)m * v3 + (int64_t)b * vv + f]) : make_double2(0.0, 0.0);
                 t1b[m] = m < no ? tb[m * nv + b] : make_double2(0.0, 0.0);
             }
-            for (int a = 0; a < na; ++a) {
-                const int pab = vpos_ab[(a0 + a) * nv + b];
-                if (pab < 0) continue;
-                cd acc = vb[(int64_t)(a0 + a) * v3 + (int64_t)b * vv + f];
+            // eight a at a time: their pair positions and <ab||ef> loaded together, without
+            // branches, before any is used (one memory round trip per eight instead of one each)
+            for (int a1 = 0; a1 < na; a1 += 8) {
+                int pabs[8];
+                double vx[8], vy[8];
 #pragma unroll
-                for (int m = 0; m < OM; ++m)
-                    if (m < no) {
-                        cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
-                        acc = csub(acc, cmul(TA[m * na + a], g2[m]));
-                    }
-                put_elem(out, ((int64_t)K * pt.PV + pab) * ld + pef, acc, c64);
+                for (int u = 0; u < 8; ++u) {
+                    const int a = a0 + min(a1 + u, na - 1);
+                    pabs[u] = vpos_ab[a * nv + b];
+                    const cd v = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+                    vx[u] = v.x;
+                    vy[u] = v.y;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int a = a1 + u;
+                    if (a >= na || pabs[u] < 0) continue;
+                    cd acc = make_double2(vx[u], vy[u]);
+#pragma unroll
+                    for (int m = 0; m < OM; ++m)
+                        if (m < no) {
+                            cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
+                            acc = csub(acc, cmul(TA[m * na + a], g2[m]));
+                        }
+                    put_elem(out, ((int64_t)K * pt.PV + pabs[u]) * ld + pef, acc, c64);
+                }
             }
         }
     }
