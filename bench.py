@@ -49,14 +49,19 @@ def source_hash(key):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+def measured_record(key):
+    """The committed rocprofv3 counter record of a product kernel (HBM bytes per launch, MFMA
+    busy fraction, clock), or None when the kernel sources changed since it was taken."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
-        return rec["hbm_bytes_per_launch"] if source_hash(key) == rec["source_sha256_16"] else None
+        return rec if source_hash(key) == rec["source_sha256_16"] else None
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic(key):
+    rec = measured_record(key)
+    return rec["hbm_bytes_per_launch"] if rec else None
 
 
 def parse():
@@ -390,12 +395,23 @@ def main():
         elif head == 1 and form == 3:  # FP32 MFMA: four real products per complex MAC
             unit_flops, pk = 8.0, PEAK["fp32"]
         achieved = unit_flops * G * M * Nn * K / (avg / 1000.0) / 1e12
-        traffic = measured_traffic(f"{name}_{path}") if (grid, a.no, a.nv) == ((3, 3, 3), 8, 16) else None
-        return {"bound": "mfma", "achieved": achieved, "peak": pk, "unit": "TFLOP/s", "frac": achieved / pk,
-                "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
-                "kernel": PRODUCT_KERNEL[name] + (" (both ladders, packed pairs)" if head == 1 and name == "pp_ladder"
-                                                   else ""),
-                "avg_launch_ms": avg, "shape": {"groups": G, "M": M, "N": Nn, "K": K}}
+        # counters were taken on the default form of the profiled workload only
+        rec = (measured_record(f"{name}_{path}") if (grid, a.no, a.nv) == ((3, 3, 3), 8, 16) and form == 0
+               else None)
+        traffic = rec["hbm_bytes_per_launch"] if rec else None
+        out = {"bound": "mfma", "achieved": achieved, "peak": pk, "unit": "TFLOP/s", "frac": achieved / pk,
+               "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
+               "kernel": PRODUCT_KERNEL[name] + (" (both ladders, packed pairs)" if head == 1 and name == "pp_ladder"
+                                                  else ""),
+               "avg_launch_ms": avg, "shape": {"groups": G, "M": M, "N": Nn, "K": K}}
+        if rec and "mfma_busy" in rec:
+            # from the committed counter run: SQ_VALU_MFMA_BUSY_CYCLES over the SIMD cycles of
+            # the launch, and the clock (GRBM_GUI_ACTIVE per XCD over the launch time); the
+            # peak at that clock scales the 2.4 GHz figure
+            out["counters"] = {"mfma_busy": rec["mfma_busy"], "clock_ghz": rec["clock_ghz"],
+                               "frac_at_clock": achieved / (pk * rec["clock_ghz"] / 2.4),
+                               "source": rec["summary"]}
+        return out
 
     products = [k for k in PRODUCT_KERNEL if r["stages"][k][1]]
     dominant = max(products, key=lambda k: r["stages"][k][0])

@@ -554,16 +554,31 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     RB_LOAD(0)
     RB_STORE()
     __syncthreads();
+    using ST = decltype(IT{}.x);
+    constexpr int GU = VM * VM / 16;  // integrals of one n per thread
     for (int n = 0; n < no; ++n) {
+        // this thread's <n a||e f> of this n first (issued before the next slab's loads, so
+        // that waiting for them does not wait for those), all together and without branches,
+        // kept as stored until used
+        ST gx[GU], gy[GU];
+        {
+            const IT *g = gb + ((int64_t)n * nv + (aa < nv ? aa : 0)) * nv * nv;
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int ef = ks + 16 * u, e = ef / VM, f = ef % VM;
+                const IT v = g[e < nv && f < nv ? e * nv + f : 0];
+                gx[u] = v.x;
+                gy[u] = v.y;
+            }
+        }
         if (n + 1 < no) RB_LOAD(n + 1)
         // P1a(i, a) += sum_{ef} t2(i,n,e,f) <n a||e f>, this thread's (e, f) = ks + 16 u
         if (aa < nv) {
-            const IT *g = gb + ((int64_t)n * nv + aa) * nv * nv;
-#pragma unroll 4
-            for (int u = 0; u < VM * VM / 16; ++u) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
                 const int ef = ks + 16 * u, e = ef / VM, f = ef % VM;
                 if (e < nv && f < nv) {
-                    const cd gv = to_cd(g[e * nv + f]);
+                    const cd gv = make_double2((double)gx[u], (double)gy[u]);
 #pragma unroll
                     for (int i = 0; i < OM; ++i) cfma(acc[i], TS[(i * VM + e) * VP + f], gv);
                 }
