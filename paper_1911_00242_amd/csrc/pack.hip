@@ -178,12 +178,14 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // grid covers only those blocks (pt.dblk), so the work is spread evenly over the XCDs.
 // <m kb, a ka||e f> is staged for as many a at a time as fit 2048 elements (all of them
 // when o v^2 <= 2048).  For n_occ <= OM and o v <= 2048.
-template <int OM>
+// EX: exactly n_occ = OM, n_vir = 16 as constants (the branches on the orbital counts fold
+// away, so the LDS reads of consecutive m are issued together)
+template <int OM, bool EX = false>
 __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
                                                          int64_t ld, bool c64) {
     __shared__ cd G1[2048];
     __shared__ cd TA[OM * 64];
-    const int N = s.d.N, no = s.d.no, nv = s.d.nv, vv = nv * nv;
+    const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? 16 : s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
     const int64_t nblk = (int64_t)pt.ndblk * nv;
     const int64_t per = (nblk + 7) / 8;
@@ -327,8 +329,10 @@ void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, u
     if (!dress_pack_ok(s.d))
         hipLaunchKernelGGL(k_vvvv_dress_pack_plain, pack_grid(N * pt.PV * (pt.PV / 8)), dim3(256), 0, st, s, pt, t1,
                            out, ld, c64);
+    else if (s.d.no == 8 && nv == 16)
+        hipLaunchKernelGGL((k_vvvv_dress_pack<8, true>), grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else if (s.d.no <= 8)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<8>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
+        hipLaunchKernelGGL((k_vvvv_dress_pack<8>), grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else if (s.d.no <= 16)
         hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else
