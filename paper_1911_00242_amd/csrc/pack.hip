@@ -605,18 +605,36 @@ __global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, Dii
     }
 }
 
-// out[0..1] = ep1 + sum_b ep2 (fixed order)
-__global__ __launch_bounds__(256) void k_energy_final(const double *ep1, const double *ep2, int nb, double *out) {
-    __shared__ double sh[2][256];
-    double er = 0.0, ei = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        er += ep2[b];
-        ei += ep2[nb + b];
+// out[0..1] = ep1 + sum_b ep2, in a fixed order: one workgroup of 1024 threads, each with
+// four independent partial sums over a fixed strided subset (so that four loads of each
+// part are in flight), combined in a fixed order and then by a fixed LDS tree
+__global__ __launch_bounds__(1024) void k_energy_final(const double *ep1, const double *ep2, int nb, double *out) {
+    __shared__ double sh[2][1024];
+    const int t = threadIdx.x;
+    double vr[4] = {0.0, 0.0, 0.0, 0.0}, vi[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b0 = t; b0 < nb; b0 += 4 * 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * 1024;
+            if (b < nb) {
+                vr[u] += ep2[b];
+                vi[u] += ep2[nb + b];
+            }
+        }
     }
-    blk_sum2(er, ei, sh);
-    if (threadIdx.x == 0) {
-        out[0] = ep1[0] + er;
-        out[1] = ep1[1] + ei;
+    sh[0][t] = (vr[0] + vr[1]) + (vr[2] + vr[3]);
+    sh[1][t] = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = ep1[0] + sh[0][0];
+        out[1] = ep1[1] + sh[1][0];
     }
 }
 
@@ -643,29 +661,14 @@ __global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt,
     cd *hist = hp.p[self];
     __shared__ double sh[16][256];
     const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
-    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, np = n1 + (int64_t)pt.nablk * bs;
+    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv;
+    const int vv = nv * nv;
     double v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = 0.0;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < np; idx += (int64_t)gridDim.x * blockDim.x) {
-        double D, w = 1.0;
-        int64_t full;  // position in the full (t1 | t2) vector
-        if (idx < n1) {
-            const int x = (int)idx;
-            const int a = x % nv, i = (x / nv) % no, k = x / (no * nv);
-            D = s.eo[k * no + i] - s.ev[k * nv + a];
-            full = idx;
-        } else {
-            const int64_t r = (idx - n1) / bs;
-            const int x = (int)(idx - n1 - r * bs);
-            const int blk = pt.ablk[r];
-            const int b = x % nv, a = (x / nv) % nv, j = (x / (nv * nv)) % no, i = x / (nv * nv * no);
-            const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
-            const int kb = s.kc[blk];
-            D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
-            w = pack_weight(N, blk, s.kc);
-            full = n1 + (int64_t)blk * bs + x;
-        }
+    // one element: packed position idx, position in the full (t1 | t2) vector, denominator,
+    // overlap weight
+    auto elem = [&](int64_t idx, int64_t full, double D, double w) {
         const cd rv = idx < n1 ? r1[idx] : to_cd(r2[full - n1]);
         const cd tv = t[full];
         // the stored error vectors of this element, loaded before any is used and without
@@ -703,6 +706,35 @@ __global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt,
                 v[j] = fma(w, fma(ed.x, b.x, ed.y * b.y), v[j]);
             }
         err[idx] = es;
+    };
+    // t1: spread over the grid
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n1; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)idx;
+        const int a = x % nv, i = (x / nv) % no, k = x / (no * nv);
+        elem(idx, idx, s.eo[k * no + i] - s.ev[k * nv + a], 1.0);
+    }
+    // t2: (representative block, i, j) slabs of v^2 elements, a workgroup pass covering one
+    // slab (v^2 >= 256: its block, momenta and weight are the same for the whole workgroup) or
+    // 256 / v^2 consecutive slabs, so that the table look-ups are made once per slab
+    const int64_t nslab = (int64_t)pt.nablk * no * no;
+    const int spw = vv >= 256 ? 1 : 256 / vv;
+    const int lane_slab = vv >= 256 ? 0 : (int)threadIdx.x / vv;
+    const int x0 = vv >= 256 ? (int)threadIdx.x : (int)threadIdx.x % vv, xs = vv >= 256 ? 256 : vv;
+    for (int64_t s0 = (int64_t)blockIdx.x * spw; s0 < nslab; s0 += (int64_t)gridDim.x * spw) {
+        const int64_t sl = s0 + lane_slab;
+        if (lane_slab >= spw || sl >= nslab) continue;
+        const int64_t r = sl / (no * no);
+        const int ij = (int)(sl - r * no * no), i = ij / no, j = ij % no;
+        const int blk = pt.ablk[r];
+        const int ka = blk % N, kj = (blk / N) % N, ki = blk / (N * N);
+        const int kb = s.kc[blk];
+        const double w = pack_weight(N, blk, s.kc);
+        const double Dij = s.eo[ki * no + i] + s.eo[kj * no + j];
+        for (int x = x0; x < vv; x += xs) {
+            const int a = x / nv, b = x % nv;
+            const int64_t xb = (int64_t)ij * vv + x;
+            elem(n1 + r * bs + xb, n1 + (int64_t)blk * bs + xb, Dij - s.ev[ka * nv + a] - s.ev[kb * nv + b], w);
+        }
     }
     blk_sum16(v, sh);
     if (threadIdx.x == 0)
@@ -838,7 +870,7 @@ void launch_lincomb_packed(const SysDev &s, const PairTabs &pt, const cd *const 
 }
 
 void launch_energy_packed(const Dims &d, const PairTabs &pt, const double *epart, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, epart, epart + 2, (int)lincomb_pack_blocks(d, pt), out);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, epart, epart + 2, (int)lincomb_pack_blocks(d, pt), out);
     CK_CHECK(hipGetLastError());
 }
 
