@@ -206,9 +206,9 @@ int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable);
 
 /* Two streams in a mixed-precision residual (on by default).  When one system is iterated
  * (or evaluated by ccsd_k_residual) on the context's stream, the kernels that do not feed the
- * next grouped product (the F sums of eq. ori_EqSingle, the T1-dressed <ab||ef>, the X seed
- * of the ring terms, the T1 residual) run on a second stream of the library's, ordered by
- * events, beside the five grouped products and their seeds.  Results are bitwise those of
+ * next grouped product (the X seed of the ring terms, the T1-dressed <ab||ef>, the T1
+ * residual of eq. ori_EqSingle) run on a second stream of the library's, ordered by events,
+ * beside the W_mbej, ring and ladder products.  Results are bitwise those of
  * enable = 0, under which everything runs on the context's stream in one order.  Off while
  * stage timing is on, so that each product is timed alone; systems iterated together
  * already run side by side and keep one stream each.  Returns CCSD_K_EINVAL on a null

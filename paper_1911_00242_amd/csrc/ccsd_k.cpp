@@ -861,36 +861,43 @@ void residual_device(ccsd_k_ctx *c, System &S, hipStream_t st) {
         run_gemm(c, S, 2, st);  // hole-hole ladder
         ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), st);
     } else {
-        // Two chains that meet only at the ring and ladder products and at the end: the
-        // products with their seeds (tau, the W_mnij and W_mbej seeds), and the side kernels
-        // (the F sums, the dressed <ab||ef>, the X seed, R1).  With a side stream the second
-        // chain runs beside the first, ordered by events; without one, before it on st.
-        // Every kernel writes buffers the other chain neither reads nor writes (the dressing
-        // and tau write disjoint 64-byte chunks of pk_B), so the results are the same.
+        // Two chains after the F sums: the products with their seeds (tau, the W_mnij and
+        // W_mbej seeds), and the side kernels (the X seed's Q and one-pass seed, the dressed
+        // <ab||ef>, R1), which meet the first at the ring and ladder products and at the end.
+        // With a side stream the second chain is forked when the W_mbej product is issued,
+        // so that it runs beside that product instead of delaying the seeds before it;
+        // without one, everything runs on st in one order. Every kernel writes buffers the other chain neither reads nor writes
+        // (the dressing and tau write disjoint 64-byte chunks of pk_B), so the results are
+        // the same.
         const int64_t R = S.PV + S.PO;
         const hipStream_t sb = side_stream(c, S, st);
-        const hipStream_t s2 = sb ? sb : st;
-        if (sb) {
-            CK_CHECK(hipEventRecord(c->sev[0], st));
-            CK_CHECK(hipStreamWaitEvent(sb, c->sev[0], 0));
-        }
-        ck::launch_f(s, S.t1(), S.t2(), S.fw, s2);
-        ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, S.c64_lad(), s2);
-        if (sb) CK_CHECK(hipEventRecord(c->sev[1], sb));
-        ck::launch_ring_x(s, S.t1(), S.t2(), S.fw, S.scrq, S.X, s2);
-        if (sb) CK_CHECK(hipEventRecord(c->sev[2], sb));
-        ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), s2);
-        if (sb) CK_CHECK(hipEventRecord(c->sev[3], sb));
-
         if (!S.sp_ok) ck::launch_operand(S.n2(), S.t2(), S.sp_t2, S.c64_ring(), st);
         S.sp_ok = true;
         ck::launch_tau_pack(S.d, S.dkc, S.pairs(), S.t1(), S.t2(), S.pk_A, R, S.pk_B + 4 * (int64_t)S.PV, R,
                             S.c64_lad(), st);
         ck::launch_wmnij_init(s, S.t1(), S.WT, true, st);
         run_gemm(c, S, 0, st);  // W_mnij += 1/2 tau <mn||ef>, written split into pk_A
+        ck::launch_f(s, S.t1(), S.t2(), S.fw, st);
         ck::launch_ring_w(s, S.t1(), S.scr, S.WR, st);
+        auto side = [&](hipStream_t s2) {
+            ck::launch_ring_x(s, S.t1(), S.t2(), S.fw, S.scrq, S.X, s2);
+            if (sb) CK_CHECK(hipEventRecord(c->sev[2], sb));
+            ck::launch_vvvv_dress_pack(s, S.pairs(), S.t1(), S.pk_B, R, S.c64_lad(), s2);
+            if (sb) CK_CHECK(hipEventRecord(c->sev[1], sb));
+            ck::launch_r1(s, S.t1(), S.t2(), S.fw, S.P1, S.r1(), s2);
+            if (sb) CK_CHECK(hipEventRecord(c->sev[3], sb));
+        };
+        if (sb) {
+            CK_CHECK(hipEventRecord(c->sev[0], st));
+            CK_CHECK(hipStreamWaitEvent(sb, c->sev[0], 0));
+        } else {
+            side(st);
+        }
         run_gemm(c, S, 3, st);  // W_mbej += 1/2 t2 <mn||ef>, written split
-        if (sb) CK_CHECK(hipStreamWaitEvent(st, c->sev[2], 0));
+        if (sb) {
+            side(sb);
+            CK_CHECK(hipStreamWaitEvent(st, c->sev[2], 0));
+        }
         run_gemm(c, S, 4, st);  // X += t2 W_mbej
         if (sb) CK_CHECK(hipStreamWaitEvent(st, c->sev[1], 0));
         run_gemm(c, S, 1, st);  // both ladders on canonical pairs, into Lp
