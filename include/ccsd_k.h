@@ -55,11 +55,12 @@ extern "C" {
 
 #define CCSD_K_PREC_FP64 0  /* complex128 storage, FP64 MFMA contractions            */
 #define CCSD_K_PREC_MIXED 1 /* complex64 operands of the big contractions, split-BF16
-                               MFMA products accumulated in FP32; the side terms read
-                               complex64 copies of the integral classes, R2 and the DIIS
-                               error vectors are stored in complex64; FP64 master
-                               amplitudes and DIIS amplitude history, denominators, F
-                               intermediates, norm and energy sums                     */
+                               MFMA products accumulated in FP32; the integral classes
+                               are kept in complex64 only (rounded from the complex128
+                               values given or generated), R2 and the DIIS error vectors
+                               are stored in complex64; FP64 master amplitudes and DIIS
+                               amplitude history, denominators, F intermediates, norm and
+                               energy sums                                              */
 
 /* Grouping of the hole-hole terms of the T2 equation.  STANDARD: Sec. 2 (eq. ori_EqDouble)
  * with W_mnij built once from tau and applied once, 1/2 tau_mn^ab W_mnij.  REARRANGED (FP64
@@ -98,8 +99,9 @@ int ccsd_k_workspace_bytes(const ccsd_k_ctx *ctx, uint64_t *bytes);
  * where requested, and sets every amplitude to zero.  ENOMEM if bytes is too small. */
 int ccsd_k_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes);
 
-/* Copy one system's Fock matrix and integral classes from host memory (layouts above).
- * EINVAL when an orbital energy (real part of a Fock diagonal element) is not finite or
+/* Copy one system's Fock matrix and integral classes from host memory (layouts above;
+ * the mixed path rounds the classes to its complex64 copies, passing them through a
+ * device staging buffer a range at a time).  EINVAL when an orbital energy (real part of a Fock diagonal element) is not finite or
  * when a T1 or T2 denominator of the update (Sec. 4.4) is zero.  Resets the system's DIIS
  * history. */
 int ccsd_k_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const double *const eri[6]);

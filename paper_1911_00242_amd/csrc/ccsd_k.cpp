@@ -65,8 +65,11 @@ struct System {
     bool rearranged() const { return desc.grouping == CCSD_K_GROUPING_REARRANGED; }
     cd *ovvoT = nullptr;  // static ovvo, ovvv, oovv classes with their last two indices swapped
     cd *ovvvT = nullptr, *oovvT = nullptr;
-    // mixed path: complex64 copies in place of the three above, and of ovvv and oovv
+    // mixed path: the integral classes in complex64 only (eri[] is not kept): the three
+    // swapped copies above, oovv and ovvv, oooo and ooov, and <ab||ef> on the blocks that
+    // hold its doubly canonical pairs (ka <= kb, ke <= kf: the dblk list of ptab, in order)
     ck::cf *ovvoT_c = nullptr, *ovvv_c = nullptr, *ovvvT_c = nullptr, *oovv_c = nullptr, *oovvT_c = nullptr;
+    ck::cf *oooo_c = nullptr, *ooov_c = nullptr, *vvvv_c = nullptr;
     ck::cf *r2c = nullptr;  // mixed path: R2 in complex64 (res then holds R1 only)
     cd *zeros = nullptr;  // 256 zero bytes: load target of out-of-range GEMM operand elements
     ck::FWork fw{};
@@ -83,7 +86,8 @@ struct System {
     int64_t pl_t2 = 0;  // element count of the T2-shaped split operands, padded
     // the ladder products run on antisymmetric pairs (pack.hip): canonical pair lists per
     // group (host and device, int32), the packed products and their split operands
-    // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v] | opos [N][N][o][o] | dblk | ablk
+    // vlist [N][PV] | olist [N][PO] | vpos [N][N][v][v] | opos [N][N][o][o] | dblk | ablk |
+    // vblk [N][N][N] (a block's place in dblk, -1 when it is not there)
     std::vector<int32_t> ptab;
     int PV = 0, PO = 0, ndblk = 0, nablk = 0;
     int32_t *dptab = nullptr;
@@ -152,17 +156,25 @@ struct System {
         s.ovvoT_c = ovvoT_c;
         s.oovvT_c = oovvT_c;
         s.oovv_c = oovv_c;
+        s.oooo_c = oooo_c;
+        s.ooov_c = ooov_c;
+        s.vvvv_c = vvvv_c;
+        s.vblk = mixed ? dblk_dev() + ndblk + nablk : nullptr;
         return s;
     }
-    ck::StaticCopies statics() const {
-        return ck::StaticCopies{ovvoT, ovvvT, oovvT, ovvoT_c, ovvv_c, ovvvT_c, oovv_c, oovvT_c};
+    ck::StaticCopies statics() const { return ck::StaticCopies{ovvoT, ovvvT, oovvT}; }
+    // offset of dblk in ptab (host) and dptab (device)
+    int64_t dblk_off() const {
+        const int64_t N = d.N, nv = d.nv, no = d.no;
+        return N * (PV + PO) + N * N * (nv * nv + no * no);
     }
+    const int32_t *dblk_dev() const { return dptab + dblk_off(); }
     ck::PairTabs pairs() const {
         const int64_t N = d.N;
         const int64_t nv = d.nv;
         const int64_t no = d.no;
         const int32_t *vpos = dptab + N * (PV + PO), *opos = vpos + N * N * nv * nv;
-        const int32_t *dblk = opos + N * N * no * no;
+        const int32_t *dblk = opos + N * N * no * no;  // == dblk_dev()
         return ck::PairTabs{dptab, dptab + N * PV, vpos, opos, dblk, dblk + ndblk, PV, PO, ndblk, nablk};
     }
 };
@@ -285,6 +297,9 @@ void build_pair_tables(System &S) {
     S.ptab.assign(N * PV + N * PO + N * N * vv + N * N * oo, -1);
     S.ptab.insert(S.ptab.end(), dblk.begin(), dblk.end());
     S.ptab.insert(S.ptab.end(), ablk.begin(), ablk.end());
+    std::vector<int32_t> vblk(N * N * N, -1);
+    for (size_t L = 0; L < dblk.size(); ++L) vblk[dblk[L]] = (int32_t)L;
+    S.ptab.insert(S.ptab.end(), vblk.begin(), vblk.end());
     int32_t *vlist = S.ptab.data(), *olist = vlist + N * PV, *vpos = olist + N * PO, *opos = vpos + N * N * vv;
     for (int64_t K = 0; K < N; ++K) {
         for (size_t p = 0; p < vl[K].size(); ++p) {
@@ -460,7 +475,8 @@ void carve(System &S, Carver &c) {
     const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, n = o + v, N3 = N * N * N;
     const int64_t cls[6] = {o * o * o * o, o * o * o * v, o * o * v * v, o * v * v * o, o * v * v * v, v * v * v * v};
     c.take(S.fock, N * n * n);
-    for (int i = 0; i < 6; ++i) c.take(S.eri[i], N3 * cls[i]);
+    if (!S.mixed)
+        for (int i = 0; i < 6; ++i) c.take(S.eri[i], N3 * cls[i]);
     c.take(S.amp, S.n1() + S.n2());
     c.take(S.res, S.mixed ? S.n1() : S.n1() + S.n2());
     if (S.mixed) c.take(S.r2c, S.n2());
@@ -498,6 +514,9 @@ void carve(System &S, Carver &c) {
         c.take(S.ovvvT_c, N3 * cls[4]);
         c.take(S.oovv_c, S.n2());
         c.take(S.oovvT_c, S.n2());
+        c.take(S.oooo_c, N3 * cls[0]);
+        c.take(S.ooov_c, N3 * cls[1]);
+        c.take(S.vvvv_c, (int64_t)S.ndblk * cls[5]);
     } else {
         c.take(S.ovvoT, S.n2());
         c.take(S.ovvvT, N3 * cls[4]);
@@ -938,10 +957,61 @@ void clear_packed(System &S, hipStream_t st) {
     CK_CHECK(hipMemsetAsync(S.pk_B, 0, 4 * S.d.N * (int64_t)S.PV * R * sizeof(uint16_t), st));
 }
 
-// split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij)
+// split forms of the static <oo||vv> class (full for the ring W product, packed for W_mnij),
+// from its complex64 copy widened into X (a scratch buffer of the same size, rewritten by
+// every residual)
 void static_split(System &S, hipStream_t st) {
-    ck::launch_operand(S.n2(), S.eri[2], S.sp_oovv, S.c64_ring(), st);
-    ck::launch_oovv_pack(S.d, S.dkc, S.pairs(), S.eri[2], S.pk_oovv, S.c64_lad(), st);
+    ck::launch_to_c128(S.n2(), S.oovv_c, S.X, st);
+    ck::launch_operand(S.n2(), S.X, S.sp_oovv, S.c64_ring(), st);
+    ck::launch_oovv_pack(S.d, S.dkc, S.pairs(), S.X, S.pk_oovv, S.c64_lad(), st);
+}
+
+// The mixed path's integral classes (complex64 only) from complex128 values, the device
+// generator's (host == nullptr) or the caller's: each class passes through X (N^3 o^2 v^2
+// complex128 elements, free until the first residual) a range at a time.  <ab||ef> is kept
+// on the dblk blocks only, in their order.
+void mixed_inputs(System &S, const double *const *host, hipStream_t st) {
+    static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
+    const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, N3 = N * N * N;
+    const int64_t bsz[6] = {o * o * o * o, o * o * o * v, o * o * v * v, o * v * v * o, o * v * v * v, v * v * v * v};
+    const int32_t *dblk = S.ptab.data() + S.dblk_off();
+    cd *stage = S.X;
+    const int64_t cap = S.n2();
+    // elements c0 .. c0+len-1 of class i (of its kept blocks for <ab||ef>) into the stage
+    auto fill = [&](int i, int64_t c0, int64_t len) {
+        if (!host) {
+            ck::launch_synth_eri_range(S.mesh, (int)o, (int)v, S.desc.seed, S.desc.eri_scale, cls[i],
+                                       i == 5 ? S.dblk_dev() : nullptr, c0, len, stage, st);
+            return;
+        }
+        for (int64_t c = c0; c < c0 + len;) {  // contiguous runs of the caller's array
+            int64_t src = c, n = c0 + len - c;
+            if (i == 5) {
+                const int64_t off = c % bsz[5];
+                src = (int64_t)dblk[c / bsz[5]] * bsz[5] + off;
+                n = std::min(n, bsz[5] - off);
+            }
+            CK_CHECK(hipMemcpyAsync(stage + (c - c0), host[i] + 2 * src, n * sizeof(cd), hipMemcpyHostToDevice, st));
+            c += n;
+        }
+    };
+    // <oo||vv> and <ov||vo> are exactly the size of the stage
+    fill(2, 0, cap);
+    ck::launch_round_c64(cap, stage, S.oovv_c, st);
+    ck::launch_swap_last2_c64(N3 * o * o, (int)v, stage, S.oovvT_c, st);
+    fill(3, 0, cap);
+    ck::launch_ovvo_transpose_c64(S.d, stage, S.ovvoT_c, st);
+    ck::cf *const dst[6] = {S.oooo_c, S.ooov_c, nullptr, nullptr, S.ovvv_c, S.vvvv_c};
+    for (int i : {0, 1, 4, 5}) {
+        const int64_t total = (i == 5 ? (int64_t)S.ndblk : N3) * bsz[i];
+        for (int64_t c0 = 0; c0 < total; c0 += cap) {
+            const int64_t len = std::min(cap, total - c0);  // a multiple of v^2 for ovvv
+            fill(i, c0, len);
+            ck::launch_round_c64(len, stage, dst[i] + c0, st);
+            if (i == 4) ck::launch_swap_last2_c64(len / (v * v), (int)v, stage, S.ovvvT_c + c0, st);
+        }
+    }
+    static_split(S, st);
 }
 
 double read_scalar(ccsd_k_ctx *c, const double *dptr) {
@@ -1062,12 +1132,15 @@ int impl_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
             if (S.desc.synthetic) {
                 static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
                 ck::launch_synth_fock(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.fock, ctx->stream);
-                for (int i = 0; i < 6; ++i)
-                    ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
-                                         ctx->stream);
                 ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
-                ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
-                if (S.mixed) static_split(S, ctx->stream);
+                if (S.mixed) {
+                    mixed_inputs(S, nullptr, ctx->stream);
+                } else {
+                    for (int i = 0; i < 6; ++i)
+                        ck::launch_synth_eri(S.mesh, S.d.no, S.d.nv, S.desc.seed, S.desc.eri_scale, cls[i], S.eri[i],
+                                             ctx->stream);
+                    ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
+                }
                 S.inputs = true;
             }
         }
@@ -1130,11 +1203,14 @@ int impl_set_inputs(ccsd_k_ctx *ctx, int32_t sys, const double *fock, const doub
     }
     try {
         CK_CHECK(hipMemcpyAsync(S.fock, fock, N * n * n * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
-        for (int i = 0; i < 6; ++i)
-            CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
         ck::launch_diag(S.d, S.fock, S.eo, S.ev, ctx->stream);
-        ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
-        if (S.mixed) static_split(S, ctx->stream);
+        if (S.mixed) {
+            mixed_inputs(S, eri, ctx->stream);
+        } else {
+            for (int i = 0; i < 6; ++i)
+                CK_CHECK(hipMemcpyAsync(S.eri[i], eri[i], N3 * cls[i] * sizeof(cd), hipMemcpyHostToDevice, ctx->stream));
+            ck::launch_static_copies(S.dev(), S.statics(), ctx->stream);
+        }
         S.e_ok = false;
         CK_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (const ck::HipError &e) {

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
     const cf *g1b = s.ovvv_c + blk3(N, kb, ka, ke) * ov3 + (int64_t)e * nv;
     const cf *g2b = s.ovvv_c + blk3(N, ka, kb, ke) * ov3 + (int64_t)e * nv;
     const cd *ta = t1 + (int64_t)ka * no * nv, *tb = t1 + (int64_t)kb * no * nv;
-    const cd *vb = s.vvvv + blk * v4 + (int64_t)e * nv;
+    const cf *vb = s.vvvv_c + (L / nv) * v4 + (int64_t)e * nv;  // the kept blocks follow dblk
     const int32_t *vpos_ab = pt.vpos + ((int64_t)K * N + ka) * vv;
     const int32_t *vpos_ef = pt.vpos + ((int64_t)K * N + ke) * vv + e * nv;
     // a chunk of ac values of a: no * ac * nv <= 2048 and no * ac <= OM * 64
@@ -227,12 +227,12 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
             // branches, before any is used (one memory round trip per eight instead of one each)
             for (int a1 = 0; a1 < na; a1 += 8) {
                 int pabs[8];
-                double vx[8], vy[8];
+                float vx[8], vy[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int a = a0 + min(a1 + u, na - 1);
                     pabs[u] = vpos_ab[a * nv + b];
-                    const cd v = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
+                    const cf v = vb[(int64_t)a * v3 + (int64_t)b * vv + f];
                     vx[u] = v.x;
                     vy[u] = v.y;
                 }
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
                 for (int u = 0; u < 8; ++u) {
                     const int a = a1 + u;
                     if (a >= na || pabs[u] < 0) continue;
-                    cd acc = make_double2(vx[u], vy[u]);
+                    cd acc = make_double2((double)vx[u], (double)vy[u]);
 #pragma unroll
                     for (int m = 0; m < OM; ++m)
                         if (m < no) {
@@ -275,12 +275,14 @@ __global__ void k_vvvv_dress_pack_plain(SysDev s, PairTabs pt, const cd *t1, uin
             const int ka = pab / vv, a = (pab / nv) % nv, b = pab % nv;
             const int ke = pef / vv, e = (pef / nv) % nv, f = pef % nv;
             const int kb = kcv(s.kc, N, K, 0, ka);
-            cd acc = s.vvvv[blk3(N, ka, kb, ke) * v4 + (((int64_t)a * nv + b) * nv + e) * nv + f];
-            const cd *g1 = s.ovvv + blk3(N, kb, ka, ke) * ov3 + ((int64_t)a * nv + e) * nv + f;
-            const cd *g2 = s.ovvv + blk3(N, ka, kb, ke) * ov3 + ((int64_t)b * nv + e) * nv + f;
+            // (ka, kb, ke) is a kept block of <ab||ef>: ka <= kb and ke <= kf for canonical pairs
+            const int64_t vk = s.vblk[blk3(N, ka, kb, ke)];
+            cd acc = to_cd(s.vvvv_c[vk * v4 + (((int64_t)a * nv + b) * nv + e) * nv + f]);
+            const cf *g1 = s.ovvv_c + blk3(N, kb, ka, ke) * ov3 + ((int64_t)a * nv + e) * nv + f;
+            const cf *g2 = s.ovvv_c + blk3(N, ka, kb, ke) * ov3 + ((int64_t)b * nv + e) * nv + f;
             for (int m = 0; m < no; ++m) {
-                cfma(acc, t1[((int64_t)kb * no + m) * nv + b], g1[(int64_t)m * v3]);
-                acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], g2[(int64_t)m * v3]));
+                cfma(acc, t1[((int64_t)kb * no + m) * nv + b], to_cd(g1[(int64_t)m * v3]));
+                acc = csub(acc, cmul(t1[((int64_t)ka * no + m) * nv + a], to_cd(g2[(int64_t)m * v3])));
             }
             v[q] = acc;
         }

@@ -427,35 +427,47 @@ __device__ inline cd anti_A(const Mesh &m, int n, uint64_t st, double scale, int
     return make_double2(0.25 * ((a.x + d.x) - (b.x + c.x)), 0.25 * ((a.y + d.y) - (b.y + c.y)));
 }
 
-__global__ void k_synth_eri(Mesh m, int no, int nv, uint64_t st, double scale, int4 dim, int4 off, cd *out) {
+// Elements c0 .. c0+len-1 of a class into out[0 .. len-1]; with a block list, element c
+// lies in block blist[c / block size] (the class stored on those blocks only).
+__global__ void k_synth_eri(Mesh m, int no, int nv, uint64_t st, double scale, int4 dim, int4 off,
+                            const int32_t *blist, int64_t c0, int64_t len, cd *out) {
     const int n = no + nv;
     const int64_t blk = (int64_t)dim.x * dim.y * dim.z * dim.w;
-    GRID_STRIDE(idx, (int64_t)m.N * m.N * m.N * blk) {
+    GRID_STRIDE(i, len) {
+        const int64_t idx = c0 + i;
         int s = (int)(idx % dim.w), r = (int)((idx / dim.w) % dim.z);
         int q = (int)((idx / ((int64_t)dim.w * dim.z)) % dim.y);
         int p = (int)((idx / ((int64_t)dim.w * dim.z * dim.y)) % dim.x);
         int64_t b = idx / blk;
+        if (blist) b = blist[b];
         int kr = (int)(b % m.N), kq = (int)((b / m.N) % m.N), kp = (int)(b / ((int64_t)m.N * m.N));
         int ks = kc_mesh(m, kp, kq, kr);
         int P = p + off.x, Q = q + off.y, R = r + off.z, S = s + off.w;
         cd x = anti_A(m, n, st, scale, kp, kq, kr, P, Q, R, S);
         cd y = anti_A(m, n, st, scale, kr, ks, kp, R, S, P, Q);
-        out[idx] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        out[i] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
     }
 }
 
-void launch_synth_eri(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls, cd *out,
-                      hipStream_t st) {
+void launch_synth_eri_range(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls,
+                            const int32_t *blist, int64_t c0, int64_t len, cd *out, hipStream_t st) {
     int d[4], o[4];
     for (int t = 0; t < 4; ++t) {
         d[t] = cls[t] == 'o' ? no : (cls[t] == 'v' ? nv : no + nv);
         o[t] = cls[t] == 'v' ? no : 0;
     }
     uint64_t state = mix64_host(mix64_host(seed) ^ 2ULL);
-    int64_t total = (int64_t)m.N * m.N * m.N * d[0] * d[1] * d[2] * d[3];
-    hipLaunchKernelGGL(k_synth_eri, grid_for(total), dim3(256), 0, st, m, no, nv, state, scale,
-                       make_int4(d[0], d[1], d[2], d[3]), make_int4(o[0], o[1], o[2], o[3]), out);
+    if (len <= 0) return;
+    hipLaunchKernelGGL(k_synth_eri, grid_for(len), dim3(256), 0, st, m, no, nv, state, scale,
+                       make_int4(d[0], d[1], d[2], d[3]), make_int4(o[0], o[1], o[2], o[3]), blist, c0, len, out);
     CK_CHECK(hipGetLastError());
+}
+
+void launch_synth_eri(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls, cd *out,
+                      hipStream_t st) {
+    int64_t total = (int64_t)m.N * m.N * m.N;
+    for (int t = 0; t < 4; ++t) total *= cls[t] == 'o' ? no : (cls[t] == 'v' ? nv : no + nv);
+    launch_synth_eri_range(m, no, nv, seed, scale, cls, nullptr, 0, total, out, st);
 }
 
 __global__ void k_synth_fock(int N, int no, int nv, uint64_t st, cd *fock) {

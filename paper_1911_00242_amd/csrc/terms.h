@@ -1,7 +1,7 @@
 // Launchers of the residual's elementwise / small-contraction kernels and of the
 // reductions, update and DIIS kernels (internal to libccsdk).
 #pragma once
-#include "common.h"
+#include "sysdev.h"
 
 namespace ck {
 
@@ -45,14 +45,21 @@ void launch_ring_x(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, 
                    hipStream_t st);
 // r2 = <ab||ij> + P(ij)P(ab) X
 void launch_assemble_r2(const SysDev &s, const cd *X, cd *r2, hipStream_t st);
-// Relaid-out copies of the static classes, made once per set of inputs: ovvoT, ovvvT and
-// oovvT (the last two indices swapped) on the FP64 path; on the mixed path (ovvv_c
-// non-null) complex64 ovvoT, ovvv, ovvvT, oovv and oovvT instead.
+// Relaid-out copies of the static classes, made once per set of inputs on the FP64 path:
+// ovvoT, ovvvT and oovvT (the last two indices swapped).
 struct StaticCopies {
     cd *ovvoT, *ovvvT, *oovvT;
-    cf *ovvoT_c, *ovvv_c, *ovvvT_c, *oovv_c, *oovvT_c;
 };
 void launch_static_copies(const SysDev &s, const StaticCopies &c, hipStream_t st);
+// The mixed path keeps its integral classes in complex64 only; they are made once per set
+// of inputs from complex128 values passed through a staging buffer, a range at a time:
+// dst = src rounded to complex64 (round_c64: exactly n elements, no padding) or widened
+// to complex128 (to_c128) over n elements; nblocks blocks of v x v with their two indices
+// swapped, rounded; the whole ovvo class (staged) into the swapped complex64 copy ovvoT_c.
+void launch_round_c64(int64_t n, const cd *src, cf *dst, hipStream_t st);
+void launch_to_c128(int64_t n, const cf *src, cd *dst, hipStream_t st);
+void launch_swap_last2_c64(int64_t nblocks, int v, const cd *src, cf *dst, hipStream_t st);
+void launch_ovvo_transpose_c64(const Dims &d, const cd *ovvo, cf *ovvoT, hipStream_t st);
 void launch_r1(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, cd *P1, cd *r1, hipStream_t st);
 // the two halves of launch_r1: the t2 x integral partial sums (which need no intermediate),
 // then R1 from t1, t2, F and those partials
@@ -110,6 +117,10 @@ void launch_lincomb(int64_t n, const cd *const *src, const DiisDev &dd, Gate gat
 void launch_synth_fock(const Mesh &m, int no, int nv, uint64_t seed, cd *fock, hipStream_t st);
 void launch_synth_eri(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls, cd *out,
                       hipStream_t st);
+// elements c0 .. c0+len-1 of class cls into out[0 .. len-1]; with blist, the class stored on
+// the listed momentum blocks only (element c in block blist[c / block size])
+void launch_synth_eri_range(const Mesh &m, int no, int nv, uint64_t seed, double scale, const char *cls,
+                            const int32_t *blist, int64_t c0, int64_t len, cd *out, hipStream_t st);
 void launch_diag(const Dims &d, const cd *fock, double *eo, double *ev, hipStream_t st);
 
 }  // namespace ck

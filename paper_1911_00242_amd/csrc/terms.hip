@@ -73,6 +73,7 @@ __global__ void k_block_transpose(Dims d, const cd *src, cd *dst) {
 //   Poo[k][kn][ke](m,i) = 1/2 sum_{n,e,f} taut[k,kn,ke](i,n,e,f) <m k, n kn || e ke, f kf>
 //   Pvv[k][km][kn](a,e) = -1/2 sum_{m,n,f} taut[km,kn,k](m,n,a,f) <m km, n kn || e k, f kf>
 // (one thread per block and output element; the block's rows are shared by a wave)
+template <class IT>
 __global__ void k_foo_partial(SysDev s, const cd *t1, const cd *t2, cd *Poo) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     GRID_STRIDE(idx, (int64_t)N * N * N * no * no) {
@@ -87,12 +88,13 @@ __global__ void k_foo_partial(SysDev s, const cd *t1, const cd *t2, cd *Poo) {
                 for (int f = 0; f < nv; ++f) {
                     int64_t ti = b + (((int64_t)i * no + nn) * nv + e) * nv + f;
                     cd tt = tau_el(t1, t2, ti, k, kn, ke, kf, i, nn, e, f, no, nv, 0.5);
-                    cfma(acc, tt, s.oovv[b + (((int64_t)m * no + nn) * nv + e) * nv + f]);
+                    cfma(acc, tt, to_cd(oovv_of<IT>(s)[b + (((int64_t)m * no + nn) * nv + e) * nv + f]));
                 }
         Poo[idx] = cscale(acc, 0.5);
     }
 }
 
+template <class IT>
 __global__ void k_fvv_partial(SysDev s, const cd *t1, const cd *t2, cd *Pvv) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     GRID_STRIDE(idx, (int64_t)N * N * N * nv * nv) {
@@ -107,7 +109,7 @@ __global__ void k_fvv_partial(SysDev s, const cd *t1, const cd *t2, cd *Pvv) {
                 for (int f = 0; f < nv; ++f) {
                     int64_t ti = b + (((int64_t)mm * no + nn) * nv + a) * nv + f;
                     cd tt = tau_el(t1, t2, ti, km, kn, k, kf, mm, nn, a, f, no, nv, 0.5);
-                    cfma(acc, tt, s.oovv[b + (((int64_t)mm * no + nn) * nv + e) * nv + f]);
+                    cfma(acc, tt, to_cd(oovv_of<IT>(s)[b + (((int64_t)mm * no + nn) * nv + e) * nv + f]));
                 }
         Pvv[idx] = cscale(acc, -0.5);
     }
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(RB_NT) void k_r1_blocks(SysDev s, const cd *t2, cd 
     auto stage_h = [&](int n, int m0, int nm) {
         for (int x = tid; x < nm * no * nv; x += RB_NT) {
             const int m = x / (no * nv), i = (x / nv) % no, f = x % nv;
-            Hs[(m * no + i) * rs + f] = s.ooov[hb + (((int64_t)(m0 + m) * no + n) * no + i) * nv + f];
+            Hs[(m * no + i) * rs + f] = to_cd(ooov_of<IT>(s)[hb + (((int64_t)(m0 + m) * no + n) * no + i) * nv + f]);
         }
     };
     const bool one = (int64_t)no * nv * rs <= RB_T && (int64_t)nv * (vv + 1) <= RB_G && (int64_t)no * no * rs <= RB_H;
@@ -521,8 +523,9 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     const int64_t tb = blk * s.d.t2blk();
     const int64_t ov3 = (int64_t)no * nv * nv * nv, o3v = (int64_t)no * no * no * nv;
     const IT *gb = ovvv_of<IT>(s) + blk3(N, q, p, r) * ov3;  // (n, a, e, f)
-    const cd *hb = s.ooov + blk * o3v;                       // (m, n, i, f)
-    cd pt[PT], ph[PH];
+    const IT *hb = ooov_of<IT>(s) + blk * o3v;               // (m, n, i, f)
+    cd pt[PT];
+    IT ph[PH];  // in the stored type until written to LDS
 #define RB_LOAD(n)                                                                          \
     _Pragma("unroll") for (int u = 0; u < PT; ++u) {                                        \
         const int x = tid + 256 * u, row = x / (VM * VM), e = (x / VM) % VM, f = x % VM;    \
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     _Pragma("unroll") for (int u = 0; u < PH; ++u) {                                        \
         const int x = tid + 256 * u, m = x / (OM * VM), i = (x / VM) % OM, f = x % VM;      \
         ph[u] = (m < no && i < no && f < nv) ? hb[(((int64_t)m * no + (n)) * no + i) * nv + f] \
-                                             : make_double2(0.0, 0.0);                      \
+                                             : IT{};                                        \
     }
 #define RB_STORE()                                                                          \
     _Pragma("unroll") for (int u = 0; u < PT; ++u) {                                        \
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(256) void k_r1_blocks_t(SysDev s, const cd *t2, cd 
     }                                                                                       \
     _Pragma("unroll") for (int u = 0; u < PH; ++u) {                                        \
         const int x = tid + 256 * u, m = x / (OM * VM), i = (x / VM) % OM, f = x % VM;      \
-        HS[(m * OM + i) * VP + f] = ph[u];                                                  \
+        HS[(m * OM + i) * VP + f] = to_cd(ph[u]);                                           \
     }
     // P1a roles
     const int aa = tid / 16, ks = tid % 16;
@@ -634,6 +637,7 @@ __device__ inline cd wave_sum(cd v) {
 // F_ov[k](m,e) = f_me + sum_{kn,n,f} t_{n kn}^{f kn} <m k, n kn || e k, f kn>: one wave per
 // output element, the lanes over (kn, n, f) (runs of n_vir contiguous integrals), then a
 // fixed-order wave reduction.
+template <class IT>
 __global__ __launch_bounds__(64) void k_fov(SysDev s, const cd *t1, cd *Fov) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv, ov = no * nv;
     const int64_t idx = blockIdx.x;
@@ -642,13 +646,14 @@ __global__ __launch_bounds__(64) void k_fov(SysDev s, const cd *t1, cd *Fov) {
     cd acc = make_double2(0.0, 0.0);
     for (int u = lane; u < N * ov; u += 64) {
         const int kn = u / ov, nn = (u / nv) % no, f = u % nv;
-        const cd *g = s.oovv + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)m * no * nv * nv;
-        cfma(acc, t1[(int64_t)u], g[((int64_t)nn * nv + e) * nv + f]);
+        const IT *g = oovv_of<IT>(s) + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)m * no * nv * nv;
+        cfma(acc, t1[(int64_t)u], to_cd(g[((int64_t)nn * nv + e) * nv + f]));
     }
     acc = wave_sum(acc);
     if (lane == 0) Fov[idx] = cadd(s.fock[((int64_t)k * n + m) * n + no + e], acc);
 }
 
+template <class IT>
 __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd *Fov, const cd *Poo,
                                                 const cd *Pvv, cd *Foo, cd *Fvv) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
@@ -663,8 +668,8 @@ __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd
         // sum_{kn, n, e} t_{n kn}^{e kn} <m k, n kn || i k, e kn>
         for (int u = lane; u < N * ov; u += 64) {
             const int kn = u / ov, nn = (u / nv) % no, e = u % nv;
-            const cd *g = s.ooov + blk3(N, k, kn, k) * ((int64_t)no * no * no * nv);
-            cfma(acc, t1[((int64_t)kn * no + nn) * nv + e], g[(((int64_t)m * no + nn) * no + i) * nv + e]);
+            const IT *g = ooov_of<IT>(s) + blk3(N, k, kn, k) * ((int64_t)no * no * no * nv);
+            cfma(acc, t1[((int64_t)kn * no + nn) * nv + e], to_cd(g[(((int64_t)m * no + nn) * no + i) * nv + e]));
         }
         for (int u = lane; u < ns * N * N; u += 64)  // split sp = u / N^2, then the momenta of the block
             acc = cadd(acc, Poo[(((int64_t)(u / (N * N)) * n3 + (int64_t)k * N * N + u % (N * N)) * no + m) * no + i]);
@@ -682,8 +687,8 @@ __global__ __launch_bounds__(64) void k_foo_fvv(SysDev s, const cd *t1, const cd
         // -<m km, a k || e k, f km> (ovvv block [km,k,k])
         for (int u = lane; u < N * ov; u += 64) {
             const int km = u / ov, m = (u / nv) % no, f = u % nv;
-            const cd *g = s.ovvv + blk3(N, km, k, k) * ((int64_t)no * nv * nv * nv);
-            cfma(acc, t1[((int64_t)km * no + m) * nv + f], g[(((int64_t)m * nv + a) * nv + e) * nv + f]);
+            const IT *g = ovvv_of<IT>(s) + blk3(N, km, k, k) * ((int64_t)no * nv * nv * nv);
+            cfma(acc, t1[((int64_t)km * no + m) * nv + f], to_cd(g[(((int64_t)m * nv + a) * nv + e) * nv + f]));
         }
         acc = make_double2(-acc.x, -acc.y);
         for (int u = lane; u < ns * N * N; u += 64)
@@ -721,6 +726,7 @@ __global__ void k_ftilde(Dims d, const cd *t1, const cd *Foo, const cd *Fvv, con
 
 // ------------------------------------------------------------------ hole-hole intermediate
 // WT[ki][kj][km](i,j,m,n) = <mn||ij> + t_j^e <mn||ie> - t_i^e <mn||je>   (tau part by GEMM)
+template <class IT>
 __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o4 = (int64_t)no * no * no * no, o3v = (int64_t)no * no * no * nv;
@@ -730,13 +736,13 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
         int64_t blk = idx / o4;
         int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
         int kn = kcv(s.kc, N, ki, kj, km);
-        cd acc = s.oooo[blk3(N, km, kn, ki) * o4 + (((int64_t)m * no + nn) * no + i) * no + j];
-        const cd *g1 = s.ooov + blk3(N, km, kn, ki) * o3v + (((int64_t)m * no + nn) * no + i) * nv;
-        const cd *g2 = s.ooov + blk3(N, km, kn, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv;
+        cd acc = to_cd(oooo_of<IT>(s)[blk3(N, km, kn, ki) * o4 + (((int64_t)m * no + nn) * no + i) * no + j]);
+        const IT *g1 = ooov_of<IT>(s) + blk3(N, km, kn, ki) * o3v + (((int64_t)m * no + nn) * no + i) * nv;
+        const IT *g2 = ooov_of<IT>(s) + blk3(N, km, kn, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv;
 #pragma unroll 8
         for (int e = 0; e < nv; ++e) {
-            cfma(acc, t1[((int64_t)kj * no + j) * nv + e], g1[e]);
-            cd p = cmul(t1[((int64_t)ki * no + i) * nv + e], g2[e]);
+            cfma(acc, t1[((int64_t)kj * no + j) * nv + e], to_cd(g1[e]));
+            cd p = cmul(t1[((int64_t)ki * no + i) * nv + e], to_cd(g2[e]));
             acc = csub(acc, p);
         }
         WT[idx] = acc;
@@ -803,7 +809,7 @@ __global__ void k_hh_t1_rest(SysDev s, const cd *t1, const cd *Y, const cd *X, c
 // both t1 blocks in LDS, so every ooov / oooo element is read once with contiguous loads;
 // a thread owns (n, i) and two j.  LDS rows are padded to n_vir + 1 and ordered so that
 // the lanes of a wave (consecutive n, then i) read distinct banks.
-template <int OM, int VM, bool EX = false>
+template <int OM, int VM, bool EX = false, class IT = cd>
 __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon);
 
 // ------------------------------------------------------------------ XCD-aware block order
@@ -909,12 +915,12 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_t(SysDev s, const cd *t1, cd
 // last two indices swapped, made once per set of inputs so that every ring seed below
 // reads contiguous runs.
 template <class OT>
-__global__ void k_ovvo_transpose(SysDev s, OT *ovvoT) {
-    const int no = s.d.no, nv = s.d.nv;
-    GRID_STRIDE(idx, s.d.t2()) {
+__global__ void k_ovvo_transpose(Dims d, const cd *ovvo, OT *ovvoT) {
+    const int no = d.no, nv = d.nv;
+    GRID_STRIDE(idx, d.t2()) {
         int e = (int)(idx % nv), j = (int)((idx / nv) % no);
         int64_t mb = idx / ((int64_t)no * nv);  // (block, m, b)
-        from_cd(s.ovvo[(mb * nv + e) * no + j], ovvoT[idx]);
+        from_cd(ovvo[(mb * nv + e) * no + j], ovvoT[idx]);
     }
 }
 
@@ -934,6 +940,9 @@ __global__ void k_swap_last2(int64_t nblocks, int v, const cd *src, OT *dst) {
 __global__ void k_to_c64(int64_t n, const cd *src, cf *dst) {
     GRID_STRIDE(idx, n) from_cd(src[idx], dst[idx]);
 }
+__global__ void k_to_c128(int64_t n, const cf *src, cd *dst) {
+    GRID_STRIDE(idx, n) dst[idx] = to_cd(src[idx]);
+}
 
 // Z[km][kb][ke](m,n,j,e) = <m km, n kb || e ke, j kj> + sum_f t_j^f <m km, n kb || e ke, f kj>
 template <class IT>
@@ -947,7 +956,7 @@ __global__ void k_ring_z(SysDev s, const cd *t1, cd *Z) {
         int ke = (int)(blk % N), kb = (int)((blk / N) % N), km = (int)(blk / ((int64_t)N * N));
         int kj = kcv(s.kc, N, km, kb, ke);
         // <mn||ej> = -<mn||je>  (ooov block [km,kb,kj])
-        cd acc = s.ooov[blk3(N, km, kb, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv + e];
+        cd acc = to_cd(ooov_of<IT>(s)[blk3(N, km, kb, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv + e]);
         acc = make_double2(-acc.x, -acc.y);
         const IT *g = oovvT_of<IT>(s) + blk * s.d.t2blk() + ((int64_t)m * no + nn) * nv * nv + e;
         #pragma unroll 8
@@ -996,7 +1005,7 @@ __global__ void k_ring_q(SysDev s, const cd *t1, cd *Q) {
         cd acc = make_double2(0.0, 0.0);
         #pragma unroll 8
         for (int e = 0; e < nv; ++e) cfma(acc, t1[((int64_t)ki * no + i) * nv + e], to_cd(g[e]));
-        cd h = s.ooov[blk3(N, ki, kj, ka) * o3v + (((int64_t)i * no + j) * no + m) * nv + b];
+        cd h = to_cd(ooov_of<IT>(s)[blk3(N, ki, kj, ka) * o3v + (((int64_t)i * no + j) * no + m) * nv + b]);
         acc.x += 0.5 * h.x;
         acc.y -= 0.5 * h.y;
         Q[idx] = acc;
@@ -1027,11 +1036,11 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *__rest
     cd gr[VM];
 #pragma unroll
     for (int f = 0; f < VM; ++f) gr[f] = f < nv ? to_cd(g[(int64_t)f * nv]) : make_double2(0.0, 0.0);
-    const cd *h = s.ooov + blk3(N, km, kb, kj) * o3v + ((int64_t)m * no + nn) * no * nv + e;
+    const IT *h = ooov_of<IT>(s) + blk3(N, km, kb, kj) * o3v + ((int64_t)m * no + nn) * no * nv + e;
     cd *z = Z + blk * o3v + ((int64_t)m * no + nn) * no * nv + e;
     for (int j = 0; j < no; ++j) {
         // <mn||ej> = -<mn||je>
-        const cd x = h[(int64_t)j * nv];
+        const cd x = to_cd(h[(int64_t)j * nv]);
         cd acc = make_double2(-x.x, -x.y);
 #pragma unroll
         for (int f = 0; f < VM; ++f)
@@ -1234,12 +1243,12 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     }
     if (!act) return;
     const int j = jb / nv, b = jb % nv;
-    const cd *h = s.ooov + blk3(N, ki, kj, ka) * o3v + ((int64_t)j * no + m) * nv + b;
+    const IT *h = ooov_of<IT>(s) + blk3(N, ki, kj, ka) * o3v + ((int64_t)j * no + m) * nv + b;
     cd *qo = Q + blk * o3v + (int64_t)m * no * no * nv + jb;
 #pragma unroll
     for (int i = 0; i < OM; ++i) {
         if (i >= no) break;
-        const cd x = h[(int64_t)i * no * no * nv];
+        const cd x = to_cd(h[(int64_t)i * no * no * nv]);
         cd v = acc[i];
         v.x += 0.5 * x.x;
         v.y -= 0.5 * x.y;
@@ -1254,6 +1263,7 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
 //                                                 P(ij)P(ab) gives P(ij) / -P(ab) of them)
 //   + 1/2 t_ij^af Fvt(b,f), - 1/2 t_in^ab Fot(n,j) (antisymmetric in ij / in ab, likewise)
 // This uses the antisymmetry of t2 in (i,j) and (a,b).
+template <class IT>
 __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, const cd *Fot, const cd *Fvt,
                              cd *X) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
@@ -1273,9 +1283,9 @@ __global__ void k_ring_xinit(SysDev s, const cd *t1, const cd *t2, const cd *Q, 
         acc = make_double2(-acc.x, -acc.y);
         // -1/2 sum_c t_i^c conj(<j kj, c ki || a ka, b kb>)
         cd y = make_double2(0.0, 0.0);
-        const cd *g = s.ovvv + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
+        const IT *g = ovvv_of<IT>(s) + blk3(N, kj, ki, ka) * ov3 + (int64_t)j * nv * nv * nv + (int64_t)a * nv + b;
         #pragma unroll 8
-        for (int c = 0; c < nv; ++c) cfma(y, t1[((int64_t)ki * no + i) * nv + c], cconj(g[(int64_t)c * nv * nv]));
+        for (int c = 0; c < nv; ++c) cfma(y, t1[((int64_t)ki * no + i) * nv + c], cconj(to_cd(g[(int64_t)c * nv * nv])));
         // +1/2 sum_f t_ij^af Fvt[kb](b,f)  - 1/2 sum_n t_in^ab Fot[kj](n,j)
         const int64_t tb = blk3(N, ki, kj, ka) * s.d.t2blk();
         const cd *ta = t2 + tb + (((int64_t)i * no + j) * nv + a) * nv;
@@ -1508,6 +1518,7 @@ __global__ void k_assemble_r2(SysDev s, const cd *X, cd *r2) {
 // P1[k][kx][ky](i,a): the two t2-integral terms of the T1 equation, one momentum block each
 //   +1/2 sum_{n,e,f} t2[k,kx,ky](i,n,e,f) <a k, n kx || e ky, f kf>        (ky = k_e)
 //   -1/2 sum_{m,n,f} t2[kx,ky,k](m,n,a,f) <m kx, n ky || i k, f kf>        (kx = k_m, ky = k_n)
+template <class IT>
 __global__ void k_r1_partial(SysDev s, const cd *t2, cd *P1) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o3v = (int64_t)no * no * no * nv, ov3 = (int64_t)no * nv * nv * nv;
@@ -1519,19 +1530,19 @@ __global__ void k_r1_partial(SysDev s, const cd *t2, cd *P1) {
         {
             // <a k, n kx||e f> = -<n kx, a k||e f>  (ovvv block [kx,k,ky])
             const cd *t = t2 + blk3(N, k, kx, ky) * s.d.t2blk() + (int64_t)i * no * nv * nv;
-            const cd *g = s.ovvv + blk3(N, kx, k, ky) * ov3 + (int64_t)a * nv * nv;
+            const IT *g = ovvv_of<IT>(s) + blk3(N, kx, k, ky) * ov3 + (int64_t)a * nv * nv;
             for (int nn = 0; nn < no; ++nn)
                 for (int ef = 0; ef < nv * nv; ++ef)
-                    acc = csub(acc, cmul(t[(int64_t)nn * nv * nv + ef], g[(int64_t)nn * nv * nv * nv + ef]));
+                    acc = csub(acc, cmul(t[(int64_t)nn * nv * nv + ef], to_cd(g[(int64_t)nn * nv * nv * nv + ef])));
         }
         {
             const cd *t = t2 + blk3(N, kx, ky, k) * s.d.t2blk() + (int64_t)a * nv;
-            const cd *g = s.ooov + blk3(N, kx, ky, k) * o3v + (int64_t)i * nv;
+            const IT *g = ooov_of<IT>(s) + blk3(N, kx, ky, k) * o3v + (int64_t)i * nv;
             for (int mm = 0; mm < no; ++mm)
                 for (int nn = 0; nn < no; ++nn)
                     for (int f = 0; f < nv; ++f)
                         acc = csub(acc, cmul(t[((int64_t)mm * no + nn) * nv * nv + f],
-                                             g[((int64_t)mm * no + nn) * no * nv + f]));
+                                             to_cd(g[((int64_t)mm * no + nn) * no * nv + f])));
         }
         P1[idx] = cscale(acc, 0.5);
     }
@@ -1543,6 +1554,7 @@ __global__ void k_r1_partial(SysDev s, const cd *t2, cd *P1) {
 // the N_k^2 partial sums are spread over the lanes (consecutive lanes read consecutive
 // elements) and combined by a wave reduction, so the kernel is not limited by a few
 // hundred threads each running the whole sum.
+template <class IT>
 __global__ __launch_bounds__(64) void k_r1_wave(SysDev s, const cd *t1, const cd *t2, const cd *Foo, const cd *Fvv,
                                                 const cd *Fov, const cd *P1, int nparts, cd *r1) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv, n = no + nv;
@@ -1557,11 +1569,12 @@ __global__ __launch_bounds__(64) void k_r1_wave(SysDev s, const cd *t1, const cd
         const cd *t = t2 + blk3(N, k, kn, k) * s.d.t2blk() + (int64_t)i * no * nv * nv + (int64_t)a * nv;
         cfma(acc, t[(int64_t)nn * nv * nv + f], Fov[((int64_t)kn * no + nn) * nv + f]);
     }
-    // sum_{kn, r, c} t_{r kn}^{c kn} <r kn, a k || c kn, i k>   (ovvo block [kn,k,kn])
+    // sum_{kn, r, c} t_{r kn}^{c kn} <r kn, a k || c kn, i k>   (ovvo block [kn,k,kn], read
+    // from its copy with the last two indices swapped, ovvoT(r, a, i, c))
     for (int u = lane; u < N * ov; u += 64) {
         const int kn = u / ov, r = (u / nv) % no, c = u % nv;
-        const cd *g = s.ovvo + blk3(N, kn, k, kn) * s.d.t2blk() + (int64_t)a * nv * no + i;
-        cfma(acc, t1[((int64_t)kn * no + r) * nv + c], g[(int64_t)r * nv * nv * no + (int64_t)c * no]);
+        const IT *g = ovvoT_of<IT>(s) + blk3(N, kn, k, kn) * s.d.t2blk() + ((int64_t)a * no + i) * nv + c;
+        cfma(acc, t1[((int64_t)kn * no + r) * nv + c], to_cd(g[(int64_t)r * nv * no * nv]));
     }
     // the per-block partial sums
     const int64_t np = (int64_t)N * N * N * no * nv;
@@ -1636,7 +1649,10 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
 
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
-    hipLaunchKernelGGL(k_fov, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
+    if (s.ovvv_c)
+        hipLaunchKernelGGL(k_fov<cf>, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
+    else
+        hipLaunchKernelGGL(k_fov<cd>, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, w.Fov);
     CK_CHECK(hipGetLastError());
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo, w.Pvv);
@@ -1647,17 +1663,23 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
         else
             hipLaunchKernelGGL(k_f_blocks<cd>, grid, dim3(FB_NT), 0, st, s, t1, t2, w.Poo, w.Pvv);
         CK_CHECK(hipGetLastError());
+    } else if (s.ovvv_c) {
+        LAUNCH(k_foo_partial<cf>, N * N * N * no * no, s, t1, t2, w.Poo);
+        LAUNCH(k_fvv_partial<cf>, N * N * N * nv * nv, s, t1, t2, w.Pvv);
     } else {
-        LAUNCH(k_foo_partial, N * N * N * no * no, s, t1, t2, w.Poo);
-        LAUNCH(k_fvv_partial, N * N * N * nv * nv, s, t1, t2, w.Pvv);
+        LAUNCH(k_foo_partial<cd>, N * N * N * no * no, s, t1, t2, w.Poo);
+        LAUNCH(k_fvv_partial<cd>, N * N * N * nv * nv, s, t1, t2, w.Pvv);
     }
-    hipLaunchKernelGGL(k_foo_fvv, dim3((unsigned)(N * no * no + N * nv * nv)), dim3(64), 0, st, s, t1, w.Fov, w.Poo,
-                       w.Pvv, w.Foo, w.Fvv);
+    const dim3 gf((unsigned)(N * no * no + N * nv * nv));
+    if (s.ovvv_c)
+        hipLaunchKernelGGL(k_foo_fvv<cf>, gf, dim3(64), 0, st, s, t1, w.Fov, w.Poo, w.Pvv, w.Foo, w.Fvv);
+    else
+        hipLaunchKernelGGL(k_foo_fvv<cd>, gf, dim3(64), 0, st, s, t1, w.Fov, w.Poo, w.Pvv, w.Foo, w.Fvv);
     CK_CHECK(hipGetLastError());
     LAUNCH(k_ftilde, N * no * no + N * nv * nv, s.d, t1, w.Foo, w.Fvv, w.Fov, w.Fot, w.Fvt);
 }
 
-template <int OM, int VM, bool EX>
+template <int OM, int VM, bool EX, class IT>
 __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd *WT, bool canon) {
     static_assert(OM == 8, "thread roles assume n_occ <= 8");
     constexpr int VP = VM + 1;
@@ -1678,13 +1700,13 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
     const int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
     const int kn = kcv(s.kc, N, ki, kj, km);
     if (canon && (ki > kj || km > kn)) return;
-    const cd *g1 = s.ooov + blk3(N, km, kn, ki) * o3v + (int64_t)m * no * no * nv;  // (n, i, e)
-    const cd *g2 = s.ooov + blk3(N, km, kn, kj) * o3v + (int64_t)m * no * no * nv;  // (n, j, e)
-    const cd *g0 = s.oooo + blk3(N, km, kn, ki) * o4 + (int64_t)m * no * no * no;    // (n, i, j)
+    const IT *g1 = ooov_of<IT>(s) + blk3(N, km, kn, ki) * o3v + (int64_t)m * no * no * nv;  // (n, i, e)
+    const IT *g2 = ooov_of<IT>(s) + blk3(N, km, kn, kj) * o3v + (int64_t)m * no * no * nv;  // (n, j, e)
+    const IT *g0 = oooo_of<IT>(s) + blk3(N, km, kn, ki) * o4 + (int64_t)m * no * no * no;    // (n, i, j)
     for (int x = threadIdx.x; x < no * no * nv; x += blockDim.x) {
         const int n = x / (no * nv), i = (x / nv) % no, e = x % nv;
-        A1[(i * OM + n) * VP + e] = g1[x];
-        A2[(i * OM + n) * VP + e] = g2[x];
+        A1[(i * OM + n) * VP + e] = to_cd(g1[x]);
+        A2[(i * OM + n) * VP + e] = to_cd(g2[x]);
     }
     for (int x = threadIdx.x; x < no * nv; x += blockDim.x) {
         T1I[(x / nv) * VP + x % nv] = t1[(int64_t)ki * no * nv + x];
@@ -1692,7 +1714,7 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
     }
     for (int x = threadIdx.x; x < no * no * no; x += blockDim.x) {
         const int n = x / (no * no), i = (x / no) % no, j = x % no;
-        O4[(n * OM + i) * OM + j] = g0[x];
+        O4[(n * OM + i) * OM + j] = to_cd(g0[x]);
     }
     __syncthreads();
     const int n = threadIdx.x % OM, i = (threadIdx.x / OM) % OM, j0 = 2 * (threadIdx.x / (OM * OM));
@@ -1716,9 +1738,11 @@ __global__ __launch_bounds__(256) void k_wmnij_init_t(SysDev s, const cd *t1, cd
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
     if (no <= 8 && nv <= 16) {
-        LAUNCH_T(k_wmnij_init_t, xcd_grid(N * N * N * no), dim3(256), s, t1, WT, canon);
+        LAUNCH_TI(k_wmnij_init_t, xcd_grid(N * N * N * no), dim3(256), s, t1, WT, canon);
+    } else if (s.ovvv_c) {
+        LAUNCH(k_wmnij_init<cf>, N * N * N * no * no * no * no, s, t1, WT);
     } else {
-        LAUNCH(k_wmnij_init, N * N * N * no * no * no * no, s, t1, WT);
+        LAUNCH(k_wmnij_init<cd>, N * N * N * no * no * no * no, s, t1, WT);
     }
 }
 
@@ -1857,17 +1881,18 @@ void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st) {
 
 void launch_static_copies(const SysDev &s, const StaticCopies &c, hipStream_t st) {
     const int64_t N3 = (int64_t)s.d.N * s.d.N * s.d.N, o = s.d.no, v = s.d.nv;
-    if (c.ovvv_c) {
-        LAUNCH(k_ovvo_transpose<cf>, s.d.t2(), s, c.ovvoT_c);
-        LAUNCH(k_to_c64, N3 * o * v * v * v, N3 * o * v * v * v, s.ovvv, c.ovvv_c);
-        LAUNCH(k_swap_last2<cf>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, c.ovvvT_c);
-        LAUNCH(k_to_c64, s.d.t2(), s.d.t2(), s.oovv, c.oovv_c);
-        LAUNCH(k_swap_last2<cf>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, c.oovvT_c);
-    } else {
-        LAUNCH(k_ovvo_transpose<cd>, s.d.t2(), s, c.ovvoT);
-        LAUNCH(k_swap_last2<cd>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, c.ovvvT);
-        LAUNCH(k_swap_last2<cd>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, c.oovvT);
-    }
+    LAUNCH(k_ovvo_transpose<cd>, s.d.t2(), s.d, s.ovvo, c.ovvoT);
+    LAUNCH(k_swap_last2<cd>, N3 * o * v * v * v, N3 * o * v, (int)v, s.ovvv, c.ovvvT);
+    LAUNCH(k_swap_last2<cd>, N3 * o * o * v * v, N3 * o * o, (int)v, s.oovv, c.oovvT);
+}
+
+void launch_round_c64(int64_t n, const cd *src, cf *dst, hipStream_t st) { LAUNCH(k_to_c64, n, n, src, dst); }
+void launch_to_c128(int64_t n, const cf *src, cd *dst, hipStream_t st) { LAUNCH(k_to_c128, n, n, src, dst); }
+void launch_swap_last2_c64(int64_t nblocks, int v, const cd *src, cf *dst, hipStream_t st) {
+    LAUNCH(k_swap_last2<cf>, nblocks * v * v, nblocks, v, src, dst);
+}
+void launch_ovvo_transpose_c64(const Dims &d, const cd *ovvo, cf *ovvoT, hipStream_t st) {
+    LAUNCH(k_ovvo_transpose<cf>, d.t2(), d, ovvo, ovvoT);
 }
 
 // The W_mbej seed: Z into scratch, then W0 (reads Z) into WR.
@@ -1930,8 +1955,10 @@ void launch_ring_x(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, 
             LAUNCH_WI(16, 16, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 16), s, t1, t2, scratch, w.Fot, w.Fvt, X);
         else
             LAUNCH_WI(16, 32, k_xinit_t, xcd_grid(n3 * nv), dim3(16 * 32), s, t1, t2, scratch, w.Fot, w.Fvt, X);
+    } else if (s.ovvv_c) {
+        LAUNCH(k_ring_xinit<cf>, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     } else {
-        LAUNCH(k_ring_xinit, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
+        LAUNCH(k_ring_xinit<cd>, n3 * no * nv * no * nv, s, t1, t2, scratch, w.Fot, w.Fvt, X);
     }
 }
 
@@ -1966,16 +1993,22 @@ void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
         else
             hipLaunchKernelGGL(k_r1_blocks<cd>, grid, dim3(RB_NT), 0, st, s, t2, P1, P1 + ns * np);
         CK_CHECK(hipGetLastError());
+    } else if (s.ovvv_c) {
+        LAUNCH(k_r1_partial<cf>, N * N * N * no * nv, s, t2, P1);
     } else {
-        LAUNCH(k_r1_partial, N * N * N * no * nv, s, t2, P1);
+        LAUNCH(k_r1_partial<cd>, N * N * N * no * nv, s, t2, P1);
     }
 }
 
 void launch_r1_final(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, const cd *P1, cd *r1,
                      hipStream_t st) {
     const int64_t N = s.d.N, no = s.d.no, nv = s.d.nv;
-    hipLaunchKernelGGL(k_r1_wave, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv, w.Fov, P1,
-                       r1_parts(s.d), r1);
+    if (s.ovvv_c)
+        hipLaunchKernelGGL(k_r1_wave<cf>, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv,
+                           w.Fov, P1, r1_parts(s.d), r1);
+    else
+        hipLaunchKernelGGL(k_r1_wave<cd>, dim3((unsigned)(N * no * nv)), dim3(64), 0, st, s, t1, t2, w.Foo, w.Fvv,
+                           w.Fov, P1, r1_parts(s.d), r1);
     CK_CHECK(hipGetLastError());
 }
 
