@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--batch-summary", type=int, default=1,
                     help="also run the 96-system batched form on the mixed path and report it under 'batch'")
+    ap.add_argument("--largest", default="5,4,2",
+                    help="with the default workload, also time the mixed path on this mesh (the largest that "
+                         "fits one MI355X at n_occ=8, n_vir=16) and report it under 'largest_instance' (0 = skip)")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the N_k=27 workload: the batched form, this many independent seeded "
                          "systems (shapes drawn from seed 40000), converged on both paths")
@@ -160,6 +163,26 @@ def run_path(ck, torch, prec, grid, no, nv, seed, diis, steps, warmup, converge,
     del ctx
     torch.cuda.empty_cache()
     return out
+
+
+def largest_instance(ck, torch, a):
+    """The mixed path on the largest mesh one GPU holds at the workload's block shape: its
+    step time (captured iterations, as for the main line) and its dominant product."""
+    grid = tuple(int(x) for x in a.largest.split(","))
+    N = grid[0] * grid[1] * grid[2]
+    steps = 3
+    r = run_path(ck, torch, 1, grid, a.no, a.nv, a.seed, a.diis, steps, 1, 0, a.tol_mixed, a.max_iter)
+    ms = 1000.0 * r["seconds"] / steps
+    dom = max((k for k in PRODUCT_KERNEL if r["stages"][k][1]), key=lambda k: r["stages"][k][0])
+    tot, n = r["stages"][dom]
+    G, M, Nn, K = r["shapes"][dom]
+    achieved = 24.0 * G * M * Nn * K / (tot / n / 1000.0) / 1e12
+    return {"grid": list(grid), "N_k": N, "n_occ": a.no, "n_vir": a.nv, "evals_per_s": 1000.0 / ms,
+            "ms_per_step": ms, "steps": steps, "workspace_gb": r["workspace_bytes"] / 1e9,
+            "tflops": r["exec_flops"] / (ms / 1000.0) / 1e12,
+            "dominant_product": {"kernel": PRODUCT_KERNEL[dom], "avg_launch_ms": tot / n,
+                                 "achieved_tflops": achieved, "frac_of_bf16_peak": achieved / PEAK["bf16"]},
+            "stages_ms_per_step": {k: v[0] / steps for k, v in r["stages"].items()}}
 
 
 def _cpu_model():
@@ -453,6 +476,8 @@ def main():
                                      "reference": "FP64 GPU path converged to ||R|| < tol"}
     if a.batch_summary and (grid, a.no, a.nv) == ((3, 3, 3), 8, 16):
         line["batch"] = batch_summary(a)
+    if a.largest != "0" and (grid, a.no, a.nv) == ((3, 3, 3), 8, 16):
+        line["largest_instance"] = largest_instance(ck, torch, a)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(a.no, a.nv, N)
