@@ -176,14 +176,18 @@ __global__ void k_oovv_pack(Dims d, const int32_t *kc, PairTabs pt, const cd *oo
 // LDS, <m ka, b kb||e f> over m in registers), restricted to the blocks and elements that
 // are canonical in both pairs: a quarter of the reads and writes of the full copy.  The
 // grid covers only those blocks (pt.dblk), so the work is spread evenly over the XCDs.
-// <m kb, a ka||e f> is staged for as many a at a time as fit 2048 elements (all of them
-// when o v^2 <= 2048).  For n_occ <= OM and o v <= 2048.
+// <m kb, a ka||e f> is staged in LDS (element type GT, GC elements) for as many a at a
+// time as fit (all of them when o v^2 <= GC).  For n_occ <= OM and o v <= 2048.
 // EX: exactly n_occ = OM, n_vir = 16 as constants (the branches on the orbital counts fold
-// away, so the LDS reads of consecutive m are issued together)
-template <int OM, bool EX = false>
+// away, so the LDS reads of consecutive m are issued together).  For 8 < n_occ <= 32 the
+// complex64 values are staged as read (GT = cf, 8192 of them in 64 KB): n_occ = 12 with
+// n_vir = 24 takes one pass over a instead of four (3.6 -> 2.6 ms at N_k=8, 12 x 32; those
+// kernels are limited to two waves per SIMD by their registers anyway).  For n_occ <= 8
+// the smaller stage keeps three workgroups per CU, which measured faster than one pass.
+template <int OM, bool EX = false, class GT = cd, int GC = 2048>
 __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, const cd *t1, uint16_t *out,
                                                          int64_t ld, bool c64) {
-    __shared__ cd G1[2048];
+    __shared__ GT G1[GC];
     __shared__ cd TA[OM * 64];
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? 16 : s.d.nv, vv = nv * nv;
     const int64_t v3 = (int64_t)vv * nv, v4 = v3 * nv, ov3 = (int64_t)no * v3;
@@ -202,14 +206,14 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
     const cf *vb = s.vvvv_c + (L / nv) * v4 + (int64_t)e * nv;  // the kept blocks follow dblk
     const int32_t *vpos_ab = pt.vpos + ((int64_t)K * N + ka) * vv;
     const int32_t *vpos_ef = pt.vpos + ((int64_t)K * N + ke) * vv + e * nv;
-    // a chunk of ac values of a: no * ac * nv <= 2048 and no * ac <= OM * 64
-    const int ac = min(nv, 2048 / (no * nv));
+    // a chunk of ac values of a: no * ac * nv <= GC and no * ac <= OM * 64
+    const int ac = min(min(nv, GC / (no * nv)), OM * 64 / no);
     for (int a0 = 0; a0 < nv; a0 += ac) {
         const int na = min(ac, nv - a0), anv = na * nv;
         if (a0) __syncthreads();
         for (int x = threadIdx.x; x < no * anv; x += blockDim.x) {
             const int m = x / anv, af = x % anv;
-            G1[x] = to_cd(g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv]);
+            from_cd(to_cd(g1b[(int64_t)m * v3 + (int64_t)(a0 + af / nv) * vv + af % nv]), G1[x]);
         }
         for (int x = threadIdx.x; x < no * na; x += blockDim.x) TA[x] = ta[(x / na) * nv + a0 + x % na];
         __syncthreads();
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(256) void k_vvvv_dress_pack(SysDev s, PairTabs pt, 
 #pragma unroll
                     for (int m = 0; m < OM; ++m)
                         if (m < no) {
-                            cfma(acc, t1b[m], G1[(m * na + a) * nv + f]);
+                            cfma(acc, t1b[m], to_cd(G1[(m * na + a) * nv + f]));
                             acc = csub(acc, cmul(TA[m * na + a], g2[m]));
                         }
                     put_elem(out, ((int64_t)K * pt.PV + pabs[u]) * ld + pef, acc, c64);
@@ -336,9 +340,9 @@ void launch_vvvv_dress_pack(const SysDev &s, const PairTabs &pt, const cd *t1, u
     else if (s.d.no <= 8)
         hipLaunchKernelGGL((k_vvvv_dress_pack<8>), grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else if (s.d.no <= 16)
-        hipLaunchKernelGGL(k_vvvv_dress_pack<16>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
+        hipLaunchKernelGGL((k_vvvv_dress_pack<16, false, cf, 8192>), grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     else
-        hipLaunchKernelGGL(k_vvvv_dress_pack<32>, grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
+        hipLaunchKernelGGL((k_vvvv_dress_pack<32, false, cf, 8192>), grid, dim3(256), 0, st, s, pt, t1, out, ld, c64);
     CK_CHECK(hipGetLastError());
 }
 

@@ -1911,13 +1911,10 @@ void launch_ring_w(const SysDev &s, const cd *t1, cd *scratch, cd *WR, hipStream
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_WI(16, 16, k_ring_z_t, grid, dim3(16 * 16), s, t1, scratch);
         LAUNCH_WI(16, 16, k_ring_w0_t, grid, dim3(16 * 16), s, t1, scratch, WR);
-    } else if (no <= 16 && nv <= 32) {  // the W0 seed's Z slab (o^2 v) would not fit LDS
+    } else if (no <= 16 && nv <= 32) {  // the W0 seed's Z slab: 128 KB of LDS, one workgroup per CU
         const dim3 grid = xcd_grid(n3 * no);
         LAUNCH_WI(16, 32, k_ring_z_t, grid, dim3(16 * 32), s, t1, scratch);
-        if (s.ovvv_c)
-            LAUNCH(k_ring_w0<cf>, n3 * no * nv * no * nv, s, t1, scratch, WR);
-        else
-            LAUNCH(k_ring_w0<cd>, n3 * no * nv * no * nv, s, t1, scratch, WR);
+        LAUNCH_WI(16, 32, k_ring_w0_t, grid, dim3(32 * 32), s, t1, scratch, WR);
     } else {
         if (s.ovvv_c) {
             LAUNCH(k_ring_z<cf>, n3 * no * no * no * nv, s, t1, scratch);
