@@ -123,7 +123,7 @@ int ccsd_k_residual(ccsd_k_ctx *ctx, int32_t sys, const double *t1, const double
  * DIIS when diis_space > 0).  Stops when every system has ||R|| < tol or after max_iter
  * residual evaluations.  *iters: evaluations done (max over systems); *max_rnorm: largest
  * last norm.  Returns CCSD_K_NOT_CONVERGED if some system did not converge.  With more than one
- * system active, the systems run side by side on four internal streams (default priority,
+ * system active, the systems run side by side on eight internal streams (default priority,
  * created on the first such call, destroyed by ccsd_k_free), ordered after the work already
  * on the context's stream and joined back into it before each host synchronization; each
  * system's results do not depend on this. */
@@ -218,7 +218,7 @@ int ccsd_k_set_graphs(ccsd_k_ctx *ctx, int32_t enable);
 int ccsd_k_set_overlap(ccsd_k_ctx *ctx, int32_t enable);
 
 /* Precision escalation in ccsd_k_iterate (on by default): a mixed-precision system whose
- * residual norm has not halved for four iterations while above the tolerance has reached
+ * residual norm has not halved for three iterations while above the tolerance has reached
  * the rounding floor of its products (two-term split products, FP32 accumulation); its
  * two-term products are then switched to CCSD_K_FORM_SPLIT3 and every product accumulates
  * in FP32 over chunks of 256 k only, the chunks added in FP64; a second such stall

@@ -682,7 +682,9 @@ void collect_timing(ccsd_k_ctx *c) {
 }
 
 // ---------------------------------------------------------------- systems side by side
-constexpr int NLANES = 4;
+// (eight streams: the 96-system batch measured 183 ms per iteration against 192 with four;
+// twelve and sixteen measured the same as eight)
+constexpr int NLANES = 8;
 
 // The streams for a set of systems: the context's own stream for one system; for several,
 // the lanes, each system to the lane with the least work so far (largest first, work
@@ -744,7 +746,7 @@ void apply_form(ccsd_k_ctx *c, System &S, int slot, int a);
 // from one iteration to the next (the two-term split ~2^-16 relative per product, FP32
 // accumulation ~2^-24 sqrt(steps) of the running sum), so the residual of a mixed system
 // has a floor that grows with the coupling strength; a system whose residual norm has not
-// halved for four iterations while still above the tolerance is at that floor.  Every
+// halved for three iterations while still above the tolerance is at that floor.  Every
 // product it runs in a two-term form is then raised to the three-term split, and every
 // product accumulates in FP32 over chunks of 256 k only, adding the chunks in FP64; a
 // second stall shortens the chunks to 64 k.
@@ -755,7 +757,7 @@ void watch_stagnation(ccsd_k_ctx *c, System &S) {
         S.stall = 0;
         return;
     }
-    if (++S.stall < 4) return;
+    if (++S.stall < 3) return;
     S.stall = 0;
     S.rn_ref = S.rnorm;
     if (S.kchunk == 0) {
