@@ -970,8 +970,8 @@ void static_split(System &S, hipStream_t st) {
 
 // The mixed path's integral classes (complex64 only) from complex128 values, the device
 // generator's (host == nullptr) or the caller's: each class passes through X (N^3 o^2 v^2
-// complex128 elements, free until the first residual) a range at a time.  <ab||ef> is kept
-// on the dblk blocks only, in their order.
+// complex128 elements, scratch that every residual rewrites) a range at a time.  <ab||ef>
+// is kept on the dblk blocks only, in their order.
 void mixed_inputs(System &S, const double *const *host, hipStream_t st) {
     static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
     const int64_t N = S.d.N, o = S.d.no, v = S.d.nv, N3 = N * N * N;
