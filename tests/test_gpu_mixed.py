@@ -258,9 +258,10 @@ def test_storage_changes_keep_packed_padding(grid, no, nv):
 @pytest.mark.timeout(600)
 def test_strong_coupling_converges_with_escalation():
     """A 2x2x2-mesh system with n_occ=12, n_vir=24 and integrals x 0.05/N_k, the shape whose
-    mixed-precision residual stalls near 2e-7, above the mixed tolerance 1e-7 (its FP32
-    accumulation over up to 2304 k is the floor: the three-term split alone does not lower
-    it): with precision escalation (three-term split, FP32 accumulation over 256-k chunks
+    mixed-precision residual stalls near 2e-7, above the mixed tolerance 1e-7 (FP32
+    accumulation over up to 2304 k and the two-term split's storage error both set that
+    floor; the three-term split alone does not lower it): with precision escalation
+    (three-term split, FP32 accumulation over 256-k chunks
     added in FP64, floor near 6e-8) the mixed path converges to 1e-7 and its energy is within
     1e-8 Eh of the FP64 path (which matches the oracle); without escalation it stalls."""
     grid, no, nv = (2, 2, 2), 12, 24
