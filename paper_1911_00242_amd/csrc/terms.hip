@@ -1609,17 +1609,8 @@ void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, 
 }
 
 // the blocked side kernels at the workload's exact block shape (n_occ = 8, n_vir = 16) take
-// the sizes as constants: every bound check folds away and index divisions become shifts
-#define LAUNCH_T(K, grid, block, ...)                                                     \
-    do {                                                                                  \
-        if (s.d.no == 8 && s.d.nv == 16)                                                  \
-            hipLaunchKernelGGL((K<8, 16, true>), grid, block, 0, st, __VA_ARGS__);        \
-        else                                                                              \
-            hipLaunchKernelGGL((K<8, 16, false>), grid, block, 0, st, __VA_ARGS__);       \
-        CK_CHECK(hipGetLastError());                                                      \
-    } while (0)
-
-// the same with the element type of the ovvv copy a kernel reads (complex64 on the
+// the sizes as constants (every bound check folds away and index divisions become shifts),
+// with the element type of the integral copies a kernel reads (complex64 on the
 // mixed-precision path)
 #define LAUNCH_TI(K, grid, block, ...)                                                    \
     do {                                                                                  \
