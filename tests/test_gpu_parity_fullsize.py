@@ -206,3 +206,22 @@ def test_mixed_residual_at_t1_matches_oracle(runs, oracle_t):
     assert _rel(got, ref) <= 1e-5
     assert _rel(runs["r1_t_mixed"][R1_KS], oracle_t["R1"][R1_KS]) <= 1e-5
     assert abs(runs["e_t_mixed"] - oracle_t["e"]) <= 1e-8
+
+
+@pytest.mark.timeout(600)
+def test_converged_mixed_energy_within_1e8_of_fp64():
+    """Both paths iterated to convergence from t = 0 at the full size (FP64 to ||R|| < 1e-10,
+    the mixed path to its tolerance 1e-7, DIIS(6)): the converged correlation energies agree
+    within 1e-8 Eh, the bar on mixed-precision energies (observed about 6e-10)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    out = {}
+    for prec, tol in ((ck.PREC_FP64, 1e-10), (ck.PREC_MIXED, 1e-7)):
+        torch.cuda.empty_cache()
+        with ck.Context([_desc(prec)], device="cuda:0") as c:
+            rc, it, rn = c.iterate(40, tol)
+            out[prec] = (rc, it, rn, c.energy(0))
+        _log(f"{('FP64', 'mixed')[prec]} path: rc={rc} evaluations={it} |R|={rn:.2e} E={out[prec][3]}")
+    torch.cuda.empty_cache()
+    assert out[ck.PREC_FP64][0] == ck.OK and out[ck.PREC_MIXED][0] == ck.OK
+    assert abs(out[ck.PREC_MIXED][3] - out[ck.PREC_FP64][3]) <= 1e-8
