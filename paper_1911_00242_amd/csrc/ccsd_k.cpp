@@ -456,7 +456,9 @@ void build_tables(System &S) {
     put(g5, 5, N * Mph, [&](int64_t x) { int64_t y = x % Mph; return (y / ov) * ov * ov + y % ov; });
     g5.op.G = (int)N; g5.op.M = (int)Mph; g5.op.N = (int)Mph; g5.op.K = (int)Mph;
     g5.op.alpha = 1.0; g5.op.beta = 1.0; g5.stage = ST_RING;
-    if (S.mixed) build_pair_tables(S);
+    // the pair tables serve the packed products of the mixed path and the packed DIIS
+    // history of both paths
+    build_pair_tables(S);
 }
 
 // ---------------------------------------------------------------- workspace plan
@@ -497,8 +499,8 @@ void carve(System &S, Carver &c) {
         c.take(S.Lp, N * PO * PV);
         c.take(S.npart, ck::assemble_pack_blocks(S.d, S.pairs()));
         c.take(S.epart, 2 + 2 * ck::lincomb_pack_blocks(S.d, S.pairs()));
-        c.take(S.dptab, (int64_t)S.ptab.size());
     }
+    c.take(S.dptab, (int64_t)S.ptab.size());
     c.take(S.WT, N3 * cls[0]);
     if (S.rearranged()) {
         c.take(S.t2T, S.n2());
@@ -551,8 +553,9 @@ void carve(System &S, Carver &c) {
         S.derr.assign(S.mixed ? 0 : m, nullptr);
         S.derr32.assign(S.mixed ? m : 0, nullptr);
     }
-    // mixed path: packed history (t1 in full, t2 on the antisymmetry-orbit representatives)
-    const int64_t hl = S.mixed ? ck::packed_len(S.d, S.pairs()) : S.n1() + S.n2();
+    // packed history (t1 in full, t2 on the antisymmetry-orbit representatives); error
+    // vectors in complex64 on the mixed path, complex128 on the FP64 path
+    const int64_t hl = ck::packed_len(S.d, S.pairs());
     for (int i = 0; i < m; ++i) {
         cd *vec = nullptr, *err = nullptr;
         ck::cf *err32 = nullptr;
@@ -1125,11 +1128,9 @@ int impl_bind_workspace(ccsd_k_ctx *ctx, void *device_ptr, uint64_t bytes) {
             CK_CHECK(hipMemsetAsync(S.res, 0, (S.mixed ? S.n1() : S.n1() + S.n2()) * sizeof(cd), ctx->stream));
             if (S.mixed) CK_CHECK(hipMemsetAsync(S.r2c, 0, S.n2() * sizeof(ck::cf), ctx->stream));
             CK_CHECK(hipMemsetAsync(S.zeros, 0, 16 * sizeof(cd), ctx->stream));
-            if (S.mixed) {
-                CK_CHECK(hipMemcpyAsync(S.dptab, S.ptab.data(), S.ptab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                        ctx->stream));
-                clear_packed(S, ctx->stream);
-            }
+            CK_CHECK(hipMemcpyAsync(S.dptab, S.ptab.data(), S.ptab.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    ctx->stream));
+            if (S.mixed) clear_packed(S, ctx->stream);
             bind_ops(S);
             if (S.desc.synthetic) {
                 static const char *cls[6] = {"oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv"};
@@ -1286,8 +1287,9 @@ void enqueue_iteration(ccsd_k_ctx *c, const std::vector<System *> &active, doubl
             ck::launch_lincomb_packed(sd, S.pairs(), src.data(), S.diis(), gate, S.amp, S.sp_t2, S.c64_ring(), S.epart,
                                       st);
         } else {
-            ck::launch_update_diis(sd, S.amp, S.res, S.r2(), S.derr.data(), S.dvec.data(), S.diis(), gate, S.red, st);
-            ck::launch_lincomb(S.n1() + S.n2(), src.data(), S.diis(), gate, S.amp, st);
+            ck::launch_update_diis_pack(sd, S.pairs(), S.amp, S.res, S.r2(), S.derr.data(), S.dvec.data(), S.diis(),
+                                        gate, S.red, st);
+            ck::launch_lincomb_packed(sd, S.pairs(), src.data(), S.diis(), gate, S.amp, nullptr, false, nullptr, st);
         }
     }
     join_lanes(c, ls);

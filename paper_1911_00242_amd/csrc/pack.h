@@ -32,17 +32,21 @@ void launch_oovv_pack(const Dims &d, const int32_t *kc, const PairTabs &pt, cons
 struct LincombArgs {
     const cd *src[16];
 };
-// Packed DIIS history of the mixed path: vectors of packed_len elements, t1 in full then t2
-// on the orbit representatives pt.ablk (whole blocks).  The update writes hist = packed
-// (t + D^-1 R) and err = packed D^-1 R (complex64) and the weighted overlaps out[j] =
-// Re <e, y_j> over the full vector (partials: 16 * 4096 doubles); the extrapolation
-// t = sum_j c[j] src[j] writes t (full), its operand copy sp in the ring family's storage
-// and the energy at the new amplitudes as partial sums (2 + 2 * lincomb_pack_blocks
-// doubles, reduced into out[0..1] by launch_energy_packed).
+// Packed DIIS history (both paths): vectors of packed_len elements, t1 in full then t2 on
+// the orbit representatives pt.ablk (whole blocks).  The update writes hist = packed
+// (t + D^-1 R) and err = packed D^-1 R (complex64 on the mixed path, whose R2 is complex64;
+// complex128 on the FP64 path) and the weighted overlaps out[j] = Re <e, y_j> over the full
+// vector (partials: 16 * 4096 doubles); the extrapolation t = sum_j c[j] src[j] writes t
+// (full) and, on the mixed path (epart non-null), its operand copy sp in the ring family's
+// storage and the energy at the new amplitudes as partial sums (2 + 2 *
+// lincomb_pack_blocks doubles, reduced into out[0..1] by launch_energy_packed).
 int64_t packed_len(const Dims &d, const PairTabs &pt);
 int64_t lincomb_pack_blocks(const Dims &d, const PairTabs &pt);
 void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cf *r2,
                              cf *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
+                             hipStream_t st);
+void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cd *r2,
+                             cd *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
                              hipStream_t st);
 void launch_lincomb_packed(const SysDev &s, const PairTabs &pt, const cd *const *src, const DiisDev &dd, Gate gate,
                            cd *t, uint16_t *sp, bool c64, double *epart, hipStream_t st);

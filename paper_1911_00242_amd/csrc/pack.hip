@@ -559,13 +559,14 @@ __device__ inline void blk_sum2(double &x, double &y, double (*sh)[256]) {
 
 constexpr int LINPACK_VMAX = 48;  // largest n_vir whose v x (v + 1) slab the extrapolation keeps in LDS
 
-struct ErrPackF {
-    cf *p[16];
+template <class ET>
+struct ErrPack {
+    ET *p[16];
 };
 struct HistPackD {
     cd *p[16];
 };
-constexpr int UPD_PACK_BLOCKS = 4096;
+constexpr int UPD_PACK_BLOCKS = UPD_BLOCKS;  // the partials buffer is sized for UPD_BLOCKS
 
 // sixteen running sums over the workgroup (fixed order); valid in v after the call
 __device__ inline void blk_sum16(double (&v)[16], double (*sh)[256]) {
@@ -605,7 +606,7 @@ __global__ __launch_bounds__(256) void k_lincomb_t1(SysDev s, LincombArgs L, Dii
         ei += p.y;
     }
     blk_sum2(er, ei, sh);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && ep1) {
         ep1[0] = er;
         ep1[1] = ei;
     }
@@ -645,8 +646,8 @@ __global__ __launch_bounds__(1024) void k_energy_final(const double *ep1, const 
 }
 
 // ------------------------------------------------------------------ packed DIIS history
-// The DIIS vectors of the mixed path hold t1 in full and t2 only on the representative block
-// of each antisymmetry orbit (pt.ablk: ki <= kj, ka <= kb; the whole o^2 v^2 block):
+// The DIIS vectors hold t1 in full and t2 only on the representative block of each
+// antisymmetry orbit (pt.ablk: ki <= kj, ka <= kb; the whole o^2 v^2 block):
 // packed element (r, x) is t2[ablk[r]][x].  Every orbit member is +- a representative
 // element (t_ij^ab = -t_ji^ab = -t_ij^ba with the momenta), so an overlap over the full
 // vector is the packed overlap with weight w(r) = (ki < kj ? 2 : 1) (ka < kb ? 2 : 1) on
@@ -657,13 +658,15 @@ __device__ inline double pack_weight(int N, int blk, const int32_t *kc) {
     return (ki < kj ? 2.0 : 1.0) * (ka < kb ? 2.0 : 1.0);
 }
 
-template <bool EX>
-__global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt, const cd *t, const cd *r1, const cf *r2,
-                                                          ErrPackF y, HistPackD hp, DiisDev dd, Gate gate,
+// RT: element type of R2 (complex64 on the mixed path), ET: of the stored error vectors
+template <bool EX, class RT, class ET>
+__global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt, const cd *t, const cd *r1, const RT *r2,
+                                                          ErrPack<ET> y, HistPackD hp, DiisDev dd, Gate gate,
                                                           double *partials) {
     if (!gate.open()) return;
+    using EV = decltype(ET{}.x);
     const int self = dd.state[0], m = min(dd.state[1] + 1, dd.m);
-    cf *err = y.p[self];
+    ET *err = y.p[self];
     cd *hist = hp.p[self];
     __shared__ double sh[16][256];
     const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
@@ -682,19 +685,19 @@ __global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt,
         // memory round trip for the element instead of one each: the first eight
         // unconditionally, those beyond the space in use re-reading vector 0 (a cache hit);
         // larger spaces load the rest one by one
-        float bx[16], by[16];
+        EV bx[16], by[16];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const cf b = (j < m ? y.p[j] : y.p[0])[idx];
+            const ET b = (j < m ? y.p[j] : y.p[0])[idx];
             bx[j] = b.x;
             by[j] = b.y;
         }
 #pragma unroll
         for (int j = 8; j < 16; ++j) {
-            bx[j] = 0.f;
-            by[j] = 0.f;
+            bx[j] = EV(0);
+            by[j] = EV(0);
             if (j < m) {
-                const cf b = y.p[j][idx];
+                const ET b = y.p[j][idx];
                 bx[j] = b.x;
                 by[j] = b.y;
             }
@@ -702,7 +705,7 @@ __global__ __launch_bounds__(256) void k_update_diis_pack(SysDev s, PairTabs pt,
         const double iD = 1.0 / D;
         const cd e = make_double2(rv.x * iD, rv.y * iD);
         hist[idx] = cadd(tv, e);
-        cf es;
+        ET es;
         from_cd(e, es);
         const cd ed = to_cd(es);
 #pragma unroll
@@ -808,6 +811,7 @@ __global__ __launch_bounds__(256) void k_lincomb_t2_pack(SysDev s, PairTabs pt, 
         auto put = [&](int k1, int k2, int k3, int x, int y, int a, int b, cd v) {
             const int64_t o = blk3(N, k1, k2, k3) * bs + ((int64_t)x * no + y) * vv + (int64_t)a * nv + b;
             t[n1 + o] = v;
+            if (!ep2) return;  // the FP64 path: no operand copy, the energy by its own pass
             put_elem(sp, o, v, c64);
             cd wv = cscale(v, 0.25);
             if (k3 == k1)
@@ -832,6 +836,7 @@ __global__ __launch_bounds__(256) void k_lincomb_t2_pack(SysDev s, PairTabs pt, 
             }
         }
     }
+    if (!ep2) return;
     blk_sum2(er, ei, sh);
     if (threadIdx.x == 0) {
         ep2[blockIdx.x] = er;
@@ -841,23 +846,34 @@ __global__ __launch_bounds__(256) void k_lincomb_t2_pack(SysDev s, PairTabs pt, 
 
 int64_t packed_len(const Dims &d, const PairTabs &pt) { return d.t1() + (int64_t)pt.nablk * d.t2blk(); }
 
-void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cf *r2,
-                             cf *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
+template <class RT, class ET>
+static void update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const RT *r2,
+                             ET *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
                              hipStream_t st) {
-    ErrPackF pk{};
+    ErrPack<ET> pk{};
     HistPackD hp{};
     for (int j = 0; j < dd.m; ++j) {
         pk.p[j] = err[j];
         hp.p[j] = hist[j];
     }
     if (s.d.no == 8 && s.d.nv == 16)
-        hipLaunchKernelGGL((k_update_diis_pack<true>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1, r2, pk,
-                           hp, dd, gate, partials);
+        hipLaunchKernelGGL((k_update_diis_pack<true, RT, ET>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1,
+                           r2, pk, hp, dd, gate, partials);
     else
-        hipLaunchKernelGGL((k_update_diis_pack<false>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1, r2, pk,
-                           hp, dd, gate, partials);
+        hipLaunchKernelGGL((k_update_diis_pack<false, RT, ET>), dim3(UPD_PACK_BLOCKS), dim3(256), 0, st, s, pt, t, r1,
+                           r2, pk, hp, dd, gate, partials);
     CK_CHECK(hipGetLastError());
     launch_diis_solve(dd, gate, partials, UPD_PACK_BLOCKS, st);
+}
+void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cf *r2,
+                             cf *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
+                             hipStream_t st) {
+    update_diis_pack(s, pt, t, r1, r2, err, hist, dd, gate, partials, st);
+}
+void launch_update_diis_pack(const SysDev &s, const PairTabs &pt, const cd *t, const cd *r1, const cd *r2,
+                             cd *const *err, cd *const *hist, const DiisDev &dd, Gate gate, double *partials,
+                             hipStream_t st) {
+    update_diis_pack(s, pt, t, r1, r2, err, hist, dd, gate, partials, st);
 }
 
 int64_t lincomb_pack_blocks(const Dims &d, const PairTabs &pt) { return std::max<int64_t>(1, (int64_t)pt.nablk * d.no * d.no); }
@@ -871,7 +887,7 @@ void launch_lincomb_packed(const SysDev &s, const PairTabs &pt, const cd *const 
     const int64_t nb = lincomb_pack_blocks(s.d, pt);
     const size_t lds = s.d.nv <= LINPACK_VMAX ? (size_t)s.d.nv * (s.d.nv + 1) * sizeof(cd) : 0;
     hipLaunchKernelGGL(k_lincomb_t2_pack, dim3((unsigned)nb), dim3(256), lds, st, s, pt, L, dd, gate, t, sp, c64,
-                       epart + 2);
+                       epart ? epart + 2 : nullptr);
     CK_CHECK(hipGetLastError());
 }
 

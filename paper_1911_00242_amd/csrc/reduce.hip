@@ -1,5 +1,5 @@
-// FP64 reductions, amplitude update and DIIS vector kernels, plus the device twin of the
-// synthetic input recipe.
+// FP64 reductions, the plain amplitude update and the DIIS step on the device, plus the
+// device twin of the synthetic input recipe.
 //
 // Reductions are deterministic: a fixed grid of RED_BLOCKS workgroups, each summing a fixed
 // strided subset in a fixed order, a fixed LDS tree, and a single-block final pass.
@@ -157,104 +157,6 @@ void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, 
     CK_CHECK(hipGetLastError());
 }
 
-// The DIIS step of one iteration in one pass: e = D^-1 R, hist = t + e (the new amplitudes,
-// written only to their history slot: the extrapolation, or a copy when there is none,
-// writes t afterwards), err = e stored as E (complex128, or complex64 on the mixed path,
-// whose residual is itself accurate to about 1e-7 relative and is stored as E too), and the
-// partial sums of
-// Re <e, y_j> for the m held error vectors, all taken from the stored values (y[self] is
-// err itself, whose product is taken from e, rounded to E, before it is stored).
-// A fixed grid of UPD_BLOCKS workgroups and a fixed summation order, so the dots are
-// deterministic.  The grid is larger than RED_BLOCKS because this pass streams 3 + m
-// vectors and needs the memory parallelism; the t2 index is split once per element into a
-// momentum block and a 32-bit offset inside it.
-template <class E>
-struct ErrPack {
-    E *p[16];
-};
-struct HistPack {
-    cd *p[16];
-};
-
-// EX: n_occ = 8, n_vir = 16 as constants (the index decode becomes shifts).  The slot and
-// the number of held vectors come from the device DIIS state; nothing happens when the
-// gate is closed (the system converged at this residual).
-template <class E, bool EX>
-__global__ __launch_bounds__(256) void k_update_diis(SysDev s, const cd *t, const cd *r1, const E *r2, ErrPack<E> y,
-                                                     HistPack hp, DiisDev dd, Gate gate, double *partials) {
-    if (!gate.open()) return;
-    const int self = dd.state[0], m = min(dd.state[1] + 1, dd.m);
-    E *err = y.p[self];
-    cd *hist = hp.p[self];
-    __shared__ double sh[16][256];
-    const int N = s.d.N, no = EX ? 8 : s.d.no, nv = EX ? 16 : s.d.nv;
-    const int64_t n1 = (int64_t)N * no * nv, bs = (int64_t)no * no * nv * nv, n2 = (int64_t)N * N * N * bs;
-    double v[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = 0.0;
-    GRID_STRIDE(idx, n1 + n2) {
-        double D;
-        if (idx < n1) {
-            const int x = (int)idx;
-            const int a = x % nv, i = (x / nv) % no, k = x / (no * nv);
-            D = s.eo[k * no + i] - s.ev[k * nv + a];
-        } else {
-            const int64_t blk = (idx - n1) / bs;
-            const int x = (int)(idx - n1 - blk * bs);
-            const int b = x % nv, a = (x / nv) % nv, j = (x / (nv * nv)) % no, i = x / (nv * nv * no);
-            const int kb3 = (int)blk;
-            const int ka = kb3 % N, kj = (kb3 / N) % N, ki = kb3 / (N * N);
-            const int kb = s.kc[kb3];  // kc is indexed by the block triple (ki, kj, ka)
-            D = s.eo[ki * no + i] + s.eo[kj * no + j] - s.ev[ka * nv + a] - s.ev[kb * nv + b];
-        }
-        const cd rv = idx < n1 ? r1[idx] : to_cd(r2[idx - n1]);
-        const double iD = 1.0 / D;
-        const cd e = make_double2(rv.x * iD, rv.y * iD);
-        hist[idx] = cadd(t[idx], e);
-        E es;
-        from_cd(e, es);
-        const cd ed = to_cd(es);
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (j < m) {
-                const cd b = j == self ? ed : to_cd(y.p[j][idx]);
-                v[j] = fma(ed.x, b.x, fma(ed.y, b.y, v[j]));
-            }
-        err[idx] = es;
-    }
-    block_sum<16>(v, sh);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < m; ++j) partials[(int64_t)j * UPD_BLOCKS + blockIdx.x] = v[j];
-}
-
-template <class E>
-void launch_update_diis_t(const SysDev &s, const cd *t, const cd *r1, const E *r2, E *const *err, cd *const *hist,
-                          const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
-    ErrPack<E> pk{};
-    HistPack hp{};
-    for (int j = 0; j < dd.m; ++j) {
-        pk.p[j] = err[j];
-        hp.p[j] = hist[j];
-    }
-    if (s.d.no == 8 && s.d.nv == 16)
-        hipLaunchKernelGGL((k_update_diis<E, true>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, pk, hp, dd, gate,
-                           partials);
-    else
-        hipLaunchKernelGGL((k_update_diis<E, false>), dim3(UPD_BLOCKS), dim3(256), 0, st, s, t, r1, r2, pk, hp, dd,
-                           gate, partials);
-    CK_CHECK(hipGetLastError());
-    launch_diis_solve(dd, gate, partials, UPD_BLOCKS, st);
-}
-
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *const *err, cd *const *hist,
-                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
-    launch_update_diis_t<cd>(s, t, r1, r2, err, hist, dd, gate, partials, st);
-}
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *const *err, cd *const *hist,
-                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st) {
-    launch_update_diis_t<cf>(s, t, r1, r2, err, hist, dd, gate, partials, st);
-}
-
 // The DIIS step on the device, one workgroup: the overlaps of the new error vector with the
 // held ones (sums of the update pass's partials, fixed order) become row and column `slot`
 // of B; with two or more vectors held the bordered system
@@ -335,34 +237,6 @@ void launch_diis_solve(const DiisDev &dd, Gate gate, const double *partials, int
     hipLaunchKernelGGL(k_diis_solve, dim3(1), dim3(256), 0, st, dd, gate, partials, nparts);
     CK_CHECK(hipGetLastError());
 }
-
-struct PtrPack {
-    const cd *p[16];
-};
-
-// dst = sum_j coef[j] src_j over the vectors held (device state, after the DIIS step)
-__global__ void k_lincomb(int64_t n, PtrPack src, DiisDev dd, Gate gate, cd *dst) {
-    if (!gate.open()) return;
-    const int m = dd.state[1];
-    GRID_STRIDE(i, n) {
-        cd acc = make_double2(0.0, 0.0);
-        for (int j = 0; j < m; ++j) {
-            const cd s = src.p[j][i];
-            const double c = dd.coef[j];
-            acc.x = fma(c, s.x, acc.x);
-            acc.y = fma(c, s.y, acc.y);
-        }
-        dst[i] = acc;
-    }
-}
-
-void launch_lincomb(int64_t n, const cd *const *src, const DiisDev &dd, Gate gate, cd *dst, hipStream_t st) {
-    PtrPack pk{};
-    for (int j = 0; j < dd.m; ++j) pk.p[j] = src[j];
-    hipLaunchKernelGGL(k_lincomb, grid_for(n), dim3(256), 0, st, n, pk, dd, gate, dst);
-    CK_CHECK(hipGetLastError());
-}
-
 
 __global__ void k_diag(Dims d, const cd *fock, double *eo, double *ev) {
     const int n = d.no + d.nv;

@@ -99,19 +99,10 @@ void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cd *r2, 
                    hipStream_t st);
 void launch_update(const SysDev &s, cd *t1, cd *t2, const cd *r1, const cf *r2, cd *err1, cd *err2, Gate gate,
                    hipStream_t st);
-// DIIS form of the update over the contiguous (t1, t2) vector (FP64 path): e = r / D
-// (r = r1 | r2), hist[slot] = t + e (t itself is not written), err[slot] = e, the overlaps
-// Re <e, err_j> of the held vectors over the stored values, then the DIIS step on the
-// device (launch_diis_solve); partials: 16 * UPD_BLOCKS
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cd *r2, cd *const *err, cd *const *hist,
-                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st);
-void launch_update_diis(const SysDev &s, const cd *t, const cd *r1, const cf *r2, cf *const *err, cd *const *hist,
-                        const DiisDev &dd, Gate gate, double *partials, hipStream_t st);
 // the DIIS step: overlaps from nparts partial sums per held vector, B, the bordered solve,
-// the coefficients and the FIFO advance (one workgroup)
+// the coefficients and the FIFO advance (one workgroup); the update pass and the
+// extrapolation on the packed history are in pack.h
 void launch_diis_solve(const DiisDev &dd, Gate gate, const double *partials, int nparts, hipStream_t st);
-// dst = sum_j coef[j] * src_j over n complex elements, the held vectors of dd
-void launch_lincomb(int64_t n, const cd *const *src, const DiisDev &dd, Gate gate, cd *dst, hipStream_t st);
 
 // device synthetic inputs (same recipe as the host generator) ------------------------
 void launch_synth_fock(const Mesh &m, int no, int nv, uint64_t seed, cd *fock, hipStream_t st);
