@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Write ``cfg1_converged.json``: the oracle's converged CCSD solution of the 2x2x2-mesh
+"""Write ``converged_nk8_o8_v24.json``: the oracle's converged CCSD solution of the 2x2x2-mesh
 (N_k = 8) system with n_occ = 8, n_vir = 24 spin orbitals per k.
 
 Inputs: the seeded synthetic recipe (seed 202, complex Gaussians x 0.05/N_k, antisymmetrized
@@ -43,7 +43,7 @@ def sample_positions(kc):
 
 
 def main():
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg1_converged.json")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "converged_nk8_o8_v24.json")
     f, eris = synth.system(SEED, GRID, NO, NV, scale=SCALE)
     t0 = time.time()
 

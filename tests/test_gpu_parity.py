@@ -118,7 +118,7 @@ def test_device_synthetic_inputs_match_host_generator():
     assert N == 3
 
 
-def test_jacobi_converged_energy_cfg0():
+def test_jacobi_converged_energy_nk2_o4_v8():
     """N_k=2 (1-D), n_occ=4, n_vir=8, plain successive substitution to ||R|| < 1e-10."""
     grid, no, nv = (2, 1, 1), 4, 8
     f, eris = synth.system(101, grid, no, nv)
@@ -228,10 +228,10 @@ def test_error_paths():
 
 
 @pytest.mark.timeout(900)
-def test_residual_matches_oracle_cfg1_size():
+def test_residual_matches_oracle_nk8_o8_v24():
     """3-D 2x2x2 mesh (N_k=8), n_occ=8, n_vir=24: one residual at random amplitudes."""
     grid, no, nv = (2, 2, 2), 8, 24
-    print("cfg1-size residual: generating inputs", flush=True)
+    print("N_k=8 8x24 residual: generating inputs", flush=True)
     f, eris = synth.system(202, grid, no, nv)
     t1, t2 = synth.test_amplitudes(21, grid, no, nv, scale=0.02)
     print("oracle residual", flush=True)
@@ -269,21 +269,21 @@ def test_general_inputs_rotated_orbitals():
 
 
 @pytest.mark.timeout(600)
-def test_cfg1_converged_matches_oracle_golden():
+def test_converged_nk8_o8_v24_matches_oracle_golden():
     """2x2x2 mesh (N_k=8), n_occ=8, n_vir=24, integrals x 0.05/N_k, DIIS(6) to ||R|| < 1e-12
     on the FP64 path against the oracle's converged solution of the same system, stored by
-    tests/golden/make_cfg1_converged.py: energy within 1e-11 Eh, t1 and the sampled t2
+    tests/golden/make_converged_nk8_o8_v24.py: energy within 1e-11 Eh, t1 and the sampled t2
     elements within 1e-10.  Inputs are generated on the device by the same seeded recipe
     (equal to the host generator up to the last bits of its transcendental functions)."""
     import json
     import os
 
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg1_converged.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "converged_nk8_o8_v24.json")
     g = json.load(open(path))
     grid, no, nv = tuple(g["grid"]), g["n_occ"], g["n_vir"]
     desc = dict(grid=grid, no=no, nv=nv, diis_space=g["diis_space"], synthetic=1, seed=g["seed"],
                 eri_scale=g["eri_scale"])
-    print("cfg1 converged: iterating on the GPU", flush=True)
+    print("N_k=8 8x24 converged: iterating on the GPU", flush=True)
     with _ctx([desc]) as c:
         rc, iters, rn = c.iterate(60, g["tol"])
         e = c.energy(0)

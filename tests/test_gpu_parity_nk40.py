@@ -1,5 +1,5 @@
 """The largest mesh one GPU holds, N_k=40 (5x4x2), n_occ=8, n_vir=16 per k, on the mixed
-path (238 GB of workspace; the FP64 path would need about 600 GB), in its launch
+path (238 GB of workspace; the FP64 path would need about 450 GB), in its launch
 configuration (inputs generated on the device, DIIS(6), the constant-shape kernels).  The
 oracle cannot evaluate whole residuals at this size; it checks, block by block:
 
