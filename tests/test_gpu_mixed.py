@@ -82,6 +82,33 @@ def test_mixed_converged_energy_matches_fp64(grid, no, nv):
     assert dt2 <= 1e-6
 
 
+def test_mixed_energy_error_split_into_storage_and_arithmetic():
+    """The mixed path keeps its integral classes in complex64.  Its converged energy is
+    compared twice with the FP64 path: on the original integrals (the whole error) and on
+    the same integrals rounded to complex64 (the error of the split products alone); the
+    difference of the two FP64 energies is the part the complex64 storage contributes."""
+    grid, no, nv = (2, 1, 1), 8, 16
+    N = 2
+    f, eris = synth.system(515, grid, no, nv, scale=0.05 / N)
+    rounded = {k: v.astype(np.complex64).astype(np.complex128) for k, v in eris.items()}
+    e = {}
+    for name, prec, ints, tol in (("fp64", ck.PREC_FP64, eris, 1e-11), ("fp64_c64ints", ck.PREC_FP64, rounded, 1e-11),
+                                  ("mixed", ck.PREC_MIXED, eris, 1e-9)):
+        with ck.Context([dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=6)]) as c:
+            c.set_inputs(0, f, ints)
+            rc, it, rn = c.iterate(60, tol)
+            assert rc == ck.OK, name
+            e[name] = c.energy(0)
+    whole = abs(e["mixed"] - e["fp64"])
+    arith = abs(e["mixed"] - e["fp64_c64ints"])
+    storage = abs(e["fp64_c64ints"] - e["fp64"])
+    print(f"mixed vs FP64: {whole:.2e} Eh; vs FP64 on complex64 integrals: {arith:.2e} Eh; "
+          f"storage part: {storage:.2e} Eh", flush=True)
+    assert whole <= 1e-8 and arith <= 1e-8
+    # rounding the integrals moves the FP64 energy by about 2^-24 of the correlation energy
+    assert storage <= 1e-7 * abs(e["fp64"])
+
+
 @pytest.mark.parametrize("grid,no,nv", [((2, 2, 1), 3, 5), ((2, 1, 1), 8, 16)])
 def test_mixed_extrapolation_caches_match_fresh_passes(grid, no, nv):
     """The mixed DIIS extrapolation also writes the split copy of t2 and the energy partial
