@@ -93,7 +93,7 @@ def test_mixed_energy_error_split_into_storage_and_arithmetic():
     rounded = {k: v.astype(np.complex64).astype(np.complex128) for k, v in eris.items()}
     e = {}
     for name, prec, ints, tol in (("fp64", ck.PREC_FP64, eris, 1e-11), ("fp64_c64ints", ck.PREC_FP64, rounded, 1e-11),
-                                  ("mixed", ck.PREC_MIXED, eris, 1e-9)):
+                                  ("mixed", ck.PREC_MIXED, eris, 1e-7)):
         with ck.Context([dict(grid=grid, no=no, nv=nv, precision=prec, diis_space=6)]) as c:
             c.set_inputs(0, f, ints)
             rc, it, rn = c.iterate(60, tol)
