@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libccsdk.so")
 
-SOURCES = ["gemm_f64.hip", "gemm_mixed.hip", "gemm_c64.hip", "pack.hip", "terms.hip", "reduce.hip", "noalloc.hip", "tune.cpp", "ccsd_k.cpp"]
+SOURCES = ["gemm_f64.hip", "gemm_mixed.hip", "gemm_c64.hip", "pack.hip", "terms.hip", "blocksum.hip", "reduce.hip", "noalloc.hip", "tune.cpp", "ccsd_k.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

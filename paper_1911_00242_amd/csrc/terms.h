@@ -22,6 +22,12 @@ struct FWork {
     cd *Poo, *Pvv;        // [splits][N][N][N][o][o], [splits][N][N][N][v][v] partial sums
 };
 
+// Register-tiled F and R1 block sums (blocksum.hip) for n_occ <= 16, n_vir <= 32 outside
+// the 8 x 16 tile: the same partial arrays (fr_splits slices each) as the other forms.
+bool bsum_rb_fits(const Dims &d);
+void launch_f_blocks_rb(const SysDev &s, const cd *t1, const cd *t2, cd *Poo, cd *Pvv, hipStream_t st);
+void launch_r1_blocks_rb(const SysDev &s, const cd *t2, cd *P1a, cd *P1b, hipStream_t st);
+
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st);
 // canon: only the blocks with canonical rows and columns (ki <= kj, km <= kn) are written

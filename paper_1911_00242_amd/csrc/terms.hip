@@ -1647,6 +1647,8 @@ void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t 
     CK_CHECK(hipGetLastError());
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_f_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t1, t2, w.Poo, w.Pvv);
+    } else if (bsum_rb_fits(s.d)) {
+        launch_f_blocks_rb(s, t1, t2, w.Poo, w.Pvv, st);
     } else if (f_blocks_fit(s.d)) {
         const dim3 grid((unsigned)(N * N * N * fr_splits(s.d)));
         if (s.oovv_c)
@@ -1973,6 +1975,8 @@ void launch_r1_partials(const SysDev &s, const cd *t2, cd *P1, hipStream_t st) {
     const int64_t np = N * N * N * no * nv;  // P1 holds r1_parts partial arrays of np elements
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_r1_blocks_t, dim3((unsigned)(N * N * N)), dim3(256), s, t2, P1, P1 + np);
+    } else if (bsum_rb_fits(s.d)) {
+        launch_r1_blocks_rb(s, t2, P1, P1 + fr_splits(s.d) * np, st);
     } else if (r1_blocks_fit(s.d)) {
         const int ns = fr_splits(s.d);
         const dim3 grid((unsigned)(N * N * N * ns));

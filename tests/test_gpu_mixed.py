@@ -37,7 +37,7 @@ def test_split_zgemm_error_bound(G, M, N, K):
 @pytest.mark.parametrize("grid,no,nv", [((2, 1, 1), 4, 8), ((3, 1, 1), 2, 3), ((2, 2, 1), 3, 5),
                                         ((2, 2, 2), 8, 16), ((2, 1, 1), 10, 3), ((1, 1, 1), 2, 34),
                                         ((2, 1, 1), 5, 23), ((1, 1, 1), 12, 20), ((3, 1, 1), 1, 1),
-                                        ((1, 1, 1), 17, 2)])
+                                        ((1, 1, 1), 17, 2), ((2, 1, 1), 12, 32), ((3, 1, 1), 9, 17)])
 def test_mixed_residual_close_to_oracle(grid, no, nv):
     print(f"mixed residual grid={grid} no={no} nv={nv}", flush=True)
     N = int(np.prod(grid))

@@ -67,6 +67,12 @@ RES_CASES = [
     ((2, 1, 1), 5, 23, True),
     # n_occ between 8 and 16 with n_vir between 16 and 32: 16-row ring and X seed tiles
     ((1, 1, 1), 12, 20, False),
+    # register-tiled F and R1 block sums (n_occ <= 16, n_vir <= 32): the largest batched
+    # shape, a full 16 x 24 tile with a general Fock matrix, and a mesh whose sums are split
+    # over several workgroups per block with ragged tiles
+    ((2, 1, 1), 12, 32, False),
+    ((2, 1, 1), 16, 24, True),
+    ((3, 1, 1), 9, 17, False),
 ]
 
 
