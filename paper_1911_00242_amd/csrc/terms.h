@@ -31,7 +31,7 @@ void launch_r1_blocks_rb(const SysDev &s, const cd *t2, cd *P1a, cd *P1b, hipStr
 void launch_tau(const SysDev &s, const cd *t1, const cd *t2, cd *tau, cd *tauT, hipStream_t st);
 void launch_f(const SysDev &s, const cd *t1, const cd *t2, FWork w, hipStream_t st);
 // canon: only the blocks with canonical rows and columns (ki <= kj, km <= kn) are written
-// (all that the packed W_mnij product reads); the plain fallback ignores it
+// (all that the packed W_mnij product reads)
 void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStream_t st);
 void launch_vvvv_dress(const SysDev &s, const cd *t1, cd *Vt, hipStream_t st);
 // per momentum block (o^2 x v^2) -> (v^2 x o^2)

@@ -726,8 +726,9 @@ __global__ void k_ftilde(Dims d, const cd *t1, const cd *Foo, const cd *Fvv, con
 
 // ------------------------------------------------------------------ hole-hole intermediate
 // WT[ki][kj][km](i,j,m,n) = <mn||ij> + t_j^e <mn||ie> - t_i^e <mn||je>   (tau part by GEMM)
+// canon: only the blocks with ki <= kj and km <= kn (the packed product reads no other)
 template <class IT>
-__global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
+__global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT, bool canon) {
     const int N = s.d.N, no = s.d.no, nv = s.d.nv;
     const int64_t o4 = (int64_t)no * no * no * no, o3v = (int64_t)no * no * no * nv;
     GRID_STRIDE(idx, (int64_t)N * N * N * o4) {
@@ -736,6 +737,7 @@ __global__ void k_wmnij_init(SysDev s, const cd *t1, cd *WT) {
         int64_t blk = idx / o4;
         int km = (int)(blk % N), kj = (int)((blk / N) % N), ki = (int)(blk / ((int64_t)N * N));
         int kn = kcv(s.kc, N, ki, kj, km);
+        if (canon && (ki > kj || km > kn)) continue;
         cd acc = to_cd(oooo_of<IT>(s)[blk3(N, km, kn, ki) * o4 + (((int64_t)m * no + nn) * no + i) * no + j]);
         const IT *g1 = ooov_of<IT>(s) + blk3(N, km, kn, ki) * o3v + (((int64_t)m * no + nn) * no + i) * nv;
         const IT *g2 = ooov_of<IT>(s) + blk3(N, km, kn, kj) * o3v + (((int64_t)m * no + nn) * no + j) * nv;
@@ -1181,21 +1183,27 @@ __global__ __launch_bounds__(VM * VM) void k_ring_w0_t(SysDev s, const cd *__res
         if (j < no) wr[(int64_t)j * nv * ov] = acc[j];
 }
 
-template <int OM, int VM, bool EX = false, class IT = cd>
+template <int OM, int VM, bool EX = false, class IT = cd, int IC = OM>
 __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd *Q) {
     // The <m b||e j> slab of this m goes through LDS EP values of e at a time (so that
     // many workgroups fit on a CU), at e * (no * nv + 1) + j * nv + b: a lane (j, b) reads
     // consecutive words, and the staging writes (consecutive e) are one padded row apart.
-    // The next phase's slab is loaded into registers while the current one is used.
+    // The next phase's slab is loaded into registers while the current one is used.  A
+    // workgroup forms the outputs of IC values of i (i0 .. i0 + IC - 1): with IC < OM the
+    // i range is shared by several workgroups, each reading the slab, so that a thread
+    // keeps IC accumulators in registers.
     constexpr int EP = 4;
     constexpr int NT = OM * VM;
     __shared__ cd GS[EP * (OM * VM + 1)];
     __shared__ cd T1I[OM * VM];  // t1[ki](i, e)
     const int N = s.d.N, no = EX ? OM : s.d.no, nv = EX ? VM : s.d.nv, rp = no * nv + 1;
     const int64_t o3v = (int64_t)no * no * no * nv;
-    const int64_t nblk = (int64_t)N * N * N * no;
-    const int64_t L = xcd_block(nblk);
-    if (L >= nblk) return;
+    const int nh = (no + IC - 1) / IC;
+    const int64_t nblk = (int64_t)N * N * N * no * nh;
+    const int64_t L0 = xcd_block(nblk);
+    if (L0 >= nblk) return;
+    const int i0 = (int)(L0 % nh) * IC;
+    const int64_t L = L0 / nh;
     const int m = (int)(L % no);
     const int64_t blk = L / no;
     const int ki = (int)(blk % N), kb = (int)((blk / N) % N), ka = (int)(blk / ((int64_t)N * N));
@@ -1222,9 +1230,9 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     for (int x = threadIdx.x; x < no * nv; x += blockDim.x) T1I[x] = t1[(int64_t)ki * no * nv + x];
     const int jb = threadIdx.x;
     const bool act = jb < no * nv;
-    cd acc[OM];
+    cd acc[IC];
 #pragma unroll
-    for (int i = 0; i < OM; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int i = 0; i < IC; ++i) acc[i] = make_double2(0.0, 0.0);
     for (int e0 = 0; e0 < nv; e0 += EP) {
         if (e0 > 0) __syncthreads();  // every read of the previous phase is done
         store_phase();
@@ -1236,8 +1244,8 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
                 if (e0 + el >= nv) break;
                 const cd g = GS[el * rp + jb];
 #pragma unroll
-                for (int i = 0; i < OM; ++i)
-                    if (i < no) cfma(acc[i], T1I[i * nv + e0 + el], g);
+                for (int i = 0; i < IC; ++i)
+                    if (i0 + i < no) cfma(acc[i], T1I[(i0 + i) * nv + e0 + el], g);
             }
         }
     }
@@ -1246,10 +1254,11 @@ __global__ __launch_bounds__(OM * VM) void k_ring_q_t(SysDev s, const cd *t1, cd
     const IT *h = ooov_of<IT>(s) + blk3(N, ki, kj, ka) * o3v + ((int64_t)j * no + m) * nv + b;
     cd *qo = Q + blk * o3v + (int64_t)m * no * no * nv + jb;
 #pragma unroll
-    for (int i = 0; i < OM; ++i) {
+    for (int ic = 0; ic < IC; ++ic) {
+        const int i = i0 + ic;
         if (i >= no) break;
         const cd x = to_cd(h[(int64_t)i * no * no * nv]);
-        cd v = acc[i];
+        cd v = acc[ic];
         v.x += 0.5 * x.x;
         v.y -= 0.5 * x.y;
         qo[(int64_t)i * no * nv] = v;
@@ -1733,9 +1742,9 @@ void launch_wmnij_init(const SysDev &s, const cd *t1, cd *WT, bool canon, hipStr
     if (no <= 8 && nv <= 16) {
         LAUNCH_TI(k_wmnij_init_t, xcd_grid(N * N * N * no), dim3(256), s, t1, WT, canon);
     } else if (s.ovvv_c) {
-        LAUNCH(k_wmnij_init<cf>, N * N * N * no * no * no * no, s, t1, WT);
+        LAUNCH(k_wmnij_init<cf>, N * N * N * no * no * no * no, s, t1, WT, canon);
     } else {
-        LAUNCH(k_wmnij_init<cd>, N * N * N * no * no * no * no, s, t1, WT);
+        LAUNCH(k_wmnij_init<cd>, N * N * N * no * no * no * no, s, t1, WT, canon);
     }
 }
 
@@ -1928,7 +1937,16 @@ void launch_ring_x(const SysDev &s, const cd *t1, const cd *t2, const FWork &w, 
         LAUNCH_TI(k_ring_q_t, xcd_grid(n3 * no), dim3(8 * 16), s, t1, scratch);
     } else if (no <= 8 && nv <= 32) {
         LAUNCH_32I(k_ring_q_t, xcd_grid(n3 * no), dim3(8 * 32), s, t1, scratch);
-    } else if (s.ovvv_c) {  // (the 16-row Q seed would keep its accumulators in scratch memory)
+    } else if (no <= 16 && nv <= 32) {
+        // 16-row tiles, each workgroup taking half of the i range (eight accumulators per
+        // thread; sixteen would spill)
+        const dim3 g = xcd_grid(n3 * no * ((no + 7) / 8));
+        if (s.ovvv_c)
+            hipLaunchKernelGGL((k_ring_q_t<16, 32, false, cf, 8>), g, dim3(16 * 32), 0, st, s, t1, scratch);
+        else
+            hipLaunchKernelGGL((k_ring_q_t<16, 32, false, cd, 8>), g, dim3(16 * 32), 0, st, s, t1, scratch);
+        CK_CHECK(hipGetLastError());
+    } else if (s.ovvv_c) {
         LAUNCH(k_ring_q<cf>, n3 * no * no * no * nv, s, t1, scratch);
     } else {
         LAUNCH(k_ring_q<cd>, n3 * no * no * no * nv, s, t1, scratch);
