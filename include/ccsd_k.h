@@ -182,17 +182,37 @@ int ccsd_k_product_shape(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, in
 int ccsd_k_set_product_form(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t form);
 int ccsd_k_get_product_form(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *form);
 
-/* Autotuner: choose the form of every product of mixed-precision system sys.  For each
+/* Tile shapes of the FP64 products (complex outputs per 256-thread workgroup, rows x
+ * columns).  Every shape takes the same k stages and the same order of MFMA operations
+ * along k for each output element, so all of them give bitwise the same result; they trade
+ * data reuse per workgroup against the number of workgroups. */
+#define CCSD_K_TILE_32X32 0 /* the initial shape of a product with few 64 x 64 tiles */
+#define CCSD_K_TILE_64X64 1 /* the initial shape otherwise */
+#define CCSD_K_TILE_128X64 2
+#define CCSD_K_TILE_64X128 3
+
+/* Set / read the tile shape of product (0..4, numbering of ccsd_k_timing_get) of FP64
+ * system sys.  EINVAL for a mixed-precision system (its products have one tile shape) or an
+ * unknown tile.  A product starts in 32 x 32 tiles while 64 x 64 ones would give fewer than
+ * 4096 workgroups, in 64 x 64 tiles otherwise.  The products of the rearranged hole-hole
+ * grouping other than these five run in 64 x 64 tiles. */
+int ccsd_k_set_product_tile(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t tile);
+int ccsd_k_get_product_tile(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *tile);
+
+/* Autotuner.  Mixed-precision system: choose the form of every product.  For each
  * product it measures every form's average launch time on the system's own operands and
  * tables (the workspace must be bound; the overwritten intermediates are recomputed by the
  * next residual) and every form's error, max|C_form - C_fp64| / max|C_fp64| on seeded
  * operands of the product's K (and up to 256 rows and columns) against the FP64 MFMA kernel.
  * Per family it keeps the faster of the two storages whose products all stay within budget
  * (each product of a complex64 family taking its fastest admissible form); if none does,
- * the most accurate forms.  cache_path (NULL: none): a text file of measurements keyed by
- * device and product shape, read before measuring and appended to after.  forms[5]
- * (optional) receives the chosen form per product (-1 for product 1); report (optional,
- * 5 x 4 x 2 doubles) the measured (ms, error) per product and form. */
+ * the most accurate forms.  FP64 system: choose the tile shape of every product, the one
+ * with the shortest measured launch time (all shapes give the same result, so budget, which
+ * must still be positive, plays no part).  cache_path (NULL: none): a text file of
+ * measurements keyed by device and product shape, read before measuring and appended to
+ * after.  forms[5] (optional) receives the chosen form per product (-1 for product 1), or
+ * the chosen tile shape per product on an FP64 system; report (optional, 5 x 4 x 2 doubles)
+ * the measured (ms, error) per product and form, or (ms, 0) per product and tile shape. */
 int ccsd_k_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache_path, int32_t *forms,
                     double *report);
 
@@ -236,8 +256,9 @@ int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t 
 /* Diagnostic: dense grouped complex product C[g] = A[g] . B[g]^T on the device with the
  * tiled FP64 MFMA kernel (reference = 0), the one-thread-per-element FP64 kernel
  * (reference = 1), the split-BF16 MFMA kernel of the mixed path on pre-split operands
- * (reference = 2), or the complex64-operand kernel in one of its arithmetic forms:
- * two-term split-BF16 (3), three-term split-BF16 (4) or FP32 MFMA (5).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
+ * (reference = 2), the complex64-operand kernel in one of its arithmetic forms:
+ * two-term split-BF16 (3), three-term split-BF16 (4) or FP32 MFMA (5), or the tiled FP64
+ * kernel in tile shape t (reference = 10 + t, t one of CCSD_K_TILE_*).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
  * Allocates and frees its own device buffers; synchronizes the default stream. */
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
                        double *C, int32_t reference);

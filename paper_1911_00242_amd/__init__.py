@@ -33,6 +33,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, 1, -1, -2, -3,
 PREC_FP64, PREC_MIXED = 0, 1
 GROUPING_STANDARD, GROUPING_REARRANGED = 0, 1
 FORM_SPLIT2_PRESPLIT, FORM_SPLIT2, FORM_SPLIT3, FORM_FP32 = 0, 1, 2, 3
+TILE_32X32, TILE_64X64, TILE_128X64, TILE_64X128 = 0, 1, 2, 3
 FORMS = ("split2_presplit", "split2", "split3", "fp32")
 CLASSES = ("oooo", "ooov", "oovv", "ovvo", "ovvv", "vvvv")
 STAGES = ("pp_ladder", "hh_ladder", "w_mnij", "w_mbej", "ring", "residual")
@@ -71,6 +72,8 @@ _lib_flops = _sig("ccsd_k_flops", ctypes.c_int, [_p, _i32, _dp, _dp])
 _lib_shape = _sig("ccsd_k_product_shape", ctypes.c_int, [_p, _i32, _i32] + [ctypes.POINTER(_i64)] * 4)
 _lib_set_form = _sig("ccsd_k_set_product_form", ctypes.c_int, [_p, _i32, _i32, _i32])
 _lib_get_form = _sig("ccsd_k_get_product_form", ctypes.c_int, [_p, _i32, _i32, ctypes.POINTER(_i32)])
+_lib_set_tile = _sig("ccsd_k_set_product_tile", ctypes.c_int, [_p, _i32, _i32, _i32])
+_lib_get_tile = _sig("ccsd_k_get_product_tile", ctypes.c_int, [_p, _i32, _i32, ctypes.POINTER(_i32)])
 _lib_autotune = _sig("ccsd_k_autotune", ctypes.c_int, [_p, _i32, _f64, ctypes.c_char_p, ctypes.POINTER(_i32), _dp])
 _lib_escalation = _sig("ccsd_k_set_escalation", ctypes.c_int, [_p, _i32])
 _lib_graphs = _sig("ccsd_k_set_graphs", ctypes.c_int, [_p, _i32])
@@ -85,7 +88,8 @@ _lib_err = _sig("ccsd_k_last_error", ctypes.c_char_p, [_p])
 SYMBOLS = ("ccsd_k_init", "ccsd_k_workspace_bytes", "ccsd_k_bind_workspace", "ccsd_k_set_inputs",
            "ccsd_k_residual", "ccsd_k_iterate", "ccsd_k_residual_norm", "ccsd_k_energy",
            "ccsd_k_get_amplitudes", "ccsd_k_set_amplitudes", "ccsd_k_flops", "ccsd_k_product_shape",
-           "ccsd_k_set_product_form", "ccsd_k_get_product_form", "ccsd_k_autotune", "ccsd_k_set_escalation", "ccsd_k_set_graphs", "ccsd_k_set_overlap",
+           "ccsd_k_set_product_form", "ccsd_k_get_product_form", "ccsd_k_set_product_tile",
+           "ccsd_k_get_product_tile", "ccsd_k_autotune", "ccsd_k_set_escalation", "ccsd_k_set_graphs", "ccsd_k_set_overlap",
            "ccsd_k_timing",
            "ccsd_k_timing_get", "ccsd_k_debug_zgemm", "ccsd_k_zgemm_noalloc", "ccsd_k_free", "ccsd_k_last_error")
 
@@ -202,6 +206,16 @@ def ccsd_k_get_product_form(ctx, sys, product) -> int:
     return int(f.value)
 
 
+def ccsd_k_set_product_tile(ctx, sys, product, tile):
+    return _check(_lib_set_tile(ctx, sys, product, tile), ctx)
+
+
+def ccsd_k_get_product_tile(ctx, sys, product) -> int:
+    t = _i32()
+    _check(_lib_get_tile(ctx, sys, product, ctypes.byref(t)), ctx)
+    return int(t.value)
+
+
 def ccsd_k_autotune(ctx, sys, budget, cache_path=None):
     """Returns (forms per product, report[product][form] = (ms, error))."""
     forms = (_i32 * 5)()
@@ -236,7 +250,8 @@ def ccsd_k_timing_get(ctx, stage: int):
 def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference=False) -> np.ndarray:
     """C[g] = A[g] @ B[g].T on the device (A [G,M,K], B [G,N,K] complex128).
     reference: False/0 tiled FP64 MFMA, True/1 per-element FP64, 2 split-BF16 MFMA on pre-split
-    operands; on complex64 operands 3 two-term split-BF16, 4 three-term split-BF16, 5 FP32 MFMA."""
+    operands; on complex64 operands 3 two-term split-BF16, 4 three-term split-BF16, 5 FP32 MFMA;
+    10 + t the tiled FP64 kernel in tile shape t (TILE_*)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     B = np.ascontiguousarray(B, dtype=np.complex128)
     G, M, K = A.shape
@@ -328,6 +343,12 @@ class Context:
 
     def product_form(self, product, sys=0):
         return ccsd_k_get_product_form(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product)
+
+    def set_product_tile(self, product, tile, sys=0):
+        ccsd_k_set_product_tile(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product, tile)
+
+    def product_tile(self, product, sys=0):
+        return ccsd_k_get_product_tile(self.ctx, sys, STAGES.index(product) if isinstance(product, str) else product)
 
     def autotune(self, budget, cache_path=None, sys=0):
         return ccsd_k_autotune(self.ctx, sys, budget, cache_path)

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "common.h"
+#include "gemm_tiles.h"
 #include "mixed.h"
 #include "noalloc.h"
 #include "pack.h"
@@ -110,6 +111,9 @@ struct System {
     // otherwise (a PRESPLIT2 product of a complex64 family then runs as SPLIT2)
     int arith[5] = {ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2, ck::ARITH_PRESPLIT2,
                     ck::ARITH_PRESPLIT2};
+    // tile shape of each FP64 product (ck::F64Tile, indexed like g)
+    int tile[5] = {ck::F64_TILE_64x64, ck::F64_TILE_64x64, ck::F64_TILE_64x64, ck::F64_TILE_64x64,
+                   ck::F64_TILE_64x64};
     bool c64_lad() const { return ck::arith_c64(arith[0]) || ck::arith_c64(arith[1]); }
     bool c64_ring() const { return ck::arith_c64(arith[3]) || ck::arith_c64(arith[4]); }
     bool c64_of(int slot) const { return slot < 3 ? c64_lad() : c64_ring(); }
@@ -814,7 +818,7 @@ void run_gemm(ccsd_k_ctx *c, System &S, int i, hipStream_t st) {
     EventPair ep{};
     stage_begin(c, ep, (S.mixed && i < 2 ? S.gp[i] : S.g[i]).stage, st);
     if (S.mixed) run_split_product(S, i, st);
-    else ck::gemm_f64(S.g[i].op, st);
+    else ck::gemm_f64_tile(S.g[i].op, S.tile[i], st);
     stage_end(c, ep, st);
 }
 
@@ -1091,6 +1095,7 @@ int impl_init(const ccsd_k_system *sys, int32_t n_sys, void *hip_stream, ccsd_k_
             for (int b = 0; b < N; ++b)
                 for (int k = 0; k < N; ++k) S.kc[((int64_t)a * N + b) * N + k] = kcons(S.mesh, a, b, k);
         build_tables(S);
+        for (int i = 0; i < 5; ++i) S.tile[i] = ck::f64_default_tile(S.g[i].op.G, S.g[i].op.M, S.g[i].op.N);
     }
     *out = holder.release();
     return CCSD_K_OK;
@@ -1305,6 +1310,7 @@ std::vector<int64_t> iteration_signature(ccsd_k_ctx *c, double tol) {
     for (const System &S : c->sys) {
         sig.push_back(S.converged ? -1 : 1);
         for (int a : S.arith) sig.push_back(a);
+        for (int t : S.tile) sig.push_back(t);
         sig.push_back(S.kchunk);
         sig.push_back(S.sp_ok ? 1 : 0);
     }
@@ -1552,6 +1558,93 @@ int impl_get_product_form(const ccsd_k_ctx *cctx, int32_t sys, int32_t product, 
     return CCSD_K_OK;
 }
 
+int check_fp64_product(ccsd_k_ctx *ctx, int32_t sys, int32_t product) {
+    int rc = check_sys(ctx, sys, false);
+    if (rc) return rc;
+    if (ctx->sys[sys].mixed) return fail(ctx, CCSD_K_EINVAL, "tile shapes apply to FP64 systems");
+    if (product < 0 || product > 4) return fail(ctx, CCSD_K_EINVAL, "product must be in 0..4");
+    return CCSD_K_OK;
+}
+
+int impl_set_product_tile(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t tile) {
+    int rc = check_fp64_product(ctx, sys, product);
+    if (rc) return rc;
+    if (tile < 0 || tile >= ck::F64_TILE_COUNT) return fail(ctx, CCSD_K_EINVAL, "tile must be in 0..3");
+    ctx->sys[sys].tile[kSlotOfProduct[product]] = tile;
+    return CCSD_K_OK;
+}
+
+int impl_get_product_tile(const ccsd_k_ctx *cctx, int32_t sys, int32_t product, int32_t *tile) {
+    ccsd_k_ctx *ctx = const_cast<ccsd_k_ctx *>(cctx);
+    int rc = check_fp64_product(ctx, sys, product);
+    if (rc) return rc;
+    if (!tile) return fail(ctx, CCSD_K_EINVAL, "null tile");
+    *tile = ctx->sys[sys].tile[kSlotOfProduct[product]];
+    return CCSD_K_OK;
+}
+
+// Average launch time (ms) of FP64 product slot i with tile shape t; its outputs (the
+// W_mnij and W_mbej seeds, X, r2) are rewritten by the next residual before use.
+double time_tile(ccsd_k_ctx *c, System &S, int slot, int t, int reps) {
+    hipEvent_t e0, e1;
+    CK_CHECK(hipEventCreate(&e0));
+    CK_CHECK(hipEventCreate(&e1));
+    float ms = 0.f;
+    try {
+        ck::gemm_f64_tile(S.g[slot].op, t, c->stream);  // warm-up
+        CK_CHECK(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) ck::gemm_f64_tile(S.g[slot].op, t, c->stream);
+        CK_CHECK(hipEventRecord(e1, c->stream));
+        CK_CHECK(hipEventSynchronize(e1));
+        CK_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms / reps;
+}
+
+// FP64 system: the fastest tile shape per product (all shapes give the same result).
+int autotune_tiles(ccsd_k_ctx *ctx, System &S, const char *cache_path, int32_t *forms, double *report) {
+    static_assert(ck::F64_TILE_COUNT <= ck::ARITH_COUNT, "tile times share the record layout");
+    ck::TuneRecord rec[5];
+    try {
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+        const std::string dev = ck::device_key();
+        for (int slot = 0; slot < 5; ++slot) {
+            const ck::GemmOps<cd> &o = S.g[slot].op;
+            const std::string key = "f64tile:" + ck::tune_key(dev, o.G, o.M, o.N, o.K, 0);
+            if (ck::cache_lookup(cache_path, key, rec[slot])) continue;
+            ck::TuneRecord r;
+            for (int t = 0; t < ck::F64_TILE_COUNT; ++t) r.ms[t] = time_tile(ctx, S, slot, t, 3);
+            rec[slot] = r;
+            ck::cache_store(cache_path, key, r);
+        }
+        for (int slot = 0; slot < 5; ++slot) {
+            int b = ck::F64_TILE_64x64;
+            for (int t = 0; t < ck::F64_TILE_COUNT; ++t)
+                if (rec[slot].ms[t] < rec[slot].ms[b]) b = t;
+            S.tile[slot] = b;
+        }
+        amplitudes_changed(S);
+        CK_CHECK(hipStreamSynchronize(ctx->stream));
+        if (forms)
+            for (int p = 0; p < 5; ++p) forms[p] = S.tile[kSlotOfProduct[p]];
+        if (report)
+            for (int p = 0; p < 5; ++p)
+                for (int a = 0; a < ck::ARITH_COUNT; ++a) {
+                    report[(p * ck::ARITH_COUNT + a) * 2] = a < ck::F64_TILE_COUNT ? rec[kSlotOfProduct[p]].ms[a] : 0.0;
+                    report[(p * ck::ARITH_COUNT + a) * 2 + 1] = 0.0;
+                }
+    } catch (const ck::HipError &e) {
+        return fail(ctx, CCSD_K_EDEVICE, e.what);
+    }
+    return CCSD_K_OK;
+}
+
 // Average launch time (ms) of product slot i in arithmetic form a on the system's own
 // operands and tables.  Timing does not depend on the values; the outputs it overwrites
 // (W_mnij / W_mbej operands, Lp, X) are all recomputed by the next residual before use.
@@ -1591,8 +1684,8 @@ int impl_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache
     int rc = check_sys(ctx, sys, false);
     if (rc) return rc;
     System &S = ctx->sys[sys];
-    if (!S.mixed) return fail(ctx, CCSD_K_EINVAL, "arithmetic forms apply to mixed-precision systems");
     if (!(budget > 0.0)) return fail(ctx, CCSD_K_EINVAL, "budget must be positive");
+    if (!S.mixed) return autotune_tiles(ctx, S, cache_path, forms, report);
     static const int slots[4] = {0, 1, 3, 4};  // W_mnij, ladders, W_mbej, ring
     ck::TuneRecord rec[5];
     try {
@@ -1792,6 +1885,8 @@ int impl_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A
             CK_CHECK(hipDeviceSynchronize());
             (void)hipFree(cA);
             (void)hipFree(cB);
+        } else if (reference >= 10 && reference < 10 + ck::F64_TILE_COUNT) {
+            ck::gemm_f64_tile(op, reference - 10, nullptr);  // the FP64 kernel in one tile shape
         } else {
             ck::gemm_f64(op, nullptr);
         }
@@ -1886,6 +1981,14 @@ int ccsd_k_set_product_form(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32
 
 int ccsd_k_get_product_form(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *form) {
     return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_get_product_form(ctx, sys, product, form); });
+}
+
+int ccsd_k_set_product_tile(ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t tile) {
+    return guarded(ctx, [&] { return impl_set_product_tile(ctx, sys, product, tile); });
+}
+
+int ccsd_k_get_product_tile(const ccsd_k_ctx *ctx, int32_t sys, int32_t product, int32_t *tile) {
+    return guarded(const_cast<ccsd_k_ctx *>(ctx), [&] { return impl_get_product_tile(ctx, sys, product, tile); });
 }
 
 int ccsd_k_autotune(ccsd_k_ctx *ctx, int32_t sys, double budget, const char *cache_path, int32_t *forms,

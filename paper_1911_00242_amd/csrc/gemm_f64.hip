@@ -14,6 +14,7 @@
 // v_mfma_f64_16x16x4 products (re*re, -im*im into the real accumulator; re*im, im*re into
 // the imaginary one).
 #include "common.h"
+#include "gemm_tiles.h"
 
 namespace ck {
 
@@ -75,8 +76,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
 
     // Staged elements of the next stage and the k-table offsets of the one after it.
     // Every iteration loads (out-of-range elements read the zero buffer), so no
-    // data-dependent select sits between a load and its LDS store.
+    // data-dependent select sits between a load and its LDS store.  Four rows per thread
+    // (the 64 x 64 tile) in named registers; other tiles in component arrays (an array of
+    // HIP vector structs would be kept in scratch memory).
+    constexpr bool R4 = RA == 4 && RB == 4;
     cd ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    double rax[RA], ray[RA], rbx[RB], rby[RB];
     int64_t ak_cur = 0, bk_cur = 0;
 #define CK_KOFS(k0, ak, bk)                                \
     {                                                      \
@@ -87,26 +92,45 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmOps<cd> op) {
 #define CK_LOAD(k0)                                                                                     \
     {                                                                                                   \
         const bool kin_ = (k0) + kl < K;                                                                \
-        static_assert(RA == 4 && RB == 4, "loader written for four rows per thread");                   \
-        ra0 = *((kin_ && aok[0]) ? op.A + arow[0] + ak_cur : op.zeros);                                 \
-        ra1 = *((kin_ && aok[1]) ? op.A + arow[1] + ak_cur : op.zeros);                                 \
-        ra2 = *((kin_ && aok[2]) ? op.A + arow[2] + ak_cur : op.zeros);                                 \
-        ra3 = *((kin_ && aok[3]) ? op.A + arow[3] + ak_cur : op.zeros);                                 \
-        rb0 = *((kin_ && bok[0]) ? op.B + bcol[0] + bk_cur : op.zeros);                                 \
-        rb1 = *((kin_ && bok[1]) ? op.B + bcol[1] + bk_cur : op.zeros);                                 \
-        rb2 = *((kin_ && bok[2]) ? op.B + bcol[2] + bk_cur : op.zeros);                                 \
-        rb3 = *((kin_ && bok[3]) ? op.B + bcol[3] + bk_cur : op.zeros);                                 \
+        if constexpr (R4) {                                                                             \
+            ra0 = *((kin_ && aok[0]) ? op.A + arow[0] + ak_cur : op.zeros);                             \
+            ra1 = *((kin_ && aok[1]) ? op.A + arow[1] + ak_cur : op.zeros);                             \
+            ra2 = *((kin_ && aok[2]) ? op.A + arow[2] + ak_cur : op.zeros);                             \
+            ra3 = *((kin_ && aok[3]) ? op.A + arow[3] + ak_cur : op.zeros);                             \
+            rb0 = *((kin_ && bok[0]) ? op.B + bcol[0] + bk_cur : op.zeros);                             \
+            rb1 = *((kin_ && bok[1]) ? op.B + bcol[1] + bk_cur : op.zeros);                             \
+            rb2 = *((kin_ && bok[2]) ? op.B + bcol[2] + bk_cur : op.zeros);                             \
+            rb3 = *((kin_ && bok[3]) ? op.B + bcol[3] + bk_cur : op.zeros);                             \
+        } else {                                                                                        \
+            _Pragma("unroll") for (int i_ = 0; i_ < RA; ++i_) {                                         \
+                const cd v_ = *((kin_ && aok[i_]) ? op.A + arow[i_] + ak_cur : op.zeros);               \
+                rax[i_] = v_.x;                                                                         \
+                ray[i_] = v_.y;                                                                         \
+            }                                                                                           \
+            _Pragma("unroll") for (int i_ = 0; i_ < RB; ++i_) {                                         \
+                const cd v_ = *((kin_ && bok[i_]) ? op.B + bcol[i_] + bk_cur : op.zeros);               \
+                rbx[i_] = v_.x;                                                                         \
+                rby[i_] = v_.y;                                                                         \
+            }                                                                                           \
+        }                                                                                               \
     }
-#define CK_STORE(buf)                                          \
-    {                                                          \
-        As[buf][kl][rl] = ra0;                                 \
-        As[buf][kl][rl + ROWS_PER_PASS] = ra1;                 \
-        As[buf][kl][rl + 2 * ROWS_PER_PASS] = ra2;             \
-        As[buf][kl][rl + 3 * ROWS_PER_PASS] = ra3;             \
-        Bs[buf][kl][rl] = rb0;                                 \
-        Bs[buf][kl][rl + ROWS_PER_PASS] = rb1;                 \
-        Bs[buf][kl][rl + 2 * ROWS_PER_PASS] = rb2;             \
-        Bs[buf][kl][rl + 3 * ROWS_PER_PASS] = rb3;             \
+#define CK_STORE(buf)                                                                                  \
+    {                                                                                                  \
+        if constexpr (R4) {                                                                            \
+            As[buf][kl][rl] = ra0;                                                                     \
+            As[buf][kl][rl + ROWS_PER_PASS] = ra1;                                                     \
+            As[buf][kl][rl + 2 * ROWS_PER_PASS] = ra2;                                                 \
+            As[buf][kl][rl + 3 * ROWS_PER_PASS] = ra3;                                                 \
+            Bs[buf][kl][rl] = rb0;                                                                     \
+            Bs[buf][kl][rl + ROWS_PER_PASS] = rb1;                                                     \
+            Bs[buf][kl][rl + 2 * ROWS_PER_PASS] = rb2;                                                 \
+            Bs[buf][kl][rl + 3 * ROWS_PER_PASS] = rb3;                                                 \
+        } else {                                                                                       \
+            _Pragma("unroll") for (int i_ = 0; i_ < RA; ++i_)                                          \
+                As[buf][kl][rl + i_ * ROWS_PER_PASS] = make_double2(rax[i_], ray[i_]);                 \
+            _Pragma("unroll") for (int i_ = 0; i_ < RB; ++i_)                                          \
+                Bs[buf][kl][rl + i_ * ROWS_PER_PASS] = make_double2(rbx[i_], rby[i_]);                 \
+        }                                                                                              \
     }
 
     const int nk = (K + BK - 1) / BK;
@@ -195,13 +219,28 @@ __global__ void k_gemm_f64_reference(GemmOps<cd> op) {
     *p = v;
 }
 
-void gemm_f64(const GemmOps<cd> &op, hipStream_t s) {
-    if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
-    constexpr int BM = 64, BN = 64, BK = 16;
+template <int BM, int BN>
+static void launch_f64(const GemmOps<cd> &op, hipStream_t s) {
     const dim3 grid = gemm_tile_grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, op.G);
-    hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, 2, 2>), grid, dim3(256), 0, s, op);
+    hipLaunchKernelGGL((k_gemm_f64<BM, BN, 16, 2, 2>), grid, dim3(256), 0, s, op);
     CK_CHECK(hipGetLastError());
 }
+
+// Tile shapes of the FP64 product (gemm_tiles.h).  Every shape takes the same sixteen k
+// per stage and the same order of MFMAs along k for each output element, so all of them
+// give bitwise the same result; they differ in data reuse against the number of
+// workgroups.
+void gemm_f64_tile(const GemmOps<cd> &op, int tile, hipStream_t s) {
+    if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
+    switch (tile) {
+        case F64_TILE_32x32: launch_f64<32, 32>(op, s); break;
+        case F64_TILE_128x64: launch_f64<128, 64>(op, s); break;
+        case F64_TILE_64x128: launch_f64<64, 128>(op, s); break;
+        default: launch_f64<64, 64>(op, s); break;
+    }
+}
+
+void gemm_f64(const GemmOps<cd> &op, hipStream_t s) { gemm_f64_tile(op, F64_TILE_64x64, s); }
 
 void gemm_f64_reference(const GemmOps<cd> &op, hipStream_t s) {
     int64_t total = (int64_t)op.G * op.M * op.N;

@@ -1,0 +1,19 @@
+// Tile shapes of the FP64 grouped complex product (gemm_f64.hip), chosen per product by the
+// autotuner or the caller.  All shapes give bitwise the same result.
+#pragma once
+#include "common.h"
+
+namespace ck {
+
+enum F64Tile { F64_TILE_32x32 = 0, F64_TILE_64x64 = 1, F64_TILE_128x64 = 2, F64_TILE_64x128 = 3, F64_TILE_COUNT = 4 };
+
+void gemm_f64_tile(const GemmOps<cd> &op, int tile, hipStream_t s);
+
+// The shape a product starts with: 32 x 32 while 64 x 64 tiles would give fewer than 4096
+// workgroups (a few per CU: there the smaller tile keeps more of the chip busy; measured
+// up to 3x faster on small products), 64 x 64 otherwise.  The autotuner refines it.
+inline int f64_default_tile(int64_t G, int64_t M, int64_t N) {
+    return G * ((M + 63) / 64) * ((N + 63) / 64) < 4096 ? F64_TILE_32x32 : F64_TILE_64x64;
+}
+
+}  // namespace ck

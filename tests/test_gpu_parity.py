@@ -402,3 +402,56 @@ def test_side_stream_is_bitwise_equal(grid, no, nv, diis):
         assert np.array_equal(r[0], base[0]) and np.array_equal(r[1], base[1])
         assert r[2] == base[2] and r[3] == base[3] and r[4] == base[4] and r[5] == base[5]
         assert np.array_equal(r[6][0], base[6][0]) and np.array_equal(r[6][1], base[6][1])
+
+
+@pytest.mark.parametrize("G,M,N,K", [(2, 130, 200, 70), (1, 16, 16, 4), (3, 37, 45, 29), (1, 129, 65, 33)])
+def test_fp64_tile_shapes_agree_bitwise(G, M, N, K):
+    """Every tile shape of the FP64 product against numpy, and bitwise equal to the default
+    shape (same k stages, same order of MFMA operations along k for each output)."""
+    print(f"fp64 tiles G={G} M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(G + M + N + K)
+    A = rng.standard_normal((G, M, K)) + 1j * rng.standard_normal((G, M, K))
+    B = rng.standard_normal((G, N, K)) + 1j * rng.standard_normal((G, N, K))
+    ref = np.einsum("gmk,gnk->gmn", A, B)
+    C0 = ck.ccsd_k_debug_zgemm(A, B, reference=0)
+    for t in (ck.TILE_32X32, ck.TILE_64X64, ck.TILE_128X64, ck.TILE_64X128):
+        C = ck.ccsd_k_debug_zgemm(A, B, reference=10 + t)
+        assert _rel(C, ref) <= 1e-13, t
+        assert np.array_equal(C, C0), t
+
+
+def test_fp64_autotune_tiles_and_cache(tmp_path):
+    """The autotuner on an FP64 system times every tile shape of every product and keeps the
+    fastest; the residual is bitwise the same for every choice; a second call reads the
+    cache; tiles are refused on a mixed system and out of range."""
+    grid, no, nv = (2, 1, 1), 8, 16
+    f, eris = synth.system(626, grid, no, nv, scale=0.025)
+    t1, t2 = synth.test_amplitudes(62, grid, no, nv, scale=0.05)
+    cache = str(tmp_path / "tiles.txt")
+    with _ctx([dict(grid=grid, no=no, nv=nv), dict(grid=grid, no=no, nv=nv, precision=ck.PREC_MIXED)]) as c:
+        c.set_inputs(0, f, eris)
+        r1a, r2a = c.residual(0, t1, t2)
+        tiles, rep = c.autotune(1e-2, cache)
+        print("tiles:", tiles, "\n", rep[:, :, 0], flush=True)
+        assert all(t in (0, 1, 2, 3) for t in tiles)
+        assert rep[:, :, 0].min() > 0  # every product, every tile timed
+        for p in range(5):
+            assert c.product_tile(p) == tiles[p]
+            assert rep[p, tiles[p], 0] == rep[p, :, 0].min()
+        r1b, r2b = c.residual(0, t1, t2)
+        assert np.array_equal(r2a, r2b) and np.array_equal(r1a, r1b)
+        lines = open(cache).read().splitlines()
+        assert len(lines) == len({c.product_shape(p) for p in range(5)})
+        c.autotune(1e-2, cache)
+        assert open(cache).read().splitlines() == lines  # all from the cache
+        for t in (ck.TILE_32X32, ck.TILE_128X64, ck.TILE_64X128):
+            for p in range(5):
+                c.set_product_tile(p, t)
+            r1c, r2c = c.residual(0, t1, t2)
+            assert np.array_equal(r2a, r2c) and np.array_equal(r1a, r1c), t
+        with pytest.raises(ck.CcsdKError) as e:
+            c.set_product_tile(0, 4)
+        assert e.value.code == ck.EINVAL
+        with pytest.raises(ck.CcsdKError) as e:
+            c.set_product_tile(0, ck.TILE_32X32, sys=1)
+        assert e.value.code == ck.EINVAL
