@@ -485,4 +485,11 @@ def main():
 
 
 if __name__ == "__main__":
+    # Systems iterated together run on eight streams of the library's beside the context's
+    # stream; the HIP runtime opens four hardware queues per process unless told otherwise,
+    # so streams share queues and their kernels wait behind each other.  Sixteen queues give
+    # every stream its own (the 96-system batch measured 149 ms per iteration against 155 ms
+    # with four or eight).  Set before the runtime starts: torch and the library are loaded
+    # inside main.
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
     main()
