@@ -257,8 +257,10 @@ int ccsd_k_timing_get(ccsd_k_ctx *ctx, int32_t stage, double *total_ms, int64_t 
  * tiled FP64 MFMA kernel (reference = 0), the one-thread-per-element FP64 kernel
  * (reference = 1), the split-BF16 MFMA kernel of the mixed path on pre-split operands
  * (reference = 2), the complex64-operand kernel in one of its arithmetic forms:
- * two-term split-BF16 (3), three-term split-BF16 (4) or FP32 MFMA (5), or the tiled FP64
- * kernel in tile shape t (reference = 10 + t, t one of CCSD_K_TILE_*).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
+ * two-term split-BF16 (3), three-term split-BF16 (4) or FP32 MFMA (5), the same three forms
+ * summed over 64-k chunks in FP64 in one launch (23, 24, 25: the form escalated systems
+ * use), or the tiled FP64 kernel in tile shape t (reference = 10 + t, t one of
+ * CCSD_K_TILE_*).  Host arrays, complex128: A [G][M][K], B [G][N][K], C [G][M][N].
  * Allocates and frees its own device buffers; synchronizes the default stream. */
 int ccsd_k_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A, const double *B,
                        double *C, int32_t reference);

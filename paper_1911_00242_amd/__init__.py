@@ -251,6 +251,7 @@ def ccsd_k_debug_zgemm(A: np.ndarray, B: np.ndarray, reference=False) -> np.ndar
     """C[g] = A[g] @ B[g].T on the device (A [G,M,K], B [G,N,K] complex128).
     reference: False/0 tiled FP64 MFMA, True/1 per-element FP64, 2 split-BF16 MFMA on pre-split
     operands; on complex64 operands 3 two-term split-BF16, 4 three-term split-BF16, 5 FP32 MFMA;
+    23, 24, 25 the same three forms summed over 64-k chunks in FP64 in one launch;
     10 + t the tiled FP64 kernel in tile shape t (TILE_*)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     B = np.ascontiguousarray(B, dtype=np.complex128)

@@ -778,9 +778,11 @@ void watch_stagnation(ccsd_k_ctx *c, System &S) {
 }
 
 // product slot i of the mixed path in its arithmetic form, on its family's storage.  With
-// S.kchunk > 0 the k range is cut into chunks of that many k, each a launch that adds its
-// part to the FP64 output (the first with the product's beta, the rest with 1; only the
-// last writes the split or complex64 copy): FP32 accumulation then spans one chunk.
+// S.kchunk > 0 the k range is summed in chunks of that many k: FP32 accumulation spans one
+// chunk and the chunks are added in FP64.  On complex64 storage (every product of an
+// escalated system) that is one launch that keeps the FP64 sums in registers; on split
+// storage each chunk is a launch that adds its part to the FP64 output (the first with the
+// product's beta, the rest with 1; only the last writes the split copy).
 void run_split_product(System &S, int i, hipStream_t st) {
     const bool c64 = S.c64_of(i);
     const int a = !c64 ? (int)ck::ARITH_PRESPLIT2
@@ -793,6 +795,10 @@ void run_split_product(System &S, int i, hipStream_t st) {
     const int kc = S.kchunk;
     if (kc <= 0 || op.K <= kc) {
         launch(op);
+        return;
+    }
+    if (c64) {
+        ck::gemm_c64_chunked(op, a, kc, st);
         return;
     }
     for (int k0 = 0; k0 < op.K; k0 += kc) {
@@ -1882,6 +1888,27 @@ int impl_debug_zgemm(int32_t G, int32_t M, int32_t N, int32_t K, const double *A
             so.G = G; so.M = M; so.N = N; so.K = K; so.alpha = 1.0; so.beta = 0.0;
             so.fast = (K % 8 == 0) ? 1 : 0;
             ck::gemm_c64(so, reference - 2, nullptr);
+            CK_CHECK(hipDeviceSynchronize());
+            (void)hipFree(cA);
+            (void)hipFree(cB);
+        } else if (reference >= 23 && reference <= 25) {
+            // complex64 operands, arithmetic form reference - 22, summed in FP64 over 64-k
+            // chunks in one launch
+            auto padded = [](int64_t n) { return (n + 63) / 64 * 64; };
+            int64_t pa = padded((int64_t)na), pb = padded((int64_t)nb);
+            ck::cf *cA = nullptr, *cB = nullptr;
+            CK_CHECK(hipMalloc(&cA, pa * sizeof(ck::cf)));
+            CK_CHECK(hipMalloc(&cB, pb * sizeof(ck::cf)));
+            ck::launch_to_c64((int64_t)na, dA, cA, nullptr);
+            ck::launch_to_c64((int64_t)nb, dB, cB, nullptr);
+            ck::SplitOps so{};
+            so.A = reinterpret_cast<const uint16_t *>(cA); so.B = reinterpret_cast<const uint16_t *>(cB); so.C = dC;
+            so.zeros = reinterpret_cast<const uint16_t *>(dZ);
+            so.a_row = op.a_row; so.a_k = op.a_k; so.b_col = op.b_col; so.b_k = op.b_k;
+            so.c_row = op.c_row; so.c_col = op.c_col;
+            so.G = G; so.M = M; so.N = N; so.K = K; so.alpha = 1.0; so.beta = 0.0;
+            so.fast = (K % 8 == 0) ? 1 : 0;
+            ck::gemm_c64_chunked(so, reference - 22, 64, nullptr);
             CK_CHECK(hipDeviceSynchronize());
             (void)hipFree(cA);
             (void)hipFree(cB);

@@ -20,6 +20,7 @@
 // stage, 128 contiguous bytes of complex64.
 #include "common.h"
 #include "mixed.h"
+#include "gemm_tiles.h"
 
 namespace ck {
 
@@ -32,7 +33,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BK = 16;
 constexpr int RSF = 2 * BK + 4;  // floats per LDS row: 16 complex + 16 bytes of pad
 
 // Split 8 fp32 values into NP bf16 terms (term t in part[t]), each rounded to nearest even
@@ -81,9 +82,16 @@ struct Pairs<3> {
 
 }  // namespace
 
-// MODE: 2 = SPLIT2, 3 = SPLIT3 (NP bf16 terms), 0 = FP32 MFMA
-template <int MODE, bool FAST>
-__global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
+// MODE: 2 = SPLIT2, 3 = SPLIT3 (NP bf16 terms), 0 = FP32 MFMA.  BT: square tile (128: 2 x 2
+// waves of 64 x 64; 64: 2 x 2 waves of 32 x 32).  CHUNKED: the k range is summed in chunks
+// of chk stages, each accumulated in FP32 by the MFMAs and then added to FP64 partial sums
+// held in registers (with the 64 tile, 32 doubles per lane), so FP32 accumulation spans
+// one chunk while the output is read and written once.
+template <int MODE, bool FAST, int BT = 128, bool CHUNKED = false>
+__global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op, int chk) {
+    constexpr int BM = BT, BN = BT;
+    constexpr int TI = BT / 64;          // 32 x 32 MFMA tiles per wave along each side
+    constexpr int RPW = BT / 4, NI = RPW / 8;  // rows per wave and loader passes
     __shared__ __attribute__((aligned(16))) float As[2][BM * RSF];
     __shared__ __attribute__((aligned(16))) float Bs[2][BN * RSF];
 
@@ -105,11 +113,11 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
     // loader: piece lq = lane % 8 of a row's stage (k = 2 lq, 2 lq + 1; run lc = lq / 4 of
     // eight k), rows lr + 8 i (i = 0..3) of both A and B
     const int lq = lane & 7, lc = lq >> 2;
-    const int lr = wave * 32 + (lane >> 3);
-    int64_t arow[4], bcol[4];
-    bool aok[4], bok[4];
+    const int lr = wave * RPW + (lane >> 3);
+    int64_t arow[NI], bcol[NI];
+    bool aok[NI], bok[NI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NI; ++i) {
         const int am = m0 + lr + 8 * i, bn = n0 + lr + 8 * i;
         aok[i] = am < M;
         bok[i] = bn < N;
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
         bcol[i] = op.b_col[(int64_t)g * N + (bok[i] ? bn : N - 1)];
     }
     const int kclamp = FAST ? K - 8 : K - 1;
-    f32x4 sa[4], sb[4];
+    f32x4 sa[NI], sb[NI];
 
     auto load_stage = [&](int k0) {
         if (FAST) {
@@ -127,7 +135,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
             const int64_t ak = op.a_k[(int64_t)g * kld + kk] + 2 * (lq & 3);
             const int64_t bk = op.b_k[(int64_t)g * kld + kk] + 2 * (lq & 3);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NI; ++i) {
                 const float *pa = (kok && aok[i]) ? Af + 2 * (arow[i] + ak) : Zf;
                 const float *pb = (kok && bok[i]) ? Bf + 2 * (bcol[i] + bk) : Zf;
                 sa[i] = *(const f32x4 *)pa;
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NI; ++i) {
                 f32x2 va[2], vb[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
@@ -154,19 +162,26 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NI; ++i) {
             *(f32x4 *)&As[buf][(lr + 8 * i) * RSF + 4 * lq] = sa[i];
             *(f32x4 *)&Bs[buf][(lr + 8 * i) * RSF + 4 * lq] = sb[i];
         }
     };
 
-    f32x16 cr[2][2], ci[2][2];
+    f32x16 cr[TI][TI], ci[TI][TI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TI; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) cr[i][j][r] = ci[i][j][r] = 0.f;
+    // FP64 partial sums of the finished chunks (CHUNKED only; component arrays stay in
+    // registers)
+    double dr[CHUNKED ? TI * TI * 16 : 1], di[CHUNKED ? TI * TI * 16 : 1];
+    if constexpr (CHUNKED) {
+#pragma unroll
+        for (int r = 0; r < TI * TI * 16; ++r) dr[r] = di[r] = 0.0;
+    }
 
     const int nk = (K + BK - 1) / BK;
     if (nk > 0) {
@@ -181,23 +196,23 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
                 // FP32: eight sub-steps of two k; lane (l32, lh) holds row l32, k = 2 s + lh
 #pragma unroll
                 for (int s = 0; s < BK / 2; ++s) {
-                    f32x2 a[2], b[2];
+                    f32x2 a[TI], b[TI];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i) {
-                        a[i] = *(const f32x2 *)&as[(wm * 64 + i * 32 + l32) * RSF + 2 * (2 * s + lh)];
-                        b[i] = *(const f32x2 *)&bs[(wn * 64 + i * 32 + l32) * RSF + 2 * (2 * s + lh)];
+                    for (int i = 0; i < TI; ++i) {
+                        a[i] = *(const f32x2 *)&as[(wm * (BT / 2) + i * 32 + l32) * RSF + 2 * (2 * s + lh)];
+                        b[i] = *(const f32x2 *)&bs[(wn * (BT / 2) + i * 32 + l32) * RSF + 2 * (2 * s + lh)];
                     }
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < TI; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < TI; ++j) {
                             cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].x, cr[i][j], 0, 0, 0);
                             ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[j].y, ci[i][j], 0, 0, 0);
                         }
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < TI; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < TI; ++j) {
                             cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].y, b[j].y, cr[i][j], 0, 0, 0);
                             ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[j].x, ci[i][j], 0, 0, 0);
                         }
@@ -207,12 +222,12 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
                 using PP = Pairs<NP>;
                 // lane (l32, lh) holds the 8 k of half lh of its row l32, in NP terms each for
                 // the real and the imaginary part
-                bf16x8 are[2][NP], aim[2][NP], anim[2][NP], bre[2][NP], bim[2][NP];
+                bf16x8 are[TI][NP], aim[TI][NP], anim[TI][NP], bre[TI][NP], bim[TI][NP];
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+                for (int i = 0; i < TI; ++i) {
                     float xr[8], xi[8], yr[8], yi[8];
-                    const float *pa = &as[(wm * 64 + i * 32 + l32) * RSF + 16 * lh];
-                    const float *pb = &bs[(wn * 64 + i * 32 + l32) * RSF + 16 * lh];
+                    const float *pa = &as[(wm * (BT / 2) + i * 32 + l32) * RSF + 16 * lh];
+                    const float *pb = &bs[(wn * (BT / 2) + i * 32 + l32) * RSF + 16 * lh];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const f32x4 qa = *(const f32x4 *)(pa + 4 * v), qb = *(const f32x4 *)(pb + 4 * v);
@@ -231,19 +246,33 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
                 for (int u = PP::n - 1; u >= 0; --u) {
                     const int p = PP::p[u], q = PP::q[u];
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < TI; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < TI; ++j) {
                             cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(are[i][p], bre[j][q], cr[i][j], 0, 0, 0);
                             ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(are[i][p], bim[j][q], ci[i][j], 0, 0, 0);
                         }
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < TI; ++i)
 #pragma unroll
-                        for (int j = 0; j < 2; ++j) {
+                        for (int j = 0; j < TI; ++j) {
                             cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(anim[i][p], bim[j][q], cr[i][j], 0, 0, 0);
                             ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aim[i][p], bre[j][q], ci[i][j], 0, 0, 0);
                         }
+                }
+            }
+            if constexpr (CHUNKED) {
+                if ((kt + 1) % chk == 0 || kt + 1 == nk) {  // a chunk is complete: into FP64
+#pragma unroll
+                    for (int i = 0; i < TI; ++i)
+#pragma unroll
+                        for (int j = 0; j < TI; ++j)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                dr[(i * TI + j) * 16 + r] += (double)cr[i][j][r];
+                                di[(i * TI + j) * 16 + r] += (double)ci[i][j][r];
+                                cr[i][j][r] = ci[i][j][r] = 0.f;
+                            }
                 }
             }
             if (kt + 1 < nk) store_stage(buf ^ 1);
@@ -255,36 +284,38 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
     // of column l32 of its 32 x 32 tile
     const double alpha = op.alpha, beta = op.beta;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int mb = m0 + wm * 64 + i * 32 + 4 * lh;
+    for (int i = 0; i < TI; ++i) {
+        const int mb = m0 + wm * (BT / 2) + i * 32 + 4 * lh;
         int64_t crow[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int m = mb + 8 * (r >> 2) + (r & 3);
             crow[r] = m < M ? op.c_row[(int64_t)g * M + m] : -1;
         }
-        int64_t ccol[2], cscol[2];
+        int64_t ccol[TI], cscol[TI];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = n0 + wn * 64 + j * 32 + l32;
+        for (int j = 0; j < TI; ++j) {
+            const int n = n0 + wn * (BT / 2) + j * 32 + l32;
             ccol[j] = n < N ? op.c_col[(int64_t)g * N + n] : -1;
             cscol[j] = (n < N && op.cs_col) ? op.cs_col[(int64_t)g * N + n] : ccol[j];
         }
-        cd o[2][16];
+        cd o[TI][16];
         if (beta != 0.0) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < TI; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     o[j][r] = crow[r] >= 0 && ccol[j] >= 0 ? op.C[crow[r] + ccol[j]] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < TI; ++j) {
             if (ccol[j] < 0) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 if (crow[r] < 0) continue;
-                cd v = make_double2(alpha * (double)cr[i][j][r], alpha * (double)ci[i][j][r]);
+                const double sr = CHUNKED ? dr[(i * TI + j) * 16 + r] : (double)cr[i][j][r];
+                const double si = CHUNKED ? di[(i * TI + j) * 16 + r] : (double)ci[i][j][r];
+                cd v = make_double2(alpha * sr, alpha * si);
                 if (beta != 0.0) {
                     v.x = fma(beta, o[j][r].x, v.x);
                     v.y = fma(beta, o[j][r].y, v.y);
@@ -303,17 +334,37 @@ __global__ __launch_bounds__(256) void k_gemm_c64(SplitOps op) {
 
 void gemm_c64(const SplitOps &op, int arith, hipStream_t s) {
     if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
-    const dim3 grid = gemm_tile_grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, op.G);
+    const dim3 grid = gemm_tile_grid((op.M + 127) / 128, (op.N + 127) / 128, op.G);
 #define CK_LAUNCH(MODE)                                                                 \
     if (op.fast)                                                                        \
-        hipLaunchKernelGGL((k_gemm_c64<MODE, true>), grid, dim3(256), 0, s, op);        \
+        hipLaunchKernelGGL((k_gemm_c64<MODE, true>), grid, dim3(256), 0, s, op, 0);     \
     else                                                                                \
-        hipLaunchKernelGGL((k_gemm_c64<MODE, false>), grid, dim3(256), 0, s, op);
+        hipLaunchKernelGGL((k_gemm_c64<MODE, false>), grid, dim3(256), 0, s, op, 0);
     switch (arith) {
     case ARITH_SPLIT2: CK_LAUNCH(2); break;
     case ARITH_SPLIT3: CK_LAUNCH(3); break;
     case ARITH_FP32: CK_LAUNCH(0); break;
     default: throw HipError(hipErrorInvalidValue, "gemm_c64: arithmetic form", __FILE__, __LINE__);
+    }
+#undef CK_LAUNCH
+    CK_CHECK(hipGetLastError());
+}
+
+void gemm_c64_chunked(const SplitOps &op, int arith, int kchunk, hipStream_t s) {
+    if (op.G <= 0 || op.M <= 0 || op.N <= 0) return;
+    if (kchunk < BK || kchunk % BK) throw HipError(hipErrorInvalidValue, "gemm_c64_chunked: chunk", __FILE__, __LINE__);
+    const int chk = kchunk / BK;
+    const dim3 grid = gemm_tile_grid((op.M + 63) / 64, (op.N + 63) / 64, op.G);
+#define CK_LAUNCH(MODE)                                                                         \
+    if (op.fast)                                                                                \
+        hipLaunchKernelGGL((k_gemm_c64<MODE, true, 64, true>), grid, dim3(256), 0, s, op, chk);  \
+    else                                                                                        \
+        hipLaunchKernelGGL((k_gemm_c64<MODE, false, 64, true>), grid, dim3(256), 0, s, op, chk);
+    switch (arith) {
+    case ARITH_SPLIT2: CK_LAUNCH(2); break;
+    case ARITH_SPLIT3: CK_LAUNCH(3); break;
+    case ARITH_FP32: CK_LAUNCH(0); break;
+    default: throw HipError(hipErrorInvalidValue, "gemm_c64_chunked: arithmetic form", __FILE__, __LINE__);
     }
 #undef CK_LAUNCH
     CK_CHECK(hipGetLastError());

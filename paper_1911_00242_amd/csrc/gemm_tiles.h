@@ -1,7 +1,9 @@
 // Tile shapes of the FP64 grouped complex product (gemm_f64.hip), chosen per product by the
-// autotuner or the caller.  All shapes give bitwise the same result.
+// autotuner or the caller (all shapes give bitwise the same result), and the chunked form of
+// the complex64-operand product (gemm_c64.hip).
 #pragma once
 #include "common.h"
+#include "mixed.h"
 
 namespace ck {
 
@@ -15,5 +17,12 @@ void gemm_f64_tile(const GemmOps<cd> &op, int tile, hipStream_t s);
 inline int f64_default_tile(int64_t G, int64_t M, int64_t N) {
     return G * ((M + 63) / 64) * ((N + 63) / 64) < 4096 ? F64_TILE_32x32 : F64_TILE_64x64;
 }
+
+// The complex64-operand product in arithmetic form arith (ARITH_SPLIT2, ARITH_SPLIT3 or
+// ARITH_FP32) with its k range summed in chunks of kchunk (a multiple of 16): FP32
+// accumulation within a chunk, FP64 across chunks, in one launch on 64 x 64 tiles (the
+// output is read and written once).  Same result, up to the order of the FP64 additions,
+// as one launch per chunk.
+void gemm_c64_chunked(const SplitOps &op, int arith, int kchunk, hipStream_t s);
 
 }  // namespace ck

@@ -151,6 +151,39 @@ def test_c64_zgemm_error_bound(form, bound, G, M, N, K):
         assert err.max() > 0
 
 
+# The same forms summed over 64-k chunks in FP64 in one launch (64 x 64 tiles; the form of
+# escalated systems): the same bounds, and on a long k range the chunked three-term split and
+# FP32 MFMA are more accurate than the unchunked ones (FP32 accumulation spans 4 steps).
+@pytest.mark.parametrize("form,bound", [(23, 4e-5), (24, 2e-6), (25, 2e-6)])
+@pytest.mark.parametrize("G,M,N,K", [(1, 32, 32, 16), (2, 128, 128, 64), (3, 37, 45, 29), (2, 130, 200, 300),
+                                     (1, 256, 130, 8), (1, 65, 70, 1000), (2, 5, 3, 0)])
+def test_c64_chunked_zgemm_error_bound(form, bound, G, M, N, K):
+    print(f"c64 chunked zgemm form={form} G={G} M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(G * 11 + M + N + K + form)
+    A = rng.standard_normal((G, M, K)) + 1j * rng.standard_normal((G, M, K))
+    B = rng.standard_normal((G, N, K)) + 1j * rng.standard_normal((G, N, K))
+    ref = np.einsum("gmk,gnk->gmn", A, B)
+    absb = np.einsum("gmk,gnk->gmn", np.abs(A), np.abs(B))
+    C = ck.ccsd_k_debug_zgemm(A, B, reference=form)
+    err = np.abs(C - ref)
+    assert np.all(err <= bound * absb + 1e-30)
+    if K:
+        assert err.max() > 0
+
+
+def test_c64_chunked_beats_unchunked_on_long_k():
+    rng = np.random.default_rng(5)
+    K = 4096
+    A = rng.standard_normal((1, 96, K)) + 1j * rng.standard_normal((1, 96, K))
+    B = rng.standard_normal((1, 80, K)) + 1j * rng.standard_normal((1, 80, K))
+    ref = np.einsum("gmk,gnk->gmn", A, B)
+    for plain, chunked in ((4, 24), (5, 25)):
+        e0 = np.abs(ck.ccsd_k_debug_zgemm(A, B, reference=plain) - ref).max()
+        e1 = np.abs(ck.ccsd_k_debug_zgemm(A, B, reference=chunked) - ref).max()
+        print(f"form {plain}: unchunked {e0:.2e}, chunked {e1:.2e}", flush=True)
+        assert e1 < e0
+
+
 def test_c64_split3_beats_split2():
     """The three-term split is far more accurate than the two-term one on the same data."""
     rng = np.random.default_rng(3)
