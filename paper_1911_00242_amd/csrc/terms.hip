@@ -1040,10 +1040,21 @@ __global__ __launch_bounds__(OM * VM) void k_ring_z_t(SysDev s, const cd *__rest
     for (int f = 0; f < VM; ++f) gr[f] = f < nv ? to_cd(g[(int64_t)f * nv]) : make_double2(0.0, 0.0);
     const IT *h = ooov_of<IT>(s) + blk3(N, km, kb, kj) * o3v + ((int64_t)m * no + nn) * no * nv + e;
     cd *z = Z + blk * o3v + ((int64_t)m * no + nn) * no * nv + e;
-    for (int j = 0; j < no; ++j) {
+    // the <mn||je> of every j loaded together before any is used (component arrays, clamped
+    // addresses), so the thread waits for one memory round trip instead of one per j
+    using ST = decltype(IT{}.x);
+    ST hx[OM], hy[OM];
+#pragma unroll
+    for (int j = 0; j < OM; ++j) {
+        const IT v = h[(int64_t)(j < no ? j : 0) * nv];
+        hx[j] = v.x;
+        hy[j] = v.y;
+    }
+#pragma unroll
+    for (int j = 0; j < OM; ++j) {
+        if (j >= no) break;
         // <mn||ej> = -<mn||je>
-        const cd x = to_cd(h[(int64_t)j * nv]);
-        cd acc = make_double2(-x.x, -x.y);
+        cd acc = make_double2(-(double)hx[j], -(double)hy[j]);
 #pragma unroll
         for (int f = 0; f < VM; ++f)
             if (f < nv) cfma(acc, T1J[j * nv + f], gr[f]);
